@@ -1,0 +1,207 @@
+/*
+ * tk.h -- C ABI of the MI355X (gfx950) batched silhouette-fitness library.
+ *
+ * The library evaluates, for lambda candidate states of a surgical instrument
+ * (6-DoF look-at pose + 3 joint angles per arm), the silhouette-matching
+ * objective of a CMA-ES tracker and runs the CMA-ES sample/update steps around
+ * it (arXiv 2603.11404, Sec. III-A: problem statement Eq. (objective), CMA-ES
+ * Eq. (cmaes_update), render loss Eq. (render_loss), renderer
+ * S = R(K(Pi(T_r^c T_m^r(q) v_m))), state parameterisation; Sec. III-B
+ * bi-manual block-diagonal covariance; Sec. IV mask error 1 - IoU).
+ *
+ * Conventions (all entry points):
+ *   - Pointers named d_* are DEVICE pointers, caller-allocated and caller-
+ *     freed.  Struct arguments (tk_camera, tk_mesh, tk_chain, ...) are HOST
+ *     structs read during the call; the device pointers inside tk_mesh must
+ *     stay valid until the queued work has run.
+ *   - Work is queued on the given HIP stream (0 = legacy default stream);
+ *     nothing synchronises the stream and no entry point allocates device
+ *     memory.
+ *   - Arguments are validated before anything is queued; on error nothing is
+ *     queued, the status is returned and tk_last_error() (thread-local) holds a
+ *     readable description.  A failed kernel launch returns TK_ERR_DEVICE.
+ *   - Determinism: the same inputs (and, for CMA-ES, the same seed and
+ *     generation) give bit-identical outputs.
+ *   - Mask layout: a binary H x W image is stored as ceil(H/8) x ceil(W/8)
+ *     uint64 words, row-major; pixel (x, y) is bit (y%8)*8 + (x%8) of word
+ *     [y/8][x/8]; bits of pixels outside the image are zero.
+ *   - Snapped vertices: Q8 fixed point, (X, Y) = rint(256 * clamp(u, +-32768))
+ *     with ties to even; pixel (x, y) has its centre at (256x+128, 256y+128).
+ *     A vertex that fails the near plane (or is not a number) is stored with
+ *     X = INT32_MIN.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* tk_stream; /* same type as hipStream_t */
+
+typedef enum {
+    TK_OK = 0,
+    TK_ERR_INVALID_ARGUMENT = 1,
+    TK_ERR_UNSUPPORTED = 2,
+    TK_ERR_WORKSPACE_TOO_SMALL = 3,
+    TK_ERR_DEVICE = 4
+} tk_status;
+
+/* Static description of a status code. */
+const char* tk_status_string(tk_status s);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* tk_last_error(void);
+/* Library version, e.g. 100 for 1.0.0. */
+int32_t tk_version(void);
+
+/* Pinhole camera K (Sec. III-A.2): u = fx*X/Z + cx, v = fy*Y/Z + cy, image y
+ * pointing down; vertices with Z < z_near are culled with their triangles.
+ * 1 <= width, height <= 4096. */
+typedef struct { float fx, fy, cx, cy; int32_t width, height; float z_near; } tk_camera;
+
+/* Instrument mesh v_m (Sec. III-A.2), device pointers:
+ *   vertices [n_vertices][3] float32, metres, in the frame of their link;
+ *   triangles [n_triangles][3] int32 vertex indices (either winding);
+ *   vertex_link [n_vertices] uint8 in 0..3 (shaft, wrist, jaw+, jaw-).
+ * 0 <= n_triangles <= 16M, 1 <= n_vertices <= 16M. */
+typedef struct {
+    int32_t n_vertices, n_triangles;
+    const float* vertices;
+    const int32_t* triangles;
+    const uint8_t* vertex_link;
+} tk_mesh;
+
+/* Kinematic chain of one instrument (Sec. III-A.3 and Fig. 2: end-effector
+ * frame at the wrist pitch axis, z distal):
+ *   shaft  T_0 = I;  wrist T_1 = Rx(q1);
+ *   jaw+   T_2 = Rx(q1) Tr(0,0,d_pitch_yaw) Ry(q2 + q3/2);
+ *   jaw-   T_3 = Rx(q1) Tr(0,0,d_pitch_yaw) Ry(q2 - q3/2).
+ * q_lb/q_ub are the joint limits of the cosine map; keypoints[j] = (x, y, z in
+ * metres in the frame of link id keypoints[j][3]). */
+typedef struct {
+    double d_pitch_yaw;
+    double q_lb[3], q_ub[3];
+    double keypoints[4][4];
+} tk_chain;
+
+/* ------------------------------------------------------------------ CMA-ES */
+
+/* Multipliers on the default learning rates (paper Sec. IV raises c_m and
+ * c_mu above their defaults without giving values; 1.0 = Hansen defaults) and
+ * the number of diagonal covariance blocks (1, or 2 for the bi-manual
+ * block-diagonal Sigma of Sec. III-B). */
+typedef struct {
+    double c_m_scale, c_mu_scale, c1_scale;
+    int32_t n_blocks;
+} tk_cmaes_params;
+
+/* Byte offsets of the fields of the CMA-ES state blob (see tk_cmaes_layout).
+ * Scalars are FP64 unless noted; matrices are row-major FP64. */
+typedef struct {
+    int64_t total_bytes;
+    int64_t gen;        /* int64 generation counter g */
+    int64_t seed;       /* uint64 Philox key */
+    int64_t flags;      /* int32 bit 0: an eigenvalue was floored, bit 1: sigma not finite */
+    int64_t sigma, c_sigma, d_sigma, c_c, c1, c_mu, c_m, mu_eff, chi_n, h_sigma;
+    int64_t weights;    /* [lambda] (first mu used) */
+    int64_t mean, p_sigma, p_c, offset, scale, D;   /* [n] */
+    int64_t C, B;       /* [n][n]; B columns are eigenvectors, D their sqrt eigenvalues */
+    int64_t Z, Y;       /* [lambda][n] last draws z and y = B D z */
+    int64_t order;      /* int32 [lambda] ranking of the last update */
+} tk_cmaes_layout;
+
+/* Size in bytes of a state blob for dimension n (1..18) and population
+ * lambda (2..1024); 0 on invalid sizes. */
+size_t tk_cmaes_state_bytes(int32_t n, int32_t lambda);
+tk_status tk_cmaes_layout_get(int32_t n, int32_t lambda, tk_cmaes_layout* out);
+
+/* Initialise a state blob (Sec. III-A.1; Sec. IV: Sigma^(0) = I in the
+ * normalised space): m = mean0 (normalised space, host [n]), sigma = sigma0,
+ * C = B = I, D = 1, p_sigma = p_c = 0, g = 0.  Physical candidates are
+ * theta = offset + scale * x (host [n] each).  p may be NULL for defaults.
+ * n must be divisible by p->n_blocks. */
+tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
+                        const double* offset, const double* scale, const tk_cmaes_params* p,
+                        uint64_t seed, tk_stream s);
+
+/* Replace the mean (normalised space, host [n]) without touching sigma, C or
+ * the paths (warm start from the previous frame, Sec. III-A). */
+tk_status tk_cmaes_set_mean(void* d_state, int32_t n, int32_t lambda, const double* mean, tk_stream s);
+
+/* Sample lambda candidates from N(m, sigma^2 C) (Sec. III-A.1, Eq.
+ * expected_fitness): z from Philox4x32-10 (key = seed, counter = (j, k, g, 0))
+ * with Box-Muller, y = B D z, x = m + sigma y.  Writes d_X[lambda][n] FP32
+ * physical candidates theta = offset + scale * x and keeps z, y in the state. */
+tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, tk_stream s);
+
+/* One CMA-ES update from the losses of the last sample (Sec. III-A.1, Eq.
+ * cmaes_update, completed by Hansen's tutorial): rank by (loss, index) with
+ * NaN as +inf, weighted recombination of the mu = lambda/2 best, cumulative
+ * step-size adaptation, rank-one + rank-mu covariance update, symmetrisation,
+ * optional block-diagonal masking (Sec. III-B), Jacobi eigendecomposition.
+ * d_loss: device FP64 [lambda]. */
+tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double* d_loss, tk_stream s);
+
+/* ------------------------------------------------------- fitness evaluation */
+
+/* Forward kinematics (Sec. III-A.3 and the renderer input T_r^c T_m^r(q)):
+ * d_X[batch][9*n_arms] FP32 candidates (alpha, beta, gamma, x, y, z, qhat1..3
+ * per arm) -> d_link_xf[batch][n_arms][4][12] FP32 row-major 3x4 transforms
+ * M_l = T_r^c(alpha,beta,gamma,x,y,z) T_l(q), q from the cosine map; computed
+ * in FP64 and rounded.  d_kp (nullable) [batch][n_arms][4][2] FP32 projected
+ * chain keypoints (NaN when behind z_near).  chains: host [n_arms]. */
+tk_status tk_fk_transform(const float* d_X, int32_t batch, int32_t n_arms, const tk_chain* chains,
+                          float* d_link_xf, float* d_kp, const tk_camera* cam, tk_stream s);
+
+/* Transform, project and snap every vertex (FP32 transform, Q8 snap):
+ * d_snapped[batch][sum of n_vertices][2] int32 (arms concatenated). */
+tk_status tk_snap_vertices(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
+                           const tk_camera* cam, int32_t* d_snapped, tk_stream s);
+
+/* Binary silhouette S (Sec. III-A.2: S in {0,1}^{H x W}) of every candidate:
+ * OR over the n_meshes arms (one mesh per arm, link transforms from
+ * d_link_xf[batch][n_meshes][4][12]) of the exact integer coverage with the
+ * top-left fill rule, both windings drawn, no depth test.
+ * d_masks [batch][ceil(H/8)][ceil(W/8)] uint64.  width*height <= 1280*800. */
+tk_status tk_raster_silhouette(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
+                               const tk_camera* cam, uint64_t* d_masks, tk_stream s);
+
+/* Same coverage from given snapped vertices d_snapped[batch][sum V][2]. */
+tk_status tk_raster_from_snapped(const int32_t* d_snapped, int32_t batch, const tk_mesh* meshes,
+                                 int32_t n_meshes, const tk_camera* cam, uint64_t* d_masks, tk_stream s);
+
+/* Counts of the render loss (Eq. render_loss) against the observed mask
+ * M_ref: d_counts[batch][2] int32 = {|S|, |S and M|}.  d_target: one mask. */
+tk_status tk_mask_loss(const uint64_t* d_masks, int32_t batch, const uint64_t* d_target, const tk_camera* cam,
+                       int32_t* d_counts, tk_stream s);
+
+/* d_count[batch] int32 = |S| for each mask (e.g. the target count |M|). */
+tk_status tk_mask_popcount(const uint64_t* d_masks, int32_t batch, const tk_camera* cam, int32_t* d_count,
+                           tk_stream s);
+
+/* Fused raster + counts: d_link_xf -> d_counts[batch][2] without writing
+ * masks (same coverage as tk_raster_silhouette followed by tk_mask_loss). */
+tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
+                        const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, tk_stream s);
+
+/* Loss composition in FP64 (Eq. objective and render_loss; Sec. IV):
+ *   kind 0: 1 - IoU = 1 - i/(a + m - i)  (0 when the union is empty);
+ *   kind 1: (a + m - 2i) + lambda_app*|a - m|  (sum of squared mask errors
+ *           plus the appearance term, exact on binary masks);
+ * plus, when d_kp and d_kp_ref are given and lambda_kp != 0, lambda_kp times
+ * the keypoint term of every arm (Eq. kpts_loss extended to the 4 chain
+ * keypoints: (|p_j - r_j| - tau)_+ for the shaft and wrist keypoints, the
+ * better of the two jaw-tip assignments, and the tip-midpoint term).
+ * d_counts [batch][2] from tk_mask_loss, d_target_count: device int32 |M|,
+ * d_kp [batch][n_arms][4][2], d_kp_ref [n_arms][4][2], d_loss [batch] FP64. */
+tk_status tk_compose_loss(const int32_t* d_counts, int32_t batch, const int32_t* d_target_count, int32_t kind,
+                          double lambda_app, const float* d_kp, const float* d_kp_ref, int32_t n_arms,
+                          double lambda_kp, double tau, double* d_loss, tk_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,387 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module produces DATA only: a procedural instrument mesh, the kinematic
+chain constants, pinhole cameras, seeded true poses, pixel-flip sets, occluder
+rectangles and trajectories.  It holds none of the method's arithmetic (no
+forward kinematics, no projection, no rasterisation, no CMA-ES); whoever needs
+a rendered target renders it with their own implementation.
+
+The paper's CAD mesh of the Large Needle Driver and its datasets are not
+available, so the shapes stand in for them (paper Sec. III-A, Eq. for the
+renderer input v_m; Sec. IV synthetic/real datasets: 640x480 and 700x493
+masks, joint limits, 1000-frame trajectories).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BASE_SEED = 11404
+
+# Sub-stream offsets added to a config's base seed.
+SUB_POSE, SUB_FLIPS, SUB_OCCLUDER, SUB_CMAES, SUB_TRAJ = 0, 1, 2, 3, 4
+
+LINK_SHAFT, LINK_WRIST, LINK_JAW_POS, LINK_JAW_NEG = 0, 1, 2, 3
+N_LINKS = 4
+N_PARAMS = 9  # alpha, beta, gamma, x, y, z, qhat1, qhat2, qhat3
+
+
+@dataclasses.dataclass
+class Mesh:
+    vertices: np.ndarray   # [V,3] float32, metres, link frame of vertex_link
+    triangles: np.ndarray  # [T,3] int32
+    vertex_link: np.ndarray  # [V] uint8, non-decreasing
+    shape: dict            # generator parameters
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.vertices.shape[0])
+
+    @property
+    def n_triangles(self) -> int:
+        return int(self.triangles.shape[0])
+
+
+@dataclasses.dataclass
+class Chain:
+    d_pitch_yaw: float          # distance wrist-pitch axis -> yaw axis along z (m)
+    q_lb: np.ndarray            # [3] joint lower limits (rad)
+    q_ub: np.ndarray            # [3] joint upper limits (rad)
+    keypoints: np.ndarray       # [4,4] float: x, y, z (link frame, m), link id
+
+
+@dataclasses.dataclass
+class Camera:
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    z_near: float = float(np.float32(0.01))   # 1 cm, stored as the float32 value both sides use
+
+
+# --------------------------------------------------------------------------
+# Procedural instrument mesh
+# --------------------------------------------------------------------------
+
+def _quad_grid(p0, du, dv, nu, nv):
+    """Vertices and triangles of a planar nu x nv grid p0 + i/nu*du + j/nv*dv."""
+    p0, du, dv = (np.asarray(a, dtype=np.float64) for a in (p0, du, dv))
+    ii, jj = np.meshgrid(np.arange(nu + 1), np.arange(nv + 1), indexing="ij")
+    verts = p0 + (ii[..., None] / nu) * du + (jj[..., None] / nv) * dv
+    verts = verts.reshape(-1, 3)
+    idx = np.arange((nu + 1) * (nv + 1)).reshape(nu + 1, nv + 1)
+    a = idx[:-1, :-1].ravel()
+    b = idx[1:, :-1].ravel()
+    c = idx[1:, 1:].ravel()
+    d = idx[:-1, 1:].ravel()
+    tris = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)])
+    return verts, tris
+
+
+def _tri_subdiv(p0, p1, p2, m):
+    """Split triangle p0 p1 p2 into m*m congruent triangles."""
+    p0, p1, p2 = (np.asarray(a, dtype=np.float64) for a in (p0, p1, p2))
+    verts, index = [], {}
+    for i in range(m + 1):
+        for j in range(m + 1 - i):
+            index[(i, j)] = len(verts)
+            verts.append(p0 + (i / m) * (p1 - p0) + (j / m) * (p2 - p0))
+    tris = []
+    for i in range(m):
+        for j in range(m - i):
+            tris.append((index[(i, j)], index[(i + 1, j)], index[(i, j + 1)]))
+            if j < m - i - 1:
+                tris.append((index[(i + 1, j)], index[(i + 1, j + 1)], index[(i, j + 1)]))
+    return np.array(verts), np.array(tris, dtype=np.int64)
+
+
+def instrument_mesh(segments=32, rings=28, box_div=3, wedge_div=1,
+                    jaw_scale=1.0, box_scale=1.0) -> Mesh:
+    """Procedural stand-in for the Large Needle Driver.
+
+    Link frames: the end-effector (robot) frame sits at the wrist-pitch axis
+    with z pointing distally (paper Fig. 2 caption, Sec. III-A).
+      * shaft (link 0): open cylinder r = 4 mm on z in [-0.302, -0.002];
+        `segments` around, `rings` interior rings -> 2*segments*(rings+1) tris.
+      * wrist (link 1): box x, y in +-3.5 mm (x box_scale), z in [-0.002, 0.009];
+        each face split box_div x box_div -> 12*box_div^2 tris.
+      * jaws (links 2, 3): triangular prisms in the jaw frames, base half-width
+        2.5 mm, length 14 mm (x jaw_scale), y in +-2 mm; jaw+ in x >= 0, jaw-
+        mirrored -> 16*wedge_div^2 tris.
+    Vertices are emitted sorted by link.
+    """
+    parts = []  # (verts, tris, link)
+
+    # shaft
+    r0, z0, z1 = 0.004, -0.302, -0.002
+    nz = rings + 2
+    ang = 2.0 * math.pi * np.arange(segments) / segments
+    zs = np.linspace(z0, z1, nz)
+    verts = np.stack([np.repeat(np.cos(ang)[None, :] * r0, nz, 0),
+                      np.repeat(np.sin(ang)[None, :] * r0, nz, 0),
+                      np.repeat(zs[:, None], segments, 1)], -1).reshape(-1, 3)
+    tris = []
+    for i in range(nz - 1):
+        for j in range(segments):
+            a = i * segments + j
+            b = i * segments + (j + 1) % segments
+            c = (i + 1) * segments + (j + 1) % segments
+            d = (i + 1) * segments + j
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    parts.append((verts, np.array(tris, dtype=np.int64), LINK_SHAFT))
+
+    # wrist box
+    h = 0.0035 * box_scale
+    bz0, bz1 = -0.002, 0.009
+    k = box_div
+    faces = [
+        ((-h, -h, bz0), (2 * h, 0, 0), (0, 2 * h, 0)),      # z = bz0
+        ((-h, -h, bz1), (0, 2 * h, 0), (2 * h, 0, 0)),      # z = bz1
+        ((-h, -h, bz0), (0, 0, bz1 - bz0), (2 * h, 0, 0)),  # y = -h
+        ((-h, h, bz0), (2 * h, 0, 0), (0, 0, bz1 - bz0)),   # y = +h
+        ((-h, -h, bz0), (0, 2 * h, 0), (0, 0, bz1 - bz0)),  # x = -h
+        ((h, -h, bz0), (0, 0, bz1 - bz0), (0, 2 * h, 0)),   # x = +h
+    ]
+    bv, bt = [], []
+    for p0, du, dv in faces:
+        v, t = _quad_grid(p0, du, dv, k, k)
+        bt.append(t + sum(len(x) for x in bv))
+        bv.append(v)
+    parts.append((np.concatenate(bv), np.concatenate(bt), LINK_WRIST))
+
+    # jaws
+    w = 0.0025 * jaw_scale
+    L = 0.014 * jaw_scale
+    hy = 0.002
+    m = wedge_div
+    for sign, link in ((1.0, LINK_JAW_POS), (-1.0, LINK_JAW_NEG)):
+        A = np.array([0.0, 0.0]); B = np.array([sign * w, 0.0]); C = np.array([0.0, L])
+
+        def xyz(p, y):
+            return (p[0], y, p[1])
+        wv, wt = [], []
+
+        def add(v, t):
+            wt.append(t + sum(len(x) for x in wv))
+            wv.append(v)
+        # two caps at y = -hy, +hy
+        for y in (-hy, hy):
+            add(*_tri_subdiv(xyz(A, y), xyz(B, y), xyz(C, y), m))
+        # three rectangular sides
+        for P, Q in ((A, B), (B, C), (C, A)):
+            p0 = xyz(P, -hy)
+            du = np.subtract(xyz(Q, -hy), p0)
+            dv = (0.0, 2 * hy, 0.0)
+            add(*_quad_grid(p0, du, dv, m, m))
+        parts.append((np.concatenate(wv), np.concatenate(wt), link))
+
+    all_v, all_t, all_l = [], [], []
+    off = 0
+    for v, t, link in parts:
+        all_v.append(v)
+        all_t.append(t + off)
+        all_l.append(np.full(len(v), link, dtype=np.uint8))
+        off += len(v)
+    return Mesh(np.concatenate(all_v).astype(np.float32),
+                np.concatenate(all_t).astype(np.int32),
+                np.concatenate(all_l),
+                dict(segments=segments, rings=rings, box_div=box_div, wedge_div=wedge_div,
+                     jaw_scale=jaw_scale, box_scale=box_scale))
+
+
+def mesh_for_triangles(n_tris: int, jaw_scale=1.0, box_scale=1.0) -> Mesh:
+    """Procedural mesh with a triangle count close to n_tris (exact count in .n_triangles)."""
+    if n_tris < 8000:
+        s, k, m = 32, 3, 1
+    else:
+        s, k, m = 64, 6, 4
+    rest = n_tris - 12 * k * k - 16 * m * m
+    rings = max(0, int(round(rest / (2 * s))) - 1)
+    return instrument_mesh(s, rings, k, m, jaw_scale, box_scale)
+
+
+def chain(jaw_scale=1.0) -> Chain:
+    """Chain constants matching instrument_mesh (joint limits: q1, q2 in
+    [-pi/2, pi/2], jaw q3 in [0, pi/2]; keypoints: shaft end, yaw centre, two
+    jaw tips)."""
+    d = 0.009
+    L = 0.014 * jaw_scale
+    kp = np.array([[0.0, 0.0, -0.002, LINK_SHAFT],
+                   [0.0, 0.0, d, LINK_WRIST],
+                   [0.0, 0.0, L, LINK_JAW_POS],
+                   [0.0, 0.0, L, LINK_JAW_NEG]], dtype=np.float64)
+    return Chain(d, np.array([-math.pi / 2, -math.pi / 2, 0.0]),
+                 np.array([math.pi / 2, math.pi / 2, math.pi / 2]), kp)
+
+
+def camera(width: int, height: int, f: float | None = None) -> Camera:
+    """Pinhole camera, principal point at the image centre, f = 1.25*W unless given."""
+    if f is None:
+        f = 1.25 * width
+    return Camera(float(f), float(f), width / 2.0, height / 2.0, int(width), int(height))
+
+
+# --------------------------------------------------------------------------
+# Poses, targets, trajectories
+# --------------------------------------------------------------------------
+
+def rng_for(config_index: int, sub: int) -> np.random.Generator:
+    return np.random.default_rng(BASE_SEED + config_index + 1000 * sub)
+
+
+def true_pose(rng: np.random.Generator, cam: Camera) -> np.ndarray:
+    """One seeded physical parameter vector (alpha, beta, gamma, x, y, z, qhat1..3).
+
+    Chosen by bounds, without rendering: the wrist sits at depth 8-15 cm inside
+    the central half of the field of view; alpha near pi and |gamma| <= 0.8
+    tilt the shaft 20-60 deg away from the camera so every vertex stays at
+    least ~5 cm deep; beta is uniform; joints are drawn in the unconstrained
+    coordinate.
+    """
+    z = rng.uniform(0.08, 0.15)
+    x = z * rng.uniform(-0.25, 0.25) * cam.width / cam.fx
+    y = z * rng.uniform(-0.25, 0.25) * cam.height / cam.fy
+    alpha = math.pi + rng.choice([-1.0, 1.0]) * rng.uniform(0.35, 0.8)
+    gamma = rng.choice([-1.0, 1.0]) * rng.uniform(0.2, 0.8)
+    beta = rng.uniform(-math.pi, math.pi)
+    qh1 = rng.uniform(-0.8, 0.8)
+    qh2 = rng.uniform(-0.8, 0.8)
+    qh3 = rng.uniform(0.3, 0.8)
+    return np.array([alpha, beta, gamma, x, y, z, qh1, qh2, qh3], dtype=np.float64)
+
+
+#: Normalisation scales s in theta = o + s * x (rad, rad, rad, m, m, m, rad, rad, rad).
+DEFAULT_SCALE = np.array([0.05, 0.05, 0.05, 0.005, 0.005, 0.005, 0.1, 0.1, 0.1])
+
+
+def trajectory(rng: np.random.Generator, cam: Camera, n_frames: int) -> np.ndarray:
+    """Smooth seeded trajectory [n_frames, 9]: per frame the translation moves
+    exactly 1 mm and the look-at angles exactly 0.5 deg (Euclidean in angle
+    space) along slowly turning seeded directions; the joints follow seeded
+    sinusoids in the unconstrained coordinate."""
+    th = true_pose(rng, cam)
+    out = np.empty((n_frames, N_PARAMS))
+    dir_t = rng.normal(size=3)
+    dir_r = rng.normal(size=3)
+    ph = rng.uniform(0, 2 * math.pi, size=3)
+    fr = rng.uniform(0.02, 0.06, size=3)
+    amp = np.array([0.5, 0.5, 0.2])
+    mid = np.array([0.0, 0.0, 0.55])
+    for t in range(n_frames):
+        out[t] = th
+        out[t, 6:9] = mid + amp * np.sin(fr * t + ph)
+        dir_t = dir_t + 0.3 * rng.normal(size=3)
+        dir_r = dir_r + 0.3 * rng.normal(size=3)
+        # keep the wrist inside the depth band and the shaft tilted away
+        if th[5] > 0.14:
+            dir_t[2] = -abs(dir_t[2])
+        if th[5] < 0.09:
+            dir_t[2] = abs(dir_t[2])
+        th = th.copy()
+        th[3:6] += 0.001 * dir_t / np.linalg.norm(dir_t)
+        th[0:3] += math.radians(0.5) * dir_r / np.linalg.norm(dir_r)
+        th[0] = min(max(th[0], math.pi - 0.8), math.pi + 0.8)
+        th[2] = min(max(th[2], -0.8), 0.8)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Mask layout helpers (bit ly*8+lx of word [y/8][x/8]) and corruptions
+# --------------------------------------------------------------------------
+
+def mask_words_shape(width: int, height: int) -> tuple[int, int]:
+    return ((height + 7) // 8, (width + 7) // 8)
+
+
+def words_to_image(words: np.ndarray, width: int, height: int) -> np.ndarray:
+    """[..., by, bx] uint64 words -> [..., H, W] bool image."""
+    words = np.asarray(words, dtype=np.uint64)
+    by, bx = mask_words_shape(width, height)
+    lead = words.shape[:-2]
+    bits = ((words[..., None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)).astype(bool)
+    bits = bits.reshape(*lead, by, bx, 8, 8)            # ly, lx
+    img = np.moveaxis(bits, -2, -3).reshape(*lead, by * 8, bx * 8)
+    return img[..., :height, :width]
+
+
+def image_to_words(img: np.ndarray) -> np.ndarray:
+    """[..., H, W] bool -> [..., ceil(H/8), ceil(W/8)] uint64 words (padding bits zero)."""
+    img = np.asarray(img, dtype=bool)
+    *lead, H, W = img.shape
+    by, bx = mask_words_shape(W, H)
+    pad = np.zeros((*lead, by * 8, bx * 8), dtype=bool)
+    pad[..., :H, :W] = img
+    t = pad.reshape(*lead, by, 8, bx, 8)
+    t = np.moveaxis(t, -3, -2)                          # by, bx, ly, lx
+    t = t.reshape(*lead, by, bx, 64).astype(np.uint64)
+    return (t << np.arange(64, dtype=np.uint64)).sum(-1, dtype=np.uint64)
+
+
+def flip_indices(rng: np.random.Generator, width: int, height: int, fraction=0.01) -> np.ndarray:
+    """Exactly round(fraction*W*H) distinct seeded pixel indices (y*W + x)."""
+    n = int(round(fraction * width * height))
+    return rng.choice(width * height, size=n, replace=False).astype(np.int64)
+
+
+def apply_flips(words: np.ndarray, width: int, height: int, idx: np.ndarray) -> np.ndarray:
+    """XOR-flip the given pixels of a word mask (returns a copy)."""
+    out = np.array(words, dtype=np.uint64, copy=True)
+    y, x = np.divmod(np.asarray(idx, dtype=np.int64), width)
+    bit = ((y % 8) * 8 + (x % 8)).astype(np.uint64)
+    flat = out.reshape(-1)
+    widx = (y // 8) * ((width + 7) // 8) + x // 8
+    for w, b in zip(widx, bit):
+        flat[w] ^= np.uint64(1) << b
+    return out
+
+
+def occluder_rect(img: np.ndarray, rng: np.random.Generator, lo=0.1, hi=0.3):
+    """Axis-aligned rectangle (x0, y0, x1, y1), exclusive ends, covering a
+    fraction phi ~ U[lo, hi] of the silhouette's pixels: a square grown around
+    a random silhouette pixel until it holds at least phi of them."""
+    img = np.asarray(img, dtype=bool)
+    ys, xs = np.nonzero(img)
+    total = len(ys)
+    phi = rng.uniform(lo, hi)
+    if total == 0:
+        return (0, 0, 0, 0), phi
+    i = rng.integers(total)
+    cy, cx = int(ys[i]), int(xs[i])
+    H, W = img.shape
+    csum = np.pad(img.astype(np.int64).cumsum(0).cumsum(1), ((1, 0), (1, 0)))
+    r = 0
+    while True:
+        x0, x1 = max(cx - r, 0), min(cx + r + 1, W)
+        y0, y1 = max(cy - r, 0), min(cy + r + 1, H)
+        inside = csum[y1, x1] - csum[y0, x1] - csum[y1, x0] + csum[y0, x0]
+        if inside >= phi * total or (x0 == 0 and y0 == 0 and x1 == W and y1 == H):
+            return (x0, y0, x1, y1), phi
+        r += 1
+
+
+def apply_occluder(img: np.ndarray, rect) -> np.ndarray:
+    x0, y0, x1, y1 = rect
+    out = np.array(img, dtype=bool, copy=True)
+    out[..., y0:y1, x0:x1] = False
+    return out
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def workload(name: str) -> dict:
+    """Shapes of the named synthetic workloads (see the parameter table in the
+    design notes): returns mesh/camera/lambda/generation counts."""
+    if name == "small":          # 2k tris, 320x240, f=400, lambda=16, 20 gens
+        return dict(mesh=instrument_mesh(32, 28, 3, 1), cam=camera(320, 240, 400.0),
+                    lam=16, gens=20, frames=1, index=0)
+    if name == "track640":       # 20k tris, 640x480, lambda=256, 30 gens x 100 frames
+        return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(640, 480),
+                    lam=256, gens=30, frames=100, index=1)
+    raise KeyError(name)

@@ -1,0 +1,68 @@
+"""Sanity of the seeded input generators (data only)."""
+import numpy as np
+
+import scenes
+
+
+def test_mesh_triangle_counts():
+    m = scenes.instrument_mesh(32, 28, 3, 1)
+    assert m.n_triangles == 2 * 32 * 29 + 12 * 9 + 16 == 1980
+    m2 = scenes.instrument_mesh(64, 150, 6, 4)
+    assert m2.n_triangles == 2 * 64 * 151 + 12 * 36 + 16 * 16
+    for mesh in (m, m2, scenes.mesh_for_triangles(35000, 1.3, 1.2), scenes.mesh_for_triangles(3000)):
+        assert mesh.triangles.min() >= 0 and mesh.triangles.max() < mesh.n_vertices
+        assert np.all(np.diff(mesh.vertex_link.astype(int)) >= 0)       # sorted by link
+        assert set(np.unique(mesh.vertex_link)) == {0, 1, 2, 3}
+        assert mesh.vertices.dtype == np.float32 and mesh.triangles.dtype == np.int32
+        # every triangle uses vertices of a single link
+        tl = mesh.vertex_link[mesh.triangles]
+        assert np.all(tl.min(1) == tl.max(1))
+    assert abs(scenes.mesh_for_triangles(35000).n_triangles - 35000) < 200
+
+
+def test_mask_layout_roundtrip():
+    rng = np.random.default_rng(0)
+    for W, H in [(320, 240), (13, 9), (960, 540)]:
+        img = rng.random((H, W)) < 0.5
+        w = scenes.image_to_words(img)
+        assert w.shape == ((H + 7) // 8, (W + 7) // 8)
+        np.testing.assert_array_equal(scenes.words_to_image(w, W, H), img)
+    # bit (y%8)*8 + x%8 of word [y/8][x/8]
+    img = np.zeros((16, 16), bool)
+    img[9, 3] = True
+    w = scenes.image_to_words(img)
+    assert w[1, 0] == np.uint64(1) << np.uint64(8 + 3)
+
+
+def test_flips_distinct_and_exact_count():
+    idx = scenes.flip_indices(scenes.rng_for(1, scenes.SUB_FLIPS), 640, 480)
+    assert len(idx) == 3072 and len(np.unique(idx)) == 3072
+    w = np.zeros((60, 80), np.uint64)
+    f = scenes.apply_flips(w, 640, 480, idx)
+    assert scenes.words_to_image(f, 640, 480).sum() == 3072
+
+
+def test_true_pose_ranges_and_determinism():
+    cam = scenes.camera(640, 480)
+    a = scenes.true_pose(scenes.rng_for(1, 0), cam)
+    b = scenes.true_pose(scenes.rng_for(1, 0), cam)
+    assert np.array_equal(a, b)
+    assert 0.08 <= a[5] <= 0.15
+
+
+def test_trajectory_steps():
+    cam = scenes.camera(640, 480)
+    tr = scenes.trajectory(scenes.rng_for(1, scenes.SUB_TRAJ), cam, 100)
+    assert tr.shape == (100, 9)
+    dt = np.linalg.norm(np.diff(tr[:, 3:6], axis=0), axis=1)
+    np.testing.assert_allclose(dt, 0.001, rtol=1e-9)
+
+
+def test_occluder_covers_requested_fraction():
+    img = np.zeros((100, 120), bool)
+    img[20:60, 30:100] = True
+    rect, phi = scenes.occluder_rect(img, np.random.default_rng(3))
+    x0, y0, x1, y1 = rect
+    frac = img[y0:y1, x0:x1].sum() / img.sum()
+    assert 0.1 <= phi <= 0.3 and frac >= phi
+    assert scenes.apply_occluder(img, rect).sum() == img.sum() - img[y0:y1, x0:x1].sum()
