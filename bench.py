@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Throughput of the batched CMA-ES silhouette-fitness path on one MI355X.
+
+Workload (single-instrument tracking, 640x480): 20016-triangle procedural
+instrument, lambda = 256 candidates of 9 parameters, loss = 1 - IoU + 0.1 x
+keypoint reprojection term, 30 CMA-ES generations per frame over a seeded
+100-frame trajectory with 1% pixel-flip noise in the targets and 2-degree
+noise on the joint readings.  A step is one generation: sample -> FK ->
+transform/project/snap -> raster -> counts -> loss -> update, all in HIP
+kernels; the frame loop re-initialises CMA-ES from the previous estimate.
+
+Prints ONE JSON line (rank 0).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000, help="timed generations (default: 100 frames x 30)")
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall time budget of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the graph and plain-launch comparison loops")
+    ap.add_argument("--plain-gens", type=int, default=2)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": f"bench.py measures the single-GPU path only; --gpus {args.gpus} "
+                                   f"(WORLD_SIZE {world}) is not supported by this build. How the path would "
+                                   "shard over several GPUs is described in DESIGN.md."}))
+        sys.exit(2)
+
+    import torch
+
+    import scenes
+    from paper_2603_11404_amd import tk, tracker
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = scenes.workload("track640")
+    mesh, cam, lam, G, F = wl["mesh"], wl["cam"], wl["lam"], wl["gens"], wl["frames"]
+    chain = scenes.chain()
+    scale = scenes.DEFAULT_SCALE.copy()
+    log(f"workload: {mesh.n_triangles} tris, {cam.width}x{cam.height}, lambda={lam}, {G} gens x {F} frames")
+
+    # ---------------------------------------------------------------- inputs resident in HBM
+    prob = tracker.Problem([mesh], [chain], cam, dev)
+    traj = scenes.trajectory(scenes.rng_for(wl["index"], scenes.SUB_TRAJ), cam, F)
+    theta_true = torch.as_tensor(traj.astype(np.float32), device=dev)
+    clean = prob.render(theta_true)                                   # [F, 60, 80] int64 words
+    kp_true = prob.keypoints(theta_true)                              # [F, 1, 4, 2]
+    rng_f = scenes.rng_for(wl["index"], scenes.SUB_FLIPS)
+    flips = np.stack([scenes.image_to_words(
+        np.isin(np.arange(cam.width * cam.height), scenes.flip_indices(rng_f, cam.width, cam.height))
+        .reshape(cam.height, cam.width)) for _ in range(F)])
+    targets = clean ^ torch.as_tensor(flips.view(np.int64), device=dev)
+    rng_q = scenes.rng_for(wl["index"], scenes.SUB_CMAES)
+    q_true = tracker.decode_joints(traj[:, 6:9], chain)
+    readings = tracker.encode_joints(q_true + rng_q.normal(size=q_true.shape) * math.radians(2.0), chain)
+    est0 = traj[0] + scale * rng_q.normal(size=9)
+    torch.cuda.synchronize()
+
+    gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU, lambda_kp=0.1)
+    seed0 = scenes.BASE_SEED + wl["index"] + 1000 * scenes.SUB_CMAES
+    state = {"est": est0.copy(), "frame": -1}
+
+    def start_frame(f):
+        prob.set_target(targets[f], kp_true[f])
+        mean_phys = state["est"].copy()
+        mean_phys[6:9] = readings[f]                  # joint readings initialise the joint means
+        gen.init(np.zeros(9), 1.0, mean_phys, scale, seed0 + f)
+        state["frame"] = f
+
+    def run_step(s, events=None):
+        f, g = (s // G) % F, s % G
+        if g == 0:
+            if state["frame"] >= 0:
+                state["est"] = gen.mean()             # warm start: previous frame's estimate (D2H)
+            start_frame(f)
+        tk.cmaes_sample(gen.state, gen.n, gen.lam, gen.X)
+        tk.fk_transform(gen.X, gen.lam, 1, prob.chains, gen.xf, gen.kp, cam)
+        if events is not None:
+            events[0].record()
+        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts)
+        if events is not None:
+            events[1].record()
+        tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
+                        1, 0.1, 0.0)
+        tk.cmaes_update(gen.state, gen.n, gen.lam, gen.loss)
+
+    # ---------------------------------------------------------------- warm-up and timed region
+    for s in range(args.warmup):
+        run_step(s)
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} generations)")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start.record()
+    for i in range(args.steps):
+        run_step(args.warmup + i, evs[i])
+        if (i + 1) % 500 == 0:
+            log(f"timed generations queued: {i + 1}/{args.steps}")
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = t_start.elapsed_time(t_end)
+    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    fused_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    final_est = gen.mean()
+    log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events; "
+        f"fused raster avg {fused_ms.mean() * 1e3:.1f} us")
+
+    # pose error of the last estimate against the truth of its frame
+    last_f = ((args.warmup + args.steps - 1) // G) % F
+    err_t = float(np.linalg.norm(final_est[3:6] - traj[last_f, 3:6]))
+
+    # ---------------------------------------------------------------- work per fused launch
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    acc = np.zeros(4)
+    n_st = 0
+    state["frame"] = -1
+    state["est"] = est0.copy()
+    for s in range(2 * G):
+        f, g = (s // G) % F, s % G
+        if g == 0:
+            if state["frame"] >= 0:
+                state["est"] = gen.mean()
+            start_frame(f)
+        tk.cmaes_sample(gen.state, gen.n, gen.lam, gen.X)
+        tk.fk_transform(gen.X, gen.lam, 1, prob.chains, gen.xf, gen.kp, cam)
+        tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats)
+        acc += stats.cpu().numpy()
+        n_st += 1
+        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts)
+        tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
+                        1, 0.1, 0.0)
+        tk.cmaes_update(gen.state, gen.n, gen.lam, gen.loss)
+    kept, box_px, pairs, huge = acc / n_st
+    tri_all = lam * mesh.n_triangles
+    ops = 66.0 * tri_all + 40.0 * kept + 5.0 * box_px
+    peak_ops = 256 * 64 * 2.4e9
+    achieved = ops / (fused_ms.mean() * 1e-3)
+    log(f"per launch: kept {kept:.0f} tris, {box_px:.0f} box pixels, {pairs:.0f} block pairs, {huge:.0f} wide")
+
+    out = {
+        "metric": "candidate pose evals/sec (FK+raster+loss) at 640x480; ms per CMA-ES generation",
+        "value": lam / (ms_per_step * 1e-3),
+        "unit": "candidate evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "track640: single-instrument tracking, procedural 20016-triangle instrument, "
+                               "640x480, lambda=256, 9-D, loss 1-IoU + 0.1 keypoints, 30 gens/frame, 100 frames",
+                   "triangles": mesh.n_triangles, "width": cam.width, "height": cam.height, "lambda": lam,
+                   "dims": 9, "gens_per_frame": G, "frames": F},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
+                     "frac": achieved / peak_ops, "traffic": None,
+                     "kernel": "raster_kernel<false,false,true,512> (tk_eval_fused)",
+                     "kernel_us": float(fused_ms.mean() * 1e3),
+                     "ops_per_launch": ops, "units_per_launch": {"triangles": tri_all, "kept": kept,
+                                                                 "box_pixels": box_px, "block_pairs": pairs}},
+        "fitness_evals_per_s": lam / (fused_ms.mean() * 1e-3),
+        "final_translation_error_m": err_t,
+    }
+
+    # ---------------------------------------------------------------- graph replay and plain launches
+    if not args.no_extras:
+        state["frame"] = -1
+        state["est"] = est0.copy()
+        start_frame(0)
+        graph = gen.capture()
+        torch.cuda.synchronize()
+        ng = 300
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for s in range(ng):
+            if s % G == 0:
+                start_frame((s // G) % F)
+            graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        graph_ms = a.elapsed_time(b) / ng
+        log(f"graph replay: {graph_ms * 1e3:.1f} us per generation")
+        start_frame(0)
+        torch.cuda.synchronize()
+        w = time.perf_counter()
+        for _ in range(args.plain_gens):
+            gen.step_plain()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - w) * 1e3 / args.plain_gens
+        log(f"plain per-candidate launches: {plain_ms:.2f} ms per generation")
+        out["graph_ms_per_step"] = graph_ms
+        out["plain_ms_per_step"] = plain_ms
+        out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
+
+    # ---------------------------------------------------------------- CPU baseline (oracle)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, mesh, cam, chain, traj, flips, readings, est0, lam)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):
+    """The CPU oracle (C, OpenMP over candidates; numpy CMA-ES) running the same
+    generations on frame 0 of the trajectory with its own rendered target."""
+    import oracle
+    from oracle import cmaes
+    import scenes
+
+    log("cpu baseline: oracle on the host cores")
+    target = oracle.render(traj[0], [chain], [mesh], cam) ^ flips[0]
+    ref_kp = oracle.keypoints(oracle.fk(traj[0], chain), chain, cam)
+    m_cnt = oracle.counts(target, target, cam.width, cam.height)[2]
+    mean_phys = est0.copy()
+    mean_phys[6:9] = readings[0]
+    es = cmaes.CMAES(9, lam, np.zeros(9), 1.0, mean_phys, scenes.DEFAULT_SCALE, 1)
+    threads = oracle.max_threads()
+    n_eval = 0
+    gens = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        theta = es.sample().astype(np.float32).astype(np.float64)
+        cnt = oracle.eval_batch(theta, [chain], [mesh], cam, target, n_threads=threads)
+        loss = np.empty(lam)
+        for k in range(lam):
+            kp = oracle.keypoints(oracle.fk(theta[k], chain), chain, cam)
+            loss[k] = oracle.mask_loss(cnt[k, 0], cnt[k, 1], m_cnt, 0) + 0.1 * oracle.kp_loss(kp, ref_kp)
+        es.update(loss)
+        n_eval += lam
+        gens += 1
+    el = time.perf_counter() - t0
+    log(f"cpu baseline: {gens} generations, {n_eval / el:.0f} evals/s on {threads} threads")
+    return {"value": n_eval / el, "unit": "candidate evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{gens} generations x {lam} candidates of frame 0 (same mesh/camera/loss), "
+                      f"{el:.1f} s wall, ms per generation {el * 1e3 / gens:.1f}",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

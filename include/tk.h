@@ -187,6 +187,14 @@ tk_status tk_mask_popcount(const uint64_t* d_masks, int32_t batch, const tk_came
 tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
                         const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, tk_stream s);
 
+/* Workload statistics of a raster launch over the same inputs (for
+ * measurement, not on the hot path): d_stats[4] uint64 = {triangles kept,
+ * pixel centres inside the kept triangles' clamped boxes, (triangle, 8x8
+ * block) pairs visited, triangles needing 64-bit edge functions}.  The
+ * counters are cleared on the stream first. */
+tk_status tk_raster_stats(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
+                          const tk_camera* cam, uint64_t* d_stats, tk_stream s);
+
 /* Loss composition in FP64 (Eq. objective and render_loss; Sec. IV):
  *   kind 0: 1 - IoU = 1 - i/(a + m - i)  (0 when the union is empty);
  *   kind 1: (a + m - 2i) + lambda_app*|a - m|  (sum of squared mask errors

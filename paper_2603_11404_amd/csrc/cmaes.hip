@@ -1,0 +1,475 @@
+// CMA-ES sampling and update in FP64 (paper Sec. III-A.1, Eq. expected_fitness
+// and Eq. cmaes_update; block-diagonal covariance of Sec. III-B).  Where the
+// paper leaves the rules open (step size, evolution paths, h_sigma, default
+// learning rates) the update follows Hansen's CMA-ES tutorial
+// (arXiv:1604.00772).  Random numbers: Philox4x32-10 (Salmon et al., SC'11)
+// keyed by the seed with counter (group j, candidate k, generation g, 0),
+// mapped to normals by Box-Muller.
+#include <cmath>
+#include <cstring>
+
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = uint64_t(0xD2511F53u) * c.x;
+        uint64_t p1 = uint64_t(0xCD9E8D57u) * c.z;
+        U4 o;
+        o.x = uint32_t(p1 >> 32) ^ c.y ^ k0;
+        o.y = uint32_t(p1);
+        o.z = uint32_t(p0 >> 32) ^ c.w ^ k1;
+        o.w = uint32_t(p0);
+        c = o;
+    }
+    return c;
+}
+
+__device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
+    const double u1 = (double(a) + 0.5) * 0x1p-32;
+    const double u2 = (double(b) + 0.5) * 0x1p-32;
+    const double r = sqrt(-2.0 * log(u1));
+    const double t = (2.0 * kPi) * u2;
+    *z0 = r * cos(t);
+    *z1 = r * sin(t);
+}
+
+// ---------------------------------------------------------------- init
+
+struct InitArgs {
+    double mean0[kMaxN], offset[kMaxN], scale[kMaxN];
+    double sigma0, c_m_scale, c_mu_scale, c1_scale;
+    uint64_t seed;
+    int32_t n, lambda, n_blocks;
+};
+
+__global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a) {
+    StateView S = state_view(blob, a.n, a.lambda);
+    const int n = a.n, lam = a.lambda, mu = lam / 2;
+    const int tid = threadIdx.x;
+    __shared__ double s_w[kMaxLambda];
+    for (int i = tid; i < lam; i += blockDim.x)
+        s_w[i] = i < mu ? log((lam + 1) / 2.0) - log(double(i + 1)) : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+        double sw = 0.0;
+        for (int i = 0; i < mu; i++) sw += s_w[i];
+        double sw2 = 0.0;
+        for (int i = 0; i < mu; i++) {
+            s_w[i] /= sw;
+            sw2 += s_w[i] * s_w[i];
+        }
+        const double mu_eff = 1.0 / sw2;
+        const double dn = n;
+        const double c_sigma = (mu_eff + 2.0) / (dn + mu_eff + 5.0);
+        const double d_sigma = 1.0 + 2.0 * fmax(0.0, sqrt((mu_eff - 1.0) / (dn + 1.0)) - 1.0) + c_sigma;
+        const double c_c = (4.0 + mu_eff / dn) / (dn + 4.0 + 2.0 * mu_eff / dn);
+        double c1 = 2.0 / ((dn + 1.3) * (dn + 1.3) + mu_eff);
+        double c_mu = fmin(1.0 - c1, 2.0 * (mu_eff - 2.0 + 1.0 / mu_eff) / ((dn + 2.0) * (dn + 2.0) + mu_eff));
+        c1 *= a.c1_scale;
+        c_mu = fmin(c_mu * a.c_mu_scale, 1.0 - c1);
+        *S.sigma = a.sigma0;
+        *S.c_sigma = c_sigma;
+        *S.d_sigma = d_sigma;
+        *S.c_c = c_c;
+        *S.c1 = c1;
+        *S.c_mu = c_mu;
+        *S.c_m = a.c_m_scale;
+        *S.mu_eff = mu_eff;
+        *S.chi_n = sqrt(dn) * (1.0 - 1.0 / (4.0 * dn) + 1.0 / (21.0 * dn * dn));
+        *S.h_sigma = 1.0;
+        S.hdr->gen = 0;
+        S.hdr->seed = a.seed;
+        S.hdr->flags = 0;
+        S.hdr->magic = kStateMagic;
+        S.hdr->n = n;
+        S.hdr->lambda = lam;
+        S.hdr->mu = mu;
+        S.hdr->n_blocks = a.n_blocks;
+    }
+    __syncthreads();
+    for (int i = tid; i < lam; i += blockDim.x) {
+        S.weights[i] = s_w[i];
+        S.order[i] = i;
+    }
+    for (int i = tid; i < n; i += blockDim.x) {
+        S.mean[i] = a.mean0[i];
+        S.offset[i] = a.offset[i];
+        S.scale[i] = a.scale[i];
+        S.p_sigma[i] = 0.0;
+        S.p_c[i] = 0.0;
+        S.D[i] = 1.0;
+    }
+    for (int i = tid; i < n * n; i += blockDim.x) {
+        const double v = (i / n == i % n) ? 1.0 : 0.0;
+        S.C[i] = v;
+        S.B[i] = v;
+    }
+    for (int i = tid; i < lam * n; i += blockDim.x) {
+        S.Z[i] = 0.0;
+        S.Y[i] = 0.0;
+    }
+}
+
+struct MeanArgs { double mean[kMaxN]; int32_t n, lambda; };
+
+__global__ void cmaes_set_mean_kernel(void* blob, MeanArgs a) {
+    StateView S = state_view(blob, a.n, a.lambda);
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) S.mean[i] = a.mean[i];
+}
+
+// ---------------------------------------------------------------- sample
+
+// One thread per candidate k: z (Philox + Box-Muller), y = B D z, x = m + sigma y,
+// theta = offset + scale * x.
+__global__ __launch_bounds__(256) void cmaes_sample_kernel(void* blob, int n, int lam, float* __restrict__ X) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= lam) return;
+    StateView S = state_view(blob, n, lam);
+    const uint32_t gen = uint32_t(S.hdr->gen);
+    const uint64_t seed = S.hdr->seed;
+    const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+    double z[kMaxN + 3];
+    const int groups = (n + 3) / 4;
+    for (int j = 0; j < groups; j++) {
+        U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), gen, 0u}, k0, k1);
+        box_muller(r.x, r.y, &z[4 * j], &z[4 * j + 1]);
+        box_muller(r.z, r.w, &z[4 * j + 2], &z[4 * j + 3]);
+    }
+    const double sigma = *S.sigma;
+    for (int i = 0; i < n; i++) {
+        double y = 0.0;
+        for (int j = 0; j < n; j++) y += (S.B[i * n + j] * S.D[j]) * z[j];
+        const double x = S.mean[i] + sigma * y;
+        S.Z[k * n + i] = z[i];
+        S.Y[k * n + i] = y;
+        X[k * n + i] = float(S.offset[i] + S.scale[i] * x);
+    }
+}
+
+// ---------------------------------------------------------------- update
+
+constexpr int kUpdThreads = 256;
+constexpr int kMaxSweeps = 30;
+
+__device__ inline int rr_player(int i, int round, int m) {  // circle-method tournament
+    return i == 0 ? 0 : ((i - 1 + round) % (m - 1)) + 1;
+}
+
+// dynamic LDS: elite rows Y[mu][n]
+__global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, int n, int lam,
+                                                                  const double* __restrict__ loss) {
+    extern __shared__ double s_elite[];  // [mu][n]
+    __shared__ double s_key[kMaxLambda];
+    __shared__ int s_order[kMaxLambda];
+    __shared__ double s_A[kMaxN * kMaxN], s_V[kMaxN * kMaxN];
+    __shared__ double s_yw[kMaxN], s_t[kMaxN], s_z[kMaxN];
+    __shared__ double s_cs[2 * kMaxN];
+    __shared__ int s_pq[2 * kMaxN];
+    __shared__ double s_scal[4];
+    __shared__ int s_done;
+
+    StateView S = state_view(blob, n, lam);
+    const int tid = threadIdx.x;
+    const int mu = S.hdr->mu;
+    const int n_blocks = S.hdr->n_blocks;
+    const int nb = n / n_blocks;
+
+    // 1. ranking by (loss, index), NaN as +inf
+    for (int k = tid; k < lam; k += kUpdThreads) {
+        const double v = loss[k];
+        s_key[k] = (v != v) ? INFINITY : v;
+    }
+    __syncthreads();
+    for (int k = tid; k < lam; k += kUpdThreads) {
+        const double key = s_key[k];
+        int r = 0;
+        for (int j = 0; j < lam; j++) {
+            const double kj = s_key[j];
+            r += (kj < key) || (kj == key && j < k);
+        }
+        s_order[r] = k;
+        S.order[r] = k;
+    }
+    __syncthreads();
+    for (int e = tid; e < mu * n; e += kUpdThreads) {
+        const int r = e / n, i = e % n;
+        s_elite[e] = S.Y[s_order[r] * n + i];
+    }
+    __syncthreads();
+
+    const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
+    const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
+
+    // 2. weighted recombination y_w and mean update
+    if (tid < n) {
+        double s = 0.0;
+        for (int r = 0; r < mu; r++) s += S.weights[r] * s_elite[r * n + tid];
+        s_yw[tid] = s;
+        S.mean[tid] = S.mean[tid] + c_m * sigma * s;
+    }
+    __syncthreads();
+    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w
+    if (tid < n) {
+        double s = 0.0;
+        for (int j = 0; j < n; j++) s += S.B[j * n + tid] * s_yw[j];
+        s_t[tid] = s / S.D[tid];
+    }
+    __syncthreads();
+    if (tid < n) {
+        double s = 0.0;
+        for (int j = 0; j < n; j++) s += S.B[tid * n + j] * s_t[j];
+        s_z[tid] = s;
+        S.p_sigma[tid] = (1.0 - cs) * S.p_sigma[tid] + sqrt(cs * (2.0 - cs) * mu_eff) * s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double ss = 0.0;
+        for (int i = 0; i < n; i++) ss += S.p_sigma[i] * S.p_sigma[i];
+        const double ps_norm = sqrt(ss);
+        const double g1 = double(S.hdr->gen + 1);
+        const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * g1));
+        const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
+        s_scal[0] = ps_norm;
+        s_scal[1] = h;
+        double sw = 0.0;
+        for (int r = 0; r < mu; r++) sw += S.weights[r];
+        s_scal[2] = sw;
+        *S.h_sigma = h;
+    }
+    __syncthreads();
+    const double ps_norm = s_scal[0], h_sigma = s_scal[1], sum_w = s_scal[2];
+    if (tid < n) S.p_c[tid] = (1.0 - cc) * S.p_c[tid] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[tid];
+    __syncthreads();
+
+    // 4. covariance: rank-one + rank-mu; symmetrise and mask into s_A
+    const double delta = (1.0 - h_sigma) * cc * (2.0 - cc);
+    const double keep = 1.0 - c1 - cmu * sum_w;
+    for (int e = tid; e < n * n; e += kUpdThreads) {
+        const int i = e / n, j = e % n;
+        if (j < i) continue;
+        double rmu_ij = 0.0, rmu_ji = 0.0;
+        for (int r = 0; r < mu; r++) {
+            const double w = S.weights[r];
+            rmu_ij += w * s_elite[r * n + i] * s_elite[r * n + j];
+        }
+        rmu_ji = rmu_ij;
+        const double pc_i = S.p_c[i], pc_j = S.p_c[j];
+        const double cij = keep * S.C[i * n + j] + c1 * (pc_i * pc_j + delta * S.C[i * n + j]) + cmu * rmu_ij;
+        const double cji = keep * S.C[j * n + i] + c1 * (pc_j * pc_i + delta * S.C[j * n + i]) + cmu * rmu_ji;
+        double v = 0.5 * (cij + cji);
+        if (i / nb != j / nb) v = 0.0;   // block-diagonal covariance
+        s_A[i * n + j] = v;
+        s_A[j * n + i] = v;
+    }
+    for (int e = tid; e < n * n; e += kUpdThreads) s_V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    if (tid == 0) {
+        *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
+        S.hdr->gen = S.hdr->gen + 1;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += kUpdThreads) S.C[e] = s_A[e];
+
+    // 5. cyclic Jacobi, tournament ordering: disjoint rotations in parallel
+    const int m = nb + (nb & 1);
+    const int half = m / 2;
+    const int n_pairs = n_blocks * half;
+    for (int sweep = 0; sweep < kMaxSweeps; sweep++) {
+        if (tid == 0) {
+            double off = 0.0, dia = 0.0;
+            for (int i = 0; i < n; i++)
+                for (int j = 0; j < n; j++) {
+                    const double v = s_A[i * n + j];
+                    if (i == j) dia += v * v;
+                    else off += v * v;
+                }
+            s_done = !(off > 1e-30 * dia);   // also stops on NaN
+        }
+        __syncthreads();
+        if (s_done) break;
+        for (int round = 0; round < m - 1; round++) {
+            if (tid < n_pairs) {
+                const int b = tid / half, i = tid % half;
+                int p = rr_player(i, round, m), q = rr_player(m - 1 - i, round, m);
+                if (p > q) { const int t = p; p = q; q = t; }
+                double c = 1.0, s = 0.0;
+                int valid = q < nb;
+                if (valid) {
+                    p += b * nb;
+                    q += b * nb;
+                    const double apq = s_A[p * n + q];
+                    if (apq != 0.0) {
+                        const double tau = (s_A[q * n + q] - s_A[p * n + p]) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                s_cs[2 * tid] = c;
+                s_cs[2 * tid + 1] = s;
+                s_pq[2 * tid] = valid ? p : -1;
+                s_pq[2 * tid + 1] = q;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J   (task = (pair, row within block))
+            for (int task = tid; task < n_pairs * nb; task += kUpdThreads) {
+                const int pi = task / nb, kk = task % nb;
+                const int p = s_pq[2 * pi];
+                if (p < 0) continue;
+                const int q = s_pq[2 * pi + 1];
+                const int k = (pi / half) * nb + kk;
+                const double c = s_cs[2 * pi], s = s_cs[2 * pi + 1];
+                const double akp = s_A[k * n + p], akq = s_A[k * n + q];
+                s_A[k * n + p] = c * akp - s * akq;
+                s_A[k * n + q] = s * akp + c * akq;
+                const double vkp = s_V[k * n + p], vkq = s_V[k * n + q];
+                s_V[k * n + p] = c * vkp - s * vkq;
+                s_V[k * n + q] = s * vkp + c * vkq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int task = tid; task < n_pairs * nb; task += kUpdThreads) {
+                const int pi = task / nb, kk = task % nb;
+                const int p = s_pq[2 * pi];
+                if (p < 0) continue;
+                const int q = s_pq[2 * pi + 1];
+                const int k = (pi / half) * nb + kk;
+                const double c = s_cs[2 * pi], s = s_cs[2 * pi + 1];
+                const double apk = s_A[p * n + k], aqk = s_A[q * n + k];
+                s_A[p * n + k] = c * apk - s * aqk;
+                s_A[q * n + k] = s * apk + c * aqk;
+            }
+            __syncthreads();
+        }
+    }
+    // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
+    if (tid == 0) {
+        double emax = 0.0;
+        for (int i = 0; i < n; i++) emax = fmax(emax, s_A[i * n + i]);
+        const double floor_v = 1e-20 * emax;
+        int flags = 0;
+        for (int i = 0; i < n; i++) {
+            double e = s_A[i * n + i];
+            if (!(e >= floor_v)) {
+                e = floor_v;
+                flags |= 1;
+            }
+            S.D[i] = sqrt(e);
+        }
+        const double sg = *S.sigma;
+        if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
+        S.hdr->flags = flags;
+    }
+    for (int e = tid; e < n * n; e += kUpdThreads) S.B[e] = s_V[e];
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+size_t tk_cmaes_state_bytes(int32_t n, int32_t lambda) {
+    if (n < 1 || n > kMaxN || lambda < 2 || lambda > kMaxLambda) return 0;
+    tk_cmaes_layout L;
+    cmaes_layout(n, lambda, &L);
+    return size_t(L.total_bytes);
+}
+
+tk_status tk_cmaes_layout_get(int32_t n, int32_t lambda, tk_cmaes_layout* out) {
+    clear_error();
+    TK_REQUIRE(out != nullptr, "out is NULL");
+    TK_REQUIRE(n >= 1 && n <= kMaxN, "n = %d outside 1..%d", n, kMaxN);
+    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
+    cmaes_layout(n, lambda, out);
+    return TK_OK;
+}
+
+static tk_status check_state(const void* d_state, int32_t n, int32_t lambda) {
+    TK_REQUIRE(d_state != nullptr, "state is NULL");
+    TK_REQUIRE((reinterpret_cast<uintptr_t>(d_state) & 255) == 0, "state must be 256-byte aligned");
+    TK_REQUIRE(n >= 1 && n <= kMaxN, "n = %d outside 1..%d", n, kMaxN);
+    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
+    return TK_OK;
+}
+
+tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
+                        const double* offset, const double* scale, const tk_cmaes_params* p, uint64_t seed,
+                        tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(mean0 && offset && scale, "mean0/offset/scale must be host arrays of n doubles");
+    TK_REQUIRE(sigma0 > 0.0 && std::isfinite(sigma0), "sigma0 must be finite and > 0");
+    InitArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int i = 0; i < n; i++) {
+        TK_REQUIRE(std::isfinite(mean0[i]) && std::isfinite(offset[i]) && std::isfinite(scale[i]),
+                   "non-finite mean0/offset/scale[%d]", i);
+        a.mean0[i] = mean0[i];
+        a.offset[i] = offset[i];
+        a.scale[i] = scale[i];
+    }
+    a.sigma0 = sigma0;
+    a.c_m_scale = p ? p->c_m_scale : 1.0;
+    a.c_mu_scale = p ? p->c_mu_scale : 1.0;
+    a.c1_scale = p ? p->c1_scale : 1.0;
+    a.n_blocks = p ? p->n_blocks : 1;
+    TK_REQUIRE(a.c_m_scale > 0 && a.c_mu_scale > 0 && a.c1_scale > 0, "learning-rate scales must be > 0");
+    TK_REQUIRE(a.n_blocks >= 1 && n % a.n_blocks == 0, "n_blocks = %d must divide n = %d", a.n_blocks, n);
+    a.seed = seed;
+    a.n = n;
+    a.lambda = lambda;
+    hipLaunchKernelGGL(cmaes_init_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(s), d_state, a);
+    return check_launch("tk_cmaes_init");
+}
+
+tk_status tk_cmaes_set_mean(void* d_state, int32_t n, int32_t lambda, const double* mean, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(mean != nullptr, "mean is NULL");
+    MeanArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int i = 0; i < n; i++) {
+        TK_REQUIRE(std::isfinite(mean[i]), "non-finite mean[%d]", i);
+        a.mean[i] = mean[i];
+    }
+    a.n = n;
+    a.lambda = lambda;
+    hipLaunchKernelGGL(cmaes_set_mean_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(s), d_state, a);
+    return check_launch("tk_cmaes_set_mean");
+}
+
+tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(d_X != nullptr, "X is NULL");
+    const int threads = 256;
+    hipLaunchKernelGGL(cmaes_sample_kernel, dim3((lambda + threads - 1) / threads), dim3(threads), 0,
+                       reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_X);
+    return check_launch("tk_cmaes_sample");
+}
+
+tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double* d_loss, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(d_loss != nullptr, "loss is NULL");
+    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    hipLaunchKernelGGL(cmaes_update_kernel, dim3(1), dim3(kUpdThreads), lds, reinterpret_cast<hipStream_t>(s),
+                       d_state, n, lambda, d_loss);
+    return check_launch("tk_cmaes_update");
+}
+
+}  // extern "C"

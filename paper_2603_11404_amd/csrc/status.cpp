@@ -1,0 +1,88 @@
+// Status strings, thread-local error detail and shared argument validation.
+#include <cstdarg>
+#include <cstring>
+
+#include "tk_internal.h"
+
+namespace tk {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+tk_status fail(tk_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+tk_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TK_ERR_DEVICE, "%s: launch failed: %s", what, hipGetErrorString(e));
+    return TK_OK;
+}
+
+tk_status validate_camera(const tk_camera* cam) {
+    TK_REQUIRE(cam != nullptr, "camera is NULL");
+    TK_REQUIRE(cam->width >= 1 && cam->width <= kMaxImage && cam->height >= 1 && cam->height <= kMaxImage,
+               "image size %dx%d outside 1..%d", cam->width, cam->height, kMaxImage);
+    TK_REQUIRE(cam->fx == cam->fx && cam->fy == cam->fy && cam->cx == cam->cx && cam->cy == cam->cy,
+               "camera intrinsics are NaN");
+    TK_REQUIRE(cam->z_near > 0.0f, "z_near must be > 0");
+    return TK_OK;
+}
+
+tk_status validate_meshes(const tk_mesh* meshes, int32_t n_meshes, MeshSet* out) {
+    TK_REQUIRE(meshes != nullptr, "meshes is NULL");
+    TK_REQUIRE(n_meshes >= 1 && n_meshes <= kMaxArms, "n_meshes = %d outside 1..%d", n_meshes, kMaxArms);
+    int64_t total = 0;
+    out->n_meshes = n_meshes;
+    for (int i = 0; i < n_meshes; i++) {
+        const tk_mesh& m = meshes[i];
+        TK_REQUIRE(m.n_vertices >= 1 && m.n_vertices <= (1 << 24), "mesh %d: n_vertices = %d", i, m.n_vertices);
+        TK_REQUIRE(m.n_triangles >= 0 && m.n_triangles <= (1 << 24), "mesh %d: n_triangles = %d", i,
+                   m.n_triangles);
+        TK_REQUIRE(m.vertices != nullptr && m.vertex_link != nullptr, "mesh %d: NULL vertex arrays", i);
+        TK_REQUIRE(m.n_triangles == 0 || m.triangles != nullptr, "mesh %d: NULL triangles", i);
+        TK_REQUIRE((reinterpret_cast<uintptr_t>(m.vertices) & 3) == 0 &&
+                       (reinterpret_cast<uintptr_t>(m.triangles) & 3) == 0,
+                   "mesh %d: misaligned arrays", i);
+        out->m[i].vertices = m.vertices;
+        out->m[i].triangles = m.triangles;
+        out->m[i].vertex_link = m.vertex_link;
+        out->m[i].n_vertices = m.n_vertices;
+        out->m[i].n_triangles = m.n_triangles;
+        out->m[i].vertex_offset = static_cast<int32_t>(total);
+        total += m.n_vertices;
+    }
+    for (int i = n_meshes; i < kMaxArms; i++) out->m[i] = MeshK{nullptr, nullptr, nullptr, 0, 0, 0};
+    TK_REQUIRE(total <= (1 << 24), "too many vertices in total");
+    out->total_vertices = static_cast<int32_t>(total);
+    return TK_OK;
+}
+
+}  // namespace tk
+
+extern "C" {
+
+const char* tk_status_string(tk_status s) {
+    switch (s) {
+        case TK_OK: return "TK_OK";
+        case TK_ERR_INVALID_ARGUMENT: return "TK_ERR_INVALID_ARGUMENT";
+        case TK_ERR_UNSUPPORTED: return "TK_ERR_UNSUPPORTED";
+        case TK_ERR_WORKSPACE_TOO_SMALL: return "TK_ERR_WORKSPACE_TOO_SMALL";
+        case TK_ERR_DEVICE: return "TK_ERR_DEVICE";
+    }
+    return "TK_ERR_UNKNOWN";
+}
+
+const char* tk_last_error(void) { return tk::g_last_error.c_str(); }
+
+int32_t tk_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+"""Thin ctypes binding of libtk (include/tk.h): argument marshalling only.
+
+Every step of the fitness path runs in the HIP kernels of libtk.so; torch is
+used for device memory and for the current HIP stream.  The library must be
+built (``python -m paper_2603_11404_amd.build``); on a machine with a GPU a
+missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # imported before libtk so that both share torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtk.so")
+
+TK_OK = 0
+STATUS_NAMES = {0: "TK_OK", 1: "TK_ERR_INVALID_ARGUMENT", 2: "TK_ERR_UNSUPPORTED",
+                3: "TK_ERR_WORKSPACE_TOO_SMALL", 4: "TK_ERR_DEVICE"}
+
+LOSS_IOU, LOSS_RENDER = 0, 1
+
+
+class TkError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("z_near", ctypes.c_float)]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
+                ("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p), ("vertex_link", ctypes.c_void_p)]
+
+
+class Chain(ctypes.Structure):
+    _fields_ = [("d_pitch_yaw", ctypes.c_double), ("q_lb", ctypes.c_double * 3), ("q_ub", ctypes.c_double * 3),
+                ("keypoints", (ctypes.c_double * 4) * 4)]
+
+
+class CmaesParams(ctypes.Structure):
+    _fields_ = [("c_m_scale", ctypes.c_double), ("c_mu_scale", ctypes.c_double), ("c1_scale", ctypes.c_double),
+                ("n_blocks", ctypes.c_int32)]
+
+
+_LAYOUT_FIELDS = ["total_bytes", "gen", "seed", "flags", "sigma", "c_sigma", "d_sigma", "c_c", "c1", "c_mu", "c_m",
+                  "mu_eff", "chi_n", "h_sigma", "weights", "mean", "p_sigma", "p_c", "offset", "scale", "D", "C",
+                  "B", "Z", "Y", "order"]
+
+
+class CmaesLayout(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in _LAYOUT_FIELDS]
+
+
+EXPORTS = [
+    "tk_status_string", "tk_last_error", "tk_version",
+    "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_set_mean", "tk_cmaes_sample",
+    "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
+    "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libtk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_11404_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+        L.tk_status_string.restype = ctypes.c_char_p
+        L.tk_status_string.argtypes = [ctypes.c_int]
+        L.tk_last_error.restype = ctypes.c_char_p
+        L.tk_last_error.argtypes = []
+        L.tk_version.restype = i32
+        L.tk_cmaes_state_bytes.restype = ctypes.c_size_t
+        L.tk_cmaes_state_bytes.argtypes = [i32, i32]
+        L.tk_cmaes_layout_get.argtypes = [i32, i32, P]
+        L.tk_cmaes_init.argtypes = [P, i32, i32, P, f64, P, P, P, u64, P]
+        L.tk_cmaes_set_mean.argtypes = [P, i32, i32, P, P]
+        L.tk_cmaes_sample.argtypes = [P, i32, i32, P, P]
+        L.tk_cmaes_update.argtypes = [P, i32, i32, P, P]
+        L.tk_fk_transform.argtypes = [P, i32, i32, P, P, P, P, P]
+        L.tk_snap_vertices.argtypes = [P, i32, P, i32, P, P, P]
+        L.tk_raster_silhouette.argtypes = [P, i32, P, i32, P, P, P]
+        L.tk_raster_from_snapped.argtypes = [P, i32, P, i32, P, P, P]
+        L.tk_mask_loss.argtypes = [P, i32, P, P, P, P]
+        L.tk_mask_popcount.argtypes = [P, i32, P, P, P]
+        L.tk_eval_fused.argtypes = [P, i32, P, i32, P, P, P, P]
+        L.tk_compose_loss.argtypes = [P, i32, P, i32, f64, P, P, i32, f64, f64, P, P]
+        L.tk_raster_stats.argtypes = [P, i32, P, i32, P, P, P]
+        for name in EXPORTS:
+            if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != TK_OK:
+        raise TkError(status, lib().tk_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("expected a device tensor")
+        if not t.is_contiguous():
+            raise ValueError("expected a contiguous tensor")
+        return ctypes.c_void_p(t.data_ptr())
+    raise TypeError(type(t))
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def camera(cam) -> Camera:
+    """tk_camera from any object with fx, fy, cx, cy, width, height, z_near."""
+    return Camera(cam.fx, cam.fy, cam.cx, cam.cy, int(cam.width), int(cam.height), cam.z_near)
+
+
+def chain(ch) -> Chain:
+    c = Chain()
+    c.d_pitch_yaw = float(ch.d_pitch_yaw)
+    for j in range(3):
+        c.q_lb[j] = float(ch.q_lb[j])
+        c.q_ub[j] = float(ch.q_ub[j])
+    for j in range(4):
+        for k in range(4):
+            c.keypoints[j][k] = float(ch.keypoints[j][k])
+    return c
+
+
+class DeviceMesh:
+    """Mesh arrays resident on the device plus the tk_mesh view of them."""
+
+    def __init__(self, mesh, device="cuda"):
+        self.vertices = torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float32), device=device)
+        self.triangles = torch.as_tensor(np.ascontiguousarray(mesh.triangles, np.int32), device=device)
+        self.vertex_link = torch.as_tensor(np.ascontiguousarray(mesh.vertex_link, np.uint8), device=device)
+        self.n_vertices = int(self.vertices.shape[0])
+        self.n_triangles = int(self.triangles.shape[0])
+
+    def struct(self) -> Mesh:
+        return Mesh(self.n_vertices, self.n_triangles, self.vertices.data_ptr(),
+                    self.triangles.data_ptr() if self.n_triangles else None, self.vertex_link.data_ptr())
+
+
+def _meshes(meshes):
+    arr = (Mesh * len(meshes))(*[m.struct() for m in meshes])
+    return arr, len(meshes)
+
+
+def words_shape(cam) -> tuple[int, int]:
+    return ((int(cam.height) + 7) // 8, (int(cam.width) + 7) // 8)
+
+
+# ------------------------------------------------------------------ CMA-ES
+
+def cmaes_state_bytes(n: int, lam: int) -> int:
+    return int(lib().tk_cmaes_state_bytes(n, lam))
+
+
+def cmaes_layout(n: int, lam: int) -> dict:
+    L = CmaesLayout()
+    _check(lib().tk_cmaes_layout_get(n, lam, ctypes.byref(L)))
+    return {f: int(getattr(L, f)) for f in _LAYOUT_FIELDS}
+
+
+def cmaes_alloc(n: int, lam: int, device="cuda") -> torch.Tensor:
+    """A device state blob (uint8 tensor, 256-byte aligned by the caching allocator)."""
+    t = torch.zeros(cmaes_state_bytes(n, lam), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def cmaes_init(state, n, lam, mean0, sigma0, offset, scale, seed, c_m_scale=1.0, c_mu_scale=1.0, c1_scale=1.0,
+               n_blocks=1, stream=None):
+    m = np.ascontiguousarray(mean0, np.float64)
+    o = np.ascontiguousarray(offset, np.float64)
+    s = np.ascontiguousarray(scale, np.float64)
+    p = CmaesParams(c_m_scale, c_mu_scale, c1_scale, n_blocks)
+    _check(lib().tk_cmaes_init(_ptr(state), n, lam, m.ctypes.data_as(ctypes.c_void_p), float(sigma0),
+                               o.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(p), int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))
+
+
+def cmaes_set_mean(state, n, lam, mean, stream=None):
+    m = np.ascontiguousarray(mean, np.float64)
+    _check(lib().tk_cmaes_set_mean(_ptr(state), n, lam, m.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+
+
+def cmaes_sample(state, n, lam, X, stream=None):
+    _check(lib().tk_cmaes_sample(_ptr(state), n, lam, _ptr(X), _stream(stream)))
+
+
+def cmaes_update(state, n, lam, loss, stream=None):
+    _check(lib().tk_cmaes_update(_ptr(state), n, lam, _ptr(loss), _stream(stream)))
+
+
+def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:
+    """Named views (host copies) of a state blob's fields, for tests and checkpoints."""
+    L = cmaes_layout(n, lam)
+    raw = state.detach().cpu().numpy()
+
+    def f64(off, count):
+        return raw[off:off + 8 * count].view(np.float64).copy()
+    out = {name: float(f64(L[name], 1)[0]) for name in
+           ("sigma", "c_sigma", "d_sigma", "c_c", "c1", "c_mu", "c_m", "mu_eff", "chi_n", "h_sigma")}
+    out["gen"] = int(raw[L["gen"]:L["gen"] + 8].view(np.int64)[0])
+    out["flags"] = int(raw[L["flags"]:L["flags"] + 4].view(np.int32)[0])
+    out["weights"] = f64(L["weights"], lam)
+    for name in ("mean", "p_sigma", "p_c", "offset", "scale", "D"):
+        out[name] = f64(L[name], n)
+    for name in ("C", "B"):
+        out[name] = f64(L[name], n * n).reshape(n, n)
+    for name in ("Z", "Y"):
+        out[name] = f64(L[name], lam * n).reshape(lam, n)
+    out["order"] = raw[L["order"]:L["order"] + 4 * lam].view(np.int32).copy()
+    return out
+
+
+def cmaes_write(state: torch.Tensor, n: int, lam: int, **fields):
+    """Overwrite FP64 fields of a state blob (e.g. restore a checkpoint or load
+    a given B, D).  Synchronous host-to-device copies."""
+    L = cmaes_layout(n, lam)
+    for name, val in fields.items():
+        if name == "gen":
+            arr = np.array([int(val)], np.int64).view(np.uint8)
+        else:
+            arr = np.ascontiguousarray(val, np.float64).reshape(-1).view(np.uint8)
+        state[L[name]:L[name] + arr.size].copy_(torch.from_numpy(arr.copy()).to(state.device))
+
+
+# ------------------------------------------------------------------ fitness path
+
+def fk_transform(X, batch, n_arms, chains, link_xf, kp=None, cam=None, stream=None):
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    c = camera(cam) if cam is not None else None
+    _check(lib().tk_fk_transform(_ptr(X), batch, n_arms, ch, _ptr(link_xf), _ptr(kp),
+                                 ctypes.byref(c) if c is not None else None, _stream(stream)))
+
+
+def snap_vertices(link_xf, batch, meshes, cam, snapped, stream=None):
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_snap_vertices(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(snapped), _stream(stream)))
+
+
+def raster_silhouette(link_xf, batch, meshes, cam, masks, stream=None):
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_raster_silhouette(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(masks),
+                                      _stream(stream)))
+
+
+def raster_from_snapped(snapped, batch, meshes, cam, masks, stream=None):
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_raster_from_snapped(_ptr(snapped), batch, arr, nm, ctypes.byref(c), _ptr(masks),
+                                        _stream(stream)))
+
+
+def mask_loss(masks, batch, target, cam, counts, stream=None):
+    c = camera(cam)
+    _check(lib().tk_mask_loss(_ptr(masks), batch, _ptr(target), ctypes.byref(c), _ptr(counts), _stream(stream)))
+
+
+def mask_popcount(masks, batch, cam, count, stream=None):
+    c = camera(cam)
+    _check(lib().tk_mask_popcount(_ptr(masks), batch, ctypes.byref(c), _ptr(count), _stream(stream)))
+
+
+def eval_fused(link_xf, batch, meshes, cam, target, counts, stream=None):
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_eval_fused(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(target), _ptr(counts),
+                               _stream(stream)))
+
+
+def compose_loss(counts, batch, target_count, kind, loss, lambda_app=1.0, kp=None, kp_ref=None, n_arms=1,
+                 lambda_kp=0.0, tau=0.0, stream=None):
+    _check(lib().tk_compose_loss(_ptr(counts), batch, _ptr(target_count), int(kind), float(lambda_app), _ptr(kp),
+                                 _ptr(kp_ref), int(n_arms), float(lambda_kp), float(tau), _ptr(loss),
+                                 _stream(stream)))
+
+
+def raster_stats(link_xf, batch, meshes, cam, stats, stream=None):
+    """stats: int64 device tensor [4] <- kept triangles, box pixels, block pairs, 64-bit triangles."""
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_raster_stats(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(stats), _stream(stream)))

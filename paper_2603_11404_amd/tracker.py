@@ -1,0 +1,154 @@
+"""Generation driver: device buffers and launch sequence of one CMA-ES generation.
+
+One generation (paper Sec. III-A.1 and Fig. 2: sample candidates, evaluate them
+in parallel through batched forward kinematics and rendering, rank, update):
+
+    tk_cmaes_sample -> tk_fk_transform -> tk_eval_fused -> tk_compose_loss
+    -> tk_cmaes_update
+
+All five are HIP kernels of libtk queued on one stream; `capture()` records the
+sequence once into a HIP graph (torch.cuda.CUDAGraph on ROCm) and `replay()`
+launches a whole generation with one call.  `step_plain()` is the unbatched
+baseline: the same kernels with batch = 1, looped over the candidates.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import tk
+
+
+class Problem:
+    """Meshes (one per arm), chains, camera and observation resident on the device."""
+
+    def __init__(self, meshes, chains, cam, device="cuda"):
+        assert len(meshes) == len(chains)
+        self.device = torch.device(device)
+        self.meshes = [tk.DeviceMesh(m, self.device) for m in meshes]
+        self.chains = list(chains)
+        self.cam = cam
+        self.n_arms = len(meshes)
+        self.words = tk.words_shape(cam)
+        self.target = torch.zeros(self.words, dtype=torch.int64, device=self.device)
+        self.target_count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.kp_ref = torch.zeros(self.n_arms, 4, 2, dtype=torch.float32, device=self.device)
+
+    def set_target(self, target_words: torch.Tensor, kp_ref: torch.Tensor | None = None):
+        """Copy a new observed mask (int64 view of the uint64 words) and keypoints in place."""
+        self.target.copy_(target_words.view(self.words))
+        tk.mask_popcount(self.target, 1, self.cam, self.target_count)
+        if kp_ref is not None:
+            self.kp_ref.copy_(kp_ref.view(self.n_arms, 4, 2))
+
+    def render(self, theta: torch.Tensor) -> torch.Tensor:
+        """Silhouette words of candidates theta [B, 9*n_arms] (float32, device)."""
+        B = theta.shape[0]
+        xf = torch.empty(B, self.n_arms, 4, 12, dtype=torch.float32, device=self.device)
+        tk.fk_transform(theta.contiguous(), B, self.n_arms, self.chains, xf)
+        masks = torch.empty(B, *self.words, dtype=torch.int64, device=self.device)
+        tk.raster_silhouette(xf, B, self.meshes, self.cam, masks)
+        return masks
+
+    def keypoints(self, theta: torch.Tensor) -> torch.Tensor:
+        B = theta.shape[0]
+        xf = torch.empty(B, self.n_arms, 4, 12, dtype=torch.float32, device=self.device)
+        kp = torch.empty(B, self.n_arms, 4, 2, dtype=torch.float32, device=self.device)
+        tk.fk_transform(theta.contiguous(), B, self.n_arms, self.chains, xf, kp, self.cam)
+        return kp
+
+
+class Generation:
+    """Buffers and launches of one CMA-ES generation over a Problem."""
+
+    def __init__(self, problem: Problem, lam: int, loss_kind=tk.LOSS_IOU, lambda_app=1.0, lambda_kp=0.0,
+                 tau=0.0, n_blocks=None):
+        self.p = problem
+        self.lam = int(lam)
+        self.n = 9 * problem.n_arms
+        self.n_blocks = problem.n_arms if n_blocks is None else n_blocks
+        self.loss_kind, self.lambda_app, self.lambda_kp, self.tau = loss_kind, lambda_app, lambda_kp, tau
+        d = problem.device
+        self.state = tk.cmaes_alloc(self.n, self.lam, d)
+        self.X = torch.empty(self.lam, self.n, dtype=torch.float32, device=d)
+        self.xf = torch.empty(self.lam, problem.n_arms, 4, 12, dtype=torch.float32, device=d)
+        self.kp = torch.empty(self.lam, problem.n_arms, 4, 2, dtype=torch.float32, device=d)
+        self.counts = torch.empty(self.lam, 2, dtype=torch.int32, device=d)
+        self.loss = torch.empty(self.lam, dtype=torch.float64, device=d)
+        self.masks1 = torch.empty(1, *problem.words, dtype=torch.int64, device=d)
+        self.graph = None
+
+    def init(self, mean0, sigma0, offset, scale, seed, c_m_scale=1.0, c_mu_scale=1.0, c1_scale=1.0):
+        tk.cmaes_init(self.state, self.n, self.lam, mean0, sigma0, offset, scale, seed, c_m_scale, c_mu_scale,
+                      c1_scale, self.n_blocks)
+
+    @property
+    def use_kp(self) -> bool:
+        return self.lambda_kp != 0.0
+
+    def evaluate(self):
+        """FK + fused raster/count + loss composition for the current X."""
+        p = self.p
+        tk.fk_transform(self.X, self.lam, p.n_arms, p.chains, self.xf, self.kp if self.use_kp else None,
+                        p.cam if self.use_kp else None)
+        tk.eval_fused(self.xf, self.lam, p.meshes, p.cam, p.target, self.counts)
+        tk.compose_loss(self.counts, self.lam, p.target_count, self.loss_kind, self.loss, self.lambda_app,
+                        self.kp if self.use_kp else None, p.kp_ref if self.use_kp else None, p.n_arms,
+                        self.lambda_kp, self.tau)
+
+    def step(self):
+        """One generation: sample -> FK -> raster/count -> loss -> update (5 launches)."""
+        tk.cmaes_sample(self.state, self.n, self.lam, self.X)
+        self.evaluate()
+        tk.cmaes_update(self.state, self.n, self.lam, self.loss)
+
+    def step_plain(self):
+        """Unbatched baseline: the same kernels launched once per candidate (batch = 1)."""
+        p = self.p
+        tk.cmaes_sample(self.state, self.n, self.lam, self.X)
+        for k in range(self.lam):
+            tk.fk_transform(self.X[k:k + 1], 1, p.n_arms, p.chains, self.xf[k:k + 1],
+                            self.kp[k:k + 1] if self.use_kp else None, p.cam if self.use_kp else None)
+            tk.raster_silhouette(self.xf[k:k + 1], 1, p.meshes, p.cam, self.masks1)
+            tk.mask_loss(self.masks1, 1, p.target, p.cam, self.counts[k:k + 1])
+            tk.compose_loss(self.counts[k:k + 1], 1, p.target_count, self.loss_kind, self.loss[k:k + 1],
+                            self.lambda_app, self.kp[k:k + 1] if self.use_kp else None,
+                            p.kp_ref if self.use_kp else None, p.n_arms, self.lambda_kp, self.tau)
+        tk.cmaes_update(self.state, self.n, self.lam, self.loss)
+
+    def capture(self):
+        """Record one generation into a HIP graph (replayed by replay())."""
+        s = torch.cuda.Stream(device=self.p.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.step()          # warm-up outside the graph on the side stream
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.step()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
+    def mean(self) -> np.ndarray:
+        v = tk.cmaes_view(self.state, self.n, self.lam)
+        return v["offset"] + v["scale"] * v["mean"]
+
+
+# ------------------------------------------------------------------ host-side set-up helpers
+
+def decode_joints(qhat, chain) -> np.ndarray:
+    """Cosine map of Sec. III-A.3 (unconstrained qhat -> q in [lb, ub]) on the
+    host, for building initial means from joint readings; the per-generation
+    decode runs inside tk_fk_transform."""
+    lb, ub = np.asarray(chain.q_lb), np.asarray(chain.q_ub)
+    return lb + (ub - lb) / 2.0 * (1.0 - np.cos(np.pi * (np.asarray(qhat) - lb) / (ub - lb)))
+
+
+def encode_joints(q, chain) -> np.ndarray:
+    """Inverse cosine map (Sec. III-A.3): a joint reading q, clamped to its
+    limits, to the unconstrained coordinate in [lb, ub]."""
+    lb, ub = np.asarray(chain.q_lb), np.asarray(chain.q_ub)
+    q = np.clip(np.asarray(q, dtype=np.float64), lb, ub)
+    return lb + (ub - lb) / np.pi * np.arccos(np.clip(1.0 - 2.0 * (q - lb) / (ub - lb), -1.0, 1.0))

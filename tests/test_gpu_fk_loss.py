@@ -1,0 +1,131 @@
+"""GPU parity of forward kinematics, vertex snapping and loss composition.
+
+Transforms within 1e-5 relative of the FP64 oracle; snapped vertices within
+the FP32 rounding bound; losses within FP64 rounding of the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from tests.gpu_helpers import INT32_MIN, candidates, oracle_snapped
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def tk():
+    from paper_2603_11404_amd import tk as _tk
+    return _tk
+
+
+def gpu_fk(th, chains, cam=None):
+    T = tk()
+    B = th.shape[0]
+    n_arms = len(chains)
+    X = torch.as_tensor(np.ascontiguousarray(th, np.float32), device=DEV)
+    xf = torch.empty(B, n_arms, 4, 12, dtype=torch.float32, device=DEV)
+    kp = torch.empty(B, n_arms, 4, 2, dtype=torch.float32, device=DEV) if cam is not None else None
+    T.fk_transform(X, B, n_arms, chains, xf, kp, cam)
+    torch.cuda.synchronize()
+    return xf.cpu().numpy(), (kp.cpu().numpy() if kp is not None else None)
+
+
+def test_fk_matches_fp64_oracle():
+    cam = scenes.camera(640, 480)
+    rng = np.random.default_rng(1)
+    th = np.concatenate([candidates(rng, cam, 100, spread=5.0),
+                         rng.uniform(-7, 7, size=(100, 9)).astype(np.float32)])
+    ch = scenes.chain()
+    xf, kp = gpu_fk(th, [ch], cam)
+    for k in range(th.shape[0]):
+        M = oracle.fk(th[k].astype(np.float64), ch).reshape(4, 12)
+        err = np.abs(xf[k, 0] - M).max() / max(1.0, np.abs(M).max())
+        assert err <= 1e-5, (k, err)
+    for k in range(100):
+        M = oracle.fk(th[k].astype(np.float64), ch)
+        ref = oracle.keypoints(M, ch, cam)
+        np.testing.assert_allclose(kp[k, 0], ref, rtol=1e-5, atol=1e-5 * cam.width)
+
+
+def test_fk_two_arms_and_jaw_scale():
+    cam = scenes.camera(960, 540)
+    rng = np.random.default_rng(2)
+    chains = [scenes.chain(), scenes.chain(jaw_scale=1.3)]
+    th = np.concatenate([candidates(rng, cam, 50), candidates(rng, cam, 50)], axis=1)
+    xf, kp = gpu_fk(th, chains, cam)
+    for k in range(50):
+        for a in range(2):
+            M = oracle.fk(th[k, 9 * a:9 * a + 9].astype(np.float64), chains[a])
+            assert np.abs(xf[k, a] - M.reshape(4, 12)).max() <= 1e-5 * max(1.0, np.abs(M).max())
+            np.testing.assert_allclose(kp[k, a], oracle.keypoints(M, chains[a], cam), rtol=1e-5, atol=1e-2)
+
+
+def test_snapped_vertices_within_fp32_bound():
+    """GPU FP32 transform + snap vs the FP64 oracle: same flags, |dU| within
+    256 * 1e-5 * max(|u|, W) + 1 subpixel (the transform bound plus rounding)."""
+    T = tk()
+    wl = scenes.workload("track640")
+    mesh, cam = wl["mesh"], wl["cam"]
+    ch = scenes.chain()
+    rng = np.random.default_rng(3)
+    th = candidates(rng, cam, 16, spread=3.0)
+    X = torch.as_tensor(th, device=DEV)
+    xf = torch.empty(16, 1, 4, 12, dtype=torch.float32, device=DEV)
+    T.fk_transform(X, 16, 1, [ch], xf)
+    dm = T.DeviceMesh(mesh, DEV)
+    sn = torch.empty(16, mesh.n_vertices, 2, dtype=torch.int32, device=DEV)
+    T.snap_vertices(xf, 16, [dm], cam, sn)
+    torch.cuda.synchronize()
+    got = sn.cpu().numpy()
+    exact = 0
+    for k in range(16):
+        ref, fl = oracle_snapped(th[k], ch, mesh, cam)
+        np.testing.assert_array_equal(got[k, :, 0] == INT32_MIN, fl.astype(bool))
+        ok = ~fl.astype(bool)
+        bound = 256 * 1e-5 * np.maximum(np.abs(ref[ok]) / 256.0, cam.width) + 1
+        assert np.all(np.abs(got[k][ok] - ref[ok]) <= bound)
+        exact += int(np.sum(got[k][ok] == ref[ok]))
+    assert exact > 0.9 * 16 * mesh.n_vertices * 2 * 0.9
+
+
+def test_compose_loss_matches_oracle():
+    T = tk()
+    rng = np.random.default_rng(4)
+    B = 300
+    a = rng.integers(0, 50000, B)
+    i = (a * rng.random(B)).astype(np.int64)
+    a[:3] = 0
+    i[:3] = 0
+    m = 20000
+    counts = torch.as_tensor(np.stack([a, i], 1).astype(np.int32), device=DEV)
+    tc = torch.tensor([m], dtype=torch.int32, device=DEV)
+    loss = torch.empty(B, dtype=torch.float64, device=DEV)
+    ref_kp = rng.uniform(0, 640, size=(4, 2))
+    kp = (ref_kp[None] + rng.normal(size=(B, 4, 2)) * 4).astype(np.float32)
+    kp[5, 1] = np.nan
+    for kind, lam_app in [(0, 0.0), (1, 0.7)]:
+        for lam_kp, tau in [(0.0, 0.0), (0.1, 0.0), (0.3, 2.0)]:
+            T.compose_loss(counts, B, tc, kind, loss, lambda_app=lam_app,
+                           kp=torch.as_tensor(kp.reshape(B, 1, 4, 2), device=DEV),
+                           kp_ref=torch.as_tensor(ref_kp.astype(np.float32).reshape(1, 4, 2), device=DEV),
+                           n_arms=1, lambda_kp=lam_kp, tau=tau)
+            torch.cuda.synchronize()
+            got = loss.cpu().numpy()
+            for b in range(B):
+                ref = oracle.mask_loss(a[b], i[b], m, kind, lam_app)
+                if lam_kp != 0.0:
+                    ref += lam_kp * oracle.kp_loss(kp[b].astype(np.float64), ref_kp.astype(np.float32), tau)
+                if math.isnan(ref):
+                    assert math.isnan(got[b])
+                else:
+                    assert got[b] == pytest.approx(ref, rel=1e-12, abs=1e-12), (kind, lam_kp, b)
+    # empty union
+    z = torch.zeros(1, 2, dtype=torch.int32, device=DEV)
+    tz = torch.zeros(1, dtype=torch.int32, device=DEV)
+    T.compose_loss(z, 1, tz, 0, loss[:1])
+    torch.cuda.synchronize()
+    assert float(loss[0]) == 0.0
