@@ -102,7 +102,7 @@ def main():
         tk.fk_transform(gen.X, gen.lam, 1, prob.chains, gen.xf, gen.kp, cam)
         if events is not None:
             events[0].record()
-        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts)
+        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts, gen.ws)
         if events is not None:
             events[1].record()
         tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
@@ -154,13 +154,17 @@ def main():
         tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats)
         acc += stats.cpu().numpy()
         n_st += 1
-        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts)
+        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts, gen.ws)
         tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
                         1, 0.1, 0.0)
         tk.cmaes_update(gen.state, gen.n, gen.lam, gen.loss)
     kept, box_px, pairs, huge = acc / n_st
     tri_all = lam * mesh.n_triangles
-    ops = 66.0 * tri_all + 40.0 * kept + 5.0 * box_px
+    vert_all = lam * mesh.n_vertices
+    # algorithmic integer/FP32 lane operations of one launch (see the roofline notes in the design doc):
+    # 22 per vertex transform + snap, 10 per triangle cull test, 40 per kept triangle set-up,
+    # 5 per pixel centre tested inside a kept triangle's box (3 edge functions, combine, test)
+    ops = 22.0 * vert_all + 10.0 * tri_all + 40.0 * kept + 5.0 * box_px
     peak_ops = 256 * 64 * 2.4e9
     achieved = ops / (fused_ms.mean() * 1e-3)
     log(f"per launch: kept {kept:.0f} tris, {box_px:.0f} box pixels, {pairs:.0f} block pairs, {huge:.0f} wide")
@@ -184,9 +188,10 @@ def main():
                    "dims": 9, "gens_per_frame": G, "frames": F},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
                      "frac": achieved / peak_ops, "traffic": None,
-                     "kernel": "raster_kernel<false,false,true,512> (tk_eval_fused)",
+                     "kernel": "raster_kernel<true,false,true,1024> (tk_eval_fused with workspace)",
                      "kernel_us": float(fused_ms.mean() * 1e3),
-                     "ops_per_launch": ops, "units_per_launch": {"triangles": tri_all, "kept": kept,
+                     "ops_per_launch": ops, "units_per_launch": {"vertices": vert_all, "triangles": tri_all,
+                                                                 "kept": kept,
                                                                  "box_pixels": box_px, "block_pairs": pairs}},
         "fitness_evals_per_s": lam / (fused_ms.mean() * 1e-3),
         "final_translation_error_m": err_t,

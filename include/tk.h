@@ -161,13 +161,23 @@ tk_status tk_fk_transform(const float* d_X, int32_t batch, int32_t n_arms, const
 tk_status tk_snap_vertices(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
                            const tk_camera* cam, int32_t* d_snapped, tk_stream s);
 
+/* Workspace bytes that let the raster entry points snap each vertex once per
+ * candidate (batch * total vertices * 8); 0 on invalid arguments. */
+size_t tk_raster_workspace_bytes(int32_t batch, const tk_mesh* meshes, int32_t n_meshes);
+
 /* Binary silhouette S (Sec. III-A.2: S in {0,1}^{H x W}) of every candidate:
  * OR over the n_meshes arms (one mesh per arm, link transforms from
  * d_link_xf[batch][n_meshes][4][12]) of the exact integer coverage with the
  * top-left fill rule, both windings drawn, no depth test.
- * d_masks [batch][ceil(H/8)][ceil(W/8)] uint64.  width*height <= 1280*800. */
+ * d_masks [batch][ceil(H/8)][ceil(W/8)] uint64.  The image mask lives in LDS:
+ * ceil(H/8)*ceil(W/8)*8 bytes must stay below about 136 KB (1280x720 fits;
+ * larger images return TK_ERR_UNSUPPORTED).  Triangle indices must lie in
+ * [0, n_vertices).  d_ws (nullable, device, tk_raster_workspace_bytes) holds
+ * the snapped vertices between the two phases of the kernel; with NULL each
+ * triangle transforms its own vertices (same result, more arithmetic);
+ * a smaller workspace returns TK_ERR_WORKSPACE_TOO_SMALL. */
 tk_status tk_raster_silhouette(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
-                               const tk_camera* cam, uint64_t* d_masks, tk_stream s);
+                               const tk_camera* cam, uint64_t* d_masks, void* d_ws, size_t ws_bytes, tk_stream s);
 
 /* Same coverage from given snapped vertices d_snapped[batch][sum V][2]. */
 tk_status tk_raster_from_snapped(const int32_t* d_snapped, int32_t batch, const tk_mesh* meshes,
@@ -183,9 +193,11 @@ tk_status tk_mask_popcount(const uint64_t* d_masks, int32_t batch, const tk_came
                            tk_stream s);
 
 /* Fused raster + counts: d_link_xf -> d_counts[batch][2] without writing
- * masks (same coverage as tk_raster_silhouette followed by tk_mask_loss). */
+ * masks (same coverage as tk_raster_silhouette followed by tk_mask_loss);
+ * workspace as for tk_raster_silhouette. */
 tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
-                        const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, tk_stream s);
+                        const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, void* d_ws,
+                        size_t ws_bytes, tk_stream s);
 
 /* Workload statistics of a raster launch over the same inputs (for
  * measurement, not on the hot path): d_stats[4] uint64 = {triangles kept,

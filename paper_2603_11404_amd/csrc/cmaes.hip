@@ -132,28 +132,39 @@ __global__ void cmaes_set_mean_kernel(void* blob, MeanArgs a) {
 
 // ---------------------------------------------------------------- sample
 
-// One thread per candidate k: z (Philox + Box-Muller), y = B D z, x = m + sigma y,
+// A 64-thread workgroup samples kSampCand candidates: first one thread per
+// (candidate, group of four dimensions) draws z with Philox + Box-Muller, then
+// one thread per (candidate, dimension) forms y = B D z, x = m + sigma y and
 // theta = offset + scale * x.
-__global__ __launch_bounds__(256) void cmaes_sample_kernel(void* blob, int n, int lam, float* __restrict__ X) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= lam) return;
+constexpr int kSampCand = 8;
+
+__global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int lam, float* __restrict__ X) {
+    __shared__ double s_z[kSampCand][kMaxN + 3];
+    __shared__ double s_BD[kMaxN * kMaxN];
     StateView S = state_view(blob, n, lam);
+    const int tid = threadIdx.x;
+    const int k0 = blockIdx.x * kSampCand;
     const uint32_t gen = uint32_t(S.hdr->gen);
     const uint64_t seed = S.hdr->seed;
-    const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
-    double z[kMaxN + 3];
+    const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
     const int groups = (n + 3) / 4;
-    for (int j = 0; j < groups; j++) {
-        U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), gen, 0u}, k0, k1);
-        box_muller(r.x, r.y, &z[4 * j], &z[4 * j + 1]);
-        box_muller(r.z, r.w, &z[4 * j + 2], &z[4 * j + 3]);
+    for (int e = tid; e < n * n; e += 64) s_BD[e] = S.B[e] * S.D[e % n];
+    for (int task = tid; task < kSampCand * groups; task += 64) {
+        const int kk = task / groups, j = task % groups, k = k0 + kk;
+        if (k >= lam) continue;
+        const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), gen, 0u}, key0, key1);
+        box_muller(r.x, r.y, &s_z[kk][4 * j], &s_z[kk][4 * j + 1]);
+        box_muller(r.z, r.w, &s_z[kk][4 * j + 2], &s_z[kk][4 * j + 3]);
     }
+    __syncthreads();
     const double sigma = *S.sigma;
-    for (int i = 0; i < n; i++) {
+    for (int task = tid; task < kSampCand * n; task += 64) {
+        const int kk = task / n, i = task % n, k = k0 + kk;
+        if (k >= lam) continue;
         double y = 0.0;
-        for (int j = 0; j < n; j++) y += (S.B[i * n + j] * S.D[j]) * z[j];
+        for (int j = 0; j < n; j++) y += s_BD[i * n + j] * s_z[kk][j];
         const double x = S.mean[i] + sigma * y;
-        S.Z[k * n + i] = z[i];
+        S.Z[k * n + i] = s_z[kk][i];
         S.Y[k * n + i] = y;
         X[k * n + i] = float(S.offset[i] + S.scale[i] * x);
     }
@@ -168,14 +179,21 @@ __device__ inline int rr_player(int i, int round, int m) {  // circle-method tou
     return i == 0 ? 0 : ((i - 1 + round) % (m - 1)) + 1;
 }
 
-// dynamic LDS: elite rows Y[mu][n]
+// dynamic LDS: elite rows Y[mu][n].  The state is staged in LDS first so that
+// no loop below waits on global memory; sums over the elites are split into
+// fixed-order partial sums (deterministic).
+constexpr int kParts = 8;   // partial sums per output element
+
 __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, int n, int lam,
                                                                   const double* __restrict__ loss) {
     extern __shared__ double s_elite[];  // [mu][n]
     __shared__ double s_key[kMaxLambda];
     __shared__ int s_order[kMaxLambda];
-    __shared__ double s_A[kMaxN * kMaxN], s_V[kMaxN * kMaxN];
-    __shared__ double s_yw[kMaxN], s_t[kMaxN], s_z[kMaxN];
+    __shared__ double s_w[kMaxLambda / 2];
+    __shared__ double s_A[kMaxN * kMaxN], s_V[kMaxN * kMaxN], s_T[kMaxN * kMaxN];
+    __shared__ double s_B[kMaxN * kMaxN], s_C[kMaxN * kMaxN];
+    __shared__ double s_part[kParts * kMaxN * (kMaxN + 1) / 2];
+    __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
     __shared__ double s_cs[2 * kMaxN];
     __shared__ int s_pq[2 * kMaxN];
     __shared__ double s_scal[4];
@@ -186,13 +204,30 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     const int mu = S.hdr->mu;
     const int n_blocks = S.hdr->n_blocks;
     const int nb = n / n_blocks;
+    const int nn = n * n;
+    const int ntri = n * (n + 1) / 2;
 
-    // 1. ranking by (loss, index), NaN as +inf
+    // 0. stage losses and state
     for (int k = tid; k < lam; k += kUpdThreads) {
         const double v = loss[k];
         s_key[k] = (v != v) ? INFINITY : v;
     }
+    for (int r = tid; r < mu; r += kUpdThreads) s_w[r] = S.weights[r];
+    for (int e = tid; e < nn; e += kUpdThreads) {
+        s_B[e] = S.B[e];
+        s_C[e] = S.C[e];
+    }
+    if (tid < n) {
+        s_pc[tid] = S.p_c[tid];
+        s_ps[tid] = S.p_sigma[tid];
+        s_D[tid] = S.D[tid];
+    }
+    const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
+    const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
+    const int64_t gen = S.hdr->gen;
     __syncthreads();
+
+    // 1. ranking by (loss, index), NaN as +inf
     for (int k = tid; k < lam; k += kUpdThreads) {
         const double key = s_key[k];
         int r = 0;
@@ -210,116 +245,144 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     }
     __syncthreads();
 
-    const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
-    const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
-
-    // 2. weighted recombination y_w and mean update
-    if (tid < n) {
-        double s = 0.0;
-        for (int r = 0; r < mu; r++) s += S.weights[r] * s_elite[r * n + tid];
-        s_yw[tid] = s;
-        S.mean[tid] = S.mean[tid] + c_m * sigma * s;
-    }
-    __syncthreads();
-    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w
-    if (tid < n) {
-        double s = 0.0;
-        for (int j = 0; j < n; j++) s += S.B[j * n + tid] * s_yw[j];
-        s_t[tid] = s / S.D[tid];
+    // 2. weighted recombination y_w = sum_r w_r y_{r:lambda}
+    for (int task = tid; task < kParts * n; task += kUpdThreads) {
+        const int part = task / n, i = task % n;
+        double acc = 0.0;
+        for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i];
+        s_part[part * n + i] = acc;
     }
     __syncthreads();
     if (tid < n) {
-        double s = 0.0;
-        for (int j = 0; j < n; j++) s += S.B[tid * n + j] * s_t[j];
-        s_z[tid] = s;
-        S.p_sigma[tid] = (1.0 - cs) * S.p_sigma[tid] + sqrt(cs * (2.0 - cs) * mu_eff) * s;
+        double acc = 0.0;
+        for (int part = 0; part < kParts; part++) acc += s_part[part * n + tid];
+        s_yw[tid] = acc;
+        S.mean[tid] = S.mean[tid] + c_m * sigma * acc;
+    }
+    __syncthreads();
+    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
+    if (tid < n) {
+        double acc = 0.0;
+        for (int j = 0; j < n; j++) acc += s_B[j * n + tid] * s_yw[j];
+        s_t[tid] = acc / s_D[tid];
+    }
+    __syncthreads();
+    if (tid < n) {
+        double acc = 0.0;
+        for (int j = 0; j < n; j++) acc += s_B[tid * n + j] * s_t[j];
+        s_ps[tid] = (1.0 - cs) * s_ps[tid] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
+        S.p_sigma[tid] = s_ps[tid];
     }
     __syncthreads();
     if (tid == 0) {
         double ss = 0.0;
-        for (int i = 0; i < n; i++) ss += S.p_sigma[i] * S.p_sigma[i];
+        for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
         const double ps_norm = sqrt(ss);
-        const double g1 = double(S.hdr->gen + 1);
-        const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * g1));
+        const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
         const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
         s_scal[0] = ps_norm;
         s_scal[1] = h;
         double sw = 0.0;
-        for (int r = 0; r < mu; r++) sw += S.weights[r];
+        for (int r = 0; r < mu; r++) sw += s_w[r];
         s_scal[2] = sw;
         *S.h_sigma = h;
+        *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
+        S.hdr->gen = gen + 1;
     }
     __syncthreads();
-    const double ps_norm = s_scal[0], h_sigma = s_scal[1], sum_w = s_scal[2];
-    if (tid < n) S.p_c[tid] = (1.0 - cc) * S.p_c[tid] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[tid];
-    __syncthreads();
+    const double h_sigma = s_scal[1], sum_w = s_scal[2];
+    if (tid < n) {
+        s_pc[tid] = (1.0 - cc) * s_pc[tid] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[tid];
+        S.p_c[tid] = s_pc[tid];
+    }
 
-    // 4. covariance: rank-one + rank-mu; symmetrise and mask into s_A
+    // 4. covariance: rank-one + rank-mu (upper triangle, partial sums), symmetric, block-masked
+    for (int task = tid; task < kParts * ntri; task += kUpdThreads) {
+        const int part = task / ntri, e = task % ntri;
+        int i = 0, rem = e;
+        while (rem >= n - i) { rem -= n - i; i++; }
+        const int j = i + rem;
+        double acc = 0.0;
+        for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
+        s_part[part * ntri + e] = acc;
+    }
+    __syncthreads();
     const double delta = (1.0 - h_sigma) * cc * (2.0 - cc);
     const double keep = 1.0 - c1 - cmu * sum_w;
-    for (int e = tid; e < n * n; e += kUpdThreads) {
-        const int i = e / n, j = e % n;
-        if (j < i) continue;
-        double rmu_ij = 0.0, rmu_ji = 0.0;
-        for (int r = 0; r < mu; r++) {
-            const double w = S.weights[r];
-            rmu_ij += w * s_elite[r * n + i] * s_elite[r * n + j];
-        }
-        rmu_ji = rmu_ij;
-        const double pc_i = S.p_c[i], pc_j = S.p_c[j];
-        const double cij = keep * S.C[i * n + j] + c1 * (pc_i * pc_j + delta * S.C[i * n + j]) + cmu * rmu_ij;
-        const double cji = keep * S.C[j * n + i] + c1 * (pc_j * pc_i + delta * S.C[j * n + i]) + cmu * rmu_ji;
+    for (int e = tid; e < ntri; e += kUpdThreads) {
+        int i = 0, rem = e;
+        while (rem >= n - i) { rem -= n - i; i++; }
+        const int j = i + rem;
+        double rmu = 0.0;
+        for (int part = 0; part < kParts; part++) rmu += s_part[part * ntri + e];
+        const double cij = keep * s_C[i * n + j] + c1 * (s_pc[i] * s_pc[j] + delta * s_C[i * n + j]) + cmu * rmu;
+        const double cji = keep * s_C[j * n + i] + c1 * (s_pc[j] * s_pc[i] + delta * s_C[j * n + i]) + cmu * rmu;
         double v = 0.5 * (cij + cji);
         if (i / nb != j / nb) v = 0.0;   // block-diagonal covariance
         s_A[i * n + j] = v;
         s_A[j * n + i] = v;
     }
-    for (int e = tid; e < n * n; e += kUpdThreads) s_V[e] = (e / n == e % n) ? 1.0 : 0.0;
-    if (tid == 0) {
-        *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
-        S.hdr->gen = S.hdr->gen + 1;
+    __syncthreads();
+    for (int e = tid; e < nn; e += kUpdThreads) S.C[e] = s_A[e];
+
+    // 5. Jacobi eigendecomposition, warm-started from the previous eigenvectors:
+    //    A = B^T C B (nearly diagonal when C changed little), V = B; every
+    //    rotation applies A <- J^T A J and V <- V J, so C = V diag(A) V^T at the end.
+    for (int e = tid; e < nn; e += kUpdThreads) {
+        const int i = e / n, j = e % n;
+        double t = 0.0;
+        for (int k = 0; k < n; k++) t += s_A[i * n + k] * s_B[k * n + j];
+        s_V[e] = t;                                   // C B (temporary)
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += kUpdThreads) S.C[e] = s_A[e];
+    for (int e = tid; e < nn; e += kUpdThreads) {
+        const int i = e / n, j = e % n;
+        double t = 0.0;
+        for (int k = 0; k < n; k++) t += s_B[k * n + i] * s_V[k * n + j];
+        s_T[e] = t;                                   // B^T C B
+    }
+    __syncthreads();
+    for (int e = tid; e < nn; e += kUpdThreads) {
+        const int i = e / n, j = e % n;
+        double v = 0.5 * (s_T[i * n + j] + s_T[j * n + i]);
+        if (i / nb != j / nb) v = 0.0;
+        s_A[e] = v;
+        s_V[e] = s_B[e];
+    }
+    __syncthreads();
 
-    // 5. cyclic Jacobi, tournament ordering: disjoint rotations in parallel
+    // cyclic sweeps in tournament order: disjoint rotations run in parallel; a
+    // rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|); the sweeps stop
+    // when one of them rotates nothing.
     const int m = nb + (nb & 1);
     const int half = m / 2;
     const int n_pairs = n_blocks * half;
     for (int sweep = 0; sweep < kMaxSweeps; sweep++) {
-        if (tid == 0) {
-            double off = 0.0, dia = 0.0;
-            for (int i = 0; i < n; i++)
-                for (int j = 0; j < n; j++) {
-                    const double v = s_A[i * n + j];
-                    if (i == j) dia += v * v;
-                    else off += v * v;
-                }
-            s_done = !(off > 1e-30 * dia);   // also stops on NaN
-        }
+        if (tid == 0) s_done = 1;
         __syncthreads();
-        if (s_done) break;
         for (int round = 0; round < m - 1; round++) {
             if (tid < n_pairs) {
                 const int b = tid / half, i = tid % half;
                 int p = rr_player(i, round, m), q = rr_player(m - 1 - i, round, m);
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
-                int valid = q < nb;
-                if (valid) {
+                bool rot = false;
+                if (q < nb) {
                     p += b * nb;
                     q += b * nb;
-                    const double apq = s_A[p * n + q];
-                    if (apq != 0.0) {
-                        const double tau = (s_A[q * n + q] - s_A[p * n + p]) / (2.0 * apq);
+                    const double apq = s_A[p * n + q], app = s_A[p * n + p], aqq = s_A[q * n + q];
+                    if (apq != 0.0 && apq * apq > 1e-30 * fabs(app * aqq)) {
+                        const double tau = (aqq - app) / (2.0 * apq);
                         const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
                         s = t * c;
+                        rot = true;
+                        s_done = 0;
                     }
                 }
                 s_cs[2 * tid] = c;
                 s_cs[2 * tid + 1] = s;
-                s_pq[2 * tid] = valid ? p : -1;
+                s_pq[2 * tid] = rot ? p : -1;
                 s_pq[2 * tid + 1] = q;
             }
             __syncthreads();
@@ -353,6 +416,8 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
             }
             __syncthreads();
         }
+        if (s_done) break;
+        __syncthreads();
     }
     // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
     if (tid == 0) {
@@ -456,8 +521,7 @@ tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, 
     clear_error();
     if (tk_status st = check_state(d_state, n, lambda)) return st;
     TK_REQUIRE(d_X != nullptr, "X is NULL");
-    const int threads = 256;
-    hipLaunchKernelGGL(cmaes_sample_kernel, dim3((lambda + threads - 1) / threads), dim3(threads), 0,
+    hipLaunchKernelGGL(cmaes_sample_kernel, dim3((lambda + kSampCand - 1) / kSampCand), dim3(64), 0,
                        reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_X);
     return check_launch("tk_cmaes_sample");
 }

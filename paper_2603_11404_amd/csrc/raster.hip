@@ -52,85 +52,215 @@ __device__ __forceinline__ bool project_snap(const float* __restrict__ M, float 
 
 // ---------------------------------------------------------------- triangle setup
 
-struct TriRec {            // 64 bytes
-    int64_t e0[3];         // edge functions (with bias) at the centre of the first block's first pixel
-    int32_t dx[3], dy[3];  // edge vectors in Q8 units
-    int32_t bx0, by0;      // first block
-    int32_t nbx, nby;      // blocks spanned; nby bit 16 = needs 64-bit evaluation
+// 64-byte record of one kept triangle.  The first 48 bytes are all the per-lane
+// task path reads.
+struct TriRec {
+    int32_t e0lo[3];       // low words of the edge functions at the centre of pixel (px0, py0), bias included
+    int32_t dx[3], dy[3];  // edge vectors in Q8 units (edge e runs from vertex e to vertex e+1)
+    int32_t box_x;         // px0 | px1 << 16  (clamped pixel box)
+    int32_t box_y;         // py0 | py1 << 16
+    int32_t flags;         // bit 0: 64-bit edge functions; bit 1: near (lane tasks); bits 8..: 8x8 words spanned
+    int32_t e0hi[3];       // high words of the edge functions
+    int32_t pad;
 };
 static_assert(sizeof(TriRec) == 64, "record size");
 
-constexpr int32_t kHugeBit = 1 << 16;
+constexpr int32_t kWide = 1;            // flags bit: 64-bit edge functions
+constexpr int32_t kNear = 2;            // flags bit: every vertex within 32 px of the box origin (lane tasks)
 
-// Builds the record of one triangle from its snapped vertices; false if culled.
+__device__ __forceinline__ int64_t rec_e0(const TriRec& r, int e) {
+    return int64_t((uint64_t(uint32_t(r.e0hi[e])) << 32) | uint64_t(uint32_t(r.e0lo[e])));
+}
+
+// Builds the record of one triangle from its snapped vertices; false if culled
+// (a vertex before the near plane, zero area, or no pixel centre on screen).
 __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x1, int32_t y1, int32_t x2,
                                                int32_t y2, const CamK& cam, TriRec& r) {
     if (x0 == INT32_MIN || x1 == INT32_MIN || x2 == INT32_MIN) return false;
-    const int64_t area2 = int64_t(x1 - x0) * int64_t(y2 - y0) - int64_t(y1 - y0) * int64_t(x2 - x0);
-    if (area2 == 0) return false;
-    if (area2 < 0) {  // orient positively (swap b and c)
-        int32_t t = x1; x1 = x2; x2 = t;
-        t = y1; y1 = y2; y2 = t;
-    }
     const int32_t xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
     const int32_t ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
-    // pixel centres 256 p + 128 inside [min, max]
-    int32_t px0 = (xmin - 128 + 255) >> 8, px1 = (xmax - 128) >> 8;
-    int32_t py0 = (ymin - 128 + 255) >> 8, py1 = (ymax - 128) >> 8;
-    px0 = max(px0, 0);
-    py0 = max(py0, 0);
-    px1 = min(px1, cam.width - 1);
-    py1 = min(py1, cam.height - 1);
+    // pixel centres 256 p + 128 inside [min, max], clamped to the image
+    const int32_t px0 = max((xmin - 128 + 255) >> 8, 0), px1 = min((xmax - 128) >> 8, cam.width - 1);
+    const int32_t py0 = max((ymin - 128 + 255) >> 8, 0), py1 = min((ymax - 128) >> 8, cam.height - 1);
     if (px0 > px1 || py0 > py1) return false;
-    r.bx0 = px0 >> 3;
-    r.by0 = py0 >> 3;
-    r.nbx = (px1 >> 3) - r.bx0 + 1;
-    r.nby = (py1 >> 3) - r.by0 + 1;
-    const int32_t vx[3] = {x0, x1, x2}, vy[3] = {y0, y1, y2};
-    const int64_t ox = int64_t(256) * (8 * r.bx0) + 128, oy = int64_t(256) * (8 * r.by0) + 128;
-    bool huge = false;
-    for (int e = 0; e < 3; e++) {
-        const int n = e == 2 ? 0 : e + 1;
-        const int32_t dx = vx[n] - vx[e], dy = vy[n] - vy[e];
-        const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
-        const int64_t E = int64_t(dx) * (oy - vy[e]) - int64_t(dy) * (ox - vx[e]) + (top_left ? 0 : -1);
-        r.e0[e] = E;
-        r.dx[e] = dx;
-        r.dy[e] = dy;
-        // largest |E| over every pixel centre of the spanned blocks
-        const int64_t a = int64_t(256) * (dy < 0 ? -int64_t(dy) : int64_t(dy));
-        const int64_t b = int64_t(256) * (dx < 0 ? -int64_t(dx) : int64_t(dx));
-        const int64_t bound = (E < 0 ? -E : E) + a * (8 * r.nbx - 1) + b * (8 * r.nby - 1);
-        huge |= bound >= (int64_t(1) << 31);
+    r.box_x = px0 | (px1 << 16);
+    r.box_y = py0 | (py1 << 16);
+    const int32_t w = px1 - px0, h = py1 - py0;
+    // vertices relative to the box origin (Q8)
+    const int32_t ox = px0 << 8, oy = py0 << 8;
+    int32_t rx[3] = {x0 - ox, x1 - ox, x2 - ox}, ry[3] = {y0 - oy, y1 - oy, y2 - oy};
+    const uint32_t lim = 1u << 13;   // 32 pixels
+    const bool near = (uint32_t(rx[0] + int32_t(lim)) < 2 * lim) & (uint32_t(rx[1] + int32_t(lim)) < 2 * lim) &
+                      (uint32_t(rx[2] + int32_t(lim)) < 2 * lim) & (uint32_t(ry[0] + int32_t(lim)) < 2 * lim) &
+                      (uint32_t(ry[1] + int32_t(lim)) < 2 * lim) & (uint32_t(ry[2] + int32_t(lim)) < 2 * lim);
+    bool wide = false;
+    if (near) {
+        // every vertex within 32 px of the box origin: differences < 2^14, so all
+        // products fit the 24-bit multiplier and every edge function over the box
+        // (and 7 pixels beyond it) stays below 2^30 -- exact in 32 bits
+        const int32_t area2 = __mul24(rx[1] - rx[0], ry[2] - ry[0]) - __mul24(ry[1] - ry[0], rx[2] - rx[0]);
+        if (area2 == 0) return false;
+        if (area2 < 0) {
+            int32_t t = rx[1]; rx[1] = rx[2]; rx[2] = t;
+            t = ry[1]; ry[1] = ry[2]; ry[2] = t;
+        }
+        for (int e = 0; e < 3; e++) {
+            const int n = e == 2 ? 0 : e + 1;
+            const int32_t dx = rx[n] - rx[e], dy = ry[n] - ry[e];
+            const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
+            const int32_t E = __mul24(dx, 128 - ry[e]) - __mul24(dy, 128 - rx[e]) + (top_left ? 0 : -1);
+            r.e0lo[e] = E;
+            r.e0hi[e] = E >> 31;
+            r.dx[e] = dx;
+            r.dy[e] = dy;
+        }
+    } else {
+        int32_t vx[3] = {x0, x1, x2}, vy[3] = {y0, y1, y2};
+        const int64_t area2 = int64_t(x1 - x0) * int64_t(y2 - y0) - int64_t(y1 - y0) * int64_t(x2 - x0);
+        if (area2 == 0) return false;
+        if (area2 < 0) {
+            vx[1] = x2; vx[2] = x1;
+            vy[1] = y2; vy[2] = y1;
+        }
+        const int64_t cx = int64_t(ox) + 128, cy = int64_t(oy) + 128;
+        for (int e = 0; e < 3; e++) {
+            const int n = e == 2 ? 0 : e + 1;
+            const int32_t dx = vx[n] - vx[e], dy = vy[n] - vy[e];
+            const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
+            const int64_t E = int64_t(dx) * (cy - vy[e]) - int64_t(dy) * (cx - vx[e]) + (top_left ? 0 : -1);
+            r.e0lo[e] = int32_t(uint32_t(uint64_t(E)));
+            r.e0hi[e] = int32_t(uint32_t(uint64_t(E) >> 32));
+            r.dx[e] = dx;
+            r.dy[e] = dy;
+            // largest |E| over the pixel centres within 7 pixels of the box
+            const int64_t a = int64_t(256) * (dy < 0 ? -int64_t(dy) : int64_t(dy));
+            const int64_t b = int64_t(256) * (dx < 0 ? -int64_t(dx) : int64_t(dx));
+            const int64_t bound = (E < 0 ? -E : E) + a * (w + 7) + b * (h + 7);
+            wide |= bound >= (int64_t(1) << 31);
+        }
     }
-    if (huge) r.nby |= kHugeBit;
+    const int nwords = ((px1 >> 3) - (px0 >> 3) + 1) * ((py1 >> 3) - (py0 >> 3) + 1);
+    r.flags = (wide ? kWide : 0) | (near ? kNear : 0) | (min(nwords, 0xffffff) << 8);
+    r.pad = 0;
     return true;
 }
 
-// ---------------------------------------------------------------- coverage of one triangle
+// ---------------------------------------------------------------- per-wave LDS staging (struct of arrays)
 
-__device__ __forceinline__ void cover_triangle(const TriRec& r, int lx, int ly, int lane,
-                                               unsigned long long* __restrict__ s_mask, int words_x) {
-    const int bx0 = __builtin_amdgcn_readfirstlane(r.bx0);
-    const int by0 = __builtin_amdgcn_readfirstlane(r.by0);
-    const int nbx = __builtin_amdgcn_readfirstlane(r.nbx);
-    const int nby_raw = __builtin_amdgcn_readfirstlane(r.nby);
-    const int nby = nby_raw & 0xffff;
-    if (!(nby_raw & kHugeBit)) {
-        // 32-bit modular evaluation: E(lane, block) = L + bx*8A + by*8B, exact since |E| < 2^31
+// Slot j's record is four 16-byte groups q0[j]..q3[j]: lanes reading different
+// slots read consecutive 16-byte chunks (no bank conflicts), lanes reading one
+// slot get a broadcast.
+struct WaveStage {
+    int4 q0[kWave];   // e0lo[0..2], box_x
+    int4 q1[kWave];   // dx[0..2],   box_y
+    int4 q2[kWave];   // dy[0..2],   flags
+    int4 q3[kWave];   // e0hi[0..2], inclusive prefix of the lane-task counts
+};
+
+__device__ __forceinline__ void stage_put(WaveStage& st, int j, const TriRec& r) {
+    st.q0[j] = make_int4(r.e0lo[0], r.e0lo[1], r.e0lo[2], r.box_x);
+    st.q1[j] = make_int4(r.dx[0], r.dx[1], r.dx[2], r.box_y);
+    st.q2[j] = make_int4(r.dy[0], r.dy[1], r.dy[2], r.flags);
+}
+
+__device__ __forceinline__ TriRec stage_get(const WaveStage& st, int j) {
+    TriRec r;
+    const int4 a = st.q0[j], b = st.q1[j], c = st.q2[j], d = st.q3[j];
+    r.e0lo[0] = a.x; r.e0lo[1] = a.y; r.e0lo[2] = a.z; r.box_x = a.w;
+    r.dx[0] = b.x; r.dx[1] = b.y; r.dx[2] = b.z; r.box_y = b.w;
+    r.dy[0] = c.x; r.dy[1] = c.y; r.dy[2] = c.z; r.flags = c.w;
+    r.e0hi[0] = d.x; r.e0hi[1] = d.y; r.e0hi[2] = d.z;
+    r.pad = 0;
+    return r;
+}
+
+// Lane tasks of a near triangle: 8-column windows starting at the box's left
+// column, times the 4-row bands (aligned to the mask words) the box touches.
+__device__ __forceinline__ int task_windows(int box_x) { return ((box_x >> 16) - (box_x & 0xffff)) / 8 + 1; }
+__device__ __forceinline__ int task_bands(int box_y) { return ((box_y >> 16) >> 2) - ((box_y & 0xffff) >> 2) + 1; }
+
+// ---------------------------------------------------------------- coverage of one lane task
+
+// One lane rasterises the part of a near triangle's box inside one window of
+// 8 columns x one 4-row band, with incremental 32-bit edge functions, fully
+// unrolled: each row tests 8 pixel centres right to left and collects the
+// outside flags with v_alignbit.  The 4 row bytes are then split between the
+// (at most two) mask words the window straddles and ORed into LDS.
+__device__ __forceinline__ void cover_window(const WaveStage& st, int j, int k, unsigned long long* __restrict__ s_mask,
+                                             int words_x) {
+    const int4 q0 = st.q0[j], q1 = st.q1[j], q2 = st.q2[j];
+    const int px0 = q0.w & 0xffff, px1 = q0.w >> 16;
+    const int py0 = q1.w & 0xffff, py1 = q1.w >> 16;
+    const int nwin = (px1 - px0) / 8 + 1;
+    // k = band * nwin + win  (small integers: the float quotient is exact after flooring)
+    const int band_i = int(floorf((float(k) + 0.5f) * __builtin_amdgcn_rcpf(float(nwin))));
+    const int win = k - band_i * nwin;
+    const int band = (py0 >> 2) + band_i;
+    const int xa = px0 + 8 * win, xe = min(xa + 7, px1);
+    const int ya = max(py0, 4 * band), yb = min(py1, 4 * band + 3);
+    const int32_t e0[3] = {q0.x, q0.y, q0.z}, dxs[3] = {q1.x, q1.y, q1.z}, dys[3] = {q2.x, q2.y, q2.z};
+    uint32_t A[3], E[3], B[3];
+    for (int e = 0; e < 3; e++) {
+        const int32_t dx = dxs[e], dy = dys[e];
+        A[e] = 0u - (uint32_t(dy) << 8);
+        B[e] = uint32_t(dx) << 8;
+        E[e] = uint32_t(e0[e] + __mul24(-(dy << 8), xe - px0) + __mul24(dx << 8, ya - py0));
+    }
+    const int align = 7 - (xe - xa);
+    uint32_t rows = 0u;
+#pragma unroll
+    for (int row = 0; row < 4; row++) {
+        uint32_t t0 = E[0], t1 = E[1], t2 = E[2], neg = 0u;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            neg = __builtin_amdgcn_alignbit(neg, t0 | t1 | t2, 31);
+            t0 -= A[0];
+            t1 -= A[1];
+            t2 -= A[2];
+        }
+        // bit i of neg is pixel xe - 7 + i; after the shift bit c is column xa + c
+        const uint32_t cov = (~neg & 0xFFu) >> align;
+        if (ya + row <= yb) rows |= cov << (8 * ((ya + row) & 3));
+        E[0] += B[0];
+        E[1] += B[1];
+        E[2] += B[2];
+    }
+    if (!rows) return;
+    const int wx = xa >> 3, sh = xa & 7, wy = band >> 1, half = 32 * (band & 1);
+    const uint32_t lo = (rows << sh) & (0x01010101u * ((0xFFu << sh) & 0xFFu));
+    const uint32_t hi = (rows >> (8 - sh)) & (0x01010101u * (0xFFu >> (8 - sh)));
+    if (lo) atomicOr(&s_mask[wy * words_x + wx], (unsigned long long)lo << half);
+    if (hi) atomicOr(&s_mask[wy * words_x + wx + 1], (unsigned long long)hi << half);
+}
+
+// ---------------------------------------------------------------- cooperative coverage of a big triangle
+
+// The whole wave walks the 8x8 blocks of one triangle's box: lane = pixel,
+// three edge functions per lane, the 64-lane ballot is the block's word.
+__device__ __forceinline__ void cover_big(const WaveStage& st, int j, int lx, int ly, int lane,
+                                          unsigned long long* __restrict__ s_mask, int words_x) {
+    const TriRec r = stage_get(st, j);
+    const int box_x = __builtin_amdgcn_readfirstlane(r.box_x);
+    const int box_y = __builtin_amdgcn_readfirstlane(r.box_y);
+    const int flags = __builtin_amdgcn_readfirstlane(r.flags);
+    const int px0 = box_x & 0xffff, px1 = box_x >> 16, py0 = box_y & 0xffff, py1 = box_y >> 16;
+    const int bx0 = px0 >> 3, by0 = py0 >> 3;
+    const int nbx = (px1 >> 3) - bx0 + 1, nby = (py1 >> 3) - by0 + 1;
+    const int ox = 8 * bx0 + lx - px0, oy = 8 * by0 + ly - py0;   // lane pixel offset from the box origin
+    if (!(flags & kWide)) {
+        // 32-bit modular evaluation, exact since every |E| over the blocks is < 2^31
         uint32_t L[3], SX[3], SY[3];
         for (int e = 0; e < 3; e++) {
-            const uint32_t A = 0u - (uint32_t(r.dy[e]) << 8);  // per pixel step in x: -256 dy
-            const uint32_t B = uint32_t(r.dx[e]) << 8;         // per pixel step in y: +256 dx
-            L[e] = A * uint32_t(lx) + B * uint32_t(ly) + uint32_t(r.e0[e]);
+            const uint32_t A = 0u - (uint32_t(r.dy[e]) << 8);
+            const uint32_t B = uint32_t(r.dx[e]) << 8;
+            L[e] = uint32_t(r.e0lo[e]) + A * uint32_t(ox) + B * uint32_t(oy);
             SX[e] = A * 8u;
             SY[e] = B * 8u;
         }
         for (int by = 0; by < nby; by++) {
             uint32_t E0 = L[0], E1 = L[1], E2 = L[2];
             for (int bx = 0; bx < nbx; bx++) {
-                const bool in = int32_t(E0 | E1 | E2) >= 0;
-                const unsigned long long m = __ballot(in);
+                const unsigned long long m = __ballot(int32_t(E0 | E1 | E2) >= 0);
                 if (m != 0ull && lane == 0) atomicOr(&s_mask[(by0 + by) * words_x + bx0 + bx], m);
                 E0 += SX[0];
                 E1 += SX[1];
@@ -141,13 +271,14 @@ __device__ __forceinline__ void cover_triangle(const TriRec& r, int lx, int ly, 
             L[2] += SY[2];
         }
     } else {
-        // 64-bit evaluation for triangles whose edge functions exceed 32 bits
+        int64_t e0[3];
+        for (int e = 0; e < 3; e++) e0[e] = rec_e0(r, e);
         for (int by = 0; by < nby; by++) {
             for (int bx = 0; bx < nbx; bx++) {
-                const int64_t px = 8 * bx + lx, py = 8 * by + ly;   // pixel offset from the record origin
+                const int64_t px = 8 * bx + ox, py = 8 * by + oy;
                 bool in = true;
                 for (int e = 0; e < 3; e++) {
-                    const int64_t E = r.e0[e] - int64_t(256) * r.dy[e] * px + int64_t(256) * r.dx[e] * py;
+                    const int64_t E = e0[e] - int64_t(256) * r.dy[e] * px + int64_t(256) * r.dx[e] * py;
                     in = in && (E >= 0);
                 }
                 const unsigned long long m = __ballot(in);
@@ -179,13 +310,14 @@ struct RasterArgs {
     const unsigned long long* target;
     int32_t* counts;             // [batch][2]
     int32_t batch;
+    int32_t pretransform;        // snapped points to a workspace the kernel fills first
 };
 
 template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
 __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     constexpr int NW = NT / kWave;
     extern __shared__ unsigned long long s_mask[];
-    __shared__ TriRec s_rec[NW][kWave];
+    __shared__ WaveStage s_stage[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
 
@@ -194,51 +326,107 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     const int lx = lane & 7, ly = lane >> 3;
     const CamK& cam = a.cam;
     const int words = cam.words_x * cam.words_y;
+    WaveStage& st = s_stage[wave];
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
-    if (!FROM_SNAPPED)
+    if (!FROM_SNAPPED || a.pretransform)
         for (int i = tid; i < a.meshes.n_meshes * 48; i += NT)
             s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
     __syncthreads();
+    if (FROM_SNAPPED && a.pretransform) {
+        // transform, project and snap every vertex of this candidate once into the workspace
+        int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * a.meshes.total_vertices;
+        for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
+            const MeshK& mesh = a.meshes.m[mi];
+            for (int v = tid; v < mesh.n_vertices; v += NT) {
+                const float* p = mesh.vertices + size_t(v) * 3;
+                int32_t X, Y;
+                project_snap(s_M + mi * 48 + 12 * mesh.vertex_link[v], p[0], p[1], p[2], cam, X, Y);
+                out[mesh.vertex_offset + v] = make_int2(X, Y);
+            }
+        }
+        __syncthreads();
+    }
 
     for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
         const MeshK& mesh = a.meshes.m[mi];
         const float* M = s_M + mi * 48;
-        for (int base = wave * kWave; base < mesh.n_triangles; base += NT) {
-            const int t = base + lane;
-            bool valid = false;
-            TriRec rec;
-            if (t < mesh.n_triangles) {
-                const int32_t i0 = mesh.triangles[3 * t], i1 = mesh.triangles[3 * t + 1],
-                              i2 = mesh.triangles[3 * t + 2];
-                int32_t X[3], Y[3];
-                const int32_t idx[3] = {i0, i1, i2};
+        const int T = mesh.n_triangles;
+        const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
+                           (size_t(b) * a.meshes.total_vertices + mesh.vertex_offset);
+        // indices of this lane's first triangle; later chunks are prefetched one iteration ahead
+        int t = wave * kWave + lane;
+        int32_t idx[3] = {0, 0, 0};
+        if (t < T)
+            for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * t + k];
+        for (int base = wave * kWave; base < T; base += NT) {
+            t = base + lane;
+            const bool live = t < T;
+            int32_t X[3] = {INT32_MIN, INT32_MIN, INT32_MIN}, Y[3] = {0, 0, 0};
+            float vx[3], vy[3], vz[3];
+            int link[3];
+            if (live) {
                 for (int k = 0; k < 3; k++) {
                     if (FROM_SNAPPED) {
-                        const int32_t* p =
-                            a.snapped + (size_t(b) * a.meshes.total_vertices + mesh.vertex_offset + idx[k]) * 2;
-                        X[k] = p[0];
-                        Y[k] = p[1];
+                        const int2 p = snap[idx[k]];
+                        X[k] = p.x;
+                        Y[k] = p.y;
                     } else {
                         const float* v = mesh.vertices + size_t(idx[k]) * 3;
-                        const int link = mesh.vertex_link[idx[k]];
-                        project_snap(M + 12 * link, v[0], v[1], v[2], cam, X[k], Y[k]);
+                        vx[k] = v[0];
+                        vy[k] = v[1];
+                        vz[k] = v[2];
+                        link[k] = mesh.vertex_link[idx[k]];
                     }
                 }
-                valid = setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
             }
-            if (valid) s_rec[wave][lane] = rec;
-            unsigned long long todo = __ballot(valid);
-            // records written by other lanes of this wave must be visible before they are read
+            // prefetch the next chunk's indices while this chunk is processed
+            const int tn = t + NT;
+            if (tn < T)
+                for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
+            if (!FROM_SNAPPED && live)
+                for (int k = 0; k < 3; k++) project_snap(M + 12 * link[k], vx[k], vy[k], vz[k], cam, X[k], Y[k]);
+            TriRec rec;
+            const bool valid = live && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
+            const bool near = valid && (rec.flags & kNear);
+            if (valid) stage_put(st, lane, rec);
+            // lane tasks of near triangles (at most 5 x 9 each): inclusive prefix over
+            // the wave from one ballot per bit of the count
+            const int cnt = near ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
+            int incl = cnt, total = 0;
+#pragma unroll
+            for (int bit = 0; bit < 6; bit++) {
+                const unsigned long long m = __ballot((cnt >> bit) & 1);
+                incl += int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)))
+                        << bit;
+                total += __popcll(m) << bit;
+            }
+            st.q3[lane] = make_int4(rec.e0hi[0], rec.e0hi[1], rec.e0hi[2], incl);
+            const unsigned long long big = __ballot(valid && !near);
+            // staged fields written by other lanes must be visible before they are read
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            for (int base = 0; base < total; base += kWave) {
+                const int q = base + lane;
+                if (q < total) {
+                    // slot j: first lane whose inclusive prefix exceeds q
+                    int j = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1)
+                        if (st.q3[j + step - 1].w <= q) j += step;
+                    const int k = q - (st.q3[j].w - task_windows(st.q0[j].w) * task_bands(st.q1[j].w));
+                    cover_window(st, j, k, s_mask, cam.words_x);
+                }
+            }
+            unsigned long long todo = big;
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1;
-                const TriRec r = s_rec[wave][j];
-                cover_triangle(r, lx, ly, lane, s_mask, cam.words_x);
+                cover_big(st, j, lx, ly, lane, s_mask, cam.words_x);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -276,7 +464,6 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     }
 }
 
-constexpr int kRasterThreads = 512;
 
 // ---------------------------------------------------------------- snapped vertices (debug / parity)
 
@@ -333,8 +520,8 @@ __global__ __launch_bounds__(256) void stats_kernel(RasterArgs a, unsigned long 
             TriRec r;
             if (!setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], a.cam, r)) continue;
             kept++;
-            pairs += uint64_t(r.nbx) * uint64_t(r.nby & 0xffff);
-            huge += (r.nby & kHugeBit) ? 1 : 0;
+            pairs += uint64_t(r.flags >> 8);
+            huge += (r.flags & kWide) ? 1 : 0;
             // exact pixel box from the vertices again
             const int32_t xmin = min(X[0], min(X[1], X[2])), xmax = max(X[0], max(X[1], X[2]));
             const int32_t ymin = min(Y[0], min(Y[1], Y[2])), ymax = max(Y[0], max(Y[1], Y[2]));
@@ -393,27 +580,40 @@ __global__ __launch_bounds__(256) void mask_count_kernel(const unsigned long lon
 
 size_t mask_lds_bytes(const CamK& cam) { return sizeof(unsigned long long) * size_t(cam.words_x) * cam.words_y; }
 
-constexpr size_t kStaticLds = sizeof(TriRec) * kRasterThreads + sizeof(float) * kMaxArms * 48 + 64;
 constexpr size_t kLdsLimit = 160 * 1024;
 
-template <bool FS, bool WM, bool CN>
-tk_status launch_raster(const RasterArgs& a, hipStream_t s, const char* what) {
-    const size_t lds = mask_lds_bytes(a.cam);
-    if (lds + kStaticLds > kLdsLimit)
-        return fail(TK_ERR_UNSUPPORTED, "%s: image %dx%d needs %zu bytes of LDS for its mask (limit %zu)", what,
-                    a.cam.width, a.cam.height, lds, kLdsLimit - kStaticLds);
-    if (a.batch == 0) return TK_OK;
-    auto kern = raster_kernel<FS, WM, CN, kRasterThreads>;
+template <int NT>
+constexpr size_t static_lds() {
+    return sizeof(WaveStage) * (NT / kWave) + sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (NT / kWave);
+}
+
+template <bool FS, bool WM, bool CN, int NT>
+tk_status launch_raster_nt(const RasterArgs& a, size_t lds, hipStream_t s, const char* what) {
+    auto kern = raster_kernel<FS, WM, CN, NT>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] {
         attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsLimit - kStaticLds));
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsLimit - static_lds<NT>()));
     });
     if (attr_err != hipSuccess)
         return fail(TK_ERR_DEVICE, "%s: cannot raise the dynamic LDS limit: %s", what, hipGetErrorString(attr_err));
-    hipLaunchKernelGGL(kern, dim3(a.batch), dim3(kRasterThreads), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(a.batch), dim3(NT), lds, s, a);
     return check_launch(what);
+}
+
+// One workgroup per candidate; the widest block (16, 8 or 4 waves) whose
+// staging fits in LDS next to the image mask.
+template <bool FS, bool WM, bool CN>
+tk_status launch_raster(const RasterArgs& a, hipStream_t s, const char* what) {
+    const size_t lds = mask_lds_bytes(a.cam);
+    if (lds + static_lds<256>() > kLdsLimit)
+        return fail(TK_ERR_UNSUPPORTED, "%s: image %dx%d needs %zu bytes of LDS for its mask (limit %zu)", what,
+                    a.cam.width, a.cam.height, lds, kLdsLimit - static_lds<256>());
+    if (a.batch == 0) return TK_OK;
+    if (lds + static_lds<1024>() <= kLdsLimit) return launch_raster_nt<FS, WM, CN, 1024>(a, lds, s, what);
+    if (lds + static_lds<512>() <= kLdsLimit) return launch_raster_nt<FS, WM, CN, 512>(a, lds, s, what);
+    return launch_raster_nt<FS, WM, CN, 256>(a, lds, s, what);
 }
 
 tk_status common_raster_checks(int32_t batch, const tk_mesh* meshes, int32_t n_meshes, const tk_camera* cam,
@@ -428,6 +628,21 @@ tk_status common_raster_checks(int32_t batch, const tk_mesh* meshes, int32_t n_m
     a->masks = nullptr;
     a->target = nullptr;
     a->counts = nullptr;
+    a->pretransform = 0;
+    return TK_OK;
+}
+
+// With a workspace of batch * sum(V) * 8 bytes the kernel snaps every vertex
+// once into it and rasterises from there; without one each triangle
+// transforms its own three vertices.
+tk_status attach_workspace(RasterArgs* a, void* d_ws, size_t ws_bytes, const char* what) {
+    if (d_ws == nullptr) return TK_OK;
+    const size_t need = size_t(a->batch) * size_t(a->meshes.total_vertices) * 2 * sizeof(int32_t);
+    if (ws_bytes < need)
+        return fail(TK_ERR_WORKSPACE_TOO_SMALL, "%s: workspace of %zu bytes, %zu needed", what, ws_bytes, need);
+    TK_REQUIRE((reinterpret_cast<uintptr_t>(d_ws) & 7) == 0, "%s: workspace must be 8-byte aligned", what);
+    a->snapped = static_cast<const int32_t*>(d_ws);
+    a->pretransform = 1;
     return TK_OK;
 }
 
@@ -438,14 +653,24 @@ using namespace tk;
 
 extern "C" {
 
+size_t tk_raster_workspace_bytes(int32_t batch, const tk_mesh* meshes, int32_t n_meshes) {
+    if (batch < 0 || meshes == nullptr || n_meshes < 1 || n_meshes > kMaxArms) return 0;
+    size_t v = 0;
+    for (int i = 0; i < n_meshes; i++) v += size_t(meshes[i].n_vertices > 0 ? meshes[i].n_vertices : 0);
+    return size_t(batch) * v * 2 * sizeof(int32_t);
+}
+
 tk_status tk_raster_silhouette(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
-                               const tk_camera* cam, uint64_t* d_masks, tk_stream s) {
+                               const tk_camera* cam, uint64_t* d_masks, void* d_ws, size_t ws_bytes, tk_stream s) {
     clear_error();
     RasterArgs a;
     if (tk_status st = common_raster_checks(batch, meshes, n_meshes, cam, &a)) return st;
     TK_REQUIRE(batch == 0 || (d_link_xf && d_masks), "link_xf / masks is NULL");
     a.link_xf = d_link_xf;
     a.masks = reinterpret_cast<unsigned long long*>(d_masks);
+    if (tk_status st = attach_workspace(&a, d_ws, ws_bytes, "tk_raster_silhouette")) return st;
+    if (a.pretransform)
+        return launch_raster<true, true, false>(a, reinterpret_cast<hipStream_t>(s), "tk_raster_silhouette");
     return launch_raster<false, true, false>(a, reinterpret_cast<hipStream_t>(s), "tk_raster_silhouette");
 }
 
@@ -461,7 +686,8 @@ tk_status tk_raster_from_snapped(const int32_t* d_snapped, int32_t batch, const 
 }
 
 tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
-                        const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, tk_stream s) {
+                        const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, void* d_ws,
+                        size_t ws_bytes, tk_stream s) {
     clear_error();
     RasterArgs a;
     if (tk_status st = common_raster_checks(batch, meshes, n_meshes, cam, &a)) return st;
@@ -469,6 +695,8 @@ tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* me
     a.link_xf = d_link_xf;
     a.target = reinterpret_cast<const unsigned long long*>(d_target);
     a.counts = d_counts;
+    if (tk_status st = attach_workspace(&a, d_ws, ws_bytes, "tk_eval_fused")) return st;
+    if (a.pretransform) return launch_raster<true, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_eval_fused");
     return launch_raster<false, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_eval_fused");
 }
 

@@ -7,7 +7,7 @@
 #include <cstdio>
 #include <string>
 
-#include "../../include/tk.h"
+#include "tk.h"
 
 namespace tk {
 

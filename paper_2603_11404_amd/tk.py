@@ -63,6 +63,7 @@ EXPORTS = [
     "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_set_mean", "tk_cmaes_sample",
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
+    "tk_raster_workspace_bytes",
 ]
 
 _lib = None
@@ -90,15 +91,18 @@ def lib():
         L.tk_cmaes_update.argtypes = [P, i32, i32, P, P]
         L.tk_fk_transform.argtypes = [P, i32, i32, P, P, P, P, P]
         L.tk_snap_vertices.argtypes = [P, i32, P, i32, P, P, P]
-        L.tk_raster_silhouette.argtypes = [P, i32, P, i32, P, P, P]
+        L.tk_raster_workspace_bytes.restype = ctypes.c_size_t
+        L.tk_raster_workspace_bytes.argtypes = [i32, P, i32]
+        L.tk_raster_silhouette.argtypes = [P, i32, P, i32, P, P, P, ctypes.c_size_t, P]
         L.tk_raster_from_snapped.argtypes = [P, i32, P, i32, P, P, P]
         L.tk_mask_loss.argtypes = [P, i32, P, P, P, P]
         L.tk_mask_popcount.argtypes = [P, i32, P, P, P]
-        L.tk_eval_fused.argtypes = [P, i32, P, i32, P, P, P, P]
+        L.tk_eval_fused.argtypes = [P, i32, P, i32, P, P, P, P, ctypes.c_size_t, P]
         L.tk_compose_loss.argtypes = [P, i32, P, i32, f64, P, P, i32, f64, f64, P, P]
         L.tk_raster_stats.argtypes = [P, i32, P, i32, P, P, P]
         for name in EXPORTS:
-            if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes"):
+            if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
+                            "tk_raster_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -259,10 +263,25 @@ def snap_vertices(link_xf, batch, meshes, cam, snapped, stream=None):
     _check(lib().tk_snap_vertices(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(snapped), _stream(stream)))
 
 
-def raster_silhouette(link_xf, batch, meshes, cam, masks, stream=None):
+def raster_workspace_bytes(batch, meshes) -> int:
+    arr, nm = _meshes(meshes)
+    return int(lib().tk_raster_workspace_bytes(batch, arr, nm))
+
+
+def raster_workspace(batch, meshes, device="cuda") -> torch.Tensor:
+    """A device workspace for tk_raster_silhouette / tk_eval_fused."""
+    return torch.empty(max(raster_workspace_bytes(batch, meshes), 8), dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    return (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+
+
+def raster_silhouette(link_xf, batch, meshes, cam, masks, ws=None, stream=None):
     arr, nm = _meshes(meshes)
     c = camera(cam)
-    _check(lib().tk_raster_silhouette(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(masks),
+    wp, wb = _ws(ws)
+    _check(lib().tk_raster_silhouette(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(masks), wp, wb,
                                       _stream(stream)))
 
 
@@ -283,10 +302,11 @@ def mask_popcount(masks, batch, cam, count, stream=None):
     _check(lib().tk_mask_popcount(_ptr(masks), batch, ctypes.byref(c), _ptr(count), _stream(stream)))
 
 
-def eval_fused(link_xf, batch, meshes, cam, target, counts, stream=None):
+def eval_fused(link_xf, batch, meshes, cam, target, counts, ws=None, stream=None):
     arr, nm = _meshes(meshes)
     c = camera(cam)
-    _check(lib().tk_eval_fused(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(target), _ptr(counts),
+    wp, wb = _ws(ws)
+    _check(lib().tk_eval_fused(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(target), _ptr(counts), wp, wb,
                                _stream(stream)))
 
 

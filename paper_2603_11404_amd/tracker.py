@@ -47,7 +47,7 @@ class Problem:
         xf = torch.empty(B, self.n_arms, 4, 12, dtype=torch.float32, device=self.device)
         tk.fk_transform(theta.contiguous(), B, self.n_arms, self.chains, xf)
         masks = torch.empty(B, *self.words, dtype=torch.int64, device=self.device)
-        tk.raster_silhouette(xf, B, self.meshes, self.cam, masks)
+        tk.raster_silhouette(xf, B, self.meshes, self.cam, masks, tk.raster_workspace(B, self.meshes, self.device))
         return masks
 
     def keypoints(self, theta: torch.Tensor) -> torch.Tensor:
@@ -76,6 +76,7 @@ class Generation:
         self.counts = torch.empty(self.lam, 2, dtype=torch.int32, device=d)
         self.loss = torch.empty(self.lam, dtype=torch.float64, device=d)
         self.masks1 = torch.empty(1, *problem.words, dtype=torch.int64, device=d)
+        self.ws = tk.raster_workspace(self.lam, problem.meshes, d)   # snapped vertices, one set per candidate
         self.graph = None
 
     def init(self, mean0, sigma0, offset, scale, seed, c_m_scale=1.0, c_mu_scale=1.0, c1_scale=1.0):
@@ -91,7 +92,7 @@ class Generation:
         p = self.p
         tk.fk_transform(self.X, self.lam, p.n_arms, p.chains, self.xf, self.kp if self.use_kp else None,
                         p.cam if self.use_kp else None)
-        tk.eval_fused(self.xf, self.lam, p.meshes, p.cam, p.target, self.counts)
+        tk.eval_fused(self.xf, self.lam, p.meshes, p.cam, p.target, self.counts, self.ws)
         tk.compose_loss(self.counts, self.lam, p.target_count, self.loss_kind, self.loss, self.lambda_app,
                         self.kp if self.use_kp else None, p.kp_ref if self.use_kp else None, p.n_arms,
                         self.lambda_kp, self.tau)
@@ -109,7 +110,7 @@ class Generation:
         for k in range(self.lam):
             tk.fk_transform(self.X[k:k + 1], 1, p.n_arms, p.chains, self.xf[k:k + 1],
                             self.kp[k:k + 1] if self.use_kp else None, p.cam if self.use_kp else None)
-            tk.raster_silhouette(self.xf[k:k + 1], 1, p.meshes, p.cam, self.masks1)
+            tk.raster_silhouette(self.xf[k:k + 1], 1, p.meshes, p.cam, self.masks1, self.ws)
             tk.mask_loss(self.masks1, 1, p.target, p.cam, self.counts[k:k + 1])
             tk.compose_loss(self.counts[k:k + 1], 1, p.target_count, self.loss_kind, self.loss[k:k + 1],
                             self.lambda_app, self.kp[k:k + 1] if self.use_kp else None,

@@ -168,6 +168,12 @@ def test_fused_equals_plain_and_oracle_counts():
     T.mask_loss(masks, B, target, cam, c_plain)
     c_fused = torch.empty(B, 2, dtype=torch.int32, device=DEV)
     T.eval_fused(xf, B, [dm], cam, target, c_fused)
+    # the workspace forms (vertices snapped once per candidate) give the same bits
+    ws = T.raster_workspace(B, [dm], DEV)
+    masks_ws = torch.empty_like(masks)
+    T.raster_silhouette(xf, B, [dm], cam, masks_ws, ws)
+    c_fused_ws = torch.empty(B, 2, dtype=torch.int32, device=DEV)
+    T.eval_fused(xf, B, [dm], cam, target, c_fused_ws, ws)
     # plain per-vertex snap + raster_from_snapped gives the same masks again
     sn = torch.empty(B, mesh.n_vertices, 2, dtype=torch.int32, device=DEV)
     T.snap_vertices(xf, B, [dm], cam, sn)
@@ -175,7 +181,9 @@ def test_fused_equals_plain_and_oracle_counts():
     T.raster_from_snapped(sn, B, [dm], cam, masks2)
     torch.cuda.synchronize()
     assert torch.equal(c_plain, c_fused)
+    assert torch.equal(c_plain, c_fused_ws)
     assert torch.equal(masks, masks2)
+    assert torch.equal(masks, masks_ws)
     assert int(c_plain[:, 0].max()) > 0
 
 
@@ -242,3 +250,7 @@ def test_invalid_arguments_raise_without_launch():
         T.raster_silhouette(xf, 2, [mesh], too_big, torch.empty(2, 188, 250, dtype=torch.int64, device=DEV))
     assert e.value.status == 2
     T.raster_silhouette(xf, 0, [mesh], cam, masks)        # empty batch is a no-op
+    small_ws = torch.empty(8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(T.TkError) as e:
+        T.raster_silhouette(xf, 2, [mesh], cam, masks, small_ws)
+    assert e.value.status == 3
