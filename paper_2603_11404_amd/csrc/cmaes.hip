@@ -172,11 +172,88 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
 
 // ---------------------------------------------------------------- update
 
-constexpr int kUpdThreads = 256;
+constexpr int kUpdThreads = 1024;
+constexpr int kWave64 = 64;
 constexpr int kMaxSweeps = 30;
 
-__device__ inline int rr_player(int i, int round, int m) {  // circle-method tournament
-    return i == 0 ? 0 : ((i - 1 + round) % (m - 1)) + 1;
+// Orders this wave's LDS writes before its later LDS reads (single-wave phases).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hardware FP64 reciprocal / reciprocal square root refined by one Newton
+// step: a few ulps, enough for Jacobi rotations (which only need to be
+// orthogonal to working precision), at a fraction of the latency of the
+// correctly rounded division and square root.
+__device__ __forceinline__ double rcp_fast(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    return r * (2.0 - x * r);
+}
+__device__ __forceinline__ double rsqrt_fast(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    return r * (1.5 - 0.5 * x * r * r);
+}
+__device__ __forceinline__ double sqrt_fast(double x) { return x * rsqrt_fast(x); }
+
+// Partner of local index i (0..nb-1) in round r of the circle-method
+// tournament over m = nb rounded up to even players (player nb, when it
+// exists, is a dummy): players sit at positions; position 0 keeps player 0,
+// the others rotate by r; positions pos and m-1-pos play each other.
+// Returns i itself when i meets the dummy.
+__device__ __forceinline__ int jacobi_partner(int i, int r, int m, int nb) {
+    const int k = m - 1;
+    int pos = 0;
+    if (i != 0) {
+        pos = i - 1 - r;
+        if (pos < 0) pos += k;
+        pos += 1;
+    }
+    const int opp = k - pos;
+    int q = 0;
+    if (opp != 0) {
+        q = opp - 1 + r;
+        if (q >= k) q -= k;
+        q += 1;
+    }
+    return q < nb ? q : i;
+}
+
+// Refined reciprocal square root: hardware estimate plus two Newton steps,
+// accurate to a few ulps (rotations must stay orthogonal to working precision).
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * (1.5 - 0.5 * x * r * r);
+    return r * (1.5 - 0.5 * x * r * r);
+}
+
+// Column i of the symmetric Schur rotation of the pair (p, q) = (min, max)
+// of (i, pi): J(i, i) = c and J(pi, i) = s', with s' = -s for i = p and +s
+// for i = q, where tan(theta) = t zeroes the (p, q) entry of J^T A J:
+//   t = 2 a_pq sign(d) / (|d| + sqrt(d^2 + 4 a_pq^2)),  d = a_qq - a_pp.
+// Written without a division: with w = |d| + sqrt(d^2 + 4 a_pq^2),
+// c = w / sqrt(w^2 + 4 a_pq^2) and s = 2 a_pq sign(d) / sqrt(w^2 + 4 a_pq^2).
+// The pair is rotated only when a_pq^2 > 1e-30 |a_pp a_qq|, i.e. when
+// |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|); otherwise (c, s') = (1, 0).
+// Both members of a pair evaluate the same operands in the same order, so
+// they agree bit for bit.
+__device__ __forceinline__ bool jacobi_rotation(double a_ii, double a_pp, double a_ip, bool i_is_p,
+                                                bool paired, double* c_out, double* s_out) {
+    const double app = i_is_p ? a_ii : a_pp;
+    const double aqq = i_is_p ? a_pp : a_ii;
+    const double apq = a_ip;
+    const bool rot = paired && apq != 0.0 && apq * apq > 1e-30 * fabs(app * aqq);
+    const double d = aqq - app;
+    const double q2 = 4.0 * apq * apq;
+    const double x = d * d + q2;
+    const double w = fabs(d) + x * rsqrt_fast(x);
+    const double r = rsqrt_refined(w * w + q2);
+    const double c = w * r;
+    const double sn = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * r;
+    *c_out = rot ? c : 1.0;
+    *s_out = rot ? (i_is_p ? -sn : sn) : 0.0;
+    return rot;
 }
 
 // dynamic LDS: elite rows Y[mu][n].  The state is staged in LDS first so that
@@ -194,10 +271,8 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     __shared__ double s_B[kMaxN * kMaxN], s_C[kMaxN * kMaxN];
     __shared__ double s_part[kParts * kMaxN * (kMaxN + 1) / 2];
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
-    __shared__ double s_cs[2 * kMaxN];
-    __shared__ int s_pq[2 * kMaxN];
     __shared__ double s_scal[4];
-    __shared__ int s_done;
+    __shared__ double2 s_cs[kMaxN];   // (c_i, s'_i): column i of the current rotation
 
     StateView S = state_view(blob, n, lam);
     const int tid = threadIdx.x;
@@ -227,16 +302,37 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     const int64_t gen = S.hdr->gen;
     __syncthreads();
 
-    // 1. ranking by (loss, index), NaN as +inf
-    for (int k = tid; k < lam; k += kUpdThreads) {
-        const double key = s_key[k];
+    // 1. ranking by (loss, index), NaN as +inf: rank = number of keys ordered
+    //    before.  G = 2^lg adjacent lanes share one candidate, each counting a
+    //    strided eighth-block subset of the keys, then a butterfly adds them.
+    int lg = 0;
+    while (lg < 4 && (lam << (lg + 1)) <= kUpdThreads) lg++;
+    const int G = 1 << lg;
+    for (int base = 0; base < (lam << lg); base += kUpdThreads) {   // same trip count in every lane
+        const int t = base + tid;
+        const int k = t >> lg, part = t & (G - 1);
         int r = 0;
-        for (int j = 0; j < lam; j++) {
-            const double kj = s_key[j];
-            r += (kj < key) || (kj == key && j < k);
+        if (k < lam) {
+            const double key = s_key[k];
+            for (int j = part * 8; j + 8 <= lam; j += 8 * G) {
+                double kj[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) kj[u] = s_key[j + u];
+#pragma unroll
+                for (int u = 0; u < 8; u++) r += int(kj[u] < key) | (int(kj[u] == key) & int(j + u < k));
+            }
+            if (part == 0) {
+                for (int j = lam & ~7; j < lam; j++) {
+                    const double kj = s_key[j];
+                    r += int(kj < key) | (int(kj == key) & int(j < k));
+                }
+            }
         }
-        s_order[r] = k;
-        S.order[r] = k;
+        for (int off = 1; off < G; off <<= 1) r += __shfl_xor(r, off);
+        if (k < lam && part == 0) {
+            s_order[r] = k;
+            S.order[r] = k;
+        }
     }
     __syncthreads();
     for (int e = tid; e < mu * n; e += kUpdThreads) {
@@ -249,6 +345,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     for (int task = tid; task < kParts * n; task += kUpdThreads) {
         const int part = task / n, i = task % n;
         double acc = 0.0;
+#pragma unroll 4
         for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i];
         s_part[part * n + i] = acc;
     }
@@ -274,20 +371,24 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         S.p_sigma[tid] = s_ps[tid];
     }
     __syncthreads();
-    if (tid == 0) {
-        double ss = 0.0;
-        for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
-        const double ps_norm = sqrt(ss);
-        const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
-        const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
-        s_scal[0] = ps_norm;
-        s_scal[1] = h;
+    if (tid < kWave64) {
+        // sum of the recombination weights: strided partial sums, then a fixed butterfly
         double sw = 0.0;
-        for (int r = 0; r < mu; r++) sw += s_w[r];
-        s_scal[2] = sw;
-        *S.h_sigma = h;
-        *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
-        S.hdr->gen = gen + 1;
+        for (int r = tid; r < mu; r += kWave64) sw += s_w[r];
+        for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
+        if (tid == 0) {
+            double ss = 0.0;
+            for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
+            const double ps_norm = sqrt(ss);
+            const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
+            const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
+            s_scal[0] = ps_norm;
+            s_scal[1] = h;
+            s_scal[2] = sw;
+            *S.h_sigma = h;
+            *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
+            S.hdr->gen = gen + 1;
+        }
     }
     __syncthreads();
     const double h_sigma = s_scal[1], sum_w = s_scal[2];
@@ -303,6 +404,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         while (rem >= n - i) { rem -= n - i; i++; }
         const int j = i + rem;
         double acc = 0.0;
+#pragma unroll 4
         for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
         s_part[part * ntri + e] = acc;
     }
@@ -351,82 +453,140 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     }
     __syncthreads();
 
-    // cyclic sweeps in tournament order: disjoint rotations run in parallel; a
-    // rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|); the sweeps stop
-    // when one of them rotates nothing.
+    // Cyclic Jacobi in tournament order, run by wave 0 alone (no workgroup
+    // barriers).  A round pairs every index of a block with its partner in
+    // the circle-method schedule; rounds repeat in cyclic order.  Per round:
+    //   - every lane checks its upper-triangle entries against the rotation
+    //     threshold; when no pair anywhere exceeds it, the iteration has
+    //     converged (the next sweep would rotate nothing) and stops;
+    //   - lane i < n computes column i of the rotation (c_i, s'_i) once and
+    //     publishes it in LDS;
+    //   - every lane forms its entries of A' = J^T A J (upper triangle,
+    //     mirrored) and V' = V J in the other buffer.
+    if (tid >= kWave64) return;
     const int m = nb + (nb & 1);
-    const int half = m / 2;
-    const int n_pairs = n_blocks * half;
-    for (int sweep = 0; sweep < kMaxSweeps; sweep++) {
-        if (tid == 0) s_done = 1;
-        __syncthreads();
-        for (int round = 0; round < m - 1; round++) {
-            if (tid < n_pairs) {
-                const int b = tid / half, i = tid % half;
-                int p = rr_player(i, round, m), q = rr_player(m - 1 - i, round, m);
-                if (p > q) { const int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                bool rot = false;
-                if (q < nb) {
-                    p += b * nb;
-                    q += b * nb;
-                    const double apq = s_A[p * n + q], app = s_A[p * n + p], aqq = s_A[q * n + q];
-                    if (apq != 0.0 && apq * apq > 1e-30 * fabs(app * aqq)) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                        rot = true;
-                        s_done = 0;
-                    }
-                }
-                s_cs[2 * tid] = c;
-                s_cs[2 * tid + 1] = s;
-                s_pq[2 * tid] = rot ? p : -1;
-                s_pq[2 * tid + 1] = q;
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J   (task = (pair, row within block))
-            for (int task = tid; task < n_pairs * nb; task += kUpdThreads) {
-                const int pi = task / nb, kk = task % nb;
-                const int p = s_pq[2 * pi];
-                if (p < 0) continue;
-                const int q = s_pq[2 * pi + 1];
-                const int k = (pi / half) * nb + kk;
-                const double c = s_cs[2 * pi], s = s_cs[2 * pi + 1];
-                const double akp = s_A[k * n + p], akq = s_A[k * n + q];
-                s_A[k * n + p] = c * akp - s * akq;
-                s_A[k * n + q] = s * akp + c * akq;
-                const double vkp = s_V[k * n + p], vkq = s_V[k * n + q];
-                s_V[k * n + p] = c * vkp - s * vkq;
-                s_V[k * n + q] = s * vkp + c * vkq;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int task = tid; task < n_pairs * nb; task += kUpdThreads) {
-                const int pi = task / nb, kk = task % nb;
-                const int p = s_pq[2 * pi];
-                if (p < 0) continue;
-                const int q = s_pq[2 * pi + 1];
-                const int k = (pi / half) * nb + kk;
-                const double c = s_cs[2 * pi], s = s_cs[2 * pi + 1];
-                const double apk = s_A[p * n + k], aqk = s_A[q * n + k];
-                s_A[p * n + k] = c * apk - s * aqk;
-                s_A[q * n + k] = s * apk + c * aqk;
-            }
-            __syncthreads();
+    const int k1 = m - 1;                      // rounds per sweep
+    const int ntri_b = nb * (nb + 1) / 2;
+    const int n_a = n_blocks * ntri_b;         // upper-triangle entries inside the blocks
+    const int n_v = n_blocks * nb * nb;        // all entries inside the blocks
+    constexpr int kASlots = (kMaxN * (kMaxN + 1) / 2 + kWave64 - 1) / kWave64;
+    constexpr int kVSlots = (kMaxN * kMaxN + kWave64 - 1) / kWave64;
+    const int na_slots = (n_a + kWave64 - 1) / kWave64;
+    const int nv_slots = (n_v + kWave64 - 1) / kWave64;
+    int a_i[kASlots], a_j[kASlots], a_li[kASlots], a_lj[kASlots];
+    int v_i[kVSlots], v_j[kVSlots], v_lj[kVSlots];
+#pragma unroll
+    for (int sl = 0; sl < kASlots; sl++) {
+        const int e = min(tid + kWave64 * sl, n_a - 1);
+        const int blk = e / ntri_b;
+        int li = 0, rem = e - blk * ntri_b;
+        while (rem >= nb - li) { rem -= nb - li; li++; }
+        a_li[sl] = li;
+        a_lj[sl] = li + rem;
+        a_i[sl] = blk * nb + li;
+        a_j[sl] = blk * nb + li + rem;
+    }
+#pragma unroll
+    for (int sl = 0; sl < kVSlots; sl++) {
+        const int e = min(tid + kWave64 * sl, n_v - 1);
+        const int blk = e / (nb * nb), r = e - blk * nb * nb;
+        v_i[sl] = blk * nb + r / nb;
+        v_lj[sl] = r % nb;
+        v_j[sl] = blk * nb + r % nb;
+    }
+    const int my_blk = min(tid, n - 1) / nb;
+    const int my_l = min(tid, n - 1) - my_blk * nb;
+    double* Acur = s_A;
+    double* Anext = s_T;
+    double* Vcur = s_V;
+    double* Vnext = s_C;
+    for (int e = tid; e < nn; e += kWave64) {   // entries outside the blocks stay zero in both buffers
+        const int i = e / n, j = e % n;
+        if (i / nb != j / nb) {
+            Anext[e] = 0.0;
+            Vnext[e] = 0.0;
         }
-        if (s_done) break;
-        __syncthreads();
+    }
+    wave_sync();
+    const int max_rounds = kMaxSweeps * k1;
+    int round = 0;
+    for (int it = 0; it < max_rounds; it++) {
+        // convergence test over all pairs, and the operands of this round
+        bool open = false;
+        double an_ij[kASlots], an_ipj[kASlots], an_pij[kASlots], an_pipj[kASlots];
+        int a_pi[kASlots], a_pj[kASlots];
+#pragma unroll
+        for (int sl = 0; sl < kASlots; sl++) {
+            if (sl < na_slots) {
+                const bool live = tid + kWave64 * sl < n_a;
+                const int i = a_i[sl], j = a_j[sl];
+                const int base = i - a_li[sl];
+                const int pi = base + jacobi_partner(a_li[sl], round, m, nb);
+                const int pj = base + jacobi_partner(a_lj[sl], round, m, nb);
+                a_pi[sl] = pi;
+                a_pj[sl] = pj;
+                const double aij = Acur[i * n + j];
+                const double aii = Acur[i * n + i], ajj = Acur[j * n + j];
+                open |= live && i != j && aij * aij > 1e-30 * fabs(aii * ajj);
+                an_ij[sl] = aij;
+                an_ipj[sl] = Acur[i * n + pj];
+                an_pij[sl] = Acur[pi * n + j];
+                an_pipj[sl] = Acur[pi * n + pj];
+            }
+        }
+        if (__ballot(open) == 0ull) break;
+        double vv_ij[kVSlots], vv_ipj[kVSlots];
+#pragma unroll
+        for (int sl = 0; sl < kVSlots; sl++) {
+            if (sl < nv_slots) {
+                const int base = v_j[sl] - v_lj[sl];
+                const int pj = base + jacobi_partner(v_lj[sl], round, m, nb);
+                vv_ij[sl] = Vcur[v_i[sl] * n + v_j[sl]];
+                vv_ipj[sl] = Vcur[v_i[sl] * n + pj];
+            }
+        }
+        // rotations: lane i < n computes column i of J
+        bool rot = false;
+        {
+            const int pl = jacobi_partner(my_l, round, m, nb);
+            const int i = my_blk * nb + my_l, pi = my_blk * nb + pl;
+            double c, sp;
+            rot = jacobi_rotation(Acur[i * n + i], Acur[pi * n + pi], Acur[i * n + pi], i < pi,
+                                  tid < n && pl != my_l, &c, &sp);
+            if (tid < n) s_cs[tid] = make_double2(c, sp);
+        }
+        round = round + 1 == k1 ? 0 : round + 1;
+        if (__ballot(rot) == 0ull) continue;   // nothing to rotate in this round
+        wave_sync();
+#pragma unroll
+        for (int sl = 0; sl < kASlots; sl++) {
+            if (sl < na_slots && tid + kWave64 * sl < n_a) {
+                const double2 ci = s_cs[a_i[sl]], cj = s_cs[a_j[sl]];
+                const double v = ci.x * (cj.x * an_ij[sl] + cj.y * an_ipj[sl]) +
+                                 ci.y * (cj.x * an_pij[sl] + cj.y * an_pipj[sl]);
+                Anext[a_i[sl] * n + a_j[sl]] = v;
+                Anext[a_j[sl] * n + a_i[sl]] = v;
+            }
+        }
+#pragma unroll
+        for (int sl = 0; sl < kVSlots; sl++) {
+            if (sl < nv_slots && tid + kWave64 * sl < n_v) {
+                const double2 cj = s_cs[v_j[sl]];
+                Vnext[v_i[sl] * n + v_j[sl]] = cj.x * vv_ij[sl] + cj.y * vv_ipj[sl];
+            }
+        }
+        wave_sync();
+        double* t = Acur; Acur = Anext; Anext = t;
+        t = Vcur; Vcur = Vnext; Vnext = t;
     }
     // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
     if (tid == 0) {
         double emax = 0.0;
-        for (int i = 0; i < n; i++) emax = fmax(emax, s_A[i * n + i]);
+        for (int i = 0; i < n; i++) emax = fmax(emax, Acur[i * n + i]);
         const double floor_v = 1e-20 * emax;
         int flags = 0;
         for (int i = 0; i < n; i++) {
-            double e = s_A[i * n + i];
+            double e = Acur[i * n + i];
             if (!(e >= floor_v)) {
                 e = floor_v;
                 flags |= 1;
@@ -437,7 +597,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
         S.hdr->flags = flags;
     }
-    for (int e = tid; e < n * n; e += kUpdThreads) S.B[e] = s_V[e];
+    for (int e = tid; e < nn; e += kWave64) S.B[e] = Vcur[e];
 }
 
 }  // namespace
