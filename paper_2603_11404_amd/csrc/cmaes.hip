@@ -172,7 +172,6 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
 
 // ---------------------------------------------------------------- update
 
-constexpr int kUpdThreads = 1024;
 constexpr int kWave64 = 64;
 constexpr int kMaxSweeps = 30;
 
@@ -196,29 +195,6 @@ __device__ __forceinline__ double rsqrt_fast(double x) {
     return r * (1.5 - 0.5 * x * r * r);
 }
 __device__ __forceinline__ double sqrt_fast(double x) { return x * rsqrt_fast(x); }
-
-// Partner of local index i (0..nb-1) in round r of the circle-method
-// tournament over m = nb rounded up to even players (player nb, when it
-// exists, is a dummy): players sit at positions; position 0 keeps player 0,
-// the others rotate by r; positions pos and m-1-pos play each other.
-// Returns i itself when i meets the dummy.
-__device__ __forceinline__ int jacobi_partner(int i, int r, int m, int nb) {
-    const int k = m - 1;
-    int pos = 0;
-    if (i != 0) {
-        pos = i - 1 - r;
-        if (pos < 0) pos += k;
-        pos += 1;
-    }
-    const int opp = k - pos;
-    int q = 0;
-    if (opp != 0) {
-        q = opp - 1 + r;
-        if (q >= k) q -= k;
-        q += 1;
-    }
-    return q < nb ? q : i;
-}
 
 // Refined reciprocal square root: hardware estimate plus two Newton steps,
 // accurate to a few ulps (rotations must stay orthogonal to working precision).
@@ -261,7 +237,10 @@ __device__ __forceinline__ bool jacobi_rotation(double a_ii, double a_pp, double
 // fixed-order partial sums (deterministic).
 constexpr int kParts = 8;   // partial sums per output element
 
-__global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, int n, int lam,
+// AS / VS: Jacobi entries per lane (upper-triangle / all within-block entries
+// over 64 lanes); NT: threads of the workgroup.
+template <int AS, int VS, int NT>
+__global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam,
                                                                   const double* __restrict__ loss) {
     extern __shared__ double s_elite[];  // [mu][n]
     __shared__ double s_key[kMaxLambda];
@@ -283,12 +262,12 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     const int ntri = n * (n + 1) / 2;
 
     // 0. stage losses and state
-    for (int k = tid; k < lam; k += kUpdThreads) {
+    for (int k = tid; k < lam; k += NT) {
         const double v = loss[k];
         s_key[k] = (v != v) ? INFINITY : v;
     }
-    for (int r = tid; r < mu; r += kUpdThreads) s_w[r] = S.weights[r];
-    for (int e = tid; e < nn; e += kUpdThreads) {
+    for (int r = tid; r < mu; r += NT) s_w[r] = S.weights[r];
+    for (int e = tid; e < nn; e += NT) {
         s_B[e] = S.B[e];
         s_C[e] = S.C[e];
     }
@@ -306,9 +285,9 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     //    before.  G = 2^lg adjacent lanes share one candidate, each counting a
     //    strided eighth-block subset of the keys, then a butterfly adds them.
     int lg = 0;
-    while (lg < 4 && (lam << (lg + 1)) <= kUpdThreads) lg++;
+    while (lg < 4 && (lam << (lg + 1)) <= NT) lg++;
     const int G = 1 << lg;
-    for (int base = 0; base < (lam << lg); base += kUpdThreads) {   // same trip count in every lane
+    for (int base = 0; base < (lam << lg); base += NT) {   // same trip count in every lane
         const int t = base + tid;
         const int k = t >> lg, part = t & (G - 1);
         int r = 0;
@@ -335,14 +314,14 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         }
     }
     __syncthreads();
-    for (int e = tid; e < mu * n; e += kUpdThreads) {
+    for (int e = tid; e < mu * n; e += NT) {
         const int r = e / n, i = e % n;
         s_elite[e] = S.Y[s_order[r] * n + i];
     }
     __syncthreads();
 
     // 2. weighted recombination y_w = sum_r w_r y_{r:lambda}
-    for (int task = tid; task < kParts * n; task += kUpdThreads) {
+    for (int task = tid; task < kParts * n; task += NT) {
         const int part = task / n, i = task % n;
         double acc = 0.0;
 #pragma unroll 4
@@ -398,7 +377,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     }
 
     // 4. covariance: rank-one + rank-mu (upper triangle, partial sums), symmetric, block-masked
-    for (int task = tid; task < kParts * ntri; task += kUpdThreads) {
+    for (int task = tid; task < kParts * ntri; task += NT) {
         const int part = task / ntri, e = task % ntri;
         int i = 0, rem = e;
         while (rem >= n - i) { rem -= n - i; i++; }
@@ -411,7 +390,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     __syncthreads();
     const double delta = (1.0 - h_sigma) * cc * (2.0 - cc);
     const double keep = 1.0 - c1 - cmu * sum_w;
-    for (int e = tid; e < ntri; e += kUpdThreads) {
+    for (int e = tid; e < ntri; e += NT) {
         int i = 0, rem = e;
         while (rem >= n - i) { rem -= n - i; i++; }
         const int j = i + rem;
@@ -425,26 +404,26 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         s_A[j * n + i] = v;
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += kUpdThreads) S.C[e] = s_A[e];
+    for (int e = tid; e < nn; e += NT) S.C[e] = s_A[e];
 
     // 5. Jacobi eigendecomposition, warm-started from the previous eigenvectors:
     //    A = B^T C B (nearly diagonal when C changed little), V = B; every
     //    rotation applies A <- J^T A J and V <- V J, so C = V diag(A) V^T at the end.
-    for (int e = tid; e < nn; e += kUpdThreads) {
+    for (int e = tid; e < nn; e += NT) {
         const int i = e / n, j = e % n;
         double t = 0.0;
         for (int k = 0; k < n; k++) t += s_A[i * n + k] * s_B[k * n + j];
         s_V[e] = t;                                   // C B (temporary)
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += kUpdThreads) {
+    for (int e = tid; e < nn; e += NT) {
         const int i = e / n, j = e % n;
         double t = 0.0;
         for (int k = 0; k < n; k++) t += s_B[k * n + i] * s_V[k * n + j];
         s_T[e] = t;                                   // B^T C B
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += kUpdThreads) {
+    for (int e = tid; e < nn; e += NT) {
         const int i = e / n, j = e % n;
         double v = 0.5 * (s_T[i * n + j] + s_T[j * n + i]);
         if (i / nb != j / nb) v = 0.0;
@@ -456,46 +435,69 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     // Cyclic Jacobi in tournament order, run by wave 0 alone (no workgroup
     // barriers).  A round pairs every index of a block with its partner in
     // the circle-method schedule; rounds repeat in cyclic order.  Per round:
-    //   - every lane checks its upper-triangle entries against the rotation
-    //     threshold; when no pair anywhere exceeds it, the iteration has
-    //     converged (the next sweep would rotate nothing) and stops;
     //   - lane i < n computes column i of the rotation (c_i, s'_i) once and
     //     publishes it in LDS;
-    //   - every lane forms its entries of A' = J^T A J (upper triangle,
-    //     mirrored) and V' = V J in the other buffer.
+    //   - when nothing rotates, every lane tests its upper-triangle entries
+    //     against the rotation threshold; if no pair anywhere exceeds it the
+    //     iteration has converged (another sweep would rotate nothing);
+    //   - otherwise every lane forms its entries of A' = J^T A J (upper
+    //     triangle, mirrored) and V' = V J in the other buffer.
+    // Partners are register state: for a local index l != 0 of a block the
+    // circle method pairs l with q_l(r) = ((2r - l - 1) mod k) + 1, k = m - 1,
+    // except that l meets player 0 when q_l(r) = l; index 0 meets
+    // R = (r == 0 ? k : r); a partner >= nb is the dummy (no rotation).
+    // q_l advances by 2 (mod k) from one round to the next.
     if (tid >= kWave64) return;
     const int m = nb + (nb & 1);
-    const int k1 = m - 1;                      // rounds per sweep
+    const int k1 = m - 1;                      // rounds per sweep (odd)
     const int ntri_b = nb * (nb + 1) / 2;
     const int n_a = n_blocks * ntri_b;         // upper-triangle entries inside the blocks
     const int n_v = n_blocks * nb * nb;        // all entries inside the blocks
-    constexpr int kASlots = (kMaxN * (kMaxN + 1) / 2 + kWave64 - 1) / kWave64;
-    constexpr int kVSlots = (kMaxN * kMaxN + kWave64 - 1) / kWave64;
+    constexpr int kASlots = AS;
+    constexpr int kVSlots = VS;
     const int na_slots = (n_a + kWave64 - 1) / kWave64;
     const int nv_slots = (n_v + kWave64 - 1) / kWave64;
-    int a_i[kASlots], a_j[kASlots], a_li[kASlots], a_lj[kASlots];
-    int v_i[kVSlots], v_j[kVSlots], v_lj[kVSlots];
+    auto q_start = [k1](int l) {               // q_l(0)
+        int t = (-l - 1) % k1;
+        return (t < 0 ? t + k1 : t) + 1;
+    };
+    auto q_next = [k1](int q) {
+        q += 2;
+        q -= q > k1 ? k1 : 0;
+        q -= q > k1 ? k1 : 0;
+        return q;
+    };
+    auto partner = [nb](int l, int q, int R) {
+        const int p = l == 0 ? R : (q == l ? 0 : q);
+        return p < nb ? p : l;
+    };
+    int a_i[kASlots], a_j[kASlots], a_base[kASlots], a_qi[kASlots], a_qj[kASlots];
+    int v_row[kVSlots], v_j[kVSlots], v_base[kVSlots], v_q[kVSlots];
 #pragma unroll
     for (int sl = 0; sl < kASlots; sl++) {
         const int e = min(tid + kWave64 * sl, n_a - 1);
         const int blk = e / ntri_b;
         int li = 0, rem = e - blk * ntri_b;
         while (rem >= nb - li) { rem -= nb - li; li++; }
-        a_li[sl] = li;
-        a_lj[sl] = li + rem;
+        a_base[sl] = blk * nb;
         a_i[sl] = blk * nb + li;
         a_j[sl] = blk * nb + li + rem;
+        a_qi[sl] = q_start(li);
+        a_qj[sl] = q_start(li + rem);
     }
 #pragma unroll
     for (int sl = 0; sl < kVSlots; sl++) {
         const int e = min(tid + kWave64 * sl, n_v - 1);
         const int blk = e / (nb * nb), r = e - blk * nb * nb;
-        v_i[sl] = blk * nb + r / nb;
-        v_lj[sl] = r % nb;
+        v_row[sl] = (blk * nb + r / nb) * n;
+        v_base[sl] = blk * nb;
         v_j[sl] = blk * nb + r % nb;
+        v_q[sl] = q_start(r % nb);
     }
-    const int my_blk = min(tid, n - 1) / nb;
-    const int my_l = min(tid, n - 1) - my_blk * nb;
+    const int my_t = min(tid, n - 1);
+    const int my_blk = my_t / nb;
+    const int my_l = my_t - my_blk * nb;
+    int my_q = q_start(my_l);
     double* Acur = s_A;
     double* Anext = s_T;
     double* Vcur = s_V;
@@ -511,59 +513,69 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
     const int max_rounds = kMaxSweeps * k1;
     int round = 0;
     for (int it = 0; it < max_rounds; it++) {
-        // convergence test over all pairs, and the operands of this round
-        bool open = false;
-        double an_ij[kASlots], an_ipj[kASlots], an_pij[kASlots], an_pipj[kASlots];
-        int a_pi[kASlots], a_pj[kASlots];
+        const int R = round == 0 ? k1 : round;
+        // rotation of index my_t
+        const int pt = my_blk * nb + partner(my_l, my_q, R);
+        double c_t, s_t;
+        const bool rot = jacobi_rotation(Acur[my_t * n + my_t], Acur[pt * n + pt], Acur[my_t * n + pt], my_t < pt,
+                                         tid < n && pt != my_t, &c_t, &s_t);
+        // operands of this round's updates (independent of the rotations)
+        double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
 #pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
             if (sl < na_slots) {
-                const bool live = tid + kWave64 * sl < n_a;
-                const int i = a_i[sl], j = a_j[sl];
-                const int base = i - a_li[sl];
-                const int pi = base + jacobi_partner(a_li[sl], round, m, nb);
-                const int pj = base + jacobi_partner(a_lj[sl], round, m, nb);
-                a_pi[sl] = pi;
-                a_pj[sl] = pj;
-                const double aij = Acur[i * n + j];
-                const double aii = Acur[i * n + i], ajj = Acur[j * n + j];
-                open |= live && i != j && aij * aij > 1e-30 * fabs(aii * ajj);
-                an_ij[sl] = aij;
-                an_ipj[sl] = Acur[i * n + pj];
-                an_pij[sl] = Acur[pi * n + j];
-                an_pipj[sl] = Acur[pi * n + pj];
+                const int pi = a_base[sl] + partner(a_i[sl] - a_base[sl], a_qi[sl], R);
+                const int pj = a_base[sl] + partner(a_j[sl] - a_base[sl], a_qj[sl], R);
+                const int ri = a_i[sl] * n, rp = pi * n;
+                x_ij[sl] = Acur[ri + a_j[sl]];
+                x_ipj[sl] = Acur[ri + pj];
+                x_pij[sl] = Acur[rp + a_j[sl]];
+                x_pipj[sl] = Acur[rp + pj];
             }
         }
-        if (__ballot(open) == 0ull) break;
-        double vv_ij[kVSlots], vv_ipj[kVSlots];
+        double y_ij[kVSlots], y_ipj[kVSlots];
 #pragma unroll
         for (int sl = 0; sl < kVSlots; sl++) {
             if (sl < nv_slots) {
-                const int base = v_j[sl] - v_lj[sl];
-                const int pj = base + jacobi_partner(v_lj[sl], round, m, nb);
-                vv_ij[sl] = Vcur[v_i[sl] * n + v_j[sl]];
-                vv_ipj[sl] = Vcur[v_i[sl] * n + pj];
+                const int pj = v_base[sl] + partner(v_j[sl] - v_base[sl], v_q[sl], R);
+                y_ij[sl] = Vcur[v_row[sl] + v_j[sl]];
+                y_ipj[sl] = Vcur[v_row[sl] + pj];
             }
         }
-        // rotations: lane i < n computes column i of J
-        bool rot = false;
-        {
-            const int pl = jacobi_partner(my_l, round, m, nb);
-            const int i = my_blk * nb + my_l, pi = my_blk * nb + pl;
-            double c, sp;
-            rot = jacobi_rotation(Acur[i * n + i], Acur[pi * n + pi], Acur[i * n + pi], i < pi,
-                                  tid < n && pl != my_l, &c, &sp);
-            if (tid < n) s_cs[tid] = make_double2(c, sp);
-        }
+        // advance the schedule
         round = round + 1 == k1 ? 0 : round + 1;
-        if (__ballot(rot) == 0ull) continue;   // nothing to rotate in this round
+        my_q = q_next(my_q);
+#pragma unroll
+        for (int sl = 0; sl < kASlots; sl++) {
+            a_qi[sl] = q_next(a_qi[sl]);
+            a_qj[sl] = q_next(a_qj[sl]);
+        }
+#pragma unroll
+        for (int sl = 0; sl < kVSlots; sl++) v_q[sl] = q_next(v_q[sl]);
+
+        if (__ballot(rot) == 0ull) {
+            // nothing rotates in this round: stop if no pair exceeds the threshold
+            bool open = false;
+#pragma unroll
+            for (int sl = 0; sl < kASlots; sl++) {
+                if (sl < na_slots) {
+                    const int i = a_i[sl], j = a_j[sl];
+                    const double aij = x_ij[sl];
+                    open |= tid + kWave64 * sl < n_a && i != j &&
+                            aij * aij > 1e-30 * fabs(Acur[i * n + i] * Acur[j * n + j]);
+                }
+            }
+            if (__ballot(open) == 0ull) break;
+            continue;
+        }
+        if (tid < n) s_cs[tid] = make_double2(c_t, s_t);
         wave_sync();
 #pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
             if (sl < na_slots && tid + kWave64 * sl < n_a) {
                 const double2 ci = s_cs[a_i[sl]], cj = s_cs[a_j[sl]];
-                const double v = ci.x * (cj.x * an_ij[sl] + cj.y * an_ipj[sl]) +
-                                 ci.y * (cj.x * an_pij[sl] + cj.y * an_pipj[sl]);
+                const double v = ci.x * (cj.x * x_ij[sl] + cj.y * x_ipj[sl]) +
+                                 ci.y * (cj.x * x_pij[sl] + cj.y * x_pipj[sl]);
                 Anext[a_i[sl] * n + a_j[sl]] = v;
                 Anext[a_j[sl] * n + a_i[sl]] = v;
             }
@@ -572,7 +584,7 @@ __global__ __launch_bounds__(kUpdThreads) void cmaes_update_kernel(void* blob, i
         for (int sl = 0; sl < kVSlots; sl++) {
             if (sl < nv_slots && tid + kWave64 * sl < n_v) {
                 const double2 cj = s_cs[v_j[sl]];
-                Vnext[v_i[sl] * n + v_j[sl]] = cj.x * vv_ij[sl] + cj.y * vv_ipj[sl];
+                Vnext[v_row[sl] + v_j[sl]] = cj.x * y_ij[sl] + cj.y * y_ipj[sl];
             }
         }
         wave_sync();
@@ -691,8 +703,16 @@ tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double
     if (tk_status st = check_state(d_state, n, lambda)) return st;
     TK_REQUIRE(d_loss != nullptr, "loss is NULL");
     const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
-    hipLaunchKernelGGL(cmaes_update_kernel, dim3(1), dim3(kUpdThreads), lds, reinterpret_cast<hipStream_t>(s),
-                       d_state, n, lambda, d_loss);
+    // Jacobi entries inside the blocks number at most n(n+1)/2 (upper
+    // triangle) and n^2 (all), whatever the block count: for n <= 9 they fit
+    // one and two per lane of a wave, for n <= 18 three and six.
+    if (n <= 9) {
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024>), dim3(1), dim3(1024), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss);
+    } else {
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512>), dim3(1), dim3(512), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss);
+    }
     return check_launch("tk_cmaes_update");
 }
 

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void fk_kernel(const float* __restrict__ X, Fk
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.batch * a.n_arms) return;
     const int b = idx / a.n_arms, arm = idx % a.n_arms;
-    const ChainK& ch = a.ch[arm];
+    const ChainK ch = arm == 0 ? a.ch[0] : a.ch[1];   // selected, not indexed: keeps the chain in registers
     const float* th = X + (size_t(b) * a.n_arms + arm) * 9;
     const double al = th[0], be = th[1], ga = th[2];
 
@@ -93,13 +93,20 @@ __global__ __launch_bounds__(256) void fk_kernel(const float* __restrict__ X, Fk
         aff_mul(TY, ry, M[2 + side]);
     }
     float* out = link_xf + (size_t(b) * a.n_arms + arm) * 48;
+#pragma unroll
     for (int l = 0; l < 4; l++)
+#pragma unroll
         for (int e = 0; e < 12; e++) out[12 * l + e] = float(M[l][e]);
 
     if (kp) {
         float* o = kp + (size_t(b) * a.n_arms + arm) * 8;
+#pragma unroll
         for (int j = 0; j < 4; j++) {
-            const double* m = M[int(ch.kp[j][3])];
+            const int link = int(ch.kp[j][3]);
+            double m[12];
+#pragma unroll
+            for (int e = 0; e < 12; e++)
+                m[e] = link == 0 ? M[0][e] : link == 1 ? M[1][e] : link == 2 ? M[2][e] : M[3][e];
             const double vx = ch.kp[j][0], vy = ch.kp[j][1], vz = ch.kp[j][2];
             const double Xc = m[0] * vx + m[1] * vy + m[2] * vz + m[3];
             const double Yc = m[4] * vx + m[5] * vy + m[6] * vz + m[7];
