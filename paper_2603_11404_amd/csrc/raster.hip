@@ -59,7 +59,7 @@ struct TriRec {
     int32_t dx[3], dy[3];  // edge vectors in Q8 units (edge e runs from vertex e to vertex e+1)
     int32_t box_x;         // px0 | px1 << 16  (clamped pixel box)
     int32_t box_y;         // py0 | py1 << 16
-    int32_t flags;         // bit 0: 64-bit edge functions; bit 1: near (lane tasks); bits 8..: 8x8 words spanned
+    int32_t flags;         // bit 0: 64-bit edge functions; bit 1: near (lane tasks)
     int32_t e0hi[3];       // high words of the edge functions
     int32_t pad;
 };
@@ -85,20 +85,17 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
     if (px0 > px1 || py0 > py1) return false;
     r.box_x = px0 | (px1 << 16);
     r.box_y = py0 | (py1 << 16);
-    const int32_t w = px1 - px0, h = py1 - py0;
-    // vertices relative to the box origin (Q8)
+    // vertices relative to the box origin (Q8); near: all within 32 pixels of it
     const int32_t ox = px0 << 8, oy = py0 << 8;
-    int32_t rx[3] = {x0 - ox, x1 - ox, x2 - ox}, ry[3] = {y0 - oy, y1 - oy, y2 - oy};
-    const uint32_t lim = 1u << 13;   // 32 pixels
-    const bool near = (uint32_t(rx[0] + int32_t(lim)) < 2 * lim) & (uint32_t(rx[1] + int32_t(lim)) < 2 * lim) &
-                      (uint32_t(rx[2] + int32_t(lim)) < 2 * lim) & (uint32_t(ry[0] + int32_t(lim)) < 2 * lim) &
-                      (uint32_t(ry[1] + int32_t(lim)) < 2 * lim) & (uint32_t(ry[2] + int32_t(lim)) < 2 * lim);
+    const bool near = (xmax - ox < (1 << 13)) & (xmin - ox >= -(1 << 13)) & (ymax - oy < (1 << 13)) &
+                      (ymin - oy >= -(1 << 13));
     bool wide = false;
     if (near) {
-        // every vertex within 32 px of the box origin: differences < 2^14, so all
-        // products fit the 24-bit multiplier and every edge function over the box
-        // (and 7 pixels beyond it) stays below 2^30 -- exact in 32 bits
-        const int32_t area2 = __mul24(rx[1] - rx[0], ry[2] - ry[0]) - __mul24(ry[1] - ry[0], rx[2] - rx[0]);
+        // differences < 2^14, so all products fit the 24-bit multiplier and every
+        // edge function over the box (and 7 pixels beyond it) stays below 2^30 --
+        // exact in 32 bits; the high words are never read for near triangles
+        int32_t rx[3] = {x0 - ox, x1 - ox, x2 - ox}, ry[3] = {y0 - oy, y1 - oy, y2 - oy};
+        const int32_t area2 = __mul24(x1 - x0, y2 - y0) - __mul24(y1 - y0, x2 - x0);
         if (area2 == 0) return false;
         if (area2 < 0) {
             int32_t t = rx[1]; rx[1] = rx[2]; rx[2] = t;
@@ -108,13 +105,13 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
             const int n = e == 2 ? 0 : e + 1;
             const int32_t dx = rx[n] - rx[e], dy = ry[n] - ry[e];
             const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
-            const int32_t E = __mul24(dx, 128 - ry[e]) - __mul24(dy, 128 - rx[e]) + (top_left ? 0 : -1);
-            r.e0lo[e] = E;
-            r.e0hi[e] = E >> 31;
+            r.e0lo[e] = __mul24(dx, 128 - ry[e]) + __mul24(dy, rx[e] - 128) - (top_left ? 0 : 1);
+            r.e0hi[e] = 0;
             r.dx[e] = dx;
             r.dy[e] = dy;
         }
     } else {
+        const int32_t w = px1 - px0, h = py1 - py0;
         int32_t vx[3] = {x0, x1, x2}, vy[3] = {y0, y1, y2};
         const int64_t area2 = int64_t(x1 - x0) * int64_t(y2 - y0) - int64_t(y1 - y0) * int64_t(x2 - x0);
         if (area2 == 0) return false;
@@ -139,8 +136,7 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
             wide |= bound >= (int64_t(1) << 31);
         }
     }
-    const int nwords = ((px1 >> 3) - (px0 >> 3) + 1) * ((py1 >> 3) - (py0 >> 3) + 1);
-    r.flags = (wide ? kWide : 0) | (near ? kNear : 0) | (min(nwords, 0xffffff) << 8);
+    r.flags = (wide ? kWide : 0) | (near ? kNear : 0);
     r.pad = 0;
     return true;
 }
@@ -154,7 +150,8 @@ struct WaveStage {
     int4 q0[kWave];   // e0lo[0..2], box_x
     int4 q1[kWave];   // dx[0..2],   box_y
     int4 q2[kWave];   // dy[0..2],   flags
-    int4 q3[kWave];   // e0hi[0..2], inclusive prefix of the lane-task counts
+    int4 q3[kWave];   // e0hi[0..2], inclusive prefixes of the lane-task counts (wide | narrow << 16)
+    int4 qi[kWave];   // vertex indices of each lane's triangle two chunks ahead
 };
 
 __device__ __forceinline__ void stage_put(WaveStage& st, int j, const TriRec& r) {
@@ -178,6 +175,35 @@ __device__ __forceinline__ TriRec stage_get(const WaveStage& st, int j) {
 // column, times the 4-row bands (aligned to the mask words) the box touches.
 __device__ __forceinline__ int task_windows(int box_x) { return ((box_x >> 16) - (box_x & 0xffff)) / 8 + 1; }
 __device__ __forceinline__ int task_bands(int box_y) { return ((box_y >> 16) >> 2) - ((box_y & 0xffff) >> 2) + 1; }
+
+// Narrow near triangles (box at most 2 columns wide, most of a fine mesh's
+// slivers) get their own tasks: the 2 box columns times one mask-word row of
+// 8 pixel rows.
+__device__ __forceinline__ bool is_narrow(int box_x) { return (box_x >> 16) - (box_x & 0xffff) <= 1; }
+__device__ __forceinline__ int narrow_tasks(int box_y) { return ((box_y >> 16) >> 3) - ((box_y & 0xffff) >> 3) + 1; }
+
+// Bit r of an 8-bit column mask to bit 8r of a mask word (rows of one column):
+// each nibble times 2^0 + 2^7 + 2^14 + 2^21 places its bit i at 8i with no
+// two partial products on the same bit, so no carries.
+__device__ __forceinline__ unsigned long long spread_column(uint32_t m) {
+    const uint32_t lo = ((m & 15u) * 0x204081u) & 0x01010101u;
+    const uint32_t hi = (((m >> 4) & 15u) * 0x204081u) & 0x01010101u;
+    return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4 and 8
+// within each row of 16 lanes, then each row adds the last lane of the rows
+// before it (row broadcasts of lanes 15 and 31).  Lanes whose source lies
+// outside the row, or whose row is masked off, add 0.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
 
 // ---------------------------------------------------------------- coverage of one lane task
 
@@ -231,6 +257,48 @@ __device__ __forceinline__ void cover_window(const WaveStage& st, int j, int k, 
     const uint32_t hi = (rows >> (8 - sh)) & (0x01010101u * (0xFFu >> (8 - sh)));
     if (lo) atomicOr(&s_mask[wy * words_x + wx], (unsigned long long)lo << half);
     if (hi) atomicOr(&s_mask[wy * words_x + wx + 1], (unsigned long long)hi << half);
+}
+
+// One lane rasterises task k of a narrow near triangle: columns px0 and
+// px0 + 1 (the second only if inside the box) over mask-word row
+// (py0 >> 3) + k, with incremental 32-bit edge functions (all 8 rows lie
+// within 7 pixels of the box, where near triangles' edge functions are exact
+// in 32 bits).  Each column's 8 rows are collected with v_alignbit, clipped to
+// the box rows, spread to the word's bit layout and ORed into LDS (one word,
+// or two when px0 is the last column of a word).
+__device__ __forceinline__ void cover_narrow(const WaveStage& st, int j, int k, unsigned long long* __restrict__ s_mask,
+                                             int words_x) {
+    const int4 q0 = st.q0[j], q1 = st.q1[j], q2 = st.q2[j];
+    const int px0 = q0.w & 0xffff, px1 = q0.w >> 16;
+    const int py0 = q1.w & 0xffff, py1 = q1.w >> 16;
+    const int wy = (py0 >> 3) + k;
+    const int32_t e0[3] = {q0.x, q0.y, q0.z}, dxs[3] = {q1.x, q1.y, q1.z}, dys[3] = {q2.x, q2.y, q2.z};
+    uint32_t A[3], B[3], E[3];
+    for (int e = 0; e < 3; e++) {
+        A[e] = 0u - (uint32_t(dys[e]) << 8);          // one column to the right
+        B[e] = uint32_t(dxs[e]) << 8;                 // one row down
+        E[e] = uint32_t(e0[e] + __mul24(dxs[e] << 8, 8 * wy + 7 - py0));   // bottom row of the word
+    }
+    // alignbit shifts the flags left and brings the new sign bit in at bit 0:
+    // walking the rows bottom-up leaves row 8 wy + r at bit r
+    uint32_t neg0 = 0u, neg1 = 0u;
+#pragma unroll
+    for (int row = 7; row >= 0; row--) {
+        neg0 = __builtin_amdgcn_alignbit(neg0, E[0] | E[1] | E[2], 31);
+        neg1 = __builtin_amdgcn_alignbit(neg1, (E[0] + A[0]) | (E[1] + A[1]) | (E[2] + A[2]), 31);
+        E[0] -= B[0];
+        E[1] -= B[1];
+        E[2] -= B[2];
+    }
+    const int lo = max(py0 - 8 * wy, 0), hi = min(py1 - 8 * wy, 7);
+    const uint32_t rowmask = (0xFFu << lo) & (0xFFu >> (7 - hi));
+    const uint32_t m0 = ~neg0 & rowmask;
+    const uint32_t m1 = px1 > px0 ? ~neg1 & rowmask : 0u;
+    const int wx = px0 >> 3, sh = px0 & 7;
+    unsigned long long w0 = spread_column(m0) << sh;
+    if (sh < 7) w0 |= spread_column(m1) << (sh + 1);
+    if (w0) atomicOr(&s_mask[wy * words_x + wx], w0);
+    if (sh == 7 && m1) atomicOr(&s_mask[wy * words_x + wx + 1], spread_column(m1));
 }
 
 // ---------------------------------------------------------------- cooperative coverage of a big triangle
@@ -354,60 +422,101 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
         const int T = mesh.n_triangles;
         const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
                            (size_t(b) * a.meshes.total_vertices + mesh.vertex_offset);
-        // indices of this lane's first triangle; later chunks are prefetched one iteration ahead
+        // Software pipeline over the wave's chunks of 64 triangles: while chunk c
+        // is processed, the snapped vertices of chunk c + 1 and the indices of
+        // chunk c + 2 are in flight (the vertex gathers are the long-latency
+        // loads).  Without snapped input, indices run one chunk ahead.
+        // The indices loaded for chunk c + 2 are parked in the wave's LDS stage
+        // at the end of the iteration: kept in registers across the loop they
+        // would be moved right after their load, and that move would wait for
+        // the vertex gathers issued just before.
+        const int3* tri3 = reinterpret_cast<const int3*>(mesh.triangles);
         int t = wave * kWave + lane;
         int32_t idx[3] = {0, 0, 0};
-        if (t < T)
+        int2 pv[3] = {make_int2(INT32_MIN, 0), make_int2(INT32_MIN, 0), make_int2(INT32_MIN, 0)};
+        if (FROM_SNAPPED) {
+            if (t < T) {
+                const int3 i0 = tri3[t];
+                pv[0] = snap[i0.x];
+                pv[1] = snap[i0.y];
+                pv[2] = snap[i0.z];
+            }
+            if (t + NT < T) {
+                const int3 i1 = tri3[t + NT];
+                st.qi[lane] = make_int4(i1.x, i1.y, i1.z, 0);
+            }
+        } else if (t < T) {
             for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * t + k];
+        }
         for (int base = wave * kWave; base < T; base += NT) {
             t = base + lane;
             const bool live = t < T;
             int32_t X[3] = {INT32_MIN, INT32_MIN, INT32_MIN}, Y[3] = {0, 0, 0};
             float vx[3], vy[3], vz[3];
             int link[3];
-            if (live) {
-                for (int k = 0; k < 3; k++) {
-                    if (FROM_SNAPPED) {
-                        const int2 p = snap[idx[k]];
-                        X[k] = p.x;
-                        Y[k] = p.y;
-                    } else {
+            int3 ahead;
+            if (FROM_SNAPPED) {
+                if (live)
+                    for (int k = 0; k < 3; k++) {
+                        X[k] = pv[k].x;
+                        Y[k] = pv[k].y;
+                    }
+                if (t + NT < T) {
+                    const int4 q = st.qi[lane];
+                    pv[0] = snap[q.x];
+                    pv[1] = snap[q.y];
+                    pv[2] = snap[q.z];
+                }
+                ahead = tri3[min(t + 2 * NT, T - 1)];   // unconditional: no initialised registers to guard
+            } else {
+                if (live)
+                    for (int k = 0; k < 3; k++) {
                         const float* v = mesh.vertices + size_t(idx[k]) * 3;
                         vx[k] = v[0];
                         vy[k] = v[1];
                         vz[k] = v[2];
                         link[k] = mesh.vertex_link[idx[k]];
                     }
-                }
+                // prefetch the next chunk's indices while this chunk is processed
+                const int tn = t + NT;
+                if (tn < T)
+                    for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
             }
-            // prefetch the next chunk's indices while this chunk is processed
-            const int tn = t + NT;
-            if (tn < T)
-                for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
             if (!FROM_SNAPPED && live)
                 for (int k = 0; k < 3; k++) project_snap(M + 12 * link[k], vx[k], vy[k], vz[k], cam, X[k], Y[k]);
             TriRec rec;
             const bool valid = live && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
             const bool near = valid && (rec.flags & kNear);
+            const bool narrow = near && is_narrow(rec.box_x);
             if (valid) stage_put(st, lane, rec);
-            // lane tasks of near triangles (at most 5 x 9 each): inclusive prefix over
-            // the wave from one ballot per bit of the count
-            const int cnt = near ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
-            int incl = cnt, total = 0;
-#pragma unroll
-            for (int bit = 0; bit < 6; bit++) {
-                const unsigned long long m = __ballot((cnt >> bit) & 1);
-                incl += int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)))
-                        << bit;
-                total += __popcll(m) << bit;
-            }
-            st.q3[lane] = make_int4(rec.e0hi[0], rec.e0hi[1], rec.e0hi[2], incl);
+            // lane tasks of near triangles: 8-column windows x 4-row bands (at
+            // most 5 x 9 each) for wide boxes, word rows (at most 6) for narrow
+            // ones; inclusive prefixes over the wave from one ballot per bit
+            const int cnt = near && !narrow ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
+            const int cnt_n = narrow ? narrow_tasks(rec.box_y) : 0;
+            // both counts in one scan: wide in the low, narrow in the high 16 bits
+            // (totals stay below 64 x 45)
+            const int incl_both = wave_inclusive_sum(cnt | (cnt_n << 16));
+            const int total_both = __builtin_amdgcn_readlane(incl_both, kWave - 1);
+            const int total = total_both & 0xffff, total_n = total_both >> 16;
+            st.q3[lane] = make_int4(rec.e0hi[0], rec.e0hi[1], rec.e0hi[2], incl_both);
             const unsigned long long big = __ballot(valid && !near);
             // staged fields written by other lanes must be visible before they are read
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+            for (int base = 0; base < total_n; base += kWave) {
+                const int q = base + lane;
+                if (q < total_n) {
+                    int j = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1)
+                        if ((st.q3[j + step - 1].w >> 16) <= q) j += step;
+                    const int k = q - ((st.q3[j].w >> 16) - narrow_tasks(st.q1[j].w));
+                    cover_narrow(st, j, k, s_mask, cam.words_x);
+                }
+            }
             for (int base = 0; base < total; base += kWave) {
                 const int q = base + lane;
                 if (q < total) {
@@ -415,8 +524,8 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
                     int j = 0;
 #pragma unroll
                     for (int step = kWave / 2; step > 0; step >>= 1)
-                        if (st.q3[j + step - 1].w <= q) j += step;
-                    const int k = q - (st.q3[j].w - task_windows(st.q0[j].w) * task_bands(st.q1[j].w));
+                        if ((st.q3[j + step - 1].w & 0xffff) <= q) j += step;
+                    const int k = q - ((st.q3[j].w & 0xffff) - task_windows(st.q0[j].w) * task_bands(st.q1[j].w));
                     cover_window(st, j, k, s_mask, cam.words_x);
                 }
             }
@@ -426,6 +535,7 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
                 todo &= todo - 1;
                 cover_big(st, j, lx, ly, lane, s_mask, cam.words_x);
             }
+            if (FROM_SNAPPED && t + 2 * NT < T) st.qi[lane] = make_int4(ahead.x, ahead.y, ahead.z, 0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -520,7 +630,11 @@ __global__ __launch_bounds__(256) void stats_kernel(RasterArgs a, unsigned long 
             TriRec r;
             if (!setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], a.cam, r)) continue;
             kept++;
-            pairs += uint64_t(r.flags >> 8);
+            {
+                const int bx0 = (r.box_x & 0xffff) >> 3, bx1 = (r.box_x >> 16) >> 3;
+                const int by0 = (r.box_y & 0xffff) >> 3, by1 = (r.box_y >> 16) >> 3;
+                pairs += uint64_t(bx1 - bx0 + 1) * uint64_t(by1 - by0 + 1);
+            }
             huge += (r.flags & kWide) ? 1 : 0;
             // exact pixel box from the vertices again
             const int32_t xmin = min(X[0], min(X[1], X[2])), xmax = max(X[0], max(X[1], X[2]));
