@@ -141,46 +141,70 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
     return true;
 }
 
-// ---------------------------------------------------------------- per-wave LDS staging (struct of arrays)
+// ---------------------------------------------------------------- per-wave task queues in LDS
 
-// Slot j's record is four 16-byte groups q0[j]..q3[j]: lanes reading different
-// slots read consecutive 16-byte chunks (no bank conflicts), lanes reading one
-// slot get a broadcast.
-struct WaveStage {
-    int4 q0[kWave];   // e0lo[0..2], box_x
-    int4 q1[kWave];   // dx[0..2],   box_y
-    int4 q2[kWave];   // dy[0..2],   flags
-    int4 q3[kWave];   // e0hi[0..2], inclusive prefixes of the lane-task counts (wide | narrow << 16)
-    int4 qi[kWave];   // vertex indices of each lane's triangle two chunks ahead
+// A near triangle's record for the lane tasks, 32 bytes: a = the three edge
+// functions at the centre of pixel (px0, py0) (bias included) and the packed
+// columns of the box; b = the edge vectors as 16-bit pairs (dx low, dy high:
+// a near triangle's edges are shorter than 2^14 in Q8 units) and the packed
+// rows of the box.
+struct NearRec {
+    int4 a, b;
 };
 
-__device__ __forceinline__ void stage_put(WaveStage& st, int j, const TriRec& r) {
-    st.q0[j] = make_int4(r.e0lo[0], r.e0lo[1], r.e0lo[2], r.box_x);
-    st.q1[j] = make_int4(r.dx[0], r.dx[1], r.dx[2], r.box_y);
-    st.q2[j] = make_int4(r.dy[0], r.dy[1], r.dy[2], r.flags);
+__device__ __forceinline__ NearRec pack_near(const TriRec& r) {
+    NearRec p;
+    p.a = make_int4(r.e0lo[0], r.e0lo[1], r.e0lo[2], r.box_x);
+    int32_t d[3];
+    for (int e = 0; e < 3; e++) d[e] = int32_t((uint32_t(r.dx[e]) & 0xffffu) | (uint32_t(r.dy[e]) << 16));
+    p.b = make_int4(d[0], d[1], d[2], r.box_y);
+    return p;
 }
+__device__ __forceinline__ int32_t rec_dx(int32_t v) { return int32_t(int16_t(v & 0xffff)); }
+__device__ __forceinline__ int32_t rec_dy(int32_t v) { return v >> 16; }
 
-__device__ __forceinline__ TriRec stage_get(const WaveStage& st, int j) {
-    TriRec r;
-    const int4 a = st.q0[j], b = st.q1[j], c = st.q2[j], d = st.q3[j];
-    r.e0lo[0] = a.x; r.e0lo[1] = a.y; r.e0lo[2] = a.z; r.box_x = a.w;
-    r.dx[0] = b.x; r.dx[1] = b.y; r.dx[2] = b.z; r.box_y = b.w;
-    r.dy[0] = c.x; r.dy[1] = c.y; r.dy[2] = c.z; r.flags = c.w;
-    r.e0hi[0] = d.x; r.e0hi[1] = d.y; r.e0hi[2] = d.z;
-    r.pad = 0;
-    return r;
-}
+// Each wave queues the records of its near triangles -- narrow and wide boxes
+// separately -- and runs a round of lane tasks only once 64 tasks of a class
+// are pending, so rounds run with every lane busy whatever the mix of the
+// chunk.  The queues are rings indexed by running slot counts; start[] holds
+// each queued triangle's first task number (a running count of the wave's
+// tasks of that class).  The narrow ring never holds more than 63 pending plus
+// 64 new triangles; the wide ring is drained before it would overflow.
+constexpr int kNarrowRing = 128;
+constexpr int kWideRing = 64;
+struct WaveQueues {
+    int4 na[kNarrowRing], nb[kNarrowRing];
+    int32_t nstart[kNarrowRing];
+    int4 wa[kWideRing], wb[kWideRing];
+    int32_t wstart[kWideRing];
+};
 
-// Lane tasks of a near triangle: 8-column windows starting at the box's left
-// column, times the 4-row bands (aligned to the mask words) the box touches.
+// Lane tasks of a near triangle: 8-column windows times 4-row bands, both
+// starting at the box's top-left pixel.
 __device__ __forceinline__ int task_windows(int box_x) { return ((box_x >> 16) - (box_x & 0xffff)) / 8 + 1; }
-__device__ __forceinline__ int task_bands(int box_y) { return ((box_y >> 16) >> 2) - ((box_y & 0xffff) >> 2) + 1; }
+__device__ __forceinline__ int task_bands(int box_y) { return ((box_y >> 16) - (box_y & 0xffff)) / 4 + 1; }
 
 // Narrow near triangles (box at most 2 columns wide, most of a fine mesh's
-// slivers) get their own tasks: the 2 box columns times one mask-word row of
-// 8 pixel rows.
+// slivers) get their own tasks: the 2 box columns times 8 pixel rows.
 __device__ __forceinline__ bool is_narrow(int box_x) { return (box_x >> 16) - (box_x & 0xffff) <= 1; }
-__device__ __forceinline__ int narrow_tasks(int box_y) { return ((box_y >> 16) >> 3) - ((box_y & 0xffff) >> 3) + 1; }
+__device__ __forceinline__ int narrow_tasks(int box_y) { return ((box_y >> 16) - (box_y & 0xffff)) / 8 + 1; }
+
+// ORs an 8x8 pixel block, bit 8r + c = pixel (xa + c, ya + r), into the (at
+// most 2 x 2) mask words it overlaps.  Only pixels inside the image may be set.
+__device__ __forceinline__ void or_block(unsigned long long* __restrict__ s_mask, int words_x, int xa, int ya,
+                                         unsigned long long bits) {
+    const int wx = xa >> 3, sx = xa & 7, wy = ya >> 3, sy = ya & 7;
+    const unsigned long long rows[2] = {bits << (8 * sy), sy ? bits >> (64 - 8 * sy) : 0ull};
+    const unsigned long long keep = 0x0101010101010101ull * (0xFFull >> sx);         // columns that stay
+    const unsigned long long carry = 0x0101010101010101ull * ((1ull << sx) - 1ull);  // columns that move on
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const unsigned long long w0 = (rows[h] & keep) << sx;
+        const unsigned long long w1 = (rows[h] >> (8 - sx)) & carry;
+        if (w0) atomicOr(&s_mask[(wy + h) * words_x + wx], w0);
+        if (w1) atomicOr(&s_mask[(wy + h) * words_x + wx + 1], w1);
+    }
+}
 
 // Bit r of an 8-bit column mask to bit 8r of a mask word (rows of one column):
 // each nibble times 2^0 + 2^7 + 2^14 + 2^21 places its bit i at 8i with no
@@ -208,23 +232,23 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 // ---------------------------------------------------------------- coverage of one lane task
 
 // One lane rasterises the part of a near triangle's box inside one window of
-// 8 columns x one 4-row band, with incremental 32-bit edge functions, fully
-// unrolled: each row tests 8 pixel centres right to left and collects the
-// outside flags with v_alignbit.  The 4 row bytes are then split between the
-// (at most two) mask words the window straddles and ORed into LDS.
-__device__ __forceinline__ void cover_window(const WaveStage& st, int j, int k, unsigned long long* __restrict__ s_mask,
+// 8 columns x 4 rows (windows and bands start at the box's top-left pixel),
+// with incremental 32-bit edge functions, fully unrolled: each row tests 8
+// pixel centres right to left and collects the outside flags with
+// v_alignbit.  The row bytes are ORed into the (at most 2 x 2) mask words the
+// window overlaps.
+__device__ __forceinline__ void cover_window(const int4 q0, const int4 q1, int k, unsigned long long* __restrict__ s_mask,
                                              int words_x) {
-    const int4 q0 = st.q0[j], q1 = st.q1[j], q2 = st.q2[j];
     const int px0 = q0.w & 0xffff, px1 = q0.w >> 16;
     const int py0 = q1.w & 0xffff, py1 = q1.w >> 16;
     const int nwin = (px1 - px0) / 8 + 1;
     // k = band * nwin + win  (small integers: the float quotient is exact after flooring)
     const int band_i = int(floorf((float(k) + 0.5f) * __builtin_amdgcn_rcpf(float(nwin))));
     const int win = k - band_i * nwin;
-    const int band = (py0 >> 2) + band_i;
     const int xa = px0 + 8 * win, xe = min(xa + 7, px1);
-    const int ya = max(py0, 4 * band), yb = min(py1, 4 * band + 3);
-    const int32_t e0[3] = {q0.x, q0.y, q0.z}, dxs[3] = {q1.x, q1.y, q1.z}, dys[3] = {q2.x, q2.y, q2.z};
+    const int ya = py0 + 4 * band_i, yb = min(py1, ya + 3);
+    const int32_t e0[3] = {q0.x, q0.y, q0.z};
+    const int32_t dxs[3] = {rec_dx(q1.x), rec_dx(q1.y), rec_dx(q1.z)}, dys[3] = {rec_dy(q1.x), rec_dy(q1.y), rec_dy(q1.z)};
     uint32_t A[3], E[3], B[3];
     for (int e = 0; e < 3; e++) {
         const int32_t dx = dxs[e], dy = dys[e];
@@ -246,41 +270,35 @@ __device__ __forceinline__ void cover_window(const WaveStage& st, int j, int k, 
         }
         // bit i of neg is pixel xe - 7 + i; after the shift bit c is column xa + c
         const uint32_t cov = (~neg & 0xFFu) >> align;
-        if (ya + row <= yb) rows |= cov << (8 * ((ya + row) & 3));
+        if (ya + row <= yb) rows |= cov << (8 * row);
         E[0] += B[0];
         E[1] += B[1];
         E[2] += B[2];
     }
-    if (!rows) return;
-    const int wx = xa >> 3, sh = xa & 7, wy = band >> 1, half = 32 * (band & 1);
-    const uint32_t lo = (rows << sh) & (0x01010101u * ((0xFFu << sh) & 0xFFu));
-    const uint32_t hi = (rows >> (8 - sh)) & (0x01010101u * (0xFFu >> (8 - sh)));
-    if (lo) atomicOr(&s_mask[wy * words_x + wx], (unsigned long long)lo << half);
-    if (hi) atomicOr(&s_mask[wy * words_x + wx + 1], (unsigned long long)hi << half);
+    if (rows) or_block(s_mask, words_x, xa, ya, rows);
 }
 
 // One lane rasterises task k of a narrow near triangle: columns px0 and
-// px0 + 1 (the second only if inside the box) over mask-word row
-// (py0 >> 3) + k, with incremental 32-bit edge functions (all 8 rows lie
-// within 7 pixels of the box, where near triangles' edge functions are exact
-// in 32 bits).  Each column's 8 rows are collected with v_alignbit, clipped to
-// the box rows, spread to the word's bit layout and ORed into LDS (one word,
-// or two when px0 is the last column of a word).
-__device__ __forceinline__ void cover_narrow(const WaveStage& st, int j, int k, unsigned long long* __restrict__ s_mask,
+// px0 + 1 (the second only if inside the box) over pixel rows py0 + 8k ..
+// py0 + 8k + 7, with incremental 32-bit edge functions (all 8 rows lie within
+// 7 pixels of the box, where near triangles' edge functions are exact in 32
+// bits).  Each column's rows are collected with v_alignbit, clipped to the
+// box, spread to the block layout and ORed into the mask words.
+__device__ __forceinline__ void cover_narrow(const int4 q0, const int4 q1, int k, unsigned long long* __restrict__ s_mask,
                                              int words_x) {
-    const int4 q0 = st.q0[j], q1 = st.q1[j], q2 = st.q2[j];
     const int px0 = q0.w & 0xffff, px1 = q0.w >> 16;
     const int py0 = q1.w & 0xffff, py1 = q1.w >> 16;
-    const int wy = (py0 >> 3) + k;
-    const int32_t e0[3] = {q0.x, q0.y, q0.z}, dxs[3] = {q1.x, q1.y, q1.z}, dys[3] = {q2.x, q2.y, q2.z};
+    const int ya = py0 + 8 * k;
+    const int32_t e0[3] = {q0.x, q0.y, q0.z};
+    const int32_t dxs[3] = {rec_dx(q1.x), rec_dx(q1.y), rec_dx(q1.z)}, dys[3] = {rec_dy(q1.x), rec_dy(q1.y), rec_dy(q1.z)};
     uint32_t A[3], B[3], E[3];
     for (int e = 0; e < 3; e++) {
         A[e] = 0u - (uint32_t(dys[e]) << 8);          // one column to the right
         B[e] = uint32_t(dxs[e]) << 8;                 // one row down
-        E[e] = uint32_t(e0[e] + __mul24(dxs[e] << 8, 8 * wy + 7 - py0));   // bottom row of the word
+        E[e] = uint32_t(e0[e] + __mul24(dxs[e] << 8, 8 * k + 7));   // bottom row of the window
     }
     // alignbit shifts the flags left and brings the new sign bit in at bit 0:
-    // walking the rows bottom-up leaves row 8 wy + r at bit r
+    // walking the rows bottom-up leaves row ya + r at bit r
     uint32_t neg0 = 0u, neg1 = 0u;
 #pragma unroll
     for (int row = 7; row >= 0; row--) {
@@ -290,24 +308,20 @@ __device__ __forceinline__ void cover_narrow(const WaveStage& st, int j, int k, 
         E[1] -= B[1];
         E[2] -= B[2];
     }
-    const int lo = max(py0 - 8 * wy, 0), hi = min(py1 - 8 * wy, 7);
-    const uint32_t rowmask = (0xFFu << lo) & (0xFFu >> (7 - hi));
+    const uint32_t rowmask = 0xFFu >> (7 - min(py1 - ya, 7));
     const uint32_t m0 = ~neg0 & rowmask;
     const uint32_t m1 = px1 > px0 ? ~neg1 & rowmask : 0u;
-    const int wx = px0 >> 3, sh = px0 & 7;
-    unsigned long long w0 = spread_column(m0) << sh;
-    if (sh < 7) w0 |= spread_column(m1) << (sh + 1);
-    if (w0) atomicOr(&s_mask[wy * words_x + wx], w0);
-    if (sh == 7 && m1) atomicOr(&s_mask[wy * words_x + wx + 1], spread_column(m1));
+    const unsigned long long bits = spread_column(m0) | (spread_column(m1) << 1);
+    if (bits) or_block(s_mask, words_x, px0, ya, bits);
 }
 
 // ---------------------------------------------------------------- cooperative coverage of a big triangle
 
-// The whole wave walks the 8x8 blocks of one triangle's box: lane = pixel,
-// three edge functions per lane, the 64-lane ballot is the block's word.
-__device__ __forceinline__ void cover_big(const WaveStage& st, int j, int lx, int ly, int lane,
+// The whole wave walks the 8x8 blocks of one triangle's box (record r, the
+// same in every lane): lane = pixel, three edge functions per lane, the
+// 64-lane ballot is the block's word.
+__device__ __forceinline__ void cover_big(const TriRec& r, int lx, int ly, int lane,
                                           unsigned long long* __restrict__ s_mask, int words_x) {
-    const TriRec r = stage_get(st, j);
     const int box_x = __builtin_amdgcn_readfirstlane(r.box_x);
     const int box_y = __builtin_amdgcn_readfirstlane(r.box_y);
     const int flags = __builtin_amdgcn_readfirstlane(r.flags);
@@ -367,6 +381,49 @@ __device__ __forceinline__ unsigned long long valid_bits(int wx, int wy, const C
     return m;
 }
 
+// ---------------------------------------------------------------- task rounds
+
+// Runs lane tasks done .. done + count - 1 (count <= 64, task done + i on lane
+// i) of a queue whose triangles occupy running slots tail .. head - 1.  Each
+// lane finds its triangle by binary search over the queued first-task numbers.
+// Returns the running slot of the triangle that holds task done + 64 (the new
+// tail after a full round).
+template <int RING, bool NARROW>
+__device__ __forceinline__ int run_round(const int4* __restrict__ qa, const int4* __restrict__ qb,
+                                         const int32_t* __restrict__ qstart, int tail, int head, int done, int count,
+                                         int lane, unsigned long long* __restrict__ s_mask, int words_x) {
+    const int q = done + lane;
+    int next = tail;
+    if (lane < count) {
+        const int m = head - tail;
+        int lo = 0;   // qstart of slot tail + lo is <= q
+#pragma unroll
+        for (int step = RING / 2; step > 0; step >>= 1) {
+            const int i = lo + step;
+            if (i < m && qstart[(tail + i) & (RING - 1)] <= q) lo = i;
+        }
+        const int slot = (tail + lo) & (RING - 1);
+        const int k = q - qstart[slot];
+        const int4 a = qa[slot], b = qb[slot];
+        int ntask;
+        if (NARROW) {
+            cover_narrow(a, b, k, s_mask, words_x);
+            ntask = narrow_tasks(b.w);
+        } else {
+            cover_window(a, b, k, s_mask, words_x);
+            ntask = task_windows(a.w) * task_bands(b.w);
+        }
+        next = tail + lo + (k == ntask - 1 ? 1 : 0);
+    }
+    return __builtin_amdgcn_readlane(next, kWave - 1);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- main kernel
 
 struct RasterArgs {
@@ -385,7 +442,7 @@ template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
 __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     constexpr int NW = NT / kWave;
     extern __shared__ unsigned long long s_mask[];
-    __shared__ WaveStage s_stage[NW];
+    __shared__ WaveQueues s_queue[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
 
@@ -394,7 +451,7 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     const int lx = lane & 7, ly = lane >> 3;
     const CamK& cam = a.cam;
     const int words = cam.words_x * cam.words_y;
-    WaveStage& st = s_stage[wave];
+    WaveQueues& Q = s_queue[wave];
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
     if (!FROM_SNAPPED || a.pretransform)
@@ -416,130 +473,128 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
         __syncthreads();
     }
 
+    // queue state, the same in every lane of the wave: running slot counts
+    // (head, tail) and task counts (queued, done) of the narrow and wide queues
+    int n_head = 0, n_tail = 0, n_queued = 0, n_done = 0;
+    int w_head = 0, w_tail = 0, w_queued = 0, w_done = 0;
     for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
         const MeshK& mesh = a.meshes.m[mi];
         const float* M = s_M + mi * 48;
         const int T = mesh.n_triangles;
         const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
                            (size_t(b) * a.meshes.total_vertices + mesh.vertex_offset);
-        // Software pipeline over the wave's chunks of 64 triangles: while chunk c
-        // is processed, the snapped vertices of chunk c + 1 and the indices of
-        // chunk c + 2 are in flight (the vertex gathers are the long-latency
-        // loads).  Without snapped input, indices run one chunk ahead.
-        // The indices loaded for chunk c + 2 are parked in the wave's LDS stage
-        // at the end of the iteration: kept in registers across the loop they
-        // would be moved right after their load, and that move would wait for
-        // the vertex gathers issued just before.
-        const int3* tri3 = reinterpret_cast<const int3*>(mesh.triangles);
+        // indices of this lane's first triangle; later chunks are prefetched one iteration ahead
         int t = wave * kWave + lane;
         int32_t idx[3] = {0, 0, 0};
-        int2 pv[3] = {make_int2(INT32_MIN, 0), make_int2(INT32_MIN, 0), make_int2(INT32_MIN, 0)};
-        if (FROM_SNAPPED) {
-            if (t < T) {
-                const int3 i0 = tri3[t];
-                pv[0] = snap[i0.x];
-                pv[1] = snap[i0.y];
-                pv[2] = snap[i0.z];
-            }
-            if (t + NT < T) {
-                const int3 i1 = tri3[t + NT];
-                st.qi[lane] = make_int4(i1.x, i1.y, i1.z, 0);
-            }
-        } else if (t < T) {
+        if (t < T)
             for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * t + k];
-        }
         for (int base = wave * kWave; base < T; base += NT) {
             t = base + lane;
             const bool live = t < T;
             int32_t X[3] = {INT32_MIN, INT32_MIN, INT32_MIN}, Y[3] = {0, 0, 0};
             float vx[3], vy[3], vz[3];
             int link[3];
-            int3 ahead;
-            if (FROM_SNAPPED) {
-                if (live)
-                    for (int k = 0; k < 3; k++) {
-                        X[k] = pv[k].x;
-                        Y[k] = pv[k].y;
-                    }
-                if (t + NT < T) {
-                    const int4 q = st.qi[lane];
-                    pv[0] = snap[q.x];
-                    pv[1] = snap[q.y];
-                    pv[2] = snap[q.z];
-                }
-                ahead = tri3[min(t + 2 * NT, T - 1)];   // unconditional: no initialised registers to guard
-            } else {
-                if (live)
-                    for (int k = 0; k < 3; k++) {
+            if (live) {
+                for (int k = 0; k < 3; k++) {
+                    if (FROM_SNAPPED) {
+                        const int2 p = snap[idx[k]];
+                        X[k] = p.x;
+                        Y[k] = p.y;
+                    } else {
                         const float* v = mesh.vertices + size_t(idx[k]) * 3;
                         vx[k] = v[0];
                         vy[k] = v[1];
                         vz[k] = v[2];
                         link[k] = mesh.vertex_link[idx[k]];
                     }
-                // prefetch the next chunk's indices while this chunk is processed
-                const int tn = t + NT;
-                if (tn < T)
-                    for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
+                }
             }
+            // prefetch the next chunk's indices while this chunk is processed
+            const int tn = t + NT;
+            if (tn < T)
+                for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
             if (!FROM_SNAPPED && live)
                 for (int k = 0; k < 3; k++) project_snap(M + 12 * link[k], vx[k], vy[k], vz[k], cam, X[k], Y[k]);
             TriRec rec;
             const bool valid = live && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
             const bool near = valid && (rec.flags & kNear);
             const bool narrow = near && is_narrow(rec.box_x);
-            if (valid) stage_put(st, lane, rec);
-            // lane tasks of near triangles: 8-column windows x 4-row bands (at
-            // most 5 x 9 each) for wide boxes, word rows (at most 6) for narrow
-            // ones; inclusive prefixes over the wave from one ballot per bit
-            const int cnt = near && !narrow ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
+            const bool wide = near && !narrow;
+            // lane tasks: 8-column windows x 4-row bands (at most 5 x 9) for wide
+            // boxes, 8-row windows (at most 5) for narrow ones; both counts in one
+            // wave scan, wide in the low and narrow in the high 16 bits
+            const int cnt_w = wide ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
             const int cnt_n = narrow ? narrow_tasks(rec.box_y) : 0;
-            // both counts in one scan: wide in the low, narrow in the high 16 bits
-            // (totals stay below 64 x 45)
-            const int incl_both = wave_inclusive_sum(cnt | (cnt_n << 16));
-            const int total_both = __builtin_amdgcn_readlane(incl_both, kWave - 1);
-            const int total = total_both & 0xffff, total_n = total_both >> 16;
-            st.q3[lane] = make_int4(rec.e0hi[0], rec.e0hi[1], rec.e0hi[2], incl_both);
-            const unsigned long long big = __ballot(valid && !near);
-            // staged fields written by other lanes must be visible before they are read
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-            for (int base = 0; base < total_n; base += kWave) {
-                const int q = base + lane;
-                if (q < total_n) {
-                    int j = 0;
-#pragma unroll
-                    for (int step = kWave / 2; step > 0; step >>= 1)
-                        if ((st.q3[j + step - 1].w >> 16) <= q) j += step;
-                    const int k = q - ((st.q3[j].w >> 16) - narrow_tasks(st.q1[j].w));
-                    cover_narrow(st, j, k, s_mask, cam.words_x);
+            const int incl = wave_inclusive_sum(cnt_w | (cnt_n << 16));
+            const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+            const unsigned long long nmask = __ballot(narrow), wmask = __ballot(wide);
+            const int n_new = __popcll(nmask), w_new = __popcll(wmask);
+            // the wide ring drains its pending tasks (fewer than 64) before it would overflow
+            if (w_head - w_tail + w_new > kWideRing) {
+                run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, w_queued - w_done, lane,
+                                            s_mask, cam.words_x);
+                w_done = w_queued;
+                w_tail = w_head;
+            }
+            if (narrow || wide) {
+                const NearRec r = pack_near(rec);
+                const unsigned long long m = narrow ? nmask : wmask;
+                const int rank = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                if (narrow) {
+                    const int slot = (n_head + rank) & (kNarrowRing - 1);
+                    Q.na[slot] = r.a;
+                    Q.nb[slot] = r.b;
+                    Q.nstart[slot] = n_queued + (incl >> 16) - cnt_n;
+                } else {
+                    const int slot = (w_head + rank) & (kWideRing - 1);
+                    Q.wa[slot] = r.a;
+                    Q.wb[slot] = r.b;
+                    Q.wstart[slot] = w_queued + (incl & 0xffff) - cnt_w;
                 }
             }
-            for (int base = 0; base < total; base += kWave) {
-                const int q = base + lane;
-                if (q < total) {
-                    // slot j: first lane whose inclusive prefix exceeds q
-                    int j = 0;
-#pragma unroll
-                    for (int step = kWave / 2; step > 0; step >>= 1)
-                        if ((st.q3[j + step - 1].w & 0xffff) <= q) j += step;
-                    const int k = q - ((st.q3[j].w & 0xffff) - task_windows(st.q0[j].w) * task_bands(st.q1[j].w));
-                    cover_window(st, j, k, s_mask, cam.words_x);
-                }
+            n_head += n_new;
+            n_queued += total >> 16;
+            w_head += w_new;
+            w_queued += total & 0xffff;
+            wave_sync();   // queued records written by other lanes are read below
+            while (n_queued - n_done >= kWave) {
+                n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, n_tail, n_head, n_done, kWave, lane,
+                                                      s_mask, cam.words_x);
+                n_done += kWave;
             }
-            unsigned long long todo = big;
+            while (w_queued - w_done >= kWave) {
+                w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, kWave, lane,
+                                                     s_mask, cam.words_x);
+                w_done += kWave;
+            }
+            // triangles needing 64-bit edge functions or big boxes: the whole wave
+            // on one triangle at a time, its record broadcast from its lane
+            unsigned long long todo = __ballot(valid && !near);
             while (todo) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1;
-                cover_big(st, j, lx, ly, lane, s_mask, cam.words_x);
+                TriRec br;
+                for (int e = 0; e < 3; e++) {
+                    br.e0lo[e] = __builtin_amdgcn_readlane(rec.e0lo[e], j);
+                    br.e0hi[e] = __builtin_amdgcn_readlane(rec.e0hi[e], j);
+                    br.dx[e] = __builtin_amdgcn_readlane(rec.dx[e], j);
+                    br.dy[e] = __builtin_amdgcn_readlane(rec.dy[e], j);
+                }
+                br.box_x = __builtin_amdgcn_readlane(rec.box_x, j);
+                br.box_y = __builtin_amdgcn_readlane(rec.box_y, j);
+                br.flags = __builtin_amdgcn_readlane(rec.flags, j);
+                br.pad = 0;
+                cover_big(br, lx, ly, lane, s_mask, cam.words_x);
             }
-            if (FROM_SNAPPED && t + 2 * NT < T) st.qi[lane] = make_int4(ahead.x, ahead.y, ahead.z, 0);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
     }
+    // the last partial rounds
+    if (n_queued > n_done)
+        run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, n_tail, n_head, n_done, n_queued - n_done, lane, s_mask,
+                                     cam.words_x);
+    if (w_queued > w_done)
+        run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, w_queued - w_done, lane, s_mask,
+                                    cam.words_x);
     __syncthreads();
 
     int32_t cnt_s = 0, cnt_i = 0;
@@ -698,7 +753,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 
 template <int NT>
 constexpr size_t static_lds() {
-    return sizeof(WaveStage) * (NT / kWave) + sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (NT / kWave);
+    return sizeof(WaveQueues) * (NT / kWave) + sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (NT / kWave);
 }
 
 template <bool FS, bool WM, bool CN, int NT>
