@@ -120,37 +120,42 @@ def main():
         mean_phys = state["est"].copy()
         mean_phys[6:9] = readings[f]                  # joint readings initialise the joint means
         gen.init(np.zeros(9), 1.0, mean_phys, scale, seed0 + f)
+        gen.ask()                                     # first candidates of the frame and their FK
         state["frame"] = f
 
     def run_step(s, events=None):
+        """One generation: raster + counts of the current candidates, then one fused
+        launch for the losses, the CMA-ES update, the next candidates and their FK."""
         f, g = (s // G) % F, s % G
         if g == 0:
             if state["frame"] >= 0:
                 state["est"] = gen.mean()             # warm start: previous frame's estimate (D2H)
             start_frame(f)
-        tk.cmaes_sample(gen.state, gen.n, gen.lam, gen.X)
-        tk.fk_transform(gen.X, gen.lam, 1, prob.chains, gen.xf, gen.kp, cam)
         if events is not None:
             events[0].record()
         tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts, gen.ws)
         if events is not None:
             events[1].record()
-        tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
-                        1, 0.1, 0.0)
-        tk.cmaes_update(gen.state, gen.n, gen.lam, gen.loss)
+        tk.cmaes_tell_ask(gen.state, gen.n, gen.lam, gen.counts, prob.target_count, tk.LOSS_IOU, prob.chains, cam,
+                          gen.X, gen.xf, kp=gen.kp, kp_ref=prob.kp_ref, lambda_kp=0.1, loss=gen.loss,
+                          kp_next=gen.kp)
 
     # ---------------------------------------------------------------- warm-up and timed region
     for s in range(args.warmup):
         run_step(s)
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} generations)")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # the raster kernel is timed on every EVENT_EVERY-th generation of the timed
+    # region (events on the launch stream around its launch)
+    EVENT_EVERY = 8
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(0, args.steps, EVENT_EVERY)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     t_start.record()
     for i in range(args.steps):
-        run_step(args.warmup + i, evs[i])
+        run_step(args.warmup + i, evs[i // EVENT_EVERY] if i % EVENT_EVERY == 0 else None)
         if (i + 1) % 500 == 0:
             log(f"timed generations queued: {i + 1}/{args.steps}")
     t_end.record()
@@ -161,7 +166,7 @@ def main():
     fused_ms = np.array([a.elapsed_time(b) for a, b in evs])
     final_est = gen.mean()
     log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events; "
-        f"fused raster avg {fused_ms.mean() * 1e3:.1f} us")
+        f"fused raster avg {fused_ms.mean() * 1e3:.1f} us over {len(fused_ms)} sampled launches")
 
     # pose error of the last estimate against the truth of its frame
     last_f = ((args.warmup + args.steps - 1) // G) % F
@@ -179,15 +184,10 @@ def main():
             if state["frame"] >= 0:
                 state["est"] = gen.mean()
             start_frame(f)
-        tk.cmaes_sample(gen.state, gen.n, gen.lam, gen.X)
-        tk.fk_transform(gen.X, gen.lam, 1, prob.chains, gen.xf, gen.kp, cam)
         tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats)
         acc += stats.cpu().numpy()
         n_st += 1
-        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts, gen.ws)
-        tk.compose_loss(gen.counts, gen.lam, prob.target_count, tk.LOSS_IOU, gen.loss, 1.0, gen.kp, prob.kp_ref,
-                        1, 0.1, 0.0)
-        tk.cmaes_update(gen.state, gen.n, gen.lam, gen.loss)
+        run_step(s)
     kept, box_px, pairs, huge = acc / n_st
     tri_all = lam * mesh.n_triangles
     vert_all = lam * mesh.n_vertices

@@ -145,13 +145,31 @@ tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, 
  * d_loss: device FP64 [lambda]. */
 tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double* d_loss, tk_stream s);
 
+/* Fused generation step ("tell" the losses of the evaluated candidates, "ask"
+ * for the next ones) in one launch, with results identical to the sequence
+ *   tk_compose_loss(d_counts, lambda, d_target_count, kind, lambda_app, d_kp,
+ *                   d_kp_ref, n_arms, lambda_kp, tau, d_loss)
+ *   tk_cmaes_update(d_state, n, lambda, d_loss)
+ *   tk_cmaes_sample(d_state, n, lambda, d_X)
+ *   tk_fk_transform(d_X, lambda, n_arms, chains, d_link_xf, d_kp_next, cam)
+ * (Eq. (3)-(4) and (5)-(8), Sec. III-A.3).  n must be 9 * n_arms.  d_loss
+ * (FP64 [lambda]) and d_kp_next are optional outputs; d_kp / d_kp_ref are the
+ * evaluated candidates' keypoints and the reference (both or neither); d_kp
+ * and d_kp_next may be the same buffer (read before written).  cam is
+ * required.  All pointers are device pointers except chains and cam. */
+tk_status tk_cmaes_tell_ask(void* d_state, int32_t n, int32_t lambda, const int32_t* d_counts,
+                            const int32_t* d_target_count, int32_t kind, double lambda_app, const float* d_kp,
+                            const float* d_kp_ref, double lambda_kp, double tau, double* d_loss,
+                            const tk_chain* chains, int32_t n_arms, const tk_camera* cam, float* d_X,
+                            float* d_link_xf, float* d_kp_next, tk_stream s);
+
 /* ------------------------------------------------------- fitness evaluation */
 
 /* Forward kinematics (Sec. III-A.3 and the renderer input T_r^c T_m^r(q)):
  * d_X[batch][9*n_arms] FP32 candidates (alpha, beta, gamma, x, y, z, qhat1..3
  * per arm) -> d_link_xf[batch][n_arms][4][12] FP32 row-major 3x4 transforms
  * M_l = T_r^c(alpha,beta,gamma,x,y,z) T_l(q), q from the cosine map; computed
- * in FP64 and rounded.  d_kp (nullable) [batch][n_arms][4][2] FP32 projected
+ * in FP32.  d_kp (nullable) [batch][n_arms][4][2] FP32 projected
  * chain keypoints (NaN when behind z_near).  chains: host [n_arms]. */
 tk_status tk_fk_transform(const float* d_X, int32_t batch, int32_t n_arms, const tk_chain* chains,
                           float* d_link_xf, float* d_kp, const tk_camera* cam, tk_stream s);

@@ -8,7 +8,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "tk_internal.h"
+#include "fitness_device.h"
 
 namespace tk {
 namespace {
@@ -44,6 +44,24 @@ __device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1
     const double t = (2.0 * kPi) * u2;
     *z0 = r * cos(t);
     *z1 = r * sin(t);
+}
+
+// Normals 4j .. 4j + 3 of candidate k in generation g: one Philox block with
+// counter (j, k, g, 0), two Box-Muller pairs.
+__device__ inline void draw_normals(uint32_t key0, uint32_t key1, uint32_t g, int k, int j, double z[4]) {
+    const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
+    box_muller(r.x, r.y, &z[0], &z[1]);
+    box_muller(r.z, r.w, &z[2], &z[3]);
+}
+
+// y_i = sum_j (B D)_ij z_j, x_i = m_i + sigma y_i, theta_i = offset_i + scale_i x_i (FP32)
+__device__ inline float candidate_coord(const double* BD, const double* z, int n, int i, double mean_i, double sigma,
+                                        double offset_i, double scale_i, double* y_out) {
+    double y = 0.0;
+    for (int j = 0; j < n; j++) y += BD[i * n + j] * z[j];
+    *y_out = y;
+    const double x = mean_i + sigma * y;
+    return float(offset_i + scale_i * x);
 }
 
 // ---------------------------------------------------------------- init
@@ -152,21 +170,17 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
     for (int task = tid; task < kSampCand * groups; task += 64) {
         const int kk = task / groups, j = task % groups, k = k0 + kk;
         if (k >= lam) continue;
-        const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), gen, 0u}, key0, key1);
-        box_muller(r.x, r.y, &s_z[kk][4 * j], &s_z[kk][4 * j + 1]);
-        box_muller(r.z, r.w, &s_z[kk][4 * j + 2], &s_z[kk][4 * j + 3]);
+        draw_normals(key0, key1, gen, k, j, &s_z[kk][4 * j]);
     }
     __syncthreads();
     const double sigma = *S.sigma;
     for (int task = tid; task < kSampCand * n; task += 64) {
         const int kk = task / n, i = task % n, k = k0 + kk;
         if (k >= lam) continue;
-        double y = 0.0;
-        for (int j = 0; j < n; j++) y += s_BD[i * n + j] * s_z[kk][j];
-        const double x = S.mean[i] + sigma * y;
+        double y;
+        X[k * n + i] = candidate_coord(s_BD, s_z[kk], n, i, S.mean[i], sigma, S.offset[i], S.scale[i], &y);
         S.Z[k * n + i] = s_z[kk][i];
         S.Y[k * n + i] = y;
-        X[k * n + i] = float(S.offset[i] + S.scale[i] * x);
     }
 }
 
@@ -237,11 +251,27 @@ __device__ __forceinline__ bool jacobi_rotation(double a_ii, double a_pp, double
 // fixed-order partial sums (deterministic).
 constexpr int kParts = 8;   // partial sums per output element
 
+// Inputs and outputs of the fused tell-ask form: the losses are composed from
+// the counts (and keypoints) of the evaluated candidates, and after the update
+// the next generation is sampled and its forward kinematics evaluated.
+struct TellAskArgs {
+    const int32_t* counts;        // [lambda][2]
+    const int32_t* target_count;  // |M|
+    const float* kp;              // nullable [lambda][n_arms][4][2]
+    const float* kp_ref;          // nullable [n_arms][4][2]
+    LossArgs la;
+    double* loss;                 // nullable [lambda], the composed losses
+    float* X;                     // [lambda][n] next candidates
+    FkArgs fk;
+    float* link_xf;               // [lambda][n_arms][4][12]
+    float* kp_next;               // nullable [lambda][n_arms][4][2]
+};
+
 // AS / VS: Jacobi entries per lane (upper-triangle / all within-block entries
-// over 64 lanes); NT: threads of the workgroup.
-template <int AS, int VS, int NT>
-__global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam,
-                                                                  const double* __restrict__ loss) {
+// over 64 lanes); NT: threads of the workgroup; FUSED: tell-ask form.
+template <int AS, int VS, int NT, bool FUSED>
+__global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam, const double* __restrict__ loss,
+                                                          TellAskArgs ta) {
     extern __shared__ double s_elite[];  // [mu][n]
     __shared__ double s_key[kMaxLambda];
     __shared__ int s_order[kMaxLambda];
@@ -251,6 +281,7 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
     __shared__ double s_part[kParts * kMaxN * (kMaxN + 1) / 2];
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
     __shared__ double s_scal[4];
+    __shared__ double s_mean[kMaxN];
     __shared__ double2 s_cs[kMaxN];   // (c_i, s'_i): column i of the current rotation
 
     StateView S = state_view(blob, n, lam);
@@ -263,7 +294,14 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
 
     // 0. stage losses and state
     for (int k = tid; k < lam; k += NT) {
-        const double v = loss[k];
+        double v;
+        if (FUSED) {
+            v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
+                                 ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
+            if (ta.loss) ta.loss[k] = v;
+        } else {
+            v = loss[k];
+        }
         s_key[k] = (v != v) ? INFINITY : v;
     }
     for (int r = tid; r < mu; r += NT) s_w[r] = S.weights[r];
@@ -333,7 +371,8 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
         double acc = 0.0;
         for (int part = 0; part < kParts; part++) acc += s_part[part * n + tid];
         s_yw[tid] = acc;
-        S.mean[tid] = S.mean[tid] + c_m * sigma * acc;
+        s_mean[tid] = S.mean[tid] + c_m * sigma * acc;
+        S.mean[tid] = s_mean[tid];
     }
     __syncthreads();
     // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
@@ -365,7 +404,8 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
             s_scal[1] = h;
             s_scal[2] = sw;
             *S.h_sigma = h;
-            *S.sigma = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
+            s_scal[3] = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
+            *S.sigma = s_scal[3];
             S.hdr->gen = gen + 1;
         }
     }
@@ -447,169 +487,209 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
     // except that l meets player 0 when q_l(r) = l; index 0 meets
     // R = (r == 0 ? k : r); a partner >= nb is the dummy (no rotation).
     // q_l advances by 2 (mod k) from one round to the next.
-    if (tid >= kWave64) return;
-    const int m = nb + (nb & 1);
-    const int k1 = m - 1;                      // rounds per sweep (odd)
-    const int ntri_b = nb * (nb + 1) / 2;
-    const int n_a = n_blocks * ntri_b;         // upper-triangle entries inside the blocks
-    const int n_v = n_blocks * nb * nb;        // all entries inside the blocks
-    constexpr int kASlots = AS;
-    constexpr int kVSlots = VS;
-    const int na_slots = (n_a + kWave64 - 1) / kWave64;
-    const int nv_slots = (n_v + kWave64 - 1) / kWave64;
-    auto q_start = [k1](int l) {               // q_l(0)
-        int t = (-l - 1) % k1;
-        return (t < 0 ? t + k1 : t) + 1;
-    };
-    auto q_next = [k1](int q) {
-        q += 2;
-        q -= q > k1 ? k1 : 0;
-        q -= q > k1 ? k1 : 0;
-        return q;
-    };
-    auto partner = [nb](int l, int q, int R) {
-        const int p = l == 0 ? R : (q == l ? 0 : q);
-        return p < nb ? p : l;
-    };
-    int a_i[kASlots], a_j[kASlots], a_base[kASlots], a_qi[kASlots], a_qj[kASlots];
-    int v_row[kVSlots], v_j[kVSlots], v_base[kVSlots], v_q[kVSlots];
-#pragma unroll
-    for (int sl = 0; sl < kASlots; sl++) {
-        const int e = min(tid + kWave64 * sl, n_a - 1);
-        const int blk = e / ntri_b;
-        int li = 0, rem = e - blk * ntri_b;
-        while (rem >= nb - li) { rem -= nb - li; li++; }
-        a_base[sl] = blk * nb;
-        a_i[sl] = blk * nb + li;
-        a_j[sl] = blk * nb + li + rem;
-        a_qi[sl] = q_start(li);
-        a_qj[sl] = q_start(li + rem);
-    }
-#pragma unroll
-    for (int sl = 0; sl < kVSlots; sl++) {
-        const int e = min(tid + kWave64 * sl, n_v - 1);
-        const int blk = e / (nb * nb), r = e - blk * nb * nb;
-        v_row[sl] = (blk * nb + r / nb) * n;
-        v_base[sl] = blk * nb;
-        v_j[sl] = blk * nb + r % nb;
-        v_q[sl] = q_start(r % nb);
-    }
-    const int my_t = min(tid, n - 1);
-    const int my_blk = my_t / nb;
-    const int my_l = my_t - my_blk * nb;
-    int my_q = q_start(my_l);
-    double* Acur = s_A;
-    double* Anext = s_T;
-    double* Vcur = s_V;
-    double* Vnext = s_C;
-    for (int e = tid; e < nn; e += kWave64) {   // entries outside the blocks stay zero in both buffers
-        const int i = e / n, j = e % n;
-        if (i / nb != j / nb) {
-            Anext[e] = 0.0;
-            Vnext[e] = 0.0;
-        }
-    }
-    wave_sync();
-    const int max_rounds = kMaxSweeps * k1;
-    int round = 0;
-    for (int it = 0; it < max_rounds; it++) {
-        const int R = round == 0 ? k1 : round;
-        // rotation of index my_t
-        const int pt = my_blk * nb + partner(my_l, my_q, R);
-        double c_t, s_t;
-        const bool rot = jacobi_rotation(Acur[my_t * n + my_t], Acur[pt * n + pt], Acur[my_t * n + pt], my_t < pt,
-                                         tid < n && pt != my_t, &c_t, &s_t);
-        // operands of this round's updates (independent of the rotations)
-        double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
-#pragma unroll
+    if (tid < kWave64) {
+        const int m = nb + (nb & 1);
+        const int k1 = m - 1;                      // rounds per sweep (odd)
+        const int ntri_b = nb * (nb + 1) / 2;
+        const int n_a = n_blocks * ntri_b;         // upper-triangle entries inside the blocks
+        const int n_v = n_blocks * nb * nb;        // all entries inside the blocks
+        constexpr int kASlots = AS;
+        constexpr int kVSlots = VS;
+        const int na_slots = (n_a + kWave64 - 1) / kWave64;
+        const int nv_slots = (n_v + kWave64 - 1) / kWave64;
+        auto q_start = [k1](int l) {               // q_l(0)
+            int t = (-l - 1) % k1;
+            return (t < 0 ? t + k1 : t) + 1;
+        };
+        auto q_next = [k1](int q) {
+            q += 2;
+            q -= q > k1 ? k1 : 0;
+            q -= q > k1 ? k1 : 0;
+            return q;
+        };
+        auto partner = [nb](int l, int q, int R) {
+            const int p = l == 0 ? R : (q == l ? 0 : q);
+            return p < nb ? p : l;
+        };
+        int a_i[kASlots], a_j[kASlots], a_base[kASlots], a_qi[kASlots], a_qj[kASlots];
+        int v_row[kVSlots], v_j[kVSlots], v_base[kVSlots], v_q[kVSlots];
+    #pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
-            if (sl < na_slots) {
-                const int pi = a_base[sl] + partner(a_i[sl] - a_base[sl], a_qi[sl], R);
-                const int pj = a_base[sl] + partner(a_j[sl] - a_base[sl], a_qj[sl], R);
-                const int ri = a_i[sl] * n, rp = pi * n;
-                x_ij[sl] = Acur[ri + a_j[sl]];
-                x_ipj[sl] = Acur[ri + pj];
-                x_pij[sl] = Acur[rp + a_j[sl]];
-                x_pipj[sl] = Acur[rp + pj];
-            }
+            const int e = min(tid + kWave64 * sl, n_a - 1);
+            const int blk = e / ntri_b;
+            int li = 0, rem = e - blk * ntri_b;
+            while (rem >= nb - li) { rem -= nb - li; li++; }
+            a_base[sl] = blk * nb;
+            a_i[sl] = blk * nb + li;
+            a_j[sl] = blk * nb + li + rem;
+            a_qi[sl] = q_start(li);
+            a_qj[sl] = q_start(li + rem);
         }
-        double y_ij[kVSlots], y_ipj[kVSlots];
-#pragma unroll
+    #pragma unroll
         for (int sl = 0; sl < kVSlots; sl++) {
-            if (sl < nv_slots) {
-                const int pj = v_base[sl] + partner(v_j[sl] - v_base[sl], v_q[sl], R);
-                y_ij[sl] = Vcur[v_row[sl] + v_j[sl]];
-                y_ipj[sl] = Vcur[v_row[sl] + pj];
+            const int e = min(tid + kWave64 * sl, n_v - 1);
+            const int blk = e / (nb * nb), r = e - blk * nb * nb;
+            v_row[sl] = (blk * nb + r / nb) * n;
+            v_base[sl] = blk * nb;
+            v_j[sl] = blk * nb + r % nb;
+            v_q[sl] = q_start(r % nb);
+        }
+        const int my_t = min(tid, n - 1);
+        const int my_blk = my_t / nb;
+        const int my_l = my_t - my_blk * nb;
+        int my_q = q_start(my_l);
+        double* Acur = s_A;
+        double* Anext = s_T;
+        double* Vcur = s_V;
+        double* Vnext = s_C;
+        for (int e = tid; e < nn; e += kWave64) {   // entries outside the blocks stay zero in both buffers
+            const int i = e / n, j = e % n;
+            if (i / nb != j / nb) {
+                Anext[e] = 0.0;
+                Vnext[e] = 0.0;
             }
         }
-        // advance the schedule
-        round = round + 1 == k1 ? 0 : round + 1;
-        my_q = q_next(my_q);
-#pragma unroll
-        for (int sl = 0; sl < kASlots; sl++) {
-            a_qi[sl] = q_next(a_qi[sl]);
-            a_qj[sl] = q_next(a_qj[sl]);
-        }
-#pragma unroll
-        for (int sl = 0; sl < kVSlots; sl++) v_q[sl] = q_next(v_q[sl]);
-
-        if (__ballot(rot) == 0ull) {
-            // nothing rotates in this round: stop if no pair exceeds the threshold
-            bool open = false;
-#pragma unroll
+        wave_sync();
+        const int max_rounds = kMaxSweeps * k1;
+        int round = 0;
+        for (int it = 0; it < max_rounds; it++) {
+            const int R = round == 0 ? k1 : round;
+            // rotation of index my_t
+            const int pt = my_blk * nb + partner(my_l, my_q, R);
+            double c_t, s_t;
+            const bool rot = jacobi_rotation(Acur[my_t * n + my_t], Acur[pt * n + pt], Acur[my_t * n + pt], my_t < pt,
+                                             tid < n && pt != my_t, &c_t, &s_t);
+            // operands of this round's updates (independent of the rotations)
+            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
+    #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
                 if (sl < na_slots) {
-                    const int i = a_i[sl], j = a_j[sl];
-                    const double aij = x_ij[sl];
-                    open |= tid + kWave64 * sl < n_a && i != j &&
-                            aij * aij > 1e-30 * fabs(Acur[i * n + i] * Acur[j * n + j]);
+                    const int pi = a_base[sl] + partner(a_i[sl] - a_base[sl], a_qi[sl], R);
+                    const int pj = a_base[sl] + partner(a_j[sl] - a_base[sl], a_qj[sl], R);
+                    const int ri = a_i[sl] * n, rp = pi * n;
+                    x_ij[sl] = Acur[ri + a_j[sl]];
+                    x_ipj[sl] = Acur[ri + pj];
+                    x_pij[sl] = Acur[rp + a_j[sl]];
+                    x_pipj[sl] = Acur[rp + pj];
                 }
             }
-            if (__ballot(open) == 0ull) break;
-            continue;
-        }
-        if (tid < n) s_cs[tid] = make_double2(c_t, s_t);
-        wave_sync();
-#pragma unroll
-        for (int sl = 0; sl < kASlots; sl++) {
-            if (sl < na_slots && tid + kWave64 * sl < n_a) {
-                const double2 ci = s_cs[a_i[sl]], cj = s_cs[a_j[sl]];
-                const double v = ci.x * (cj.x * x_ij[sl] + cj.y * x_ipj[sl]) +
-                                 ci.y * (cj.x * x_pij[sl] + cj.y * x_pipj[sl]);
-                Anext[a_i[sl] * n + a_j[sl]] = v;
-                Anext[a_j[sl] * n + a_i[sl]] = v;
+            double y_ij[kVSlots], y_ipj[kVSlots];
+    #pragma unroll
+            for (int sl = 0; sl < kVSlots; sl++) {
+                if (sl < nv_slots) {
+                    const int pj = v_base[sl] + partner(v_j[sl] - v_base[sl], v_q[sl], R);
+                    y_ij[sl] = Vcur[v_row[sl] + v_j[sl]];
+                    y_ipj[sl] = Vcur[v_row[sl] + pj];
+                }
             }
-        }
-#pragma unroll
-        for (int sl = 0; sl < kVSlots; sl++) {
-            if (sl < nv_slots && tid + kWave64 * sl < n_v) {
-                const double2 cj = s_cs[v_j[sl]];
-                Vnext[v_row[sl] + v_j[sl]] = cj.x * y_ij[sl] + cj.y * y_ipj[sl];
+            // advance the schedule
+            round = round + 1 == k1 ? 0 : round + 1;
+            my_q = q_next(my_q);
+    #pragma unroll
+            for (int sl = 0; sl < kASlots; sl++) {
+                a_qi[sl] = q_next(a_qi[sl]);
+                a_qj[sl] = q_next(a_qj[sl]);
             }
+    #pragma unroll
+            for (int sl = 0; sl < kVSlots; sl++) v_q[sl] = q_next(v_q[sl]);
+
+            if (__ballot(rot) == 0ull) {
+                // nothing rotates in this round: stop if no pair exceeds the threshold
+                bool open = false;
+    #pragma unroll
+                for (int sl = 0; sl < kASlots; sl++) {
+                    if (sl < na_slots) {
+                        const int i = a_i[sl], j = a_j[sl];
+                        const double aij = x_ij[sl];
+                        open |= tid + kWave64 * sl < n_a && i != j &&
+                                aij * aij > 1e-30 * fabs(Acur[i * n + i] * Acur[j * n + j]);
+                    }
+                }
+                if (__ballot(open) == 0ull) break;
+                continue;
+            }
+            if (tid < n) s_cs[tid] = make_double2(c_t, s_t);
+            wave_sync();
+    #pragma unroll
+            for (int sl = 0; sl < kASlots; sl++) {
+                if (sl < na_slots && tid + kWave64 * sl < n_a) {
+                    const double2 ci = s_cs[a_i[sl]], cj = s_cs[a_j[sl]];
+                    const double v = ci.x * (cj.x * x_ij[sl] + cj.y * x_ipj[sl]) +
+                                     ci.y * (cj.x * x_pij[sl] + cj.y * x_pipj[sl]);
+                    Anext[a_i[sl] * n + a_j[sl]] = v;
+                    Anext[a_j[sl] * n + a_i[sl]] = v;
+                }
+            }
+    #pragma unroll
+            for (int sl = 0; sl < kVSlots; sl++) {
+                if (sl < nv_slots && tid + kWave64 * sl < n_v) {
+                    const double2 cj = s_cs[v_j[sl]];
+                    Vnext[v_row[sl] + v_j[sl]] = cj.x * y_ij[sl] + cj.y * y_ipj[sl];
+                }
+            }
+            wave_sync();
+            double* t = Acur; Acur = Anext; Anext = t;
+            t = Vcur; Vcur = Vnext; Vnext = t;
         }
-        wave_sync();
-        double* t = Acur; Acur = Anext; Anext = t;
-        t = Vcur; Vcur = Vnext; Vnext = t;
+        // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
+        if (tid == 0) {
+            double emax = 0.0;
+            for (int i = 0; i < n; i++) emax = fmax(emax, Acur[i * n + i]);
+            const double floor_v = 1e-20 * emax;
+            int flags = 0;
+            for (int i = 0; i < n; i++) {
+                double e = Acur[i * n + i];
+                if (!(e >= floor_v)) {
+                    e = floor_v;
+                    flags |= 1;
+                }
+                S.D[i] = sqrt(e);
+                s_D[i] = S.D[i];
+            }
+            const double sg = *S.sigma;
+            if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
+            S.hdr->flags = flags;
+        }
+        for (int e = tid; e < nn; e += kWave64) {
+            S.B[e] = Vcur[e];
+            s_B[e] = Vcur[e];
+        }
     }
-    // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
-    if (tid == 0) {
-        double emax = 0.0;
-        for (int i = 0; i < n; i++) emax = fmax(emax, Acur[i * n + i]);
-        const double floor_v = 1e-20 * emax;
-        int flags = 0;
-        for (int i = 0; i < n; i++) {
-            double e = Acur[i * n + i];
-            if (!(e >= floor_v)) {
-                e = floor_v;
-                flags |= 1;
-            }
-            S.D[i] = sqrt(e);
-        }
-        const double sg = *S.sigma;
-        if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
-        S.hdr->flags = flags;
+    if (!FUSED) return;
+
+    // 7. (tell-ask form) the next generation: the same draws and arithmetic as
+    //    the sample kernel (z by Philox + Box-Muller with the incremented
+    //    generation, y = B D z, x = m + sigma y, theta = offset + scale x), then
+    //    the forward kinematics of every candidate and arm
+    __syncthreads();
+    const uint32_t gnext = uint32_t(gen + 1);
+    const uint64_t seed = S.hdr->seed;
+    const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
+    const int groups = (n + 3) / 4;
+    for (int e = tid; e < nn; e += NT) s_T[e] = s_B[e] * s_D[e % n];
+    for (int task = tid; task < lam * groups; task += NT) {
+        const int k = task / groups, j = task % groups;
+        double z[4];
+        draw_normals(key0, key1, gnext, k, j, z);
+        for (int t = 0; t < 4; t++)
+            if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
     }
-    for (int e = tid; e < nn; e += kWave64) S.B[e] = Vcur[e];
+    __syncthreads();
+    const double sigma_next = s_scal[3];
+    for (int task = tid; task < lam * n; task += NT) {
+        const int k = task / n, i = task % n;
+        double y;
+        ta.X[task] = candidate_coord(s_T, S.Z + size_t(k) * n, n, i, s_mean[i], sigma_next, S.offset[i],
+                                     S.scale[i], &y);
+        S.Y[task] = y;
+    }
+    __syncthreads();
+    for (int task = tid; task < lam * ta.fk.n_arms; task += NT) {
+        const int arm = task % ta.fk.n_arms;
+        const ChainK ch = arm == 0 ? ta.fk.ch[0] : ta.fk.ch[1];
+        fk_candidate(ta.X + size_t(task) * 9, ch, ta.fk.cam, ta.link_xf + size_t(task) * 48,
+                     ta.kp_next ? ta.kp_next + size_t(task) * 8 : nullptr);
+    }
 }
 
 }  // namespace
@@ -706,14 +786,51 @@ tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double
     // Jacobi entries inside the blocks number at most n(n+1)/2 (upper
     // triangle) and n^2 (all), whatever the block count: for n <= 9 they fit
     // one and two per lane of a wave, for n <= 18 three and six.
+    TellAskArgs none;
+    std::memset(&none, 0, sizeof none);
     if (n <= 9) {
-        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024>), dim3(1), dim3(1024), lds,
-                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss);
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, false>), dim3(1), dim3(1024), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss, none);
     } else {
-        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512>), dim3(1), dim3(512), lds,
-                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss);
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, false>), dim3(1), dim3(512), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss, none);
     }
     return check_launch("tk_cmaes_update");
+}
+
+tk_status tk_cmaes_tell_ask(void* d_state, int32_t n, int32_t lambda, const int32_t* d_counts,
+                            const int32_t* d_target_count, int32_t kind, double lambda_app, const float* d_kp,
+                            const float* d_kp_ref, double lambda_kp, double tau, double* d_loss,
+                            const tk_chain* chains, int32_t n_arms, const tk_camera* cam, float* d_X,
+                            float* d_link_xf, float* d_kp_next, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(d_counts && d_target_count, "counts / target_count is NULL");
+    TK_REQUIRE(d_X && d_link_xf, "X / link_xf is NULL");
+    TellAskArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    if (tk_status st = make_loss_args(lambda, kind, lambda_app, d_kp, d_kp_ref, n_arms, lambda_kp, tau, &ta.la))
+        return st;
+    if (tk_status st = make_fk_args(chains, n_arms, cam, &ta.fk)) return st;
+    TK_REQUIRE(n == 9 * n_arms, "n = %d must be 9 x n_arms = %d", n, 9 * n_arms);
+    ta.fk.batch = lambda;
+    ta.counts = d_counts;
+    ta.target_count = d_target_count;
+    ta.kp = d_kp;
+    ta.kp_ref = d_kp_ref;
+    ta.loss = d_loss;
+    ta.X = d_X;
+    ta.link_xf = d_link_xf;
+    ta.kp_next = d_kp_next;
+    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    if (n <= 9) {
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true>), dim3(1), dim3(1024), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
+    } else {
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, true>), dim3(1), dim3(512), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
+    }
+    return check_launch("tk_cmaes_tell_ask");
 }
 
 }  // extern "C"

@@ -1,0 +1,144 @@
+// Device functions shared by the stand-alone FK / loss kernels and the fused
+// CMA-ES tell-ask kernel, so that both paths produce identical bits.
+#pragma once
+
+#include "tk_internal.h"
+
+namespace tk {
+
+// 3x4 affine [R|t] product C = A * B (row-major)
+__device__ __forceinline__ void aff_mul(const float* A, const float* B, float* C) {
+    float t[12];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            float s = A[4 * i + 0] * B[0 + j] + A[4 * i + 1] * B[4 + j] + A[4 * i + 2] * B[8 + j];
+            if (j == 3) s += A[4 * i + 3];
+            t[4 * i + j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < 12; i++) C[i] = t[i];
+}
+
+// Cosine joint map (Sec. III-A.3): unconstrained qhat -> q in [lb, ub].
+__device__ __forceinline__ float decode_joint(float qh, float lb, float ub) {
+    constexpr float kPiF = 3.14159265358979323846f;
+    return lb + (ub - lb) * 0.5f * (1.0f - cosf(kPiF * (qh - lb) / (ub - lb)));
+}
+
+// Forward kinematics of one candidate and arm in FP32 (Sec. III-A.3 and the
+// renderer input T_r^c T_m^r(q) of Sec. III-A.2): th = (alpha, beta, gamma,
+// x, y, z, qhat1..3) -> M_l = T_r^c T_l(q) for the shaft, wrist and two jaws
+// (out[4][12], 3x4 row-major) and, when kp is not NULL, the four chain
+// keypoints projected by the pinhole camera (NaN behind the near plane).
+__device__ __forceinline__ void fk_candidate(const float* __restrict__ th, const ChainK& ch, const CamK& cam,
+                                             float* __restrict__ out, float* __restrict__ kp) {
+    float sa, ca, sb, cb, sg, cg;
+    sincosf(th[0], &sa, &ca);
+    sincosf(th[1], &sb, &cb);
+    sincosf(th[2], &sg, &cg);
+    // R = Ry(gamma) Rx(alpha) Rz(beta)
+    const float RyRx[9] = {cg, sg * sa, sg * ca, 0.0f, ca, -sa, -sg, cg * sa, cg * ca};
+    float T[12];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        T[4 * i + 0] = RyRx[3 * i + 0] * cb + RyRx[3 * i + 1] * sb;
+        T[4 * i + 1] = -RyRx[3 * i + 0] * sb + RyRx[3 * i + 1] * cb;
+        T[4 * i + 2] = RyRx[3 * i + 2];
+    }
+    T[3] = th[3];
+    T[7] = th[4];
+    T[11] = th[5];
+    float q[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) q[j] = decode_joint(th[6 + j], ch.lb[j], ch.ub[j]);
+    float s1, c1;
+    sincosf(q[0], &s1, &c1);
+    const float pitch[12] = {1, 0, 0, 0, 0, c1, -s1, 0, 0, s1, c1, 0};
+    float M[4][12];
+#pragma unroll
+    for (int e = 0; e < 12; e++) M[0][e] = T[e];             // shaft: T_0 = I
+    aff_mul(T, pitch, M[1]);                                   // wrist: Rx(q1)
+    const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * ch.d, 0, s1, c1, c1 * ch.d};
+    float TY[12];
+    aff_mul(T, yaw_origin, TY);                                // Rx(q1) Tr(0, 0, d)
+#pragma unroll
+    for (int side = 0; side < 2; side++) {                     // jaws: ... Ry(q2 +- q3 / 2)
+        const float phi = side == 0 ? q[1] + 0.5f * q[2] : q[1] - 0.5f * q[2];
+        float sp, cp;
+        sincosf(phi, &sp, &cp);
+        const float ry[12] = {cp, 0, sp, 0, 0, 1, 0, 0, -sp, 0, cp, 0};
+        aff_mul(TY, ry, M[2 + side]);
+    }
+#pragma unroll
+    for (int l = 0; l < 4; l++)
+#pragma unroll
+        for (int e = 0; e < 12; e++) out[12 * l + e] = M[l][e];
+    if (kp) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int link = ch.kp_link[j];
+            float m[12];
+#pragma unroll
+            for (int e = 0; e < 12; e++)
+                m[e] = link == 0 ? M[0][e] : link == 1 ? M[1][e] : link == 2 ? M[2][e] : M[3][e];
+            const float vx = ch.kp[j][0], vy = ch.kp[j][1], vz = ch.kp[j][2];
+            const float Xc = m[0] * vx + m[1] * vy + m[2] * vz + m[3];
+            const float Yc = m[4] * vx + m[5] * vy + m[6] * vz + m[7];
+            const float Zc = m[8] * vx + m[9] * vy + m[10] * vz + m[11];
+            if (!(Zc >= cam.z_near)) {
+                kp[2 * j] = NAN;
+                kp[2 * j + 1] = NAN;
+            } else {
+                kp[2 * j] = cam.fx * (Xc / Zc) + cam.cx;
+                kp[2 * j + 1] = cam.fy * (Yc / Zc) + cam.cy;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- loss
+
+__device__ __forceinline__ double pos_part(double x) { return x != x ? x : (x > 0.0 ? x : 0.0); }
+
+__device__ __forceinline__ double kp_dist(const float* p, const float* r) {
+    const double dx = double(p[0]) - double(r[0]), dy = double(p[1]) - double(r[1]);
+    return sqrt(dx * dx + dy * dy);
+}
+
+// Loss of one candidate in FP64 from its counts (Eq. (5), (6), (8); mask error
+// 1 - IoU of Sec. IV):
+//   kind 0: 1 - i / (a + m - i), 0 when the union is empty;
+//   kind 1: (a + m - 2i) + lambda_app |a - m|;
+// plus lambda_kp times the keypoint term of every arm when kp is given: the
+// shaft and wrist keypoints' (|p - r| - tau)_+, the better assignment of the
+// two jaw tips, and the tip midpoint.  kp: this candidate's [n_arms][4][2].
+__device__ __forceinline__ double compose_loss_one(int64_t a_cnt, int64_t inter, int64_t m, const float* kp,
+                                                   const float* kp_ref, const LossArgs& la) {
+    double L;
+    if (la.kind == 0) {
+        const int64_t uni = a_cnt + m - inter;
+        L = uni == 0 ? 0.0 : 1.0 - double(inter) / double(uni);
+    } else {
+        L = double(a_cnt + m - 2 * inter) + la.lambda_app * fabs(double(a_cnt - m));
+    }
+    if (kp && kp_ref && la.lambda_kp != 0.0) {
+        for (int arm = 0; arm < la.n_arms; arm++) {
+            const float* p = kp + arm * 8;
+            const float* r = kp_ref + arm * 8;
+            const double fixed = pos_part(kp_dist(p + 0, r + 0) - la.tau) + pos_part(kp_dist(p + 2, r + 2) - la.tau);
+            const double keep = pos_part(kp_dist(p + 4, r + 4) - la.tau) + pos_part(kp_dist(p + 6, r + 6) - la.tau);
+            const double swap = pos_part(kp_dist(p + 4, r + 6) - la.tau) + pos_part(kp_dist(p + 6, r + 4) - la.tau);
+            double tips = keep < swap ? keep : swap;
+            if (keep != keep || swap != swap) tips = NAN;
+            const double mpx = 0.5 * (double(p[4]) + double(p[6])), mpy = 0.5 * (double(p[5]) + double(p[7]));
+            const double mrx = 0.5 * (double(r[4]) + double(r[6])), mry = 0.5 * (double(r[5]) + double(r[7]));
+            const double mid = pos_part(sqrt((mpx - mrx) * (mpx - mrx) + (mpy - mry) * (mpy - mry)) - la.tau);
+            L += la.lambda_kp * (fixed + tips + mid);
+        }
+    }
+    return L;
+}
+
+}  // namespace tk

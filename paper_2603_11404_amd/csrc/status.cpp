@@ -1,4 +1,5 @@
 // Status strings, thread-local error detail and shared argument validation.
+#include <cmath>
 #include <cstdarg>
 #include <cstring>
 
@@ -34,6 +35,46 @@ tk_status validate_camera(const tk_camera* cam) {
     TK_REQUIRE(cam->fx == cam->fx && cam->fy == cam->fy && cam->cx == cam->cx && cam->cy == cam->cy,
                "camera intrinsics are NaN");
     TK_REQUIRE(cam->z_near > 0.0f, "z_near must be > 0");
+    return TK_OK;
+}
+
+tk_status make_fk_args(const tk_chain* chains, int32_t n_arms, const tk_camera* cam, FkArgs* a) {
+    TK_REQUIRE(n_arms >= 1 && n_arms <= kMaxArms, "n_arms = %d outside 1..%d", n_arms, kMaxArms);
+    TK_REQUIRE(chains != nullptr, "chains is NULL");
+    std::memset(a, 0, sizeof *a);
+    if (cam) {
+        if (tk_status st = validate_camera(cam)) return st;
+        a->cam = make_cam(*cam);
+    }
+    for (int i = 0; i < n_arms; i++) {
+        const tk_chain& c = chains[i];
+        TK_REQUIRE(std::isfinite(c.d_pitch_yaw), "chain %d: d_pitch_yaw not finite", i);
+        a->ch[i].d = float(c.d_pitch_yaw);
+        for (int j = 0; j < 3; j++) {
+            TK_REQUIRE(c.q_ub[j] > c.q_lb[j], "chain %d: joint %d has q_ub <= q_lb", i, j);
+            a->ch[i].lb[j] = float(c.q_lb[j]);
+            a->ch[i].ub[j] = float(c.q_ub[j]);
+        }
+        for (int j = 0; j < 4; j++) {
+            TK_REQUIRE(c.keypoints[j][3] >= 0 && c.keypoints[j][3] <= 3 &&
+                           c.keypoints[j][3] == double(int(c.keypoints[j][3])),
+                       "chain %d: keypoint %d has invalid link id", i, j);
+            for (int e = 0; e < 3; e++) a->ch[i].kp[j][e] = float(c.keypoints[j][e]);
+            a->ch[i].kp_link[j] = int(c.keypoints[j][3]);
+        }
+    }
+    a->n_arms = n_arms;
+    return TK_OK;
+}
+
+tk_status make_loss_args(int32_t batch, int32_t kind, double lambda_app, const float* d_kp, const float* d_kp_ref,
+                         int32_t n_arms, double lambda_kp, double tau, LossArgs* la) {
+    TK_REQUIRE(kind == 0 || kind == 1, "kind = %d must be 0 (1 - IoU) or 1 (render loss)", kind);
+    TK_REQUIRE(std::isfinite(lambda_app) && std::isfinite(lambda_kp) && std::isfinite(tau), "non-finite weights");
+    TK_REQUIRE((d_kp == nullptr) == (d_kp_ref == nullptr), "kp and kp_ref must both be given or both NULL");
+    TK_REQUIRE(d_kp == nullptr || (n_arms >= 1 && n_arms <= kMaxArms), "n_arms = %d outside 1..%d", n_arms,
+               kMaxArms);
+    *la = LossArgs{lambda_app, lambda_kp, tau, batch, kind, n_arms};
     return TK_OK;
 }
 

@@ -131,7 +131,30 @@ struct MeshSet {
     int32_t total_vertices;
 };
 
+// Kinematic chain as the kernels see it (FP32).
+struct ChainK {
+    float d, lb[3], ub[3], kp[4][3];
+    int32_t kp_link[4];
+};
+
+struct FkArgs {
+    ChainK ch[kMaxArms];
+    CamK cam;
+    int32_t batch, n_arms;
+};
+
+// Weights of the loss composition.
+struct LossArgs {
+    double lambda_app, lambda_kp, tau;
+    int32_t batch, kind, n_arms;
+};
+
 tk_status validate_camera(const tk_camera* cam);
+// Validates n_arms chains and fills a->ch, a->n_arms (and a->cam when cam is given).
+tk_status make_fk_args(const tk_chain* chains, int32_t n_arms, const tk_camera* cam, FkArgs* a);
+// Validates the loss-composition arguments and fills *la.
+tk_status make_loss_args(int32_t batch, int32_t kind, double lambda_app, const float* d_kp, const float* d_kp_ref,
+                         int32_t n_arms, double lambda_kp, double tau, LossArgs* la);
 tk_status validate_meshes(const tk_mesh* meshes, int32_t n_meshes, MeshSet* out);
 
 }  // namespace tk

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtk.so")
 
 TK_OK = 0
+TK_ERR_INVALID_ARGUMENT, TK_ERR_UNSUPPORTED, TK_ERR_WORKSPACE_TOO_SMALL, TK_ERR_DEVICE = 1, 2, 3, 4
 STATUS_NAMES = {0: "TK_OK", 1: "TK_ERR_INVALID_ARGUMENT", 2: "TK_ERR_UNSUPPORTED",
                 3: "TK_ERR_WORKSPACE_TOO_SMALL", 4: "TK_ERR_DEVICE"}
 
@@ -63,7 +64,7 @@ EXPORTS = [
     "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_set_mean", "tk_cmaes_sample",
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
-    "tk_raster_workspace_bytes",
+    "tk_raster_workspace_bytes", "tk_cmaes_tell_ask",
 ]
 
 _lib = None
@@ -100,6 +101,7 @@ def lib():
         L.tk_eval_fused.argtypes = [P, i32, P, i32, P, P, P, P, ctypes.c_size_t, P]
         L.tk_compose_loss.argtypes = [P, i32, P, i32, f64, P, P, i32, f64, f64, P, P]
         L.tk_raster_stats.argtypes = [P, i32, P, i32, P, P, P]
+        L.tk_cmaes_tell_ask.argtypes = [P, i32, i32, P, P, i32, f64, P, P, f64, f64, P, P, i32, P, P, P, P, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
                             "tk_raster_workspace_bytes"):
@@ -212,6 +214,20 @@ def cmaes_sample(state, n, lam, X, stream=None):
 
 def cmaes_update(state, n, lam, loss, stream=None):
     _check(lib().tk_cmaes_update(_ptr(state), n, lam, _ptr(loss), _stream(stream)))
+
+
+def cmaes_tell_ask(state, n, lam, counts, target_count, kind, chains, cam, X, link_xf, kp=None, kp_ref=None,
+                   lambda_app=1.0, lambda_kp=0.0, tau=0.0, loss=None, kp_next=None, stream=None):
+    """One fused generation step: compose the losses from the counts (and
+    keypoints), update the state, sample the next candidates into X and
+    evaluate their forward kinematics into link_xf (and kp_next)."""
+    n_arms = len(chains)
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    c = camera(cam)
+    _check(lib().tk_cmaes_tell_ask(_ptr(state), n, lam, _ptr(counts), _ptr(target_count), int(kind),
+                                   float(lambda_app), _ptr(kp), _ptr(kp_ref), float(lambda_kp), float(tau),
+                                   _ptr(loss), ch, n_arms, ctypes.byref(c), _ptr(X), _ptr(link_xf), _ptr(kp_next),
+                                   _stream(stream)))
 
 
 def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:

@@ -1,15 +1,22 @@
 """Generation driver: device buffers and launch sequence of one CMA-ES generation.
 
-One generation (paper Sec. III-A.1 and Fig. 2: sample candidates, evaluate them
-in parallel through batched forward kinematics and rendering, rank, update):
+One generation (paper Sec. III-A.1: sample candidates, evaluate them in
+parallel through batched forward kinematics and rendering, rank, update):
 
     tk_cmaes_sample -> tk_fk_transform -> tk_eval_fused -> tk_compose_loss
-    -> tk_cmaes_update
+    -> tk_cmaes_update                                         (step)
 
-All five are HIP kernels of libtk queued on one stream; `capture()` records the
-sequence once into a HIP graph (torch.cuda.CUDAGraph on ROCm) and `replay()`
-launches a whole generation with one call.  `step_plain()` is the unbatched
-baseline: the same kernels with batch = 1, looped over the candidates.
+or, fused into two launches per generation once the first candidates have
+been drawn (ask), with identical results:
+
+    tk_eval_fused -> tk_cmaes_tell_ask                         (tell_ask)
+
+where tell-ask composes the losses, updates the state, samples the next
+generation and evaluates its forward kinematics.  All are HIP kernels of libtk
+queued on one stream; `capture()` records a generation once into a HIP graph
+(torch.cuda.CUDAGraph on ROCm) and `replay()` launches it with one call.
+`step_plain()` is the unbatched baseline: the same kernels with batch = 1,
+looped over the candidates.
 """
 from __future__ import annotations
 
@@ -103,6 +110,24 @@ class Generation:
         self.evaluate()
         tk.cmaes_update(self.state, self.n, self.lam, self.loss)
 
+    def ask(self):
+        """Draw the first generation after init() and evaluate its forward kinematics."""
+        p = self.p
+        tk.cmaes_sample(self.state, self.n, self.lam, self.X)
+        tk.fk_transform(self.X, self.lam, p.n_arms, p.chains, self.xf, self.kp if self.use_kp else None,
+                        p.cam if self.use_kp else None)
+
+    def tell_ask(self):
+        """Evaluate the current candidates (raster + counts), then one fused launch:
+        losses, update, the next candidates and their forward kinematics."""
+        p = self.p
+        tk.eval_fused(self.xf, self.lam, p.meshes, p.cam, p.target, self.counts, self.ws)
+        kp = self.kp if self.use_kp else None
+        tk.cmaes_tell_ask(self.state, self.n, self.lam, self.counts, p.target_count, self.loss_kind, p.chains,
+                          p.cam, self.X, self.xf, kp=kp, kp_ref=p.kp_ref if self.use_kp else None,
+                          lambda_app=self.lambda_app, lambda_kp=self.lambda_kp, tau=self.tau, loss=self.loss,
+                          kp_next=kp)
+
     def step_plain(self):
         """Unbatched baseline: the same kernels launched once per candidate (batch = 1)."""
         p = self.p
@@ -117,16 +142,18 @@ class Generation:
                             p.kp_ref if self.use_kp else None, p.n_arms, self.lambda_kp, self.tau)
         tk.cmaes_update(self.state, self.n, self.lam, self.loss)
 
-    def capture(self):
-        """Record one generation into a HIP graph (replayed by replay())."""
+    def capture(self, fused=True):
+        """Record one generation (tell_ask(), or step() with fused=False) into a
+        HIP graph, replayed by replay()."""
+        run = self.tell_ask if fused else self.step
         s = torch.cuda.Stream(device=self.p.device)
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.step()          # warm-up outside the graph on the side stream
+            run()                # warm-up outside the graph on the side stream
         torch.cuda.current_stream().wait_stream(s)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.step()
+            run()
         return self.graph
 
     def replay(self):

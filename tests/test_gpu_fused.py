@@ -1,0 +1,80 @@
+"""The fused tell-ask launch (tk_cmaes_tell_ask) against the separate calls it
+replaces -- tk_compose_loss, tk_cmaes_update, tk_cmaes_sample and
+tk_fk_transform -- generation after generation: losses, state blob,
+candidates, link transforms and keypoints must agree bit for bit (one arm with
+the keypoint term, one arm with the render loss, two arms with a
+block-diagonal covariance)."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from paper_2603_11404_amd import tk, tracker
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(t):
+    return t.contiguous().view(torch.uint8)
+
+
+def _setup(n_arms, lam, kind, lambda_kp, seed=7):
+    dev = torch.device("cuda:0")
+    wl = scenes.workload("small")
+    cam = wl["cam"]
+    meshes = [wl["mesh"], scenes.instrument_mesh(32, 28, 3, 1, jaw_scale=1.3, box_scale=1.2)][:n_arms]
+    chains = [scenes.chain(), scenes.chain(jaw_scale=1.3)][:n_arms]
+    prob = tracker.Problem(meshes, chains, cam, dev)
+    rng = scenes.rng_for(0, scenes.SUB_POSE)
+    truth = np.concatenate([scenes.true_pose(rng, cam) for _ in range(n_arms)]).astype(np.float32)
+    th = torch.as_tensor(truth[None], device=dev)
+    prob.set_target(prob.render(th)[0], prob.keypoints(th)[0])
+    scale = np.tile(scenes.DEFAULT_SCALE, n_arms)
+    mean0 = truth + scale * rng.normal(size=9 * n_arms)
+    gens = []
+    for _ in range(2):
+        g = tracker.Generation(prob, lam, loss_kind=kind, lambda_kp=lambda_kp)
+        g.init(np.zeros(9 * n_arms), 1.0, mean0, scale, seed)
+        g.ask()
+        gens.append(g)
+    return prob, gens
+
+
+@pytest.mark.parametrize("n_arms,lam,kind,lambda_kp", [
+    (1, 16, tk.LOSS_IOU, 0.1),
+    (1, 64, tk.LOSS_RENDER, 0.0),
+    (2, 32, tk.LOSS_IOU, 0.1),
+])
+def test_tell_ask_matches_separate_calls(n_arms, lam, kind, lambda_kp):
+    prob, (a, b) = _setup(n_arms, lam, kind, lambda_kp)
+    use_kp = lambda_kp != 0.0
+    for gen in range(6):
+        # separate calls
+        tk.eval_fused(a.xf, a.lam, prob.meshes, prob.cam, prob.target, a.counts, a.ws)
+        tk.compose_loss(a.counts, a.lam, prob.target_count, kind, a.loss, a.lambda_app,
+                        a.kp if use_kp else None, prob.kp_ref if use_kp else None, n_arms, lambda_kp, a.tau)
+        tk.cmaes_update(a.state, a.n, a.lam, a.loss)
+        a.ask()
+        # fused
+        b.tell_ask()
+        torch.cuda.synchronize()
+        assert torch.equal(a.counts, b.counts), gen
+        assert torch.equal(_bits(a.loss), _bits(b.loss)), gen
+        assert torch.equal(_bits(a.state), _bits(b.state)), gen
+        assert torch.equal(_bits(a.X), _bits(b.X)), gen
+        assert torch.equal(_bits(a.xf), _bits(b.xf)), gen
+        if use_kp:
+            assert torch.equal(_bits(a.kp), _bits(b.kp)), gen
+
+
+def test_tell_ask_argument_errors():
+    prob, (a, _) = _setup(1, 16, tk.LOSS_IOU, 0.0)
+    with pytest.raises(tk.TkError) as e:   # n must be 9 x n_arms
+        tk.cmaes_tell_ask(a.state, a.n, a.lam, a.counts, prob.target_count, tk.LOSS_IOU, prob.chains * 2, prob.cam,
+                          a.X, a.xf)
+    assert e.value.status == tk.TK_ERR_INVALID_ARGUMENT
+    with pytest.raises(tk.TkError):        # keypoints without reference
+        tk.cmaes_tell_ask(a.state, a.n, a.lam, a.counts, prob.target_count, tk.LOSS_IOU, prob.chains, prob.cam,
+                          a.X, a.xf, kp=a.kp)
+    with pytest.raises(tk.TkError):        # bad loss kind
+        tk.cmaes_tell_ask(a.state, a.n, a.lam, a.counts, prob.target_count, 7, prob.chains, prob.cam, a.X, a.xf)
