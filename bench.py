@@ -120,12 +120,20 @@ def main():
         mean_phys = state["est"].copy()
         mean_phys[6:9] = readings[f]                  # joint readings initialise the joint means
         gen.init(np.zeros(9), 1.0, mean_phys, scale, seed0 + f)
-        gen.ask()                                     # first candidates of the frame and their FK
         state["frame"] = f
 
-    def run_step(s, events=None):
-        """One generation: raster + counts of the current candidates, then one fused
-        launch for the losses, the CMA-ES update, the next candidates and their FK."""
+    def ask_eval():
+        tk.cmaes_ask_eval(gen.state, gen.n, gen.lam, prob.chains, prob.meshes, cam, prob.target, gen.X, gen.xf,
+                          gen.counts, kp=gen.kp, ws=gen.ws)
+
+    def tell():
+        tk.cmaes_tell(gen.state, gen.n, gen.lam, gen.counts, prob.target_count, tk.LOSS_IOU, 1, kp=gen.kp,
+                      kp_ref=prob.kp_ref, lambda_kp=0.1, loss=gen.loss)
+
+    def run_step(s, events=None, between=None):
+        """One generation in two launches: draw the candidates, evaluate their FK
+        and raster counts (one workgroup per candidate); then compose the losses
+        and update CMA-ES."""
         f, g = (s // G) % F, s % G
         if g == 0:
             if state["frame"] >= 0:
@@ -133,12 +141,12 @@ def main():
             start_frame(f)
         if events is not None:
             events[0].record()
-        tk.eval_fused(gen.xf, gen.lam, prob.meshes, cam, prob.target, gen.counts, gen.ws)
+        ask_eval()
         if events is not None:
             events[1].record()
-        tk.cmaes_tell_ask(gen.state, gen.n, gen.lam, gen.counts, prob.target_count, tk.LOSS_IOU, prob.chains, cam,
-                          gen.X, gen.xf, kp=gen.kp, kp_ref=prob.kp_ref, lambda_kp=0.1, loss=gen.loss,
-                          kp_next=gen.kp)
+        if between is not None:
+            between()
+        tell()
 
     # ---------------------------------------------------------------- warm-up and timed region
     for s in range(args.warmup):
@@ -166,7 +174,7 @@ def main():
     fused_ms = np.array([a.elapsed_time(b) for a, b in evs])
     final_est = gen.mean()
     log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events; "
-        f"fused raster avg {fused_ms.mean() * 1e3:.1f} us over {len(fused_ms)} sampled launches")
+        f"ask-eval avg {fused_ms.mean() * 1e3:.1f} us over {len(fused_ms)} sampled launches")
 
     # pose error of the last estimate against the truth of its frame
     last_f = ((args.warmup + args.steps - 1) // G) % F
@@ -179,15 +187,9 @@ def main():
     state["frame"] = -1
     state["est"] = est0.copy()
     for s in range(2 * G):
-        f, g = (s // G) % F, s % G
-        if g == 0:
-            if state["frame"] >= 0:
-                state["est"] = gen.mean()
-            start_frame(f)
-        tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats)
+        run_step(s, between=lambda: tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats))
         acc += stats.cpu().numpy()
         n_st += 1
-        run_step(s)
     kept, box_px, pairs, huge = acc / n_st
     tri_all = lam * mesh.n_triangles
     vert_all = lam * mesh.n_vertices
@@ -219,7 +221,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
                      "frac": achieved / peak_ops, "traffic": raster_traffic(),
                      "traffic_unit": "B per launch",
-                     "kernel": "raster_kernel<true,false,true,1024> (tk_eval_fused with workspace)",
+                     "kernel": "raster_kernel<true,false,true,1024> (tk_cmaes_ask_eval: draw, FK, raster, "
+                               "counts; with workspace)",
                      "kernel_us": float(fused_ms.mean() * 1e3),
                      "ops_per_launch": ops, "units_per_launch": {"vertices": vert_all, "triangles": tri_all,
                                                                  "kept": kept,

@@ -145,6 +145,16 @@ tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, 
  * d_loss: device FP64 [lambda]. */
 tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double* d_loss, tk_stream s);
 
+/* Loss composition and update in one launch ("tell"), identical to
+ *   tk_compose_loss(d_counts, lambda, d_target_count, kind, lambda_app, d_kp,
+ *                   d_kp_ref, n_arms, lambda_kp, tau, d_loss)
+ *   tk_cmaes_update(d_state, n, lambda, d_loss)
+ * (Eq. (3)-(4), (5)-(8)).  d_loss (FP64 [lambda]) is an optional output. */
+tk_status tk_cmaes_tell(void* d_state, int32_t n, int32_t lambda, const int32_t* d_counts,
+                        const int32_t* d_target_count, int32_t kind, double lambda_app, const float* d_kp,
+                        const float* d_kp_ref, int32_t n_arms, double lambda_kp, double tau, double* d_loss,
+                        tk_stream s);
+
 /* Fused generation step ("tell" the losses of the evaluated candidates, "ask"
  * for the next ones) in one launch, with results identical to the sequence
  *   tk_compose_loss(d_counts, lambda, d_target_count, kind, lambda_app, d_kp,
@@ -216,6 +226,20 @@ tk_status tk_mask_popcount(const uint64_t* d_masks, int32_t batch, const tk_came
 tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
                         const tk_camera* cam, const uint64_t* d_target, int32_t* d_counts, void* d_ws,
                         size_t ws_bytes, tk_stream s);
+
+/* Sampling and evaluation of a whole generation in one launch ("ask" and
+ * evaluate), one workgroup per candidate, identical to
+ *   tk_cmaes_sample(d_state, n, lambda, d_X)
+ *   tk_fk_transform(d_X, lambda, n_arms, chains, d_link_xf, d_kp, cam)
+ *   tk_eval_fused(d_link_xf, lambda, meshes, n_arms, cam, d_target, d_counts,
+ *                 d_ws, ws_bytes)
+ * (Eq. (3)-(4) sampling, Sec. III-A.3, Eq. (7), Eq. (6) counts).  n must be
+ * 9 * n_arms, one mesh per arm; d_kp (nullable) receives the keypoints;
+ * workspace as for tk_eval_fused. */
+tk_status tk_cmaes_ask_eval(void* d_state, int32_t n, int32_t lambda, const tk_chain* chains, int32_t n_arms,
+                            const tk_mesh* meshes, const tk_camera* cam, const uint64_t* d_target, float* d_X,
+                            float* d_link_xf, float* d_kp, int32_t* d_counts, void* d_ws, size_t ws_bytes,
+                            tk_stream s);
 
 /* Workload statistics of a raster launch over the same inputs (for
  * measurement, not on the hot path): d_stats[4] uint64 = {triangles kept,

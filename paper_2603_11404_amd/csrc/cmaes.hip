@@ -9,60 +9,10 @@
 #include <cstring>
 
 #include "fitness_device.h"
+#include "sample_device.h"
 
 namespace tk {
 namespace {
-
-constexpr double kPi = 3.14159265358979323846;
-
-// ---------------------------------------------------------------- Philox4x32-10
-
-struct U4 { uint32_t x, y, z, w; };
-
-__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; r++) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        uint64_t p0 = uint64_t(0xD2511F53u) * c.x;
-        uint64_t p1 = uint64_t(0xCD9E8D57u) * c.z;
-        U4 o;
-        o.x = uint32_t(p1 >> 32) ^ c.y ^ k0;
-        o.y = uint32_t(p1);
-        o.z = uint32_t(p0 >> 32) ^ c.w ^ k1;
-        o.w = uint32_t(p0);
-        c = o;
-    }
-    return c;
-}
-
-__device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
-    const double u1 = (double(a) + 0.5) * 0x1p-32;
-    const double u2 = (double(b) + 0.5) * 0x1p-32;
-    const double r = sqrt(-2.0 * log(u1));
-    const double t = (2.0 * kPi) * u2;
-    *z0 = r * cos(t);
-    *z1 = r * sin(t);
-}
-
-// Normals 4j .. 4j + 3 of candidate k in generation g: one Philox block with
-// counter (j, k, g, 0), two Box-Muller pairs.
-__device__ inline void draw_normals(uint32_t key0, uint32_t key1, uint32_t g, int k, int j, double z[4]) {
-    const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
-    box_muller(r.x, r.y, &z[0], &z[1]);
-    box_muller(r.z, r.w, &z[2], &z[3]);
-}
-
-// y_i = sum_j (B D)_ij z_j, x_i = m_i + sigma y_i, theta_i = offset_i + scale_i x_i (FP32)
-__device__ inline float candidate_coord(const double* BD, const double* z, int n, int i, double mean_i, double sigma,
-                                        double offset_i, double scale_i, double* y_out) {
-    double y = 0.0;
-    for (int j = 0; j < n; j++) y += BD[i * n + j] * z[j];
-    *y_out = y;
-    const double x = mean_i + sigma * y;
-    return float(offset_i + scale_i * x);
-}
 
 // ---------------------------------------------------------------- init
 
@@ -268,8 +218,9 @@ struct TellAskArgs {
 };
 
 // AS / VS: Jacobi entries per lane (upper-triangle / all within-block entries
-// over 64 lanes); NT: threads of the workgroup; FUSED: tell-ask form.
-template <int AS, int VS, int NT, bool FUSED>
+// over 64 lanes); NT: threads of the workgroup; COMPOSE: losses composed from
+// counts (tell); ASK: the next generation drawn at the end (tell-ask).
+template <int AS, int VS, int NT, bool COMPOSE, bool ASK>
 __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam, const double* __restrict__ loss,
                                                           TellAskArgs ta) {
     extern __shared__ double s_elite[];  // [mu][n]
@@ -295,7 +246,7 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
     // 0. stage losses and state
     for (int k = tid; k < lam; k += NT) {
         double v;
-        if (FUSED) {
+        if (COMPOSE) {
             v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
                                  ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
             if (ta.loss) ta.loss[k] = v;
@@ -655,7 +606,7 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
             s_B[e] = Vcur[e];
         }
     }
-    if (!FUSED) return;
+    if (!ASK) return;
 
     // 7. (tell-ask form) the next generation: the same draws and arithmetic as
     //    the sample kernel (z by Philox + Box-Muller with the incremented
@@ -789,13 +740,40 @@ tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double
     TellAskArgs none;
     std::memset(&none, 0, sizeof none);
     if (n <= 9) {
-        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, false>), dim3(1), dim3(1024), lds,
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, false, false>), dim3(1), dim3(1024), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss, none);
     } else {
-        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, false>), dim3(1), dim3(512), lds,
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, false, false>), dim3(1), dim3(512), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, d_loss, none);
     }
     return check_launch("tk_cmaes_update");
+}
+
+tk_status tk_cmaes_tell(void* d_state, int32_t n, int32_t lambda, const int32_t* d_counts,
+                        const int32_t* d_target_count, int32_t kind, double lambda_app, const float* d_kp,
+                        const float* d_kp_ref, int32_t n_arms, double lambda_kp, double tau, double* d_loss,
+                        tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(d_counts && d_target_count, "counts / target_count is NULL");
+    TellAskArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    if (tk_status st = make_loss_args(lambda, kind, lambda_app, d_kp, d_kp_ref, n_arms, lambda_kp, tau, &ta.la))
+        return st;
+    ta.counts = d_counts;
+    ta.target_count = d_target_count;
+    ta.kp = d_kp;
+    ta.kp_ref = d_kp_ref;
+    ta.loss = d_loss;
+    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    if (n <= 9) {
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true, false>), dim3(1), dim3(1024), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
+    } else {
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, true, false>), dim3(1), dim3(512), lds,
+                           reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
+    }
+    return check_launch("tk_cmaes_tell");
 }
 
 tk_status tk_cmaes_tell_ask(void* d_state, int32_t n, int32_t lambda, const int32_t* d_counts,
@@ -824,10 +802,10 @@ tk_status tk_cmaes_tell_ask(void* d_state, int32_t n, int32_t lambda, const int3
     ta.kp_next = d_kp_next;
     const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
     if (n <= 9) {
-        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true>), dim3(1), dim3(1024), lds,
+        hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true, true>), dim3(1), dim3(1024), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
     } else {
-        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, true>), dim3(1), dim3(512), lds,
+        hipLaunchKernelGGL((cmaes_update_kernel<3, 6, 512, true, true>), dim3(1), dim3(512), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
     }
     return check_launch("tk_cmaes_tell_ask");

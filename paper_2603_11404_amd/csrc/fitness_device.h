@@ -27,50 +27,86 @@ __device__ __forceinline__ float decode_joint(float qh, float lb, float ub) {
     return lb + (ub - lb) * 0.5f * (1.0f - cosf(kPiF * (qh - lb) / (ub - lb)));
 }
 
-// Forward kinematics of one candidate and arm in FP32 (Sec. III-A.3 and the
-// renderer input T_r^c T_m^r(q) of Sec. III-A.2): th = (alpha, beta, gamma,
-// x, y, z, qhat1..3) -> M_l = T_r^c T_l(q) for the shaft, wrist and two jaws
-// (out[4][12], 3x4 row-major) and, when kp is not NULL, the four chain
-// keypoints projected by the pinhole camera (NaN behind the near plane).
-__device__ __forceinline__ void fk_candidate(const float* __restrict__ th, const ChainK& ch, const CamK& cam,
-                                             float* __restrict__ out, float* __restrict__ kp) {
+// Forward kinematics in FP32 (Sec. III-A.3 and the renderer input
+// T_r^c T_m^r(q) of Sec. III-A.2), in three pieces so that lanes can share
+// the work of one candidate and still compute every output with the same
+// operations: the pose T_r^c and joint angles, one link transform
+// M_l = T_r^c T_l(q) (shaft, wrist, jaw+, jaw-), one projected keypoint.
+struct FkPose {
+    float T[12];   // T_r^c, 3x4 row-major
+    float q[3];    // decoded joint angles
+    float s1, c1;  // sin, cos of q1
+};
+
+__device__ __forceinline__ void fk_pose(const float* __restrict__ th, const ChainK& ch, FkPose& P) {
     float sa, ca, sb, cb, sg, cg;
     sincosf(th[0], &sa, &ca);
     sincosf(th[1], &sb, &cb);
     sincosf(th[2], &sg, &cg);
     // R = Ry(gamma) Rx(alpha) Rz(beta)
     const float RyRx[9] = {cg, sg * sa, sg * ca, 0.0f, ca, -sa, -sg, cg * sa, cg * ca};
-    float T[12];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        T[4 * i + 0] = RyRx[3 * i + 0] * cb + RyRx[3 * i + 1] * sb;
-        T[4 * i + 1] = -RyRx[3 * i + 0] * sb + RyRx[3 * i + 1] * cb;
-        T[4 * i + 2] = RyRx[3 * i + 2];
+        P.T[4 * i + 0] = RyRx[3 * i + 0] * cb + RyRx[3 * i + 1] * sb;
+        P.T[4 * i + 1] = -RyRx[3 * i + 0] * sb + RyRx[3 * i + 1] * cb;
+        P.T[4 * i + 2] = RyRx[3 * i + 2];
     }
-    T[3] = th[3];
-    T[7] = th[4];
-    T[11] = th[5];
-    float q[3];
+    P.T[3] = th[3];
+    P.T[7] = th[4];
+    P.T[11] = th[5];
 #pragma unroll
-    for (int j = 0; j < 3; j++) q[j] = decode_joint(th[6 + j], ch.lb[j], ch.ub[j]);
-    float s1, c1;
-    sincosf(q[0], &s1, &c1);
-    const float pitch[12] = {1, 0, 0, 0, 0, c1, -s1, 0, 0, s1, c1, 0};
-    float M[4][12];
+    for (int j = 0; j < 3; j++) P.q[j] = decode_joint(th[6 + j], ch.lb[j], ch.ub[j]);
+    sincosf(P.q[0], &P.s1, &P.c1);
+}
+
+// Link l: 0 shaft (T_0 = I), 1 wrist Rx(q1), 2 / 3 jaws Rx(q1) Tr(0, 0, d) Ry(q2 +- q3 / 2).
+__device__ __forceinline__ void fk_link(int l, const FkPose& P, const ChainK& ch, float* __restrict__ M) {
+    const float s1 = P.s1, c1 = P.c1;
+    if (l == 0) {
 #pragma unroll
-    for (int e = 0; e < 12; e++) M[0][e] = T[e];             // shaft: T_0 = I
-    aff_mul(T, pitch, M[1]);                                   // wrist: Rx(q1)
-    const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * ch.d, 0, s1, c1, c1 * ch.d};
-    float TY[12];
-    aff_mul(T, yaw_origin, TY);                                // Rx(q1) Tr(0, 0, d)
-#pragma unroll
-    for (int side = 0; side < 2; side++) {                     // jaws: ... Ry(q2 +- q3 / 2)
-        const float phi = side == 0 ? q[1] + 0.5f * q[2] : q[1] - 0.5f * q[2];
+        for (int e = 0; e < 12; e++) M[e] = P.T[e];
+    } else if (l == 1) {
+        const float pitch[12] = {1, 0, 0, 0, 0, c1, -s1, 0, 0, s1, c1, 0};
+        aff_mul(P.T, pitch, M);
+    } else {
+        const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * ch.d, 0, s1, c1, c1 * ch.d};
+        float TY[12];
+        aff_mul(P.T, yaw_origin, TY);
+        const float phi = l == 2 ? P.q[1] + 0.5f * P.q[2] : P.q[1] - 0.5f * P.q[2];
         float sp, cp;
         sincosf(phi, &sp, &cp);
         const float ry[12] = {cp, 0, sp, 0, 0, 1, 0, 0, -sp, 0, cp, 0};
-        aff_mul(TY, ry, M[2 + side]);
+        aff_mul(TY, ry, M);
     }
+}
+
+// Keypoint j of the chain, given the transform M of its link: pinhole
+// projection, NaN behind the near plane.
+__device__ __forceinline__ void fk_keypoint(const float* __restrict__ M, const ChainK& ch, int j, const CamK& cam,
+                                            float* __restrict__ kp2) {
+    const float vx = ch.kp[j][0], vy = ch.kp[j][1], vz = ch.kp[j][2];
+    const float Xc = M[0] * vx + M[1] * vy + M[2] * vz + M[3];
+    const float Yc = M[4] * vx + M[5] * vy + M[6] * vz + M[7];
+    const float Zc = M[8] * vx + M[9] * vy + M[10] * vz + M[11];
+    if (!(Zc >= cam.z_near)) {
+        kp2[0] = NAN;
+        kp2[1] = NAN;
+    } else {
+        kp2[0] = cam.fx * (Xc / Zc) + cam.cx;
+        kp2[1] = cam.fy * (Yc / Zc) + cam.cy;
+    }
+}
+
+// Whole forward kinematics of one candidate and arm: th = (alpha, beta,
+// gamma, x, y, z, qhat1..3) -> out[4][12], and the four keypoints into kp
+// (when not NULL).
+__device__ __forceinline__ void fk_candidate(const float* __restrict__ th, const ChainK& ch, const CamK& cam,
+                                             float* __restrict__ out, float* __restrict__ kp) {
+    FkPose P;
+    fk_pose(th, ch, P);
+    float M[4][12];
+#pragma unroll
+    for (int l = 0; l < 4; l++) fk_link(l, P, ch, M[l]);
 #pragma unroll
     for (int l = 0; l < 4; l++)
 #pragma unroll
@@ -83,17 +119,7 @@ __device__ __forceinline__ void fk_candidate(const float* __restrict__ th, const
 #pragma unroll
             for (int e = 0; e < 12; e++)
                 m[e] = link == 0 ? M[0][e] : link == 1 ? M[1][e] : link == 2 ? M[2][e] : M[3][e];
-            const float vx = ch.kp[j][0], vy = ch.kp[j][1], vz = ch.kp[j][2];
-            const float Xc = m[0] * vx + m[1] * vy + m[2] * vz + m[3];
-            const float Yc = m[4] * vx + m[5] * vy + m[6] * vz + m[7];
-            const float Zc = m[8] * vx + m[9] * vy + m[10] * vz + m[11];
-            if (!(Zc >= cam.z_near)) {
-                kp[2 * j] = NAN;
-                kp[2 * j + 1] = NAN;
-            } else {
-                kp[2 * j] = cam.fx * (Xc / Zc) + cam.cx;
-                kp[2 * j + 1] = cam.fy * (Yc / Zc) + cam.cy;
-            }
+            fk_keypoint(m, ch, j, cam, kp + 2 * j);
         }
     }
 }

@@ -23,7 +23,8 @@
 #include <cstring>
 #include <mutex>
 
-#include "tk_internal.h"
+#include "fitness_device.h"
+#include "sample_device.h"
 
 namespace tk {
 namespace {
@@ -139,6 +140,13 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
     r.flags = (wide ? kWide : 0) | (near ? kNear : 0);
     r.pad = 0;
     return true;
+}
+
+// Orders this wave's LDS writes before its later LDS reads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- per-wave task queues in LDS
@@ -418,12 +426,6 @@ __device__ __forceinline__ int run_round(const int4* __restrict__ qa, const int4
     return __builtin_amdgcn_readlane(next, kWave - 1);
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------- main kernel
 
 struct RasterArgs {
@@ -436,7 +438,63 @@ struct RasterArgs {
     int32_t* counts;             // [batch][2]
     int32_t batch;
     int32_t pretransform;        // snapped points to a workspace the kernel fills first
+    // ask-eval form: each workgroup first draws its CMA-ES candidate and
+    // evaluates its forward kinematics (link transforms written to link_xf_out)
+    int32_t ask;
+    int32_t n, lam;
+    void* state;
+    FkArgs fk;
+    float* X;                    // [batch][n]
+    float* link_xf_out;          // [batch][n_meshes][4][12]
+    float* kp;                   // nullable [batch][n_meshes][4][2]
 };
+
+// Ask-eval prologue, run by wave 0 of workgroup b: candidate b of the current
+// generation is drawn exactly as the sample kernel draws it (same generator,
+// same B D product and arithmetic), written to X and the state's Z and Y, and
+// its forward kinematics (same device function as the FK kernel) goes to the
+// LDS transforms s_M and to link_xf_out / kp.  scratch: >= 2.9 KB of LDS.
+__device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
+    const int n = a.n;
+    StateView S = state_view(a.state, n, a.lam);
+    double* s_BD = reinterpret_cast<double*>(scratch);              // [n][n]
+    double* s_z = s_BD + kMaxN * kMaxN;                              // [n + 3]
+    float* s_X = reinterpret_cast<float*>(s_z + kMaxN + 3);         // [n]
+    const uint32_t gen = uint32_t(S.hdr->gen);
+    const uint64_t seed = S.hdr->seed;
+    const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
+    const int groups = (n + 3) / 4;
+    for (int e = lane; e < n * n; e += kWave) s_BD[e] = S.B[e] * S.D[e % n];
+    if (lane < 2 * groups) draw_normal_pair(key0, key1, gen, b, lane >> 1, lane & 1, s_z + 2 * lane);
+    wave_sync();
+    if (lane < n) {
+        double y;
+        const float x = candidate_coord(s_BD, s_z, n, lane, S.mean[lane], *S.sigma, S.offset[lane], S.scale[lane], &y);
+        S.Z[size_t(b) * n + lane] = s_z[lane];
+        S.Y[size_t(b) * n + lane] = y;
+        a.X[size_t(b) * n + lane] = x;
+        s_X[lane] = x;
+    }
+    wave_sync();
+    // forward kinematics spread over lanes: (arm, link) on lanes 0 .. 4 n_arms - 1,
+    // (arm, keypoint) on lanes 8 .. 8 + 4 n_arms - 1
+    const int n_arms = a.fk.n_arms;
+    const int arm = (lane & 7) >> 2, part = lane & 3;
+    if ((lane < 8 && arm < n_arms) || (lane >= 8 && lane < 16 && arm < n_arms && a.kp)) {
+        const ChainK ch = arm == 0 ? a.fk.ch[0] : a.fk.ch[1];
+        FkPose P;
+        fk_pose(s_X + 9 * arm, ch, P);
+        if (lane < 8) {
+            fk_link(part, P, ch, s_M + 48 * arm + 12 * part);
+        } else {
+            float M[12];
+            fk_link(ch.kp_link[part], P, ch, M);
+            fk_keypoint(M, ch, part, a.fk.cam, a.kp + (size_t(b) * n_arms + arm) * 8 + 2 * part);
+        }
+    }
+    wave_sync();
+    for (int e = lane; e < n_arms * 48; e += kWave) a.link_xf_out[size_t(b) * n_arms * 48 + e] = s_M[e];
+}
 
 template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
 __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
@@ -454,9 +512,12 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     WaveQueues& Q = s_queue[wave];
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
-    if (!FROM_SNAPPED || a.pretransform)
+    if (a.ask) {
+        if (wave == 0) ask_candidate(a, b, lane, s_M, reinterpret_cast<char*>(&s_queue[0]));   // queue not in use yet
+    } else if (!FROM_SNAPPED || a.pretransform) {
         for (int i = tid; i < a.meshes.n_meshes * 48; i += NT)
             s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
+    }
     __syncthreads();
     if (FROM_SNAPPED && a.pretransform) {
         // transform, project and snap every vertex of this candidate once into the workspace
@@ -795,6 +856,7 @@ tk_status common_raster_checks(int32_t batch, const tk_mesh* meshes, int32_t n_m
     a->link_xf = nullptr;
     a->snapped = nullptr;
     a->masks = nullptr;
+    a->ask = 0;
     a->target = nullptr;
     a->counts = nullptr;
     a->pretransform = 0;
@@ -867,6 +929,36 @@ tk_status tk_eval_fused(const float* d_link_xf, int32_t batch, const tk_mesh* me
     if (tk_status st = attach_workspace(&a, d_ws, ws_bytes, "tk_eval_fused")) return st;
     if (a.pretransform) return launch_raster<true, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_eval_fused");
     return launch_raster<false, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_eval_fused");
+}
+
+tk_status tk_cmaes_ask_eval(void* d_state, int32_t n, int32_t lambda, const tk_chain* chains, int32_t n_arms,
+                            const tk_mesh* meshes, const tk_camera* cam, const uint64_t* d_target, float* d_X,
+                            float* d_link_xf, float* d_kp, int32_t* d_counts, void* d_ws, size_t ws_bytes,
+                            tk_stream s) {
+    clear_error();
+    TK_REQUIRE(d_state != nullptr && (reinterpret_cast<uintptr_t>(d_state) & 255) == 0,
+               "state must be a 256-byte aligned device pointer");
+    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
+    TK_REQUIRE(n_arms >= 1 && n_arms <= kMaxArms && n == 9 * n_arms, "n = %d must be 9 x n_arms (n_arms = %d)", n,
+               n_arms);
+    RasterArgs a;
+    if (tk_status st = common_raster_checks(lambda, meshes, n_arms, cam, &a)) return st;
+    TK_REQUIRE(d_X && d_link_xf && d_target && d_counts, "X / link_xf / target / counts is NULL");
+    if (tk_status st = make_fk_args(chains, n_arms, cam, &a.fk)) return st;
+    a.fk.batch = lambda;
+    a.ask = 1;
+    a.n = n;
+    a.lam = lambda;
+    a.state = d_state;
+    a.X = d_X;
+    a.link_xf_out = d_link_xf;
+    a.kp = d_kp;
+    a.target = reinterpret_cast<const unsigned long long*>(d_target);
+    a.counts = d_counts;
+    if (tk_status st = attach_workspace(&a, d_ws, ws_bytes, "tk_cmaes_ask_eval")) return st;
+    if (a.pretransform)
+        return launch_raster<true, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_cmaes_ask_eval");
+    return launch_raster<false, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_cmaes_ask_eval");
 }
 
 tk_status tk_snap_vertices(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,

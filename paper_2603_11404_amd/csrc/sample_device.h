@@ -1,0 +1,73 @@
+// Device functions of CMA-ES sampling shared by the sample kernel, the fused
+// tell-ask kernel and the ask-eval raster kernel, so that every path draws
+// identical candidates.  Random numbers: Philox4x32-10 (Salmon et al., SC'11)
+// keyed by the seed with counter (group j, candidate k, generation g, 0),
+// mapped to normals by Box-Muller in FP64.
+#pragma once
+
+#include "tk_internal.h"
+
+namespace tk {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = uint64_t(0xD2511F53u) * c.x;
+        uint64_t p1 = uint64_t(0xCD9E8D57u) * c.z;
+        U4 o;
+        o.x = uint32_t(p1 >> 32) ^ c.y ^ k0;
+        o.y = uint32_t(p1);
+        o.z = uint32_t(p0 >> 32) ^ c.w ^ k1;
+        o.w = uint32_t(p0);
+        c = o;
+    }
+    return c;
+}
+
+__device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
+    const double u1 = (double(a) + 0.5) * 0x1p-32;
+    const double u2 = (double(b) + 0.5) * 0x1p-32;
+    const double r = sqrt(-2.0 * log(u1));
+    const double t = (2.0 * kPi) * u2;
+    *z0 = r * cos(t);
+    *z1 = r * sin(t);
+}
+
+// Normals 4j + 2h, 4j + 2h + 1 (h = 0, 1) of candidate k in generation g:
+// Philox block (j, k, g, 0), its h-th Box-Muller pair.
+__device__ inline void draw_normal_pair(uint32_t key0, uint32_t key1, uint32_t g, int k, int j, int h, double z[2]) {
+    const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
+    if (h == 0)
+        box_muller(r.x, r.y, &z[0], &z[1]);
+    else
+        box_muller(r.z, r.w, &z[0], &z[1]);
+}
+
+// Normals 4j .. 4j + 3 of candidate k in generation g: one Philox block with
+// counter (j, k, g, 0), two Box-Muller pairs.
+__device__ inline void draw_normals(uint32_t key0, uint32_t key1, uint32_t g, int k, int j, double z[4]) {
+    const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
+    box_muller(r.x, r.y, &z[0], &z[1]);
+    box_muller(r.z, r.w, &z[2], &z[3]);
+}
+
+// y_i = sum_j (B D)_ij z_j, x_i = m_i + sigma y_i, theta_i = offset_i + scale_i x_i (FP32)
+__device__ inline float candidate_coord(const double* BD, const double* z, int n, int i, double mean_i, double sigma,
+                                        double offset_i, double scale_i, double* y_out) {
+    double y = 0.0;
+    for (int j = 0; j < n; j++) y += BD[i * n + j] * z[j];
+    *y_out = y;
+    const double x = mean_i + sigma * y;
+    return float(offset_i + scale_i * x);
+}
+
+}  // namespace tk

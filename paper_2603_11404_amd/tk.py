@@ -64,7 +64,7 @@ EXPORTS = [
     "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_set_mean", "tk_cmaes_sample",
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
-    "tk_raster_workspace_bytes", "tk_cmaes_tell_ask",
+    "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
 ]
 
 _lib = None
@@ -102,6 +102,8 @@ def lib():
         L.tk_compose_loss.argtypes = [P, i32, P, i32, f64, P, P, i32, f64, f64, P, P]
         L.tk_raster_stats.argtypes = [P, i32, P, i32, P, P, P]
         L.tk_cmaes_tell_ask.argtypes = [P, i32, i32, P, P, i32, f64, P, P, f64, f64, P, P, i32, P, P, P, P, P]
+        L.tk_cmaes_tell.argtypes = [P, i32, i32, P, P, i32, f64, P, P, i32, f64, f64, P, P]
+        L.tk_cmaes_ask_eval.argtypes = [P, i32, i32, P, i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
                             "tk_raster_workspace_bytes"):
@@ -228,6 +230,25 @@ def cmaes_tell_ask(state, n, lam, counts, target_count, kind, chains, cam, X, li
                                    float(lambda_app), _ptr(kp), _ptr(kp_ref), float(lambda_kp), float(tau),
                                    _ptr(loss), ch, n_arms, ctypes.byref(c), _ptr(X), _ptr(link_xf), _ptr(kp_next),
                                    _stream(stream)))
+
+
+def cmaes_tell(state, n, lam, counts, target_count, kind, n_arms=1, kp=None, kp_ref=None, lambda_app=1.0,
+               lambda_kp=0.0, tau=0.0, loss=None, stream=None):
+    """Compose the losses from the counts (and keypoints) and update the state, in one launch."""
+    _check(lib().tk_cmaes_tell(_ptr(state), n, lam, _ptr(counts), _ptr(target_count), int(kind), float(lambda_app),
+                               _ptr(kp), _ptr(kp_ref), int(n_arms), float(lambda_kp), float(tau), _ptr(loss),
+                               _stream(stream)))
+
+
+def cmaes_ask_eval(state, n, lam, chains, meshes, cam, target, X, link_xf, counts, kp=None, ws=None, stream=None):
+    """Draw the generation's candidates, evaluate their FK and their fused raster counts, in one launch."""
+    n_arms = len(chains)
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    wp, wb = _ws(ws)
+    _check(lib().tk_cmaes_ask_eval(_ptr(state), n, lam, ch, n_arms, arr, ctypes.byref(c), _ptr(target), _ptr(X),
+                                   _ptr(link_xf), _ptr(kp), _ptr(counts), wp, wb, _stream(stream)))
 
 
 def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:

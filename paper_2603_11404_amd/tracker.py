@@ -6,13 +6,14 @@ parallel through batched forward kinematics and rendering, rank, update):
     tk_cmaes_sample -> tk_fk_transform -> tk_eval_fused -> tk_compose_loss
     -> tk_cmaes_update                                         (step)
 
-or, fused into two launches per generation once the first candidates have
-been drawn (ask), with identical results:
+or, fused into two launches per generation with identical results:
 
-    tk_eval_fused -> tk_cmaes_tell_ask                         (tell_ask)
+    tk_cmaes_ask_eval -> tk_cmaes_tell                         (ask_eval_tell)
 
-where tell-ask composes the losses, updates the state, samples the next
-generation and evaluates its forward kinematics.  All are HIP kernels of libtk
+where ask-eval draws the candidates, evaluates their forward kinematics and
+their raster counts (one workgroup per candidate) and tell composes the
+losses and updates the state.  A third form, tk_eval_fused -> tk_cmaes_tell_ask
+(tell_ask, after ask()), draws the next generation inside the update launch.  All are HIP kernels of libtk
 queued on one stream; `capture()` records a generation once into a HIP graph
 (torch.cuda.CUDAGraph on ROCm) and `replay()` launches it with one call.
 `step_plain()` is the unbatched baseline: the same kernels with batch = 1,
@@ -128,6 +129,16 @@ class Generation:
                           lambda_app=self.lambda_app, lambda_kp=self.lambda_kp, tau=self.tau, loss=self.loss,
                           kp_next=kp)
 
+    def ask_eval_tell(self):
+        """One generation in two launches: draw + FK + raster counts, then loss + update."""
+        p = self.p
+        kp = self.kp if self.use_kp else None
+        tk.cmaes_ask_eval(self.state, self.n, self.lam, p.chains, p.meshes, p.cam, p.target, self.X, self.xf,
+                          self.counts, kp=kp, ws=self.ws)
+        tk.cmaes_tell(self.state, self.n, self.lam, self.counts, p.target_count, self.loss_kind, p.n_arms, kp=kp,
+                      kp_ref=p.kp_ref if self.use_kp else None, lambda_app=self.lambda_app,
+                      lambda_kp=self.lambda_kp, tau=self.tau, loss=self.loss)
+
     def step_plain(self):
         """Unbatched baseline: the same kernels launched once per candidate (batch = 1)."""
         p = self.p
@@ -143,9 +154,9 @@ class Generation:
         tk.cmaes_update(self.state, self.n, self.lam, self.loss)
 
     def capture(self, fused=True):
-        """Record one generation (tell_ask(), or step() with fused=False) into a
-        HIP graph, replayed by replay()."""
-        run = self.tell_ask if fused else self.step
+        """Record one generation (ask_eval_tell(), or step() with fused=False)
+        into a HIP graph, replayed by replay()."""
+        run = self.ask_eval_tell if fused else self.step
         s = torch.cuda.Stream(device=self.p.device)
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):

@@ -78,3 +78,52 @@ def test_tell_ask_argument_errors():
                           a.X, a.xf, kp=a.kp)
     with pytest.raises(tk.TkError):        # bad loss kind
         tk.cmaes_tell_ask(a.state, a.n, a.lam, a.counts, prob.target_count, 7, prob.chains, prob.cam, a.X, a.xf)
+
+
+@pytest.mark.parametrize("n_arms,lam,kind,lambda_kp", [
+    (1, 16, tk.LOSS_IOU, 0.1),
+    (1, 64, tk.LOSS_RENDER, 0.0),
+    (2, 32, tk.LOSS_IOU, 0.1),
+])
+def test_ask_eval_and_tell_match_separate_calls(n_arms, lam, kind, lambda_kp):
+    """tk_cmaes_ask_eval = sample + FK + fused raster counts; tk_cmaes_tell =
+    compose + update: same bits as the separate calls, generation after
+    generation (with and without a workspace)."""
+    prob, (a, b) = _setup(n_arms, lam, kind, lambda_kp)
+    use_kp = lambda_kp != 0.0
+    for gen in range(6):
+        ws_b = b.ws if gen % 2 == 0 else None
+        # separate calls (a): sample -> FK -> fused raster -> compose -> update
+        a.ask()
+        tk.eval_fused(a.xf, a.lam, prob.meshes, prob.cam, prob.target, a.counts, a.ws)
+        tk.compose_loss(a.counts, a.lam, prob.target_count, kind, a.loss, a.lambda_app,
+                        a.kp if use_kp else None, prob.kp_ref if use_kp else None, n_arms, lambda_kp, a.tau)
+        # fused (b)
+        kp = b.kp if use_kp else None
+        tk.cmaes_ask_eval(b.state, b.n, b.lam, prob.chains, prob.meshes, prob.cam, prob.target, b.X, b.xf,
+                          b.counts, kp=kp, ws=ws_b)
+        torch.cuda.synchronize()
+        assert torch.equal(_bits(a.state), _bits(b.state)), gen      # Z and Y written by the draws
+        assert torch.equal(_bits(a.X), _bits(b.X)), gen
+        assert torch.equal(_bits(a.xf), _bits(b.xf)), gen
+        if use_kp:
+            assert torch.equal(_bits(a.kp), _bits(b.kp)), gen
+        assert torch.equal(a.counts, b.counts), gen
+        tk.cmaes_update(a.state, a.n, a.lam, a.loss)
+        tk.cmaes_tell(b.state, b.n, b.lam, b.counts, prob.target_count, kind, n_arms, kp=kp,
+                      kp_ref=prob.kp_ref if use_kp else None, lambda_kp=lambda_kp, loss=b.loss)
+        torch.cuda.synchronize()
+        assert torch.equal(_bits(a.loss), _bits(b.loss)), gen
+        assert torch.equal(_bits(a.state), _bits(b.state)), gen
+
+
+def test_ask_eval_argument_errors():
+    prob, (a, _) = _setup(1, 16, tk.LOSS_IOU, 0.0)
+    with pytest.raises(tk.TkError):        # n must be 9 x n_arms
+        tk.cmaes_ask_eval(a.state, a.n, a.lam, prob.chains * 2, prob.meshes * 2, prob.cam, prob.target, a.X, a.xf,
+                          a.counts)
+    small_ws = torch.empty(8, dtype=torch.int64, device=a.ws.device)
+    with pytest.raises(tk.TkError) as e:
+        tk.cmaes_ask_eval(a.state, a.n, a.lam, prob.chains, prob.meshes, prob.cam, prob.target, a.X, a.xf, a.counts,
+                          ws=small_ws)
+    assert e.value.status == tk.TK_ERR_WORKSPACE_TOO_SMALL
