@@ -263,12 +263,62 @@ def main():
         out["graph_ms_per_step"] = graph_ms
         out["plain_ms_per_step"] = plain_ms
         out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
+        out["bimanual960"] = bimanual_leg(dev)
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, mesh, cam, chain, traj, flips, readings, est0, lam)
 
     print(json.dumps(out), flush=True)
+
+
+def bimanual_leg(dev, gens=100):
+    """Bi-manual workload: two uneven instruments (20016 + 35188 triangles),
+    960x540, lambda = 512, 18-D with a block-diagonal covariance, target with
+    an occluding rectangle; generations of two launches (both arms in each),
+    timed eagerly and as a replayed HIP graph."""
+    import torch
+
+    import scenes
+    from paper_2603_11404_amd import tk, tracker
+
+    wl = scenes.workload("bimanual960")
+    cam, lam = wl["cam"], wl["lam"]
+    prob = tracker.Problem(wl["meshes"], wl["chains"], cam, dev)
+    rng = scenes.rng_for(wl["index"], scenes.SUB_POSE)
+    truth = np.concatenate([scenes.true_pose(rng, cam), scenes.true_pose(rng, cam)]).astype(np.float32)
+    words = prob.render(torch.as_tensor(truth[None], device=dev))[0].cpu().numpy().view(np.uint64)
+    img = scenes.words_to_image(words, cam.width, cam.height)
+    rect, _ = scenes.occluder_rect(img, scenes.rng_for(wl["index"], scenes.SUB_OCCLUDER))
+    target = scenes.image_to_words(scenes.apply_occluder(img, rect))
+    prob.set_target(torch.as_tensor(target.view(np.int64), device=dev))
+    gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU, n_blocks=wl["n_blocks"])
+    scale = np.tile(scenes.DEFAULT_SCALE, 2)
+    seed = scenes.BASE_SEED + wl["index"] + 1000 * scenes.SUB_CMAES
+    gen.init(np.zeros(18), 1.0, truth + scale * np.random.default_rng(seed).normal(size=18), scale, seed)
+    for _ in range(5):
+        gen.ask_eval_tell()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(gens):
+        gen.ask_eval_tell()
+    b.record()
+    torch.cuda.synchronize()
+    eager_ms = a.elapsed_time(b) / gens
+    gen.capture()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(gens):
+        gen.replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / gens
+    best = min(eager_ms, graph_ms)
+    log(f"bimanual960: {eager_ms * 1e3:.1f} us per generation eager, {graph_ms * 1e3:.1f} us graph replay")
+    return {"workload": "two instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D block-diagonal, occluder",
+            "ms_per_generation": eager_ms, "graph_ms_per_generation": graph_ms,
+            "candidate_evals_per_s": lam / (best * 1e-3), "generations": gens}
 
 
 def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):

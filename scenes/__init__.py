@@ -376,12 +376,17 @@ def apply_occluder(img: np.ndarray, rect) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def workload(name: str) -> dict:
-    """Shapes of the named synthetic workloads (see the parameter table in the
-    design notes): returns mesh/camera/lambda/generation counts."""
+    """Shapes of the named synthetic workloads: meshes, chains, camera, lambda,
+    generations per frame, frames, workload index (seed offset) and the number
+    of diagonal covariance blocks."""
     if name == "small":          # 2k tris, 320x240, f=400, lambda=16, 20 gens
         return dict(mesh=instrument_mesh(32, 28, 3, 1), cam=camera(320, 240, 400.0),
                     lam=16, gens=20, frames=1, index=0)
     if name == "track640":       # 20k tris, 640x480, lambda=256, 30 gens x 100 frames
         return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(640, 480),
                     lam=256, gens=30, frames=100, index=1)
+    if name == "bimanual960":    # two uneven instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D
+        meshes = [instrument_mesh(64, 150, 6, 4), instrument_mesh(100, 170, 7, 5, jaw_scale=1.3, box_scale=1.2)]
+        return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),
+                    lam=512, gens=30, frames=1, index=2, n_blocks=2)
     raise KeyError(name)
