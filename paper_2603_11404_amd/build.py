@@ -28,7 +28,27 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-result",
+    "-Rpass-analysis=kernel-resource-usage",   # per-kernel register / scratch report, checked below
 ]
+
+
+def resource_problems(diagnostics: str) -> list[str]:
+    """Kernels whose resource report shows private (scratch) memory or vector
+    register spills: every kernel of the library is meant to live in registers
+    and LDS (scalar spills go to vector-register lanes and are allowed)."""
+    bad, name = [], None
+    for line in diagnostics.splitlines():
+        if "remark:" not in line:
+            continue
+        text = line.split("remark:", 1)[1].strip()
+        if text.startswith("Function Name:"):
+            name = text.split(":", 1)[1].split("[")[0].strip()
+        for key in ("ScratchSize [bytes/lane]:", "VGPRs Spill:"):
+            if text.startswith(key):
+                value = int(text[len(key):].split("[")[0].strip())
+                if value != 0:
+                    bad.append(f"{name}: {key} {value}")
+    return bad
 
 
 def sources() -> list[str]:
@@ -46,7 +66,13 @@ def build_library(verbose: bool = False) -> str:
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libtk.so")
-    warn = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
+    diag = res.stdout + res.stderr
+    bad = resource_problems(diag)
+    if bad:
+        os.remove(tmp)
+        raise RuntimeError("kernels using scratch memory or spilling:\n  " + "\n  ".join(bad))
+    warn = "\n".join(l for l in diag.splitlines() if "packed-fp32-ops" not in l and "remark:" not in l
+                     and "Rpass-analysis" not in l and l.strip() and not l.lstrip().startswith(("|", "^")))
     if verbose and warn.strip():
         sys.stderr.write(warn + "\n")
     os.replace(tmp, LIB)

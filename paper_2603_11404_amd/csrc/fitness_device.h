@@ -80,11 +80,20 @@ __device__ __forceinline__ void fk_link(int l, const FkPose& P, const ChainK& ch
     }
 }
 
+// Element j (0..3) of four values, chosen without indexing (a per-lane index
+// into a struct would move the struct to private memory).
+template <typename T>
+__device__ __forceinline__ T select4(int j, T v0, T v1, T v2, T v3) {
+    return j == 0 ? v0 : j == 1 ? v1 : j == 2 ? v2 : v3;
+}
+
 // Keypoint j of the chain, given the transform M of its link: pinhole
 // projection, NaN behind the near plane.
 __device__ __forceinline__ void fk_keypoint(const float* __restrict__ M, const ChainK& ch, int j, const CamK& cam,
                                             float* __restrict__ kp2) {
-    const float vx = ch.kp[j][0], vy = ch.kp[j][1], vz = ch.kp[j][2];
+    const float vx = select4(j, ch.kp[0][0], ch.kp[1][0], ch.kp[2][0], ch.kp[3][0]);
+    const float vy = select4(j, ch.kp[0][1], ch.kp[1][1], ch.kp[2][1], ch.kp[3][1]);
+    const float vz = select4(j, ch.kp[0][2], ch.kp[1][2], ch.kp[2][2], ch.kp[3][2]);
     const float Xc = M[0] * vx + M[1] * vy + M[2] * vz + M[3];
     const float Yc = M[4] * vx + M[5] * vy + M[6] * vz + M[7];
     const float Zc = M[8] * vx + M[9] * vy + M[10] * vz + M[11];

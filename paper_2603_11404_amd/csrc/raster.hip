@@ -488,7 +488,7 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
             fk_link(part, P, ch, s_M + 48 * arm + 12 * part);
         } else {
             float M[12];
-            fk_link(ch.kp_link[part], P, ch, M);
+            fk_link(select4(part, ch.kp_link[0], ch.kp_link[1], ch.kp_link[2], ch.kp_link[3]), P, ch, M);
             fk_keypoint(M, ch, part, a.fk.cam, a.kp + (size_t(b) * n_arms + arm) * 8 + 2 * part);
         }
     }
@@ -496,15 +496,15 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
     for (int e = lane; e < n_arms * 48; e += kWave) a.link_xf_out[size_t(b) * n_arms * 48 + e] = s_M[e];
 }
 
+// One workgroup rasterises candidate b of the problem described by a.
 template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
-__global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
+__device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     constexpr int NW = NT / kWave;
     extern __shared__ unsigned long long s_mask[];
     __shared__ WaveQueues s_queue[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
 
-    const int b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int lx = lane & 7, ly = lane >> 3;
     const CamK& cam = a.cam;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
         // transform, project and snap every vertex of this candidate once into the workspace
         int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * a.meshes.total_vertices;
         for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
-            const MeshK& mesh = a.meshes.m[mi];
+            const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
             for (int v = tid; v < mesh.n_vertices; v += NT) {
                 const float* p = mesh.vertices + size_t(v) * 3;
                 int32_t X, Y;
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
     int n_head = 0, n_tail = 0, n_queued = 0, n_done = 0;
     int w_head = 0, w_tail = 0, w_queued = 0, w_done = 0;
     for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
-        const MeshK& mesh = a.meshes.m[mi];
+        const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
         const float* M = s_M + mi * 48;
         const int T = mesh.n_triangles;
         const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
@@ -635,6 +635,7 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
                 const int j = __builtin_ctzll(todo);
                 todo &= todo - 1;
                 TriRec br;
+#pragma unroll
                 for (int e = 0; e < 3; e++) {
                     br.e0lo[e] = __builtin_amdgcn_readlane(rec.e0lo[e], j);
                     br.e0hi[e] = __builtin_amdgcn_readlane(rec.e0hi[e], j);
@@ -691,6 +692,32 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
 }
 
 
+template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
+__global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
+    raster_body<FROM_SNAPPED, WRITE_MASK, COUNTS, NT>(a, blockIdx.x);
+}
+
+// Many problems in one launch: workgroups first[i] .. first[i + 1] - 1 draw
+// and rasterise the candidates of problem prob[i] (table entries in device
+// memory, read through a uniform pointer).
+constexpr int kMaxBatch = 128;
+struct BatchLaunch {
+    const RasterArgs* table;
+    int32_t count;
+    int32_t prob[kMaxBatch];
+    int32_t first[kMaxBatch + 1];
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void raster_batch_kernel(BatchLaunch L) {
+    const int g = blockIdx.x;
+    int lo = 0;   // last i with first[i] <= g
+    for (int step = kMaxBatch / 2; step > 0; step >>= 1)
+        if (lo + step < L.count && L.first[lo + step] <= g) lo += step;
+    const RasterArgs& a = L.table[L.prob[lo]];
+    raster_body<true, false, true, NT>(a, g - L.first[lo]);
+}
+
 // ---------------------------------------------------------------- snapped vertices (debug / parity)
 
 struct SnapArgs {
@@ -708,7 +735,7 @@ __global__ __launch_bounds__(256) void snap_kernel(SnapArgs a) {
     const int b = int(idx / TV), gv = int(idx % TV);
     int mi = 0;
     while (mi + 1 < a.meshes.n_meshes && gv >= a.meshes.m[mi + 1].vertex_offset) mi++;
-    const MeshK& mesh = a.meshes.m[mi];
+    const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
     const int v = gv - mesh.vertex_offset;
     const float* M = a.link_xf + (size_t(b) * a.meshes.n_meshes + mi) * 48 + 12 * mesh.vertex_link[v];
     const float* p = mesh.vertices + size_t(v) * 3;
@@ -734,7 +761,7 @@ __global__ __launch_bounds__(256) void stats_kernel(RasterArgs a, unsigned long 
     __syncthreads();
     unsigned long long kept = 0, pix = 0, pairs = 0, huge = 0;
     for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
-        const MeshK& mesh = a.meshes.m[mi];
+        const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
         const float* M = a.link_xf + (size_t(b) * a.meshes.n_meshes + mi) * 48;
         for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < mesh.n_triangles; t += gridDim.x * blockDim.x) {
             int32_t X[3], Y[3];
