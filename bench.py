@@ -264,6 +264,7 @@ def main():
         out["plain_ms_per_step"] = plain_ms
         out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
         out["bimanual960"] = bimanual_leg(dev)
+        out["batch64"] = batch_leg(dev)
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if not args.no_cpu_baseline:
@@ -319,6 +320,70 @@ def bimanual_leg(dev, gens=100):
     return {"workload": "two instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D block-diagonal, occluder",
             "ms_per_generation": eager_ms, "graph_ms_per_generation": graph_ms,
             "candidate_evals_per_s": lam / (best * 1e-3), "generations": gens}
+
+
+def batch_leg(dev, count=64, gens=10):
+    """Batched solves: 64 independent tracking problems of mixed size
+    (resolutions 320x240 .. 1280x720, lambda 64 .. 1024, meshes of 2k .. 50k
+    triangles, targets with 1% pixel flips) advanced together by two batched
+    launches per generation (raster grouped by the autotuned workgroup size);
+    compared with launching each problem's generation separately."""
+    import tempfile
+
+    import torch
+
+    import scenes
+    from paper_2603_11404_amd import tk, tracker
+    from paper_2603_11404_amd.autotune import Autotuner
+
+    rng = scenes.rng_for(3, scenes.SUB_POSE)
+    rng_f = scenes.rng_for(3, scenes.SUB_FLIPS)
+    gens_ = []
+    tri_total = 0
+    for i, sh in enumerate(scenes.batch_problem_shapes(count)):
+        cam = scenes.camera(sh["width"], sh["height"])
+        mesh = scenes.instrument_mesh(sh["segments"], sh["rings"], 3, 1)
+        tri_total += mesh.n_triangles * sh["lam"]
+        prob = tracker.Problem([mesh], [scenes.chain()], cam, dev)
+        truth = scenes.true_pose(rng, cam).astype(np.float32)
+        th = torch.as_tensor(truth[None], device=dev)
+        words = prob.render(th)[0].cpu().numpy().view(np.uint64)
+        words = scenes.apply_flips(words, cam.width, cam.height, scenes.flip_indices(rng_f, cam.width, cam.height))
+        prob.set_target(torch.as_tensor(words.view(np.int64), device=dev), prob.keypoints(th)[0])
+        g = tracker.Generation(prob, sh["lam"], loss_kind=tk.LOSS_IOU, lambda_kp=0.1)
+        g.init(np.zeros(9), 1.0, truth + scenes.DEFAULT_SCALE * rng.normal(size=9), scenes.DEFAULT_SCALE,
+               scenes.BASE_SEED + 3 + 1000 * scenes.SUB_CMAES + i)
+        gens_.append(g)
+    lam_total = sum(g.lam for g in gens_)
+    tuner = Autotuner(os.path.join(tempfile.gettempdir(), "tk_autotune.json"))
+    threads = [tuner.choose(g) for g in gens_]
+    batch = tk.Batch([g.problem_struct(t) for g, t in zip(gens_, threads)], device=dev)
+    for _ in range(2):
+        batch.ask_eval()
+        batch.tell()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(gens):
+        batch.ask_eval()
+        batch.tell()
+    b.record()
+    torch.cuda.synchronize()
+    batch_ms = a.elapsed_time(b) / gens
+    a.record()
+    for _ in range(3):
+        for g in gens_:
+            g.ask_eval_tell()
+    b.record()
+    torch.cuda.synchronize()
+    single_ms = a.elapsed_time(b) / 3
+    log(f"batch64: {batch_ms:.2f} ms per generation batched, {single_ms:.2f} ms launching each problem "
+        f"({lam_total} candidates, {tri_total / 1e6:.0f} M candidate-triangles)")
+    return {"workload": f"{count} problems, 320x240..1280x720, lambda 64..1024, 2k..50k tris, 1% flips",
+            "candidates_per_generation": lam_total, "ms_per_generation": batch_ms,
+            "candidate_evals_per_s": lam_total / (batch_ms * 1e-3), "per_problem_launches_ms": single_ms,
+            "batched_vs_per_problem": single_ms / batch_ms,
+            "workgroup_sizes": {str(t): threads.count(t) for t in sorted(set(threads))}}
 
 
 def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):

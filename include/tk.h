@@ -263,6 +263,59 @@ tk_status tk_compose_loss(const int32_t* d_counts, int32_t batch, const int32_t*
                           double lambda_app, const float* d_kp, const float* d_kp_ref, int32_t n_arms,
                           double lambda_kp, double tau, double* d_loss, tk_stream s);
 
+/* ------------------------------------------------------- batched problems */
+
+/* One independent tracking problem of a batched launch (host struct holding
+ * device pointers; NEXT batching form of the tracker, Sec. III-A.1 run for
+ * many problems at once): its CMA-ES state (n = 9 * n_arms, lambda), one mesh
+ * and one chain per arm, camera, observed mask and |M|, and the buffers of its
+ * candidates exactly as for tk_cmaes_ask_eval (d_X, d_link_xf, d_kp nullable,
+ * d_counts, workspace d_ws / ws_bytes required) and tk_cmaes_tell (kind,
+ * lambda_app, d_kp_ref nullable, lambda_kp, tau, d_loss nullable).  threads:
+ * raster workgroup size, 0 = the widest whose LDS fits, else 256, 512, 1024
+ * (a tuning choice; results do not depend on it). */
+typedef struct {
+    void* d_state;
+    int32_t n, lambda, n_arms;
+    tk_mesh meshes[2];
+    tk_chain chains[2];
+    tk_camera cam;
+    const uint64_t* d_target;
+    const int32_t* d_target_count;
+    float* d_X;
+    float* d_link_xf;
+    float* d_kp;
+    int32_t* d_counts;
+    void* d_ws;
+    size_t ws_bytes;
+    int32_t kind;
+    double lambda_app;
+    const float* d_kp_ref;
+    double lambda_kp;
+    double tau;
+    double* d_loss;
+    int32_t threads;
+} tk_problem;
+
+/* Bytes of the device table of n_problems (0 if n_problems is outside 1..65536). */
+size_t tk_batch_table_bytes(int32_t n_problems);
+
+/* Validates the problems and writes their device descriptors into the HOST
+ * buffer h_table (256-byte aligned, tk_batch_table_bytes); the caller copies
+ * it to a 256-byte aligned device buffer, which the batched calls read.  The
+ * table stays valid as long as the problems' device buffers do. */
+tk_status tk_batch_describe(const tk_problem* problems, int32_t n_problems, void* h_table, size_t table_bytes);
+
+/* tk_cmaes_ask_eval for every problem, with identical results; problems of
+ * one workgroup size share a launch (at most 128 problems per launch).
+ * problems: the host array given to tk_batch_describe; d_table: its device
+ * copy. */
+tk_status tk_batch_ask_eval(const tk_problem* problems, int32_t n_problems, const void* d_table, tk_stream s);
+
+/* tk_cmaes_tell for every problem, with identical results: one workgroup per
+ * problem, one launch per 128 problems (per covariance size class). */
+tk_status tk_batch_tell(const tk_problem* problems, int32_t n_problems, const void* d_table, tk_stream s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@
 // (arXiv:1604.00772).  Random numbers: Philox4x32-10 (Salmon et al., SC'11)
 // keyed by the seed with counter (group j, candidate k, generation g, 0),
 // mapped to normals by Box-Muller.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -217,12 +218,19 @@ struct TellAskArgs {
     float* kp_next;               // nullable [lambda][n_arms][4][2]
 };
 
+// One problem's tell step in a batched launch.
+struct UpdateJob {
+    void* state;
+    int32_t n, lam;
+    TellAskArgs ta;
+};
+
 // AS / VS: Jacobi entries per lane (upper-triangle / all within-block entries
 // over 64 lanes); NT: threads of the workgroup; COMPOSE: losses composed from
 // counts (tell); ASK: the next generation drawn at the end (tell-ask).
 template <int AS, int VS, int NT, bool COMPOSE, bool ASK>
-__global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam, const double* __restrict__ loss,
-                                                          TellAskArgs ta) {
+__device__ __forceinline__ void update_body(void* blob, const int n, const int lam, const double* __restrict__ loss,
+                                            const TellAskArgs& ta) {
     extern __shared__ double s_elite[];  // [mu][n]
     __shared__ double s_key[kMaxLambda];
     __shared__ int s_order[kMaxLambda];
@@ -643,7 +651,85 @@ __global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int
     }
 }
 
+
+template <int AS, int VS, int NT, bool COMPOSE, bool ASK>
+__global__ __launch_bounds__(NT) void cmaes_update_kernel(void* blob, int n, int lam, const double* __restrict__ loss,
+                                                          TellAskArgs ta) {
+    update_body<AS, VS, NT, COMPOSE, ASK>(blob, n, lam, loss, ta);
+}
+
+// Many problems in one launch: workgroup i runs the tell step (loss
+// composition + update) of problem prob[i], described in device memory.
+template <int AS, int VS, int NT>
+__global__ __launch_bounds__(NT) void cmaes_tell_batch_kernel(const UpdateJob* __restrict__ table, BatchList L) {
+    const UpdateJob& j = table[L.prob[blockIdx.x]];
+    update_body<AS, VS, NT, true, false>(j.state, j.n, j.lam, nullptr, j.ta);
+}
 }  // namespace
+}  // namespace tk
+
+namespace tk {
+
+static tk_status check_state(const void* d_state, int32_t n, int32_t lambda) {
+    TK_REQUIRE(d_state != nullptr, "state is NULL");
+    TK_REQUIRE((reinterpret_cast<uintptr_t>(d_state) & 255) == 0, "state must be 256-byte aligned");
+    TK_REQUIRE(n >= 1 && n <= kMaxN, "n = %d outside 1..%d", n, kMaxN);
+    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
+    return TK_OK;
+}
+
+size_t batch_update_entry_bytes() { return sizeof(UpdateJob); }
+
+tk_status batch_describe_update(const tk_problem& p, void* dst) {
+    if (tk_status st = check_state(p.d_state, p.n, p.lambda)) return st;
+    TK_REQUIRE(p.d_counts && p.d_target_count, "counts / target_count is NULL");
+    UpdateJob j;
+    std::memset(&j, 0, sizeof j);
+    const float* kp = p.d_kp_ref ? p.d_kp : nullptr;
+    if (tk_status st = make_loss_args(p.lambda, p.kind, p.lambda_app, kp, p.d_kp_ref, p.n_arms, p.lambda_kp, p.tau,
+                                      &j.ta.la))
+        return st;
+    j.state = p.d_state;
+    j.n = p.n;
+    j.lam = p.lambda;
+    j.ta.counts = p.d_counts;
+    j.ta.target_count = p.d_target_count;
+    j.ta.kp = kp;
+    j.ta.kp_ref = p.d_kp_ref;
+    j.ta.loss = p.d_loss;
+    std::memcpy(dst, &j, sizeof j);
+    return TK_OK;
+}
+
+// One launch per variant class (n <= 9 / n <= 18) and per kMaxBatch problems.
+tk_status batch_launch_tell(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s) {
+    const UpdateJob* table = static_cast<const UpdateJob*>(d_entries);
+    for (int large = 0; large < 2; large++) {
+        BatchList L;
+        std::memset(&L, 0, sizeof L);
+        size_t lds = 0;
+        auto flush = [&]() -> tk_status {
+            if (L.count == 0) return TK_OK;
+            if (large)
+                hipLaunchKernelGGL((cmaes_tell_batch_kernel<3, 6, 512>), dim3(L.count), dim3(512), lds, s, table, L);
+            else
+                hipLaunchKernelGGL((cmaes_tell_batch_kernel<1, 2, 1024>), dim3(L.count), dim3(1024), lds, s, table, L);
+            L.count = 0;
+            lds = 0;
+            return check_launch("tk_batch_tell");
+        };
+        for (int i = 0; i < n; i++) {
+            if ((problems[i].n > 9) != bool(large)) continue;
+            L.prob[L.count++] = i;
+            lds = std::max(lds, sizeof(double) * size_t(problems[i].lambda / 2) * size_t(problems[i].n));
+            if (L.count == kMaxBatch)
+                if (tk_status st = flush()) return st;
+        }
+        if (tk_status st = flush()) return st;
+    }
+    return TK_OK;
+}
+
 }  // namespace tk
 
 using namespace tk;
@@ -666,13 +752,6 @@ tk_status tk_cmaes_layout_get(int32_t n, int32_t lambda, tk_cmaes_layout* out) {
     return TK_OK;
 }
 
-static tk_status check_state(const void* d_state, int32_t n, int32_t lambda) {
-    TK_REQUIRE(d_state != nullptr, "state is NULL");
-    TK_REQUIRE((reinterpret_cast<uintptr_t>(d_state) & 255) == 0, "state must be 256-byte aligned");
-    TK_REQUIRE(n >= 1 && n <= kMaxN, "n = %d outside 1..%d", n, kMaxN);
-    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
-    return TK_OK;
-}
 
 tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
                         const double* offset, const double* scale, const tk_cmaes_params* p, uint64_t seed,

@@ -20,6 +20,7 @@
 //      mask with one ds_or_b64;
 //   3. after a barrier the mask is written out and/or reduced against the
 //      target with popcounts.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -700,7 +701,6 @@ __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
 // Many problems in one launch: workgroups first[i] .. first[i + 1] - 1 draw
 // and rasterise the candidates of problem prob[i] (table entries in device
 // memory, read through a uniform pointer).
-constexpr int kMaxBatch = 128;
 struct BatchLaunch {
     const RasterArgs* table;
     int32_t count;
@@ -905,6 +905,107 @@ tk_status attach_workspace(RasterArgs* a, void* d_ws, size_t ws_bytes, const cha
 }
 
 }  // namespace
+
+size_t batch_raster_entry_bytes() { return sizeof(RasterArgs); }
+
+tk_status batch_describe_raster(const tk_problem& p, void* dst) {
+    TK_REQUIRE(p.d_state != nullptr && (reinterpret_cast<uintptr_t>(p.d_state) & 255) == 0,
+               "state must be a 256-byte aligned device pointer");
+    TK_REQUIRE(p.lambda >= 2 && p.lambda <= kMaxLambda, "lambda = %d outside 2..%d", p.lambda, kMaxLambda);
+    TK_REQUIRE(p.n_arms >= 1 && p.n_arms <= kMaxArms && p.n == 9 * p.n_arms, "n = %d must be 9 x n_arms (n_arms = %d)",
+               p.n, p.n_arms);
+    RasterArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (tk_status st = common_raster_checks(p.lambda, p.meshes, p.n_arms, &p.cam, &a)) return st;
+    TK_REQUIRE(p.d_X && p.d_link_xf && p.d_target && p.d_counts, "X / link_xf / target / counts is NULL");
+    TK_REQUIRE(p.d_ws != nullptr, "batched problems need a workspace (tk_raster_workspace_bytes)");
+    TK_REQUIRE(p.threads == 0 || p.threads == 256 || p.threads == 512 || p.threads == 1024,
+               "threads = %d must be 0, 256, 512 or 1024", p.threads);
+    if (p.threads) {
+        const size_t need = mask_lds_bytes(a.cam) + (p.threads == 1024   ? static_lds<1024>()
+                                                     : p.threads == 512 ? static_lds<512>()
+                                                                        : static_lds<256>());
+        if (need > kLdsLimit)
+            return fail(TK_ERR_UNSUPPORTED, "%d threads need %zu bytes of LDS at %dx%d (limit %zu)", p.threads, need,
+                        p.cam.width, p.cam.height, kLdsLimit);
+    }
+    if (tk_status st = make_fk_args(p.chains, p.n_arms, &p.cam, &a.fk)) return st;
+    a.fk.batch = p.lambda;
+    a.ask = 1;
+    a.n = p.n;
+    a.lam = p.lambda;
+    a.state = p.d_state;
+    a.X = p.d_X;
+    a.link_xf_out = p.d_link_xf;
+    a.kp = p.d_kp;
+    a.target = reinterpret_cast<const unsigned long long*>(p.d_target);
+    a.counts = p.d_counts;
+    if (tk_status st = attach_workspace(&a, p.d_ws, p.ws_bytes, "tk_batch_describe")) return st;
+    std::memcpy(dst, &a, sizeof a);
+    return TK_OK;
+}
+
+namespace {
+
+// threads of problem p's workgroups: its choice, else the widest that fits
+int batch_threads(const tk_problem& p) {
+    if (p.threads) return p.threads;
+    const size_t lds = mask_lds_bytes(make_cam(p.cam));
+    if (lds + static_lds<1024>() <= kLdsLimit) return 1024;
+    if (lds + static_lds<512>() <= kLdsLimit) return 512;
+    return 256;
+}
+
+template <int NT>
+tk_status launch_raster_batch(const BatchLaunch& L, size_t lds, hipStream_t s) {
+    auto kern = raster_batch_kernel<NT>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] {
+        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(kLdsLimit - static_lds<NT>()));
+    });
+    if (attr_err != hipSuccess)
+        return fail(TK_ERR_DEVICE, "tk_batch_ask_eval: cannot raise the dynamic LDS limit: %s",
+                    hipGetErrorString(attr_err));
+    hipLaunchKernelGGL(kern, dim3(L.first[L.count]), dim3(NT), lds, s, L);
+    return check_launch("tk_batch_ask_eval");
+}
+
+}  // namespace
+
+// Problems grouped by workgroup size; one launch per group of at most kMaxBatch.
+tk_status batch_launch_raster(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s) {
+    const int sizes[3] = {1024, 512, 256};
+    for (int nt : sizes) {
+        BatchLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.table = static_cast<const RasterArgs*>(d_entries);
+        size_t lds = 0;
+        auto flush = [&]() -> tk_status {
+            if (L.count == 0) return TK_OK;
+            tk_status st = nt == 1024 ? launch_raster_batch<1024>(L, lds, s)
+                         : nt == 512  ? launch_raster_batch<512>(L, lds, s)
+                                      : launch_raster_batch<256>(L, lds, s);
+            L.count = 0;
+            L.first[0] = 0;
+            lds = 0;
+            return st;
+        };
+        for (int i = 0; i < n; i++) {
+            if (batch_threads(problems[i]) != nt) continue;
+            L.prob[L.count] = i;
+            L.first[L.count + 1] = L.first[L.count] + problems[i].lambda;
+            L.count++;
+            lds = std::max(lds, mask_lds_bytes(make_cam(problems[i].cam)));
+            if (L.count == kMaxBatch)
+                if (tk_status st = flush()) return st;
+        }
+        if (tk_status st = flush()) return st;
+    }
+    return TK_OK;
+}
+
 }  // namespace tk
 
 using namespace tk;

@@ -29,6 +29,7 @@ constexpr int kMaxN = 18;          // CMA-ES dimension (two arms x 9)
 constexpr int kMaxLambda = 1024;   // population size
 constexpr int kMaxArms = 2;
 constexpr int kMaxImage = 4096;    // width / height limit
+constexpr int kMaxBatch = 128;     // problems per batched launch
 constexpr int kGuardQ8 = 32768 * 256;  // guard band in Q8 units
 
 // ---------------------------------------------------------------- CMA-ES state layout
@@ -148,6 +149,22 @@ struct LossArgs {
     double lambda_app, lambda_kp, tau;
     int32_t batch, kind, n_arms;
 };
+
+// Problem list of a batched launch (kernel argument).
+struct BatchList {
+    int32_t count;
+    int32_t prob[kMaxBatch];
+};
+
+// Batched problems: each problem's device descriptors (one raster entry, one
+// update entry) are written into a host table by the describe functions and
+// read by the batched kernels from the caller's device copy.
+size_t batch_raster_entry_bytes();
+size_t batch_update_entry_bytes();
+tk_status batch_describe_raster(const tk_problem& p, void* dst);
+tk_status batch_describe_update(const tk_problem& p, void* dst);
+tk_status batch_launch_raster(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s);
+tk_status batch_launch_tell(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s);
 
 tk_status validate_camera(const tk_camera* cam);
 // Validates n_arms chains and fills a->ch, a->n_arms (and a->cam when cam is given).

@@ -45,6 +45,17 @@ class Chain(ctypes.Structure):
                 ("keypoints", (ctypes.c_double * 4) * 4)]
 
 
+class Problem(ctypes.Structure):
+    """tk_problem: one independent problem of a batched launch."""
+    _fields_ = [("d_state", ctypes.c_void_p), ("n", ctypes.c_int32), ("lambda_", ctypes.c_int32),
+                ("n_arms", ctypes.c_int32), ("meshes", Mesh * 2), ("chains", Chain * 2), ("cam", Camera),
+                ("d_target", ctypes.c_void_p), ("d_target_count", ctypes.c_void_p), ("d_X", ctypes.c_void_p),
+                ("d_link_xf", ctypes.c_void_p), ("d_kp", ctypes.c_void_p), ("d_counts", ctypes.c_void_p),
+                ("d_ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("kind", ctypes.c_int32),
+                ("lambda_app", ctypes.c_double), ("d_kp_ref", ctypes.c_void_p), ("lambda_kp", ctypes.c_double),
+                ("tau", ctypes.c_double), ("d_loss", ctypes.c_void_p), ("threads", ctypes.c_int32)]
+
+
 class CmaesParams(ctypes.Structure):
     _fields_ = [("c_m_scale", ctypes.c_double), ("c_mu_scale", ctypes.c_double), ("c1_scale", ctypes.c_double),
                 ("n_blocks", ctypes.c_int32)]
@@ -65,6 +76,7 @@ EXPORTS = [
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
     "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
+    "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
 ]
 
 _lib = None
@@ -104,9 +116,14 @@ def lib():
         L.tk_cmaes_tell_ask.argtypes = [P, i32, i32, P, P, i32, f64, P, P, f64, f64, P, P, i32, P, P, P, P, P]
         L.tk_cmaes_tell.argtypes = [P, i32, i32, P, P, i32, f64, P, P, i32, f64, f64, P, P]
         L.tk_cmaes_ask_eval.argtypes = [P, i32, i32, P, i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.tk_batch_table_bytes.restype = ctypes.c_size_t
+        L.tk_batch_table_bytes.argtypes = [i32]
+        L.tk_batch_describe.argtypes = [P, i32, P, ctypes.c_size_t]
+        L.tk_batch_ask_eval.argtypes = [P, i32, P, P]
+        L.tk_batch_tell.argtypes = [P, i32, P, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
-                            "tk_raster_workspace_bytes"):
+                            "tk_raster_workspace_bytes", "tk_batch_table_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -359,3 +376,31 @@ def raster_stats(link_xf, batch, meshes, cam, stats, stream=None):
     arr, nm = _meshes(meshes)
     c = camera(cam)
     _check(lib().tk_raster_stats(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), _ptr(stats), _stream(stream)))
+
+
+# ------------------------------------------------------------------ batched problems
+
+class Batch:
+    """Many independent problems driven by batched launches: a host array of
+    tk_problem and its device table (written once by tk_batch_describe)."""
+
+    def __init__(self, problems, device="cuda"):
+        self.problems = (Problem * len(problems))(*problems)
+        self.n = len(problems)
+        nbytes = int(lib().tk_batch_table_bytes(self.n))
+        if nbytes == 0:
+            raise TkError(TK_ERR_INVALID_ARGUMENT, f"bad number of problems {self.n}")
+        host = np.zeros(nbytes + 256, dtype=np.uint8)
+        off = (-host.ctypes.data) % 256
+        view = host[off:off + nbytes]
+        _check(lib().tk_batch_describe(self.problems, self.n, view.ctypes.data_as(ctypes.c_void_p), nbytes))
+        self.table = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        doff = (-self.table.data_ptr()) % 256
+        self.table_view = self.table[doff:doff + nbytes]
+        self.table_view.copy_(torch.from_numpy(view.copy()))
+
+    def ask_eval(self, stream=None):
+        _check(lib().tk_batch_ask_eval(self.problems, self.n, _ptr(self.table_view), _stream(stream)))
+
+    def tell(self, stream=None):
+        _check(lib().tk_batch_tell(self.problems, self.n, _ptr(self.table_view), _stream(stream)))

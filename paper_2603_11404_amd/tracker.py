@@ -170,6 +170,27 @@ class Generation:
     def replay(self):
         self.graph.replay()
 
+    def problem_struct(self, threads: int = 0) -> tk.Problem:
+        """This generation as one problem of a batched launch (tk_problem)."""
+        p = self.p
+        P = tk.Problem()
+        P.d_state = self.state.data_ptr()
+        P.n, P.lambda_, P.n_arms = self.n, self.lam, p.n_arms
+        for i in range(p.n_arms):
+            P.meshes[i] = p.meshes[i].struct()
+            P.chains[i] = tk.chain(p.chains[i])
+        P.cam = tk.camera(p.cam)
+        P.d_target = p.target.data_ptr()
+        P.d_target_count = p.target_count.data_ptr()
+        P.d_X, P.d_link_xf, P.d_counts = self.X.data_ptr(), self.xf.data_ptr(), self.counts.data_ptr()
+        P.d_kp = self.kp.data_ptr() if self.use_kp else None
+        P.d_ws, P.ws_bytes = self.ws.data_ptr(), self.ws.numel()
+        P.kind, P.lambda_app, P.lambda_kp, P.tau = self.loss_kind, self.lambda_app, self.lambda_kp, self.tau
+        P.d_kp_ref = p.kp_ref.data_ptr() if self.use_kp else None
+        P.d_loss = self.loss.data_ptr()
+        P.threads = int(threads)
+        return P
+
     def mean(self) -> np.ndarray:
         v = tk.cmaes_view(self.state, self.n, self.lam)
         return v["offset"] + v["scale"] * v["mean"]

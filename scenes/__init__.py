@@ -390,3 +390,25 @@ def workload(name: str) -> dict:
         return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),
                     lam=512, gens=30, frames=1, index=2, n_blocks=2)
     raise KeyError(name)
+
+
+BATCH_RESOLUTIONS = ((320, 240), (640, 480), (960, 540), (1280, 720))
+BATCH_LAMBDAS = (64, 128, 256, 512, 1024)
+
+
+def batch_problem_shapes(count: int = 64, seed_index: int = 3) -> list[dict]:
+    """Shapes of the batched-solves workload: problem p has resolution
+    BATCH_RESOLUTIONS[p % 4], lambda = BATCH_LAMBDAS[(p // 4) % 5] and a mesh of
+    about T = round(2000 * 25**u) triangles, u ~ U[0, 1] seeded (log-uniform
+    between 2k and 50k): an instrument with 32 (T < 8000) or 64 shaft segments
+    and as many rings as bring it closest to T."""
+    rng = rng_for(seed_index, SUB_POSE)
+    out = []
+    for p in range(count):
+        W, H = BATCH_RESOLUTIONS[p % 4]
+        target_t = int(round(2000 * 25 ** rng.uniform()))
+        seg = 32 if target_t < 8000 else 64
+        rings = max(1, int(round((target_t - 124) / (2 * seg))) - 1)
+        out.append(dict(width=W, height=H, lam=BATCH_LAMBDAS[(p // 4) % 5], segments=seg, rings=rings,
+                        target_triangles=target_t))
+    return out
