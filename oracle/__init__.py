@@ -12,6 +12,8 @@ product path.
   (paper Sec. III-A.1, completed with Hansen's tutorial where the paper is
   silent).
 * ``brute.py`` -- exact rational point-in-triangle checker for tiny images.
+* ``kalman.py`` -- constant-velocity Kalman filter of the per-frame estimates
+  in the general 2n-state matrix form (paper Sec. III-A.4).
 """
 from __future__ import annotations
 
