@@ -7,7 +7,10 @@ keypoint reprojection term, 30 CMA-ES generations per frame over a seeded
 100-frame trajectory with 1% pixel-flip noise in the targets and 2-degree
 noise on the joint readings.  A step is one generation: sample -> FK ->
 transform/project/snap -> raster -> counts -> loss -> update, all in HIP
-kernels; the frame loop re-initialises CMA-ES from the previous estimate.
+kernels.  The frame loop re-initialises CMA-ES from the previous frame's
+estimate after the constant-velocity Kalman filter (device kernels
+tk_cmaes_estimate + tk_kf_step at the end of each frame); the pose errors of
+the raw and filtered per-frame estimates are reported under "tracking".
 
 Prints ONE JSON line (rank 0).  Progress goes to stderr.
 """
@@ -116,14 +119,22 @@ def main():
 
     gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU, lambda_kp=0.1)
     seed0 = scenes.BASE_SEED + wl["index"] + 1000 * scenes.SUB_CMAES
-    state = {"est": est0.copy(), "frame": -1}
+    # frame loop: CMA-ES warm-started from the previous frame's filtered
+    # estimate (joint means from the joint readings), temporal filter on the
+    # device at the end of every frame
+    trk = tracker.Tracker(gen, scale, G, seed0, filt=wl["filter"])
+    state = {"frame": -1, "frame_step": 0, "log": None}
 
-    def start_frame(f):
-        prob.set_target(targets[f], kp_true[f])
-        mean_phys = state["est"].copy()
-        mean_phys[6:9] = readings[f]                  # joint readings initialise the joint means
-        gen.init(np.zeros(9), 1.0, mean_phys, scale, seed0 + f)
-        state["frame"] = f
+    def start_frame(f, s=0):
+        if f == 0:
+            trk.start(est0)                           # first frame of the trajectory: restart the filter
+        trk.begin_frame(f, targets[f], kp_true[f], readings[f])
+        state["frame"], state["frame_step"] = f, s
+
+    def end_frame():
+        res = trk.end_frame()                         # estimate + filter step + one 3 x 9 FP64 copy
+        if state["log"] is not None and state["frame_step"] >= args.warmup:
+            state["log"].append((state["frame"], res))
 
     def ask_eval():
         tk.cmaes_ask_eval(gen.state, gen.n, gen.lam, prob.chains, prob.meshes, cam, prob.target, gen.X, gen.xf,
@@ -140,8 +151,8 @@ def main():
         f, g = (s // G) % F, s % G
         if g == 0:
             if state["frame"] >= 0:
-                state["est"] = gen.mean()             # warm start: previous frame's estimate (D2H)
-            start_frame(f)
+                end_frame()
+            start_frame(f, s)
         if events is not None:
             events[0].record()
         ask_eval()
@@ -163,6 +174,7 @@ def main():
            for _ in range(0, args.steps, EVENT_EVERY)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    state["log"] = []
     w0 = time.perf_counter()
     t_start.record()
     for i in range(args.steps):
@@ -175,20 +187,41 @@ def main():
     gpu_ms = t_start.elapsed_time(t_end)
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     fused_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    final_est = gen.mean()
+    if (args.warmup + args.steps) % G == 0:
+        end_frame()                                   # the last timed frame is complete
+    frames_log, state["log"] = state["log"], None
     log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events; "
         f"ask-eval avg {fused_ms.mean() * 1e3:.1f} us over {len(fused_ms)} sampled launches")
 
-    # pose error of the last estimate against the truth of its frame
-    last_f = ((args.warmup + args.steps - 1) // G) % F
-    err_t = float(np.linalg.norm(final_est[3:6] - traj[last_f, 3:6]))
+    # pose errors of the frames completed in the timed region (raw CMA-ES
+    # estimates and temporally filtered ones) against the trajectory
+    tracking = None
+    if frames_log:
+        fidx = np.array([f for f, _ in frames_log])
+        truth = traj[fidx]
+        tracking = {"frames": len(frames_log)}
+        # second differences only over three consecutive frames (not across the trajectory's wrap)
+        consec = (np.diff(fidx)[1:] == 1) & (np.diff(fidx)[:-1] == 1)
+
+        def jitter_mm(x):
+            d2 = np.abs(np.diff(x[:, 3:6], 2, axis=0)).sum(1)[consec]
+            return float(d2.mean() * 1e3) if d2.size else None
+        for key in ("z", "theta"):
+            est = np.stack([r[key] for _, r in frames_log])
+            e = tracker.pose_errors(prob, est, truth)
+            tracking["raw" if key == "z" else "filtered"] = {
+                "rot_deg_mean": float(e["rot_deg"].mean()), "trans_mm_mean": float(e["trans_m"].mean() * 1e3),
+                "joint_deg_mean": float(e["joint_deg"].mean()), "trans_mm_max": float(e["trans_m"].max() * 1e3),
+                # mean |second difference| of the translation over consecutive frames
+                "jitter_mm": jitter_mm(est)}
+        tracking["truth_jitter_mm"] = jitter_mm(truth)
+        log(f"tracking over {len(frames_log)} frames: raw {tracking['raw']}, filtered {tracking['filtered']}")
 
     # ---------------------------------------------------------------- work per fused launch
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     acc = np.zeros(4)
     n_st = 0
     state["frame"] = -1
-    state["est"] = est0.copy()
     for s in range(2 * G):
         run_step(s, between=lambda: tk.raster_stats(gen.xf, gen.lam, prob.meshes, cam, stats))
         acc += stats.cpu().numpy()
@@ -231,13 +264,12 @@ def main():
                                                                  "kept": kept,
                                                                  "box_pixels": box_px, "block_pairs": pairs}},
         "fitness_evals_per_s": lam / (fused_ms.mean() * 1e-3),
-        "final_translation_error_m": err_t,
+        "tracking": tracking,
     }
 
     # ---------------------------------------------------------------- graph replay and plain launches
     if not args.no_extras:
         state["frame"] = -1
-        state["est"] = est0.copy()
         start_frame(0)
         graph = gen.capture()
         torch.cuda.synchronize()

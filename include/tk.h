@@ -263,6 +263,50 @@ tk_status tk_compose_loss(const int32_t* d_counts, int32_t batch, const int32_t*
                           double lambda_app, const float* d_kp, const float* d_kp_ref, int32_t n_arms,
                           double lambda_kp, double tau, double* d_loss, tk_stream s);
 
+/* ------------------------------------------------------- temporal filter */
+
+/* Constant-velocity Kalman filter of the per-frame estimates (Sec. III-A.4,
+ * Eq. kf_motion and the observation model that follows it): state
+ * s_t = [theta_t; theta_dot_t] (2n), s_t = [[I, dt I], [0, I]] s_{t-1} + w_t,
+ * w_t ~ N(0, Q), observation z_t = [I 0] s_t + v_t, v_t ~ N(0, R), then the
+ * filtered theta is clamped to [lo, hi] per coordinate.  Supported noise:
+ * Q = [[diag(q_pos), diag(q_cross)], [diag(q_cross), diag(q_vel)]] and
+ * R = diag(r), with P0 = diag(p0_pos, p0_vel); under these the filter is n
+ * independent 2-state filters, which the device evaluates in FP64, one lane
+ * per coordinate.  A non-finite z_i is a missing measurement: coordinate i is
+ * predicted only.  All arrays hold n used entries (n <= 18). */
+#define TK_KF_MAX_N 18
+typedef struct {
+    double dt;                                   /* frame interval, > 0 */
+    double p0_pos[TK_KF_MAX_N], p0_vel[TK_KF_MAX_N];   /* >= 0 */
+    double q_pos[TK_KF_MAX_N], q_cross[TK_KF_MAX_N], q_vel[TK_KF_MAX_N];  /* PSD 2x2 blocks */
+    double r[TK_KF_MAX_N];                       /* > 0 */
+    double lo[TK_KF_MAX_N], hi[TK_KF_MAX_N];     /* clamp limits; +-INFINITY for none */
+} tk_kf_params;
+
+/* Bytes of the device filter state for n coordinates (0 unless 1 <= n <= 18). */
+size_t tk_kf_state_bytes(int32_t n);
+
+/* (Re)start the filter at theta = x0 (host [n], inside [lo, hi]) with zero
+ * velocity and covariance P0; params: host.  d_kf: device, tk_kf_state_bytes.
+ * Errors: TK_ERR_INVALID_ARGUMENT on sizes, NULL pointers, non-finite values,
+ * a non-PSD noise block, r <= 0 or lo > hi; nothing is launched then. */
+tk_status tk_kf_init(void* d_kf, int32_t n, const double* x0, const tk_kf_params* p, tk_stream s);
+
+/* One frame: predict, update with d_z (device FP64 [n]), clamp.  Writes the
+ * filtered theta_t to d_theta and the clamped constant-velocity prediction
+ * theta_t + dt * theta_dot_t for the next frame to d_theta_next (device FP64
+ * [n] each, both nullable).  n must be the value given to tk_kf_init. */
+tk_status tk_kf_step(void* d_kf, int32_t n, const double* d_z, double* d_theta, double* d_theta_next,
+                     tk_stream s);
+
+/* The CMA-ES estimate of a frame as the filter's measurement: d_z[i] =
+ * offset_i + scale_i * m_i (device FP64 [n]), with the three joint coordinates
+ * of every arm taken through the cosine map of Sec. III-A.3 into joint angles
+ * in [q_lb, q_ub] (FP64).  n must be 9 * n_arms; chains: host [n_arms]. */
+tk_status tk_cmaes_estimate(const void* d_state, int32_t n, int32_t lambda, const tk_chain* chains,
+                            int32_t n_arms, double* d_z, tk_stream s);
+
 /* ------------------------------------------------------- batched problems */
 
 /* One independent tracking problem of a batched launch (host struct holding

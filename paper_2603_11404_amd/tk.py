@@ -77,6 +77,7 @@ EXPORTS = [
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
     "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
+    "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
 ]
 
 _lib = None
@@ -121,9 +122,14 @@ def lib():
         L.tk_batch_describe.argtypes = [P, i32, P, ctypes.c_size_t]
         L.tk_batch_ask_eval.argtypes = [P, i32, P, P]
         L.tk_batch_tell.argtypes = [P, i32, P, P]
+        L.tk_kf_state_bytes.restype = ctypes.c_size_t
+        L.tk_kf_state_bytes.argtypes = [i32]
+        L.tk_kf_init.argtypes = [P, i32, P, P, P]
+        L.tk_kf_step.argtypes = [P, i32, P, P, P, P]
+        L.tk_cmaes_estimate.argtypes = [P, i32, i32, P, i32, P, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
-                            "tk_raster_workspace_bytes", "tk_batch_table_bytes"):
+                            "tk_raster_workspace_bytes", "tk_batch_table_bytes", "tk_kf_state_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -266,6 +272,52 @@ def cmaes_ask_eval(state, n, lam, chains, meshes, cam, target, X, link_xf, count
     wp, wb = _ws(ws)
     _check(lib().tk_cmaes_ask_eval(_ptr(state), n, lam, ch, n_arms, arr, ctypes.byref(c), _ptr(target), _ptr(X),
                                    _ptr(link_xf), _ptr(kp), _ptr(counts), wp, wb, _stream(stream)))
+
+
+KF_MAX_N = 18
+
+
+class KfParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double)] + [(f, ctypes.c_double * KF_MAX_N) for f in
+                                             ("p0_pos", "p0_vel", "q_pos", "q_cross", "q_vel", "r", "lo", "hi")]
+
+
+def kf_params(n, dt, p0_pos, p0_vel, q_pos, q_vel, r, lo=None, hi=None, q_cross=0.0) -> KfParams:
+    """tk_kf_params from per-coordinate values (scalars broadcast to n)."""
+    p = KfParams()
+    p.dt = float(dt)
+    vals = {"p0_pos": p0_pos, "p0_vel": p0_vel, "q_pos": q_pos, "q_cross": q_cross, "q_vel": q_vel, "r": r,
+            "lo": -np.inf if lo is None else lo, "hi": np.inf if hi is None else hi}
+    for name, v in vals.items():
+        arr = np.broadcast_to(np.asarray(v, np.float64), (n,))
+        getattr(p, name)[:n] = [float(a) for a in arr]
+    return p
+
+
+def kf_alloc(n: int, device="cuda") -> torch.Tensor:
+    nb = int(lib().tk_kf_state_bytes(n))
+    if nb == 0:
+        raise TkError(TK_ERR_INVALID_ARGUMENT, f"tk_kf_state_bytes: n = {n} outside 1..{KF_MAX_N}")
+    return torch.zeros(nb, dtype=torch.uint8, device=device)
+
+
+def kf_init(kf, n, x0, params: KfParams, stream=None):
+    """Restart the temporal filter at x0 (host [n]) with zero velocity."""
+    x = np.ascontiguousarray(x0, np.float64)
+    _check(lib().tk_kf_init(_ptr(kf), n, x.ctypes.data_as(ctypes.c_void_p), ctypes.byref(params), _stream(stream)))
+
+
+def kf_step(kf, n, z, theta=None, theta_next=None, stream=None):
+    """Predict, update with z (device FP64 [n]) and clamp; filtered theta and
+    the next frame's prediction go to the optional device outputs."""
+    _check(lib().tk_kf_step(_ptr(kf), n, _ptr(z), _ptr(theta), _ptr(theta_next), _stream(stream)))
+
+
+def cmaes_estimate(state, n, lam, chains, z, stream=None):
+    """The CMA-ES mean as physical coordinates with joint angles (device FP64 [n])."""
+    n_arms = len(chains)
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    _check(lib().tk_cmaes_estimate(_ptr(state), n, lam, ch, n_arms, _ptr(z), _stream(stream)))
 
 
 def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:

@@ -58,6 +58,13 @@ class Problem:
         tk.raster_silhouette(xf, B, self.meshes, self.cam, masks, tk.raster_workspace(B, self.meshes, self.device))
         return masks
 
+    def transforms(self, theta: torch.Tensor) -> torch.Tensor:
+        """Link transforms [B, n_arms, 4, 3, 4] of candidates theta [B, 9*n_arms] (FP32, device)."""
+        B = theta.shape[0]
+        xf = torch.empty(B, self.n_arms, 4, 12, dtype=torch.float32, device=self.device)
+        tk.fk_transform(theta.contiguous(), B, self.n_arms, self.chains, xf)
+        return xf.view(B, self.n_arms, 4, 3, 4)
+
     def keypoints(self, theta: torch.Tensor) -> torch.Tensor:
         B = theta.shape[0]
         xf = torch.empty(B, self.n_arms, 4, 12, dtype=torch.float32, device=self.device)
@@ -194,6 +201,119 @@ class Generation:
     def mean(self) -> np.ndarray:
         v = tk.cmaes_view(self.state, self.n, self.lam)
         return v["offset"] + v["scale"] * v["mean"]
+
+
+class Tracker:
+    """Frame loop of Sec. III-A with the temporal filter of Sec. III-A.4.
+
+    Per frame: begin_frame() sets the observation and starts CMA-ES from the
+    previous frame's filtered estimate (the joint means from joint readings
+    when given); the caller runs the frame's generations (e.g.
+    Generation.ask_eval_tell()); end_frame() turns the CMA-ES mean into the
+    filter's measurement (tk_cmaes_estimate: physical pose and joint angles)
+    and filters it on the device (tk_kf_step: constant-velocity predict,
+    update, joint clamp).  One FP64 copy of 3 x n values per frame brings the
+    raw and filtered estimates to the host, where they also seed the next
+    frame.  With filt=None the raw estimate is passed through.
+
+    Estimates in the filter's coordinates hold joint angles q; CMA-ES runs on
+    the unconstrained joint coordinates qhat (the cosine map of Sec. III-A.3).
+    warm_start: "filter" starts frame t+1 from the filtered estimate of frame
+    t, "predict" from its constant-velocity prediction."""
+
+    def __init__(self, gen: Generation, scale, gens_per_frame: int, seed0: int, filt: dict | None = None,
+                 warm_start: str = "filter"):
+        assert warm_start in ("filter", "predict")
+        self.gen, self.p = gen, gen.p
+        self.n = gen.n
+        self.scale = np.asarray(scale, dtype=np.float64)
+        self.G = int(gens_per_frame)
+        self.seed0 = int(seed0)
+        self.warm_start = warm_start
+        d = self.p.device
+        self.out = torch.empty(3, self.n, dtype=torch.float64, device=d)   # z, theta, theta_next
+        self.kf = None
+        if filt is not None:
+            arms = self.p.n_arms
+            tile = lambda a: np.tile(np.asarray(a, np.float64), arms)
+            lo, hi = np.full(self.n, -np.inf), np.full(self.n, np.inf)
+            for a, ch in enumerate(self.p.chains):
+                lo[9 * a + 6:9 * a + 9] = ch.q_lb
+                hi[9 * a + 6:9 * a + 9] = ch.q_ub
+            vel = tile(filt["vel_std"])
+            self.params = tk.kf_params(self.n, filt["dt"], p0_pos=tile(filt["meas_std"]) ** 2,
+                                       p0_vel=(5.0 * vel) ** 2, q_pos=tile(filt["pos_std"]) ** 2, q_vel=vel ** 2,
+                                       r=tile(filt["meas_std"]) ** 2, lo=lo, hi=hi)
+            self.kf = tk.kf_alloc(self.n, d)
+        self.est = None
+
+    def _to_angles(self, theta) -> np.ndarray:
+        out = np.array(theta, dtype=np.float64)
+        for a, ch in enumerate(self.p.chains):
+            out[9 * a + 6:9 * a + 9] = decode_joints(out[9 * a + 6:9 * a + 9], ch)
+        return out
+
+    def _to_qhat(self, theta) -> np.ndarray:
+        out = np.array(theta, dtype=np.float64)
+        for a, ch in enumerate(self.p.chains):
+            out[9 * a + 6:9 * a + 9] = encode_joints(out[9 * a + 6:9 * a + 9], ch)
+        return out
+
+    def start(self, est0):
+        """Restart tracking from est0 (CMA-ES coordinates, [n]); restarts the filter."""
+        self.est = np.array(est0, dtype=np.float64)
+        if self.kf is not None:
+            x0 = np.clip(self._to_angles(self.est), self.params.lo[:self.n], self.params.hi[:self.n])
+            tk.kf_init(self.kf, self.n, x0, self.params)
+
+    def begin_frame(self, f: int, target=None, kp_ref=None, readings=None):
+        """Observation of frame f (target words / keypoints, optional) and CMA-ES
+        initialisation; readings: joint readings qhat [n_arms, 3] or None."""
+        if target is not None:
+            self.p.set_target(target, kp_ref)
+        mean = self.est.copy()
+        if readings is not None:
+            r = np.asarray(readings, np.float64).reshape(self.p.n_arms, 3)
+            for a in range(self.p.n_arms):
+                mean[9 * a + 6:9 * a + 9] = r[a]
+        self.gen.init(np.zeros(self.n), 1.0, mean, self.scale, self.seed0 + f)
+
+    def end_frame(self) -> dict:
+        """Measurement, filter step and the per-frame copy to the host:
+        {"z": raw estimate, "theta": filtered estimate} in the filter's coordinates."""
+        g = self.gen
+        tk.cmaes_estimate(g.state, self.n, g.lam, self.p.chains, self.out[0])
+        if self.kf is not None:
+            tk.kf_step(self.kf, self.n, self.out[0], self.out[1], self.out[2])
+        host = self.out.cpu().numpy()
+        z = host[0].copy()
+        th = host[1].copy() if self.kf is not None else z.copy()
+        nxt = host[2] if self.kf is not None and self.warm_start == "predict" else th
+        self.est = self._to_qhat(nxt)
+        return {"z": z, "theta": th}
+
+
+def pose_errors(problem: Problem, est, truth) -> dict:
+    """Per-frame pose errors of estimates est [F, n] (filter coordinates: pose
+    and joint angles) against truth [F, n] (CMA-ES coordinates, qhat joints),
+    per arm: rotation (geodesic angle between the two shaft rotations, degrees,
+    from the device forward kinematics), translation (m) and mean absolute
+    joint-angle error (degrees)."""
+    est = np.asarray(est, np.float64)
+    truth = np.asarray(truth, np.float64)
+    F = est.shape[0]
+    th = torch.as_tensor(np.concatenate([est, truth]).astype(np.float32), device=problem.device)
+    R = problem.transforms(th)[:, :, 0, :, :3].double().cpu().numpy()      # [2F, arms, 3, 3]
+    # angle = 2 asin(|R_a - R_b|_F / (2 sqrt 2)): well conditioned for small angles
+    diff = np.linalg.norm((R[:F] - R[F:]).reshape(F, problem.n_arms, 9), axis=-1)
+    rot = np.degrees(2.0 * np.arcsin(np.minimum(diff / (2.0 * np.sqrt(2.0)), 1.0)))
+    out = {"rot_deg": rot, "trans_m": np.zeros((F, problem.n_arms)), "joint_deg": np.zeros((F, problem.n_arms))}
+    for a, ch in enumerate(problem.chains):
+        s = slice(9 * a, 9 * a + 9)
+        out["trans_m"][:, a] = np.linalg.norm(est[:, s][:, 3:6] - truth[:, s][:, 3:6], axis=1)
+        q_true = np.stack([decode_joints(t[6:9], ch) for t in truth[:, s]])
+        out["joint_deg"][:, a] = np.degrees(np.abs(est[:, s][:, 6:9] - q_true).mean(axis=1))
+    return out
 
 
 # ------------------------------------------------------------------ host-side set-up helpers

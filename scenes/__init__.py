@@ -375,6 +375,20 @@ def apply_occluder(img: np.ndarray, rect) -> np.ndarray:
 # Named workloads
 # --------------------------------------------------------------------------
 
+# Noise of the temporal filter for the seeded track640 trajectories, per frame
+# (dt = 1 frame), in the filter's coordinates (look-at angles [rad],
+# translation [m], joint angles [rad]).  meas_std: robust spread (1.4826 x
+# median absolute error) of the raw per-frame CMA-ES estimates; vel_std: half
+# the RMS frame-to-frame velocity change of the trajectories; pos_std: a tenth
+# of vel_std.  Medians over trajectories 1, 12, 13 and 14 of this generator.
+FILTER_TRACK = dict(
+    dt=1.0,
+    meas_std=np.array([7.7e-4, 3.3e-4, 5.2e-4, 7.7e-6, 1.0e-5, 8.1e-5, 7.2e-4, 5.6e-4, 3.3e-4]),
+    vel_std=np.array([4.1e-4, 3.6e-4, 2.5e-4, 3.4e-5, 3.4e-5, 5.7e-5, 3.1e-4, 5.3e-4, 1.5e-4]),
+    pos_std=np.array([4.1e-5, 3.6e-5, 2.5e-5, 3.4e-6, 3.4e-6, 5.7e-6, 3.1e-5, 5.3e-5, 1.5e-5]),
+)
+
+
 def workload(name: str) -> dict:
     """Shapes of the named synthetic workloads: meshes, chains, camera, lambda,
     generations per frame, frames, workload index (seed offset) and the number
@@ -384,7 +398,7 @@ def workload(name: str) -> dict:
                     lam=16, gens=20, frames=1, index=0)
     if name == "track640":       # 20k tris, 640x480, lambda=256, 30 gens x 100 frames
         return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(640, 480),
-                    lam=256, gens=30, frames=100, index=1)
+                    lam=256, gens=30, frames=100, index=1, filter=FILTER_TRACK)
     if name == "bimanual960":    # two uneven instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D
         meshes = [instrument_mesh(64, 150, 6, 4), instrument_mesh(100, 170, 7, 5, jaw_scale=1.3, box_scale=1.2)]
         return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),

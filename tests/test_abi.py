@@ -45,3 +45,22 @@ def test_host_only_entry_points():
 def test_binding_exports_match_header():
     from paper_2603_11404_amd import tk
     assert sorted(tk.EXPORTS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtk.so not built")
+def test_filter_argument_errors_launch_nothing():
+    """tk_kf_init rejects bad parameters on the host before any launch."""
+    import numpy as np
+    from paper_2603_11404_amd import tk
+    assert tk.lib().tk_kf_state_bytes(9) >= 9 * 11 * 8 and tk.lib().tk_kf_state_bytes(19) == 0
+    assert tk.lib().tk_kf_state_bytes(0) == 0
+    good = dict(n=3, dt=1.0, p0_pos=1.0, p0_vel=1.0, q_pos=1e-4, q_vel=1e-4, r=1e-2)
+    fake = ctypes.c_void_p(256)           # never dereferenced: every case below fails validation
+    for bad in (dict(dt=0.0), dict(r=0.0), dict(q_pos=-1.0), dict(q_cross=1.0), dict(p0_vel=np.nan),
+                dict(lo=1.0, hi=0.0)):
+        p = tk.kf_params(**{**good, **bad})
+        st = tk.lib().tk_kf_init(fake, 3, np.zeros(3).ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), None)
+        assert st == 1, bad
+    p = tk.kf_params(**good, lo=0.5, hi=1.0)          # x0 = 0 outside the clamp limits
+    assert tk.lib().tk_kf_init(fake, 3, np.zeros(3).ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), None) == 1
+    assert tk.lib().tk_kf_step(fake, 0, fake, None, None, None) == 1

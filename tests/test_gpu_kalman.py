@@ -1,0 +1,148 @@
+"""Temporal filter on the device (tk_kf_init / tk_kf_step, Sec. III-A.4)
+against the oracle's general 2n-state matrix form, frame by frame, and the
+filter's measurement (tk_cmaes_estimate) against the oracle's cosine map."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from oracle.kalman import KalmanCV
+from paper_2603_11404_amd import tk, tracker
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-12, 1e-13     # FP64 on both sides; only the order of rounding differs
+
+
+def _params(rng, n, joint_clamp):
+    dt = float(rng.uniform(0.02, 0.1))
+    qp, qv = rng.uniform(1e-6, 1e-3, n), rng.uniform(1e-5, 1e-2, n)
+    qc = rng.uniform(-0.9, 0.9, n) * np.sqrt(qp * qv)          # PSD 2x2 blocks
+    r = rng.uniform(1e-4, 1e-2, n)
+    p0p, p0v = rng.uniform(1e-3, 1e-1, n), rng.uniform(1e-2, 1.0, n)
+    lo, hi = np.full(n, -np.inf), np.full(n, np.inf)
+    if joint_clamp:
+        for arm in range(n // 9):
+            lo[9 * arm + 6:9 * arm + 9] = [-0.6, -0.6, 0.0]
+            hi[9 * arm + 6:9 * arm + 9] = [0.6, 0.6, 0.9]
+    return dict(dt=dt, p0_pos=p0p, p0_vel=p0v, q_pos=qp, q_vel=qv, q_cross=qc, r=r, lo=lo, hi=hi)
+
+
+@pytest.mark.parametrize("n,frames,seed", [(9, 200, 1), (18, 150, 2), (1, 50, 3), (5, 40, 4)])
+def test_filter_matches_oracle_frame_by_frame(n, frames, seed):
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1000 + seed)
+    prm = _params(rng, n, joint_clamp=(n % 9 == 0))
+    x0 = np.clip(rng.normal(size=n) * 0.3, prm["lo"], prm["hi"])
+    ref = KalmanCV.diagonal(x0, prm["p0_pos"], prm["p0_vel"], prm["q_pos"], prm["q_vel"], prm["r"], prm["dt"],
+                            prm["lo"], prm["hi"], q_cross=prm["q_cross"])
+    kf = tk.kf_alloc(n, dev)
+    tk.kf_init(kf, n, x0, tk.kf_params(n, **prm))
+    # a constant-velocity drift with sinusoidal wobble; joints swing through
+    # their limits so that the clamp acts; a few measurements are missing
+    t = np.arange(frames)[:, None]
+    vel = rng.normal(size=n) * 0.02
+    zs = x0 + vel * t + 0.7 * np.sin(0.05 * t + rng.uniform(0, 6, n)) + 0.01 * rng.normal(size=(frames, n))
+    zs[rng.random(size=zs.shape) < 0.03] = np.nan
+    z_d = torch.as_tensor(zs, device=dev)
+    th_d = torch.empty(frames, n, dtype=torch.float64, device=dev)
+    nx_d = torch.empty_like(th_d)
+    for f in range(frames):
+        tk.kf_step(kf, n, z_d[f], th_d[f], nx_d[f])
+    th, nx = th_d.cpu().numpy(), nx_d.cpu().numpy()
+    clamped = 0
+    for f in range(frames):
+        want = ref.step(zs[f])
+        np.testing.assert_allclose(th[f], want, rtol=RTOL, atol=ATOL, err_msg=f"frame {f}")
+        np.testing.assert_allclose(nx[f], ref.predicted(), rtol=RTOL, atol=ATOL, err_msg=f"frame {f}")
+        clamped += int(np.sum((want == prm["lo"]) | (want == prm["hi"])))
+        assert np.all(th[f] >= prm["lo"]) and np.all(th[f] <= prm["hi"])
+    if n % 9 == 0:
+        assert clamped > 0            # the limits were reached and held
+
+
+def test_filter_restart_and_null_outputs():
+    dev = torch.device("cuda:0")
+    n = 9
+    prm = dict(dt=1.0, p0_pos=1.0, p0_vel=1.0, q_pos=1e-4, q_vel=1e-4, r=1e-2)
+    kf = tk.kf_alloc(n, dev)
+    z = torch.full((n,), 0.5, dtype=torch.float64, device=dev)
+    out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    for k in range(2):                # the second init restarts from scratch
+        tk.kf_init(kf, n, np.zeros(n), tk.kf_params(n, **prm))
+        tk.kf_step(kf, n, z)          # no outputs requested
+        tk.kf_step(kf, n, z, out[k])
+    torch.testing.assert_close(out[0], out[1], rtol=0, atol=0)
+    ref = KalmanCV.diagonal(np.zeros(n), 1.0, 1.0, 1e-4, 1e-4, 1e-2, 1.0)
+    ref.step(np.full(n, 0.5))
+    np.testing.assert_allclose(out[0].cpu().numpy(), ref.step(np.full(n, 0.5)), rtol=RTOL, atol=ATOL)
+
+
+@pytest.mark.parametrize("n_arms", [1, 2])
+def test_cmaes_estimate_decodes_joints(n_arms):
+    dev = torch.device("cuda:0")
+    n, lam = 9 * n_arms, 32
+    chains = [scenes.chain(), scenes.chain(1.3)][:n_arms]
+    rng = np.random.default_rng(77 + n_arms)
+    state = tk.cmaes_alloc(n, lam, dev)
+    scale = np.tile(scenes.DEFAULT_SCALE, n_arms)
+    offset = rng.normal(size=n) * 0.2
+    # means spread well beyond [lb, ub] so that the cosine map folds them back
+    tk.cmaes_init(state, n, lam, rng.normal(size=n) * 20.0, 1.0, offset, scale, 5, n_blocks=n_arms)
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    tk.cmaes_estimate(state, n, lam, chains, z)
+    v = tk.cmaes_view(state, n, lam)
+    phys = v["offset"] + v["scale"] * v["mean"]
+    want = phys.copy()
+    for arm in range(n_arms):
+        for j in range(3):
+            i = 9 * arm + 6 + j
+            want[i] = oracle.decode(phys[i], chains[arm].q_lb[j], chains[arm].q_ub[j])
+            assert chains[arm].q_lb[j] <= want[i] <= chains[arm].q_ub[j]
+    np.testing.assert_allclose(z.cpu().numpy(), want, rtol=1e-14, atol=1e-15)
+    with pytest.raises(tk.TkError):
+        tk.cmaes_estimate(state, n + 1, lam, chains, z)
+
+
+def test_tracker_filters_its_raw_estimates():
+    """Frame loop: the filtered estimates of tracker.Tracker are the oracle
+    filter run over the tracker's own raw estimates (joint angles clamped),
+    and the raw estimate of each frame is the CMA-ES mean after its
+    generations."""
+    dev = torch.device("cuda:0")
+    wl = scenes.workload("small")
+    cam, chain = wl["cam"], scenes.chain()
+    prob = tracker.Problem([wl["mesh"]], [chain], cam, dev)
+    F, G = 6, 8
+    traj = scenes.trajectory(scenes.rng_for(0, scenes.SUB_TRAJ), cam, F)
+    th = torch.as_tensor(traj.astype(np.float32), device=dev)
+    targets, kps = prob.render(th), prob.keypoints(th)
+    gen = tracker.Generation(prob, wl["lam"], loss_kind=tk.LOSS_IOU, lambda_kp=0.1)
+    filt = scenes.FILTER_TRACK
+    trk = tracker.Tracker(gen, scenes.DEFAULT_SCALE, G, 5, filt=filt)
+    trk.start(traj[0])
+    lo = np.array([-np.inf] * 6 + list(chain.q_lb))
+    hi = np.array([np.inf] * 6 + list(chain.q_ub))
+    ms, vs = filt["meas_std"], filt["vel_std"]
+    x0 = traj[0].copy()
+    x0[6:9] = tracker.decode_joints(x0[6:9], chain)
+    ref = KalmanCV.diagonal(x0, ms ** 2, (5 * vs) ** 2, filt["pos_std"] ** 2, vs ** 2, ms ** 2, filt["dt"], lo, hi)
+    for f in range(F):
+        trk.begin_frame(f, targets[f], kps[f])
+        for _ in range(G):
+            gen.ask_eval_tell()
+        v = tk.cmaes_view(gen.state, gen.n, gen.lam)
+        res = trk.end_frame()
+        phys = v["offset"] + v["scale"] * v["mean"]
+        np.testing.assert_allclose(res["z"][:6], phys[:6], rtol=0, atol=0)
+        np.testing.assert_allclose(res["z"][6:], [oracle.decode(phys[6 + j], chain.q_lb[j], chain.q_ub[j])
+                                                  for j in range(3)], rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(res["theta"], ref.step(res["z"]), rtol=RTOL, atol=ATOL)
+        assert np.all(res["theta"][6:] >= chain.q_lb) and np.all(res["theta"][6:] <= chain.q_ub)
+    raw = tracker.Tracker(gen, scenes.DEFAULT_SCALE, G, 5, filt=None)
+    raw.start(traj[0])
+    raw.begin_frame(0, targets[0], kps[0])
+    gen.ask_eval_tell()
+    r = raw.end_frame()
+    np.testing.assert_array_equal(r["theta"], r["z"])
