@@ -147,28 +147,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Hardware FP64 reciprocal / reciprocal square root refined by one Newton
-// step: a few ulps, enough for Jacobi rotations (which only need to be
-// orthogonal to working precision), at a fraction of the latency of the
-// correctly rounded division and square root.
-__device__ __forceinline__ double rcp_fast(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    return r * (2.0 - x * r);
-}
-__device__ __forceinline__ double rsqrt_fast(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-    return r * (1.5 - 0.5 * x * r * r);
-}
-__device__ __forceinline__ double sqrt_fast(double x) { return x * rsqrt_fast(x); }
-
-// Refined reciprocal square root: hardware estimate plus two Newton steps,
-// accurate to a few ulps (rotations must stay orthogonal to working precision).
-__device__ __forceinline__ double rsqrt_refined(double x) {
-    double r = __builtin_amdgcn_rsq(x);
-    r = r * (1.5 - 0.5 * x * r * r);
-    return r * (1.5 - 0.5 * x * r * r);
-}
-
+// The rotations below use the hardware FP64 reciprocal square root refined by
+// Newton steps r <- r (1.5 - 0.5 x r^2) (explicit fused multiply-adds, the
+// same in every form of the path): one step for sqrt(d^2 + 4 a_pq^2),
+// which only sets the angle, and two for the normalisation, so that c and s
+// are orthogonal to working precision, at a fraction of the latency of the
+// correctly rounded square root and division.
 // Column i of the symmetric Schur rotation of the pair (p, q) = (min, max)
 // of (i, pi): J(i, i) = c and J(pi, i) = s', with s' = -s for i = p and +s
 // for i = q, where tan(theta) = t zeroes the (p, q) entry of J^T A J:
@@ -179,22 +163,39 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
 // |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|); otherwise (c, s') = (1, 0).
 // Both members of a pair evaluate the same operands in the same order, so
 // they agree bit for bit.
-__device__ __forceinline__ bool jacobi_rotation(double a_ii, double a_pp, double a_ip, bool i_is_p,
-                                                bool paired, double* c_out, double* s_out) {
-    const double app = i_is_p ? a_ii : a_pp;
-    const double aqq = i_is_p ? a_pp : a_ii;
-    const double apq = a_ip;
-    const bool rot = paired && apq != 0.0 && apq * apq > 1e-30 * fabs(app * aqq);
-    const double d = aqq - app;
-    const double q2 = 4.0 * apq * apq;
-    const double x = d * d + q2;
-    const double w = fabs(d) + x * rsqrt_fast(x);
-    const double r = rsqrt_refined(w * w + q2);
-    const double c = w * r;
-    const double sn = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * r;
-    *c_out = rot ? c : 1.0;
-    *s_out = rot ? (i_is_p ? -sn : sn) : 0.0;
-    return rot;
+// Two such columns (positions i and j of one entry) are computed step by step
+// in lockstep so that their dependent FP64 chains overlap.
+__device__ __forceinline__ bool jacobi_rotation2(double a_ii, double a_pp, double a_ip, bool i_is_p, double a_jj,
+                                                 double a_qq, double a_jq, bool j_is_p, bool paired, double* ci,
+                                                 double* si, double* cj, double* sj) {
+    const double app1 = i_is_p ? a_ii : a_pp, aqq1 = i_is_p ? a_pp : a_ii;
+    const double app2 = j_is_p ? a_jj : a_qq, aqq2 = j_is_p ? a_qq : a_jj;
+    const double d1 = aqq1 - app1, d2 = aqq2 - app2;
+    const double p1 = a_ip * a_ip, p2 = a_jq * a_jq;
+    const double q1 = 4.0 * p1, q2 = 4.0 * p2;
+    const double x1 = fma(d1, d1, q1), x2 = fma(d2, d2, q2);
+    const double hx1 = -0.5 * x1, hx2 = -0.5 * x2;
+    double r1 = __builtin_amdgcn_rsq(x1), r2 = __builtin_amdgcn_rsq(x2);
+    r1 = r1 * fma(hx1 * r1, r1, 1.5);
+    r2 = r2 * fma(hx2 * r2, r2, 1.5);
+    const double w1 = fma(x1, r1, fabs(d1)), w2 = fma(x2, r2, fabs(d2));
+    const double y1 = fma(w1, w1, q1), y2 = fma(w2, w2, q2);
+    const double hy1 = -0.5 * y1, hy2 = -0.5 * y2;
+    double t1 = __builtin_amdgcn_rsq(y1), t2 = __builtin_amdgcn_rsq(y2);
+    t1 = t1 * fma(hy1 * t1, t1, 1.5);
+    t2 = t2 * fma(hy2 * t2, t2, 1.5);
+    t1 = t1 * fma(hy1 * t1, t1, 1.5);
+    t2 = t2 * fma(hy2 * t2, t2, 1.5);
+    const double c1 = w1 * t1, c2 = w2 * t2;
+    const double sn1 = (d1 >= 0.0 ? 2.0 * a_ip : -2.0 * a_ip) * t1;
+    const double sn2 = (d2 >= 0.0 ? 2.0 * a_jq : -2.0 * a_jq) * t2;
+    const bool rot1 = paired && a_ip != 0.0 && p1 > 1e-30 * fabs(app1 * aqq1);
+    const bool rot2 = paired && a_jq != 0.0 && p2 > 1e-30 * fabs(app2 * aqq2);
+    *ci = rot1 ? c1 : 1.0;
+    *si = rot1 ? (i_is_p ? -sn1 : sn1) : 0.0;
+    *cj = rot2 ? c2 : 1.0;
+    *sj = rot2 ? (j_is_p ? -sn2 : sn2) : 0.0;
+    return rot1 || rot2;
 }
 
 // dynamic LDS: elite rows Y[mu][n].  The state is staged in LDS first so that
@@ -241,7 +242,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
     __shared__ double s_scal[4];
     __shared__ double s_mean[kMaxN];
-    __shared__ double2 s_cs[kMaxN];   // (c_i, s'_i): column i of the current rotation
+    __shared__ int s_pos[kMaxN];          // final Jacobi position of each index
 
     StateView S = state_view(blob, n, lam);
     const int tid = threadIdx.x;
@@ -422,196 +423,192 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         s_T[e] = t;                                   // B^T C B
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += NT) {
-        const int i = e / n, j = e % n;
-        double v = 0.5 * (s_T[i * n + j] + s_T[j * n + i]);
-        if (i / nb != j / nb) v = 0.0;
-        s_A[e] = v;
-        s_V[e] = s_B[e];
-    }
-    __syncthreads();
 
-    // Cyclic Jacobi in tournament order, run by wave 0 alone (no workgroup
-    // barriers).  A round pairs every index of a block with its partner in
-    // the circle-method schedule; rounds repeat in cyclic order.  Per round:
-    //   - lane i < n computes column i of the rotation (c_i, s'_i) once and
-    //     publishes it in LDS;
-    //   - when nothing rotates, every lane tests its upper-triangle entries
-    //     against the rotation threshold; if no pair anywhere exceeds it the
-    //     iteration has converged (another sweep would rotate nothing);
-    //   - otherwise every lane forms its entries of A' = J^T A J (upper
-    //     triangle, mirrored) and V' = V J in the other buffer.
-    // Partners are register state: for a local index l != 0 of a block the
-    // circle method pairs l with q_l(r) = ((2r - l - 1) mod k) + 1, k = m - 1,
-    // except that l meets player 0 when q_l(r) = l; index 0 meets
-    // R = (r == 0 ? k : r); a partner >= nb is the dummy (no rotation).
-    // q_l advances by 2 (mod k) from one round to the next.
+    // Cyclic Jacobi in tournament order with a fixed pairing, run by wave 0
+    // alone (no workgroup barriers).  Each block is held in m = nb + (nb odd)
+    // positions (an odd block gets a zero dummy index, which never rotates):
+    // A as an m x m matrix and V as nb rows x m position columns.  In every
+    // round the pairs are the positions (2k, 2k+1); after the round, indices
+    // move to new positions (0 stays, 1 -> 3, 2 -> 1, other even p -> p - 2,
+    // other odd p -> p + 2, the last odd position -> m - 2), a round-robin in
+    // which every two indices of a block meet once per m - 1 rounds and the
+    // layout returns to the start.  The rotated A and V are written straight
+    // into their next positions, so every lane reads and writes the same LDS
+    // addresses in every round and computes them once.  Per round, every lane
+    // holding an upper-triangle entry (i, j) of A:
+    //   - reads the entries it needs and computes the rotations of positions
+    //     i and j itself (no exchange between lanes);
+    //   - when nothing rotates anywhere, tests its entry against the rotation
+    //     threshold; if no pair exceeds it the iteration has converged
+    //     (another sweep would rotate nothing);
+    //   - writes its entry of A' = J^T A J (mirrored) and two entries of
+    //     V' = V J into the other buffer, at the next round's positions (with
+    //     no rotation this only moves the indices).
     if (tid < kWave64) {
         const int m = nb + (nb & 1);
-        const int k1 = m - 1;                      // rounds per sweep (odd)
-        const int ntri_b = nb * (nb + 1) / 2;
-        const int n_a = n_blocks * ntri_b;         // upper-triangle entries inside the blocks
-        const int n_v = n_blocks * nb * nb;        // all entries inside the blocks
+        const int k1 = m - 1;                      // rounds per sweep
+        const int mm = m * m;
+        const int ntri_m = m * (m + 1) / 2;
+        const int n_a = n_blocks * ntri_m;         // upper-triangle entries of the blocks
+        const int n_v = n_blocks * nb * m;         // V entries of the blocks
+        auto move = [m](int p) {                   // position of an index in the next round
+            if (m == 2 || p == 0) return p;
+            if (p == 2) return 1;
+            if (p & 1) return p + 2 <= m - 1 ? p + 2 : m - 2;
+            return p - 2;
+        };
+        // positional layout: index l of block b starts at position l
+        for (int e = tid; e < n_blocks * mm; e += kWave64) {
+            const int b = e / mm, i = (e % mm) / m, j = e % m;
+            const int gi = b * nb + i, gj = b * nb + j;
+            s_A[e] = (i < nb && j < nb) ? 0.5 * (s_T[gi * n + gj] + s_T[gj * n + gi]) : 0.0;
+        }
+        for (int e = tid; e < n_v; e += kWave64) {
+            const int b = e / (nb * m), r = (e % (nb * m)) / m, j = e % m;
+            s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
+        }
         constexpr int kASlots = AS;
-        constexpr int kVSlots = VS;
+        static_assert(VS == 2 * AS, "two V entries per A entry");
         const int na_slots = (n_a + kWave64 - 1) / kWave64;
-        const int nv_slots = (n_v + kWave64 - 1) / kWave64;
-        auto q_start = [k1](int l) {               // q_l(0)
-            int t = (-l - 1) % k1;
-            return (t < 0 ? t + k1 : t) + 1;
-        };
-        auto q_next = [k1](int q) {
-            q += 2;
-            q -= q > k1 ? k1 : 0;
-            q -= q > k1 ? k1 : 0;
-            return q;
-        };
-        auto partner = [nb](int l, int q, int R) {
-            const int p = l == 0 ? R : (q == l ? 0 : q);
-            return p < nb ? p : l;
-        };
-        int a_i[kASlots], a_j[kASlots], a_base[kASlots], a_qi[kASlots], a_qj[kASlots];
-        int v_row[kVSlots], v_j[kVSlots], v_base[kVSlots], v_q[kVSlots];
+        // Fixed offsets of a lane's A entry (i, j), i <= j, of block b: the
+        // entry, its partner entries, the operands of the rotations of
+        // positions i and j, and its two targets.  The lane also updates two
+        // V entries, in columns i and j: row j - i of column i and row
+        // m - j + i of column j (when < nb), which covers rows 0..m of every
+        // column exactly once over a block's entries.
+        int a_ij[kASlots], a_ipj[kASlots], a_pij[kASlots], a_pipj[kASlots];
+        int a_ii[kASlots], a_jj[kASlots], a_qi[kASlots], a_qj[kASlots], a_iq[kASlots], a_jq[kASlots];
+        int a_w1[kASlots], a_w2[kASlots];
+        int v0_r[kASlots], v0_rp[kASlots], v0_w[kASlots], v1_r[kASlots], v1_rp[kASlots], v1_w[kASlots];
+        bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
     #pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
             const int e = min(tid + kWave64 * sl, n_a - 1);
-            const int blk = e / ntri_b;
-            int li = 0, rem = e - blk * ntri_b;
-            while (rem >= nb - li) { rem -= nb - li; li++; }
-            a_base[sl] = blk * nb;
-            a_i[sl] = blk * nb + li;
-            a_j[sl] = blk * nb + li + rem;
-            a_qi[sl] = q_start(li);
-            a_qj[sl] = q_start(li + rem);
+            const int b = e / ntri_m;
+            int i = 0, rem = e - b * ntri_m;
+            while (rem >= m - i) { rem -= m - i; i++; }
+            const int j = i + rem, base = b * mm, vbase = b * nb * m;
+            a_ij[sl] = base + i * m + j;
+            a_ipj[sl] = base + i * m + (j ^ 1);
+            a_pij[sl] = base + (i ^ 1) * m + j;
+            a_pipj[sl] = base + (i ^ 1) * m + (j ^ 1);
+            a_ii[sl] = base + i * m + i;
+            a_jj[sl] = base + j * m + j;
+            a_qi[sl] = base + (i ^ 1) * m + (i ^ 1);
+            a_qj[sl] = base + (j ^ 1) * m + (j ^ 1);
+            a_iq[sl] = base + i * m + (i ^ 1);
+            a_jq[sl] = base + j * m + (j ^ 1);
+            a_w1[sl] = base + move(i) * m + move(j);
+            a_w2[sl] = base + move(j) * m + move(i);
+            a_ok[sl] = tid + kWave64 * sl < n_a;
+            a_off[sl] = a_ok[sl] && i != j;
+            a_ei[sl] = (i & 1) == 0;
+            a_ej[sl] = (j & 1) == 0;
+            const int r0 = j - i, r1 = m - j + i;
+            v0_ok[sl] = a_ok[sl] && r0 < nb;
+            v1_ok[sl] = a_ok[sl] && r1 < nb;
+            v0_r[sl] = vbase + min(r0, nb - 1) * m + i;
+            v0_rp[sl] = vbase + min(r0, nb - 1) * m + (i ^ 1);
+            v0_w[sl] = vbase + min(r0, nb - 1) * m + move(i);
+            v1_r[sl] = vbase + min(r1, nb - 1) * m + j;
+            v1_rp[sl] = vbase + min(r1, nb - 1) * m + (j ^ 1);
+            v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
-    #pragma unroll
-        for (int sl = 0; sl < kVSlots; sl++) {
-            const int e = min(tid + kWave64 * sl, n_v - 1);
-            const int blk = e / (nb * nb), r = e - blk * nb * nb;
-            v_row[sl] = (blk * nb + r / nb) * n;
-            v_base[sl] = blk * nb;
-            v_j[sl] = blk * nb + r % nb;
-            v_q[sl] = q_start(r % nb);
-        }
-        const int my_t = min(tid, n - 1);
-        const int my_blk = my_t / nb;
-        const int my_l = my_t - my_blk * nb;
-        int my_q = q_start(my_l);
         double* Acur = s_A;
         double* Anext = s_T;
         double* Vcur = s_V;
         double* Vnext = s_C;
-        for (int e = tid; e < nn; e += kWave64) {   // entries outside the blocks stay zero in both buffers
-            const int i = e / n, j = e % n;
-            if (i / nb != j / nb) {
-                Anext[e] = 0.0;
-                Vnext[e] = 0.0;
-            }
-        }
         wave_sync();
         const int max_rounds = kMaxSweeps * k1;
-        int round = 0;
+        int moved = 0;                             // rounds applied (index moves) modulo k1
         for (int it = 0; it < max_rounds; it++) {
-            const int R = round == 0 ? k1 : round;
-            // rotation of index my_t
-            const int pt = my_blk * nb + partner(my_l, my_q, R);
-            double c_t, s_t;
-            const bool rot = jacobi_rotation(Acur[my_t * n + my_t], Acur[pt * n + pt], Acur[my_t * n + pt], my_t < pt,
-                                             tid < n && pt != my_t, &c_t, &s_t);
-            // operands of this round's updates (independent of the rotations)
-            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
+            // every lane reads its operands and computes the rotations of its
+            // two positions itself (the two members of a pair, and every lane
+            // needing the same position, get the same bits)
+            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots], d_i[kASlots], d_j[kASlots];
+            double ci[kASlots], si[kASlots], cj[kASlots], sj[kASlots];
+            double y0[kASlots], y0p[kASlots], y1[kASlots], y1p[kASlots];
+            bool rot = false;
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
                 if (sl < na_slots) {
-                    const int pi = a_base[sl] + partner(a_i[sl] - a_base[sl], a_qi[sl], R);
-                    const int pj = a_base[sl] + partner(a_j[sl] - a_base[sl], a_qj[sl], R);
-                    const int ri = a_i[sl] * n, rp = pi * n;
-                    x_ij[sl] = Acur[ri + a_j[sl]];
-                    x_ipj[sl] = Acur[ri + pj];
-                    x_pij[sl] = Acur[rp + a_j[sl]];
-                    x_pipj[sl] = Acur[rp + pj];
+                    x_ij[sl] = Acur[a_ij[sl]];
+                    x_ipj[sl] = Acur[a_ipj[sl]];
+                    x_pij[sl] = Acur[a_pij[sl]];
+                    x_pipj[sl] = Acur[a_pipj[sl]];
+                    d_i[sl] = Acur[a_ii[sl]];
+                    d_j[sl] = Acur[a_jj[sl]];
+                    const double q_i = Acur[a_qi[sl]], q_j = Acur[a_qj[sl]];
+                    const double o_i = Acur[a_iq[sl]], o_j = Acur[a_jq[sl]];
+                    y0[sl] = Vcur[v0_r[sl]];
+                    y0p[sl] = Vcur[v0_rp[sl]];
+                    y1[sl] = Vcur[v1_r[sl]];
+                    y1p[sl] = Vcur[v1_rp[sl]];
+                    rot |= jacobi_rotation2(d_i[sl], q_i, o_i, a_ei[sl], d_j[sl], q_j, o_j, a_ej[sl], a_ok[sl],
+                                            &ci[sl], &si[sl], &cj[sl], &sj[sl]);
                 }
             }
-            double y_ij[kVSlots], y_ipj[kVSlots];
-    #pragma unroll
-            for (int sl = 0; sl < kVSlots; sl++) {
-                if (sl < nv_slots) {
-                    const int pj = v_base[sl] + partner(v_j[sl] - v_base[sl], v_q[sl], R);
-                    y_ij[sl] = Vcur[v_row[sl] + v_j[sl]];
-                    y_ipj[sl] = Vcur[v_row[sl] + pj];
-                }
-            }
-            // advance the schedule
-            round = round + 1 == k1 ? 0 : round + 1;
-            my_q = q_next(my_q);
-    #pragma unroll
-            for (int sl = 0; sl < kASlots; sl++) {
-                a_qi[sl] = q_next(a_qi[sl]);
-                a_qj[sl] = q_next(a_qj[sl]);
-            }
-    #pragma unroll
-            for (int sl = 0; sl < kVSlots; sl++) v_q[sl] = q_next(v_q[sl]);
-
             if (__ballot(rot) == 0ull) {
                 // nothing rotates in this round: stop if no pair exceeds the threshold
                 bool open = false;
     #pragma unroll
                 for (int sl = 0; sl < kASlots; sl++) {
                     if (sl < na_slots) {
-                        const int i = a_i[sl], j = a_j[sl];
                         const double aij = x_ij[sl];
-                        open |= tid + kWave64 * sl < n_a && i != j &&
-                                aij * aij > 1e-30 * fabs(Acur[i * n + i] * Acur[j * n + j]);
+                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(d_i[sl] * d_j[sl]);
                     }
                 }
                 if (__ballot(open) == 0ull) break;
-                continue;
             }
-            if (tid < n) s_cs[tid] = make_double2(c_t, s_t);
-            wave_sync();
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
-                if (sl < na_slots && tid + kWave64 * sl < n_a) {
-                    const double2 ci = s_cs[a_i[sl]], cj = s_cs[a_j[sl]];
-                    const double v = ci.x * (cj.x * x_ij[sl] + cj.y * x_ipj[sl]) +
-                                     ci.y * (cj.x * x_pij[sl] + cj.y * x_pipj[sl]);
-                    Anext[a_i[sl] * n + a_j[sl]] = v;
-                    Anext[a_j[sl] * n + a_i[sl]] = v;
+                if (sl < na_slots && a_ok[sl]) {
+                    const double u0 = fma(cj[sl], x_ij[sl], sj[sl] * x_ipj[sl]);
+                    const double u1 = fma(cj[sl], x_pij[sl], sj[sl] * x_pipj[sl]);
+                    const double v = fma(ci[sl], u0, si[sl] * u1);
+                    Anext[a_w1[sl]] = v;
+                    Anext[a_w2[sl]] = v;
                 }
-            }
-    #pragma unroll
-            for (int sl = 0; sl < kVSlots; sl++) {
-                if (sl < nv_slots && tid + kWave64 * sl < n_v) {
-                    const double2 cj = s_cs[v_j[sl]];
-                    Vnext[v_row[sl] + v_j[sl]] = cj.x * y_ij[sl] + cj.y * y_ipj[sl];
-                }
+                if (sl < na_slots && v0_ok[sl]) Vnext[v0_w[sl]] = fma(ci[sl], y0[sl], si[sl] * y0p[sl]);
+                if (sl < na_slots && v1_ok[sl]) Vnext[v1_w[sl]] = fma(cj[sl], y1[sl], sj[sl] * y1p[sl]);
             }
             wave_sync();
             double* t = Acur; Acur = Anext; Anext = t;
             t = Vcur; Vcur = Vnext; Vnext = t;
+            moved = moved + 1 == k1 ? 0 : moved + 1;
         }
-        // 6. B = V, D = sqrt(eigenvalues) with a floor at 1e-20 * max
+        // final position of every index; 6. D = sqrt(eigenvalues) with a
+        // floor at 1e-20 * max (the maximum by a butterfly over the lanes,
+        // which ignores NaN like a running fmax from 0), B = V
+        double ev = 0.0;
+        if (tid < n) {
+            int p = tid % nb;
+            for (int r = 0; r < moved; r++) p = move(p);
+            s_pos[tid] = p;
+            ev = Acur[(tid / nb) * mm + p * m + p];
+        }
+        double emax = tid < n ? fmax(0.0, ev) : 0.0;
+        for (int off = kWave64 / 2; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off));
+        const double floor_v = 1e-20 * emax;
+        const bool floored = tid < n && !(ev >= floor_v);
+        if (tid < n) {
+            const double d = sqrt(floored ? floor_v : ev);
+            S.D[tid] = d;
+            s_D[tid] = d;
+        }
+        const bool any_floored = __ballot(floored) != 0ull;
         if (tid == 0) {
-            double emax = 0.0;
-            for (int i = 0; i < n; i++) emax = fmax(emax, Acur[i * n + i]);
-            const double floor_v = 1e-20 * emax;
-            int flags = 0;
-            for (int i = 0; i < n; i++) {
-                double e = Acur[i * n + i];
-                if (!(e >= floor_v)) {
-                    e = floor_v;
-                    flags |= 1;
-                }
-                S.D[i] = sqrt(e);
-                s_D[i] = S.D[i];
-            }
             const double sg = *S.sigma;
+            int flags = any_floored ? 1 : 0;
             if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
             S.hdr->flags = flags;
         }
+        wave_sync();
         for (int e = tid; e < nn; e += kWave64) {
-            S.B[e] = Vcur[e];
-            s_B[e] = Vcur[e];
+            const int i = e / n, j = e % n, b = i / nb;
+            const double v = b == j / nb ? Vcur[b * nb * m + (i - b * nb) * m + s_pos[j]] : 0.0;
+            S.B[e] = v;
+            s_B[e] = v;
         }
     }
     if (!ASK) return;
