@@ -11,6 +11,10 @@ product path.
 * ``cmaes.py`` -- FP64 CMA-ES with Philox4x32-10 + Box-Muller sampling
   (paper Sec. III-A.1, completed with Hansen's tutorial where the paper is
   silent).
+* ``tko_soft.c`` -- FP64 soft silhouette (sigmoid of the signed edge
+  distance, probabilistic OR over faces), its squared-error loss and the
+  analytic gradient through projection, forward kinematics and the cosine
+  joint map, plus the forward-kinematics Jacobian.
 * ``brute.py`` -- exact rational point-in-triangle checker for tiny images.
 * ``kalman.py`` -- constant-velocity Kalman filter of the per-frame estimates
   in the general 2n-state matrix form (paper Sec. III-A.4).
@@ -26,9 +30,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "tko.c")
+_SRCS = [_SRC, os.path.join(_HERE, "tko_soft.c")]
 
 BUILD_CMD = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-             "-fno-fast-math", "-o", _SO, _SRC, "-lm"]
+             "-fno-fast-math", "-o", _SO, *_SRCS, "-lm"]
 
 
 def build() -> str:
@@ -60,7 +65,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
+                os.path.getmtime(f) for f in _SRCS + [os.path.join(_HERE, "tko.h")]):
             build()
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
@@ -83,6 +89,9 @@ def lib():
         L.tko_kp_loss.argtypes = [P, P, d]
         L.tko_eval_batch.argtypes = [P, i32, i32, P, P, P, P, P, P, i32]
         L.tko_max_threads.restype = i32
+        L.tko_fk_jacobian.argtypes = [P, P, P]
+        L.tko_soft.restype = d
+        L.tko_soft.argtypes = [P, i32, P, P, P, d, P, P, P]
         _lib = L
     return _lib
 
@@ -225,6 +234,36 @@ def eval_batch(theta, chains, meshes, cam, target, n_threads=0, want_masks=False
                          _p(masks) if masks is not None else None, int(n_threads))
     del words
     return (cnt, masks) if want_masks else cnt
+
+
+def fk_jacobian(theta, chain) -> np.ndarray:
+    """d M_l / d theta_k as [9, 4, 12] (FP64)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.zeros((9, 4, 12))
+    c = _chain(chain)
+    lib().tko_fk_jacobian(_p(th), ctypes.byref(c), _p(out))
+    return out
+
+
+def soft(theta_arms, chains, meshes, cam, sigma, target=None, want_S=False, want_grad=False):
+    """Soft silhouette loss L = sum_p (S - M)^2 of the arms at theta [n_arms*9]
+    (FP64); returns (L, S [H, W] or None, dL/dtheta [n_arms*9] or None)."""
+    theta = np.ascontiguousarray(theta_arms, dtype=np.float64).reshape(-1)
+    n_arms = len(meshes)
+    ch = (_Chain * n_arms)(*[_chain(c) for c in chains])
+    keep = [(np.ascontiguousarray(m.vertices, dtype=np.float32),
+             np.ascontiguousarray(m.triangles, dtype=np.int32),
+             np.ascontiguousarray(m.vertex_link, dtype=np.uint8)) for m in meshes]
+    me = (_Mesh * n_arms)(*[_Mesh(m.n_vertices, m.n_triangles, _p(v), _p(t), _p(l))
+                            for m, (v, t, l) in zip(meshes, keep)])
+    cm = _cam(cam)
+    tgt = None if target is None else np.ascontiguousarray(target, dtype=np.uint64)
+    S = np.zeros((cam.height, cam.width)) if want_S else None
+    g = np.zeros(9 * n_arms) if want_grad else None
+    L = lib().tko_soft(_p(theta), n_arms, ch, me, ctypes.byref(cm), float(sigma),
+                       _p(tgt) if tgt is not None else None, _p(S) if S is not None else None,
+                       _p(g) if g is not None else None)
+    return float(L), S, g
 
 
 def max_threads() -> int:

@@ -8,7 +8,8 @@
  * Paper sections followed (arXiv 2603.11404):
  *   Sec. III-A.3 (state parameterisation: look-at rotation, cosine joint map),
  *   Sec. III-A.2 (renderer S = R(K(Pi(T_r^c T_m^r(q) v_m))), render loss),
- *   Sec. IV (mask error 1 - IoU, keypoint reprojection error).
+ *   Sec. IV (mask error 1 - IoU, keypoint reprojection error),
+ *   and a soft (differentiable) silhouette with its gradient (tko_soft.c).
  */
 #ifndef TKO_H
 #define TKO_H
@@ -76,6 +77,18 @@ void tko_eval_batch(const double* theta, int32_t batch, int32_t n_arms, const tk
                     int64_t* counts, uint64_t* masks_out /* nullable [batch][words] */,
                     int32_t n_threads);
 int32_t tko_max_threads(void);
+
+/* Jacobian of the link transforms of tko_fk: dM[k][l] = d M_l / d theta_k
+ * (theta as for tko_fk, joints through the cosine map), 3x4 each. */
+void tko_fk_jacobian(const double theta[9], const tko_chain* ch, double dM[9][4][12]);
+
+/* Soft silhouette of the arms at theta[n_arms * 9] (definition in
+ * tko_soft.c): returns L = sum_p (S(p) - M(p))^2 over the image, with M the
+ * word mask target (NULL: all zero).  S_out (nullable, [H][W]) gets S;
+ * grad (nullable, [n_arms * 9]) gets dL/dtheta. */
+#define TKO_SOFT_MAXP 18
+double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
+                const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad);
 
 #ifdef __cplusplus
 }
