@@ -297,6 +297,7 @@ def main():
         out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
         out["bimanual960"] = bimanual_leg(dev)
         out["batch64"] = batch_leg(dev)
+        out["soft640"] = soft_leg(dev)
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if not args.no_cpu_baseline:
@@ -416,6 +417,77 @@ def batch_leg(dev, count=64, gens=10):
             "candidate_evals_per_s": lam_total / (batch_ms * 1e-3), "per_problem_launches_ms": single_ms,
             "batched_vs_per_problem": single_ms / batch_ms,
             "workgroup_sizes": {str(t): threads.count(t) for t in sorted(set(threads))}}
+
+
+def soft_leg(dev, reps=10):
+    """Differentiable form: soft silhouette forward + backward (FK, projection,
+    binning, soft raster, loss; face-major backward, FK Jacobian) of 256
+    candidates of a 49544-triangle instrument at 640x480, sigma = 1 px; and
+    the refinement of one problem's CMA-ES mean by 5 Adam steps per generation."""
+    import torch
+
+    import scenes
+    from paper_2603_11404_amd import tk, tracker
+
+    wl = scenes.workload("soft640")
+    mesh, cam, lam, sigma = wl["mesh"], wl["cam"], wl["lam"], wl["sigma"]
+    chain = scenes.chain()
+    rng = scenes.rng_for(wl["index"], scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    prob = tracker.Problem([mesh], [chain], cam, dev)
+    th_t = torch.as_tensor(truth[None].astype(np.float32), device=dev)
+    prob.set_target(prob.render(th_t)[0])
+    theta = torch.as_tensor((truth[None] + scenes.DEFAULT_SCALE[None] * rng.normal(size=(lam, 9))).astype(np.float32),
+                            device=dev)
+    xf = torch.empty(lam, 1, 4, 12, dtype=torch.float32, device=dev)
+    ws = tk.soft_workspace(lam, prob.meshes, cam, dev)
+    loss = torch.empty(lam, dtype=torch.float64, device=dev)
+    g = torch.empty_like(theta)
+
+    def fwd_bwd():
+        tk.fk_transform(theta, lam, 1, prob.chains, xf)
+        tk.soft_forward(xf, lam, prob.meshes, cam, sigma, prob.target, loss, ws)
+        tk.soft_backward(theta, lam, prob.chains, prob.meshes, cam, sigma, g, ws)
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd_ms = bwd_ms = 0.0
+    for _ in range(reps):
+        a.record()
+        tk.fk_transform(theta, lam, 1, prob.chains, xf)
+        tk.soft_forward(xf, lam, prob.meshes, cam, sigma, prob.target, loss, ws)
+        b.record()
+        tk.soft_backward(theta, lam, prob.chains, prob.meshes, cam, sigma, g, ws)
+        c.record()
+        torch.cuda.synchronize()
+        fwd_ms += a.elapsed_time(b) / reps
+        bwd_ms += b.elapsed_time(c) / reps
+    # refinement of one problem's mean: 5 Adam steps after each generation
+    gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU)
+    gen.init(np.zeros(9), 1.0, truth + scenes.DEFAULT_SCALE * rng.normal(size=9), scenes.DEFAULT_SCALE, 7)
+    gen.ask_eval_tell()
+    gen.refine(5, 0.1, sigma)
+    torch.cuda.synchronize()
+    gens = 20
+    a.record()
+    for _ in range(gens):
+        gen.ask_eval_tell()
+    b.record()
+    for _ in range(gens):
+        gen.ask_eval_tell()
+        gen.refine(5, 0.1, sigma)
+    c.record()
+    torch.cuda.synchronize()
+    plain_gen = a.elapsed_time(b) / gens
+    refined_gen = b.elapsed_time(c) / gens
+    log(f"soft640: forward {fwd_ms:.2f} ms + backward {bwd_ms:.2f} ms for {lam} candidates; generation "
+        f"{plain_gen:.3f} ms, with 5 Adam steps on the mean {refined_gen:.3f} ms")
+    return {"workload": f"{mesh.n_triangles} tris, {cam.width}x{cam.height}, {lam} candidates, sigma {sigma} px",
+            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "candidate_grads_per_s": lam / ((fwd_ms + bwd_ms) * 1e-3),
+            "generation_ms": plain_gen, "generation_with_refine_ms": refined_gen,
+            "refine_steps_per_generation": 5}
 
 
 def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):

@@ -263,6 +263,58 @@ tk_status tk_compose_loss(const int32_t* d_counts, int32_t batch, const int32_t*
                           double lambda_app, const float* d_kp, const float* d_kp_ref, int32_t n_arms,
                           double lambda_kp, double tau, double* d_loss, tk_stream s);
 
+/* ------------------------------------------------------- differentiable form */
+
+/* Soft silhouette (a differentiable stand-in for the renderer of Sec.
+ * III-A.2; loss = the squared-error term of Eq. (6) summed over the pixels):
+ * for the pixel centre p and face j of any arm (FP32 projected corners, no
+ * snapping; faces with a corner in front of z_near or of zero area left out),
+ * d_j(p) is the signed distance to the face boundary (positive inside),
+ * prob_j = (sig(d_j / sigma) - s0) / (1 - s0) for d_j >= -10 sigma and 0
+ * below (s0 = sig(-10), so prob reaches 0 at the cutoff), S(p) = 1 -
+ * prod_j (1 - prob_j) and L = sum_p (S(p) - M(p))^2 per candidate.
+ * Deterministic: the per-pixel sums are taken in 64-bit fixed point and every
+ * other reduction in a fixed order.  Images up to 16384 8x8 tiles (1024x1024;
+ * larger return TK_ERR_UNSUPPORTED). */
+
+/* Workspace bytes of tk_soft_forward / tk_soft_backward for batch candidates
+ * (0 on invalid arguments).  It holds the projected corners, face records,
+ * tile lists (up to 32 tiles per face; larger faces on a per-candidate list),
+ * the per-pixel factor 2 (S - M)(1 - S) / sigma and partial sums. */
+size_t tk_soft_workspace_bytes(int32_t batch, const tk_mesh* meshes, int32_t n_meshes, const tk_camera* cam);
+
+/* Forward pass: d_link_xf [batch][n_meshes][4][12] (tk_fk_transform), one
+ * observed word mask d_target, sigma in pixels (0 < sigma <= 64).  Writes
+ * d_loss [batch] FP64 and, when d_S is not NULL, S [batch][H][W] FP32; keeps in
+ * d_ws (256-byte aligned, tk_soft_workspace_bytes) what the backward pass
+ * reads. */
+tk_status tk_soft_forward(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
+                          const tk_camera* cam, float sigma, const uint64_t* d_target, float* d_S, double* d_loss,
+                          void* d_ws, size_t ws_bytes, tk_stream s);
+
+/* Backward pass of the last tk_soft_forward on the same workspace, meshes,
+ * camera and sigma: d_grad_X [batch][9 n_arms] FP32 = dL/dtheta of the
+ * candidates d_X [batch][9 n_arms] (the theta the link transforms came from),
+ * through the pinhole projection, the link transforms and the forward
+ * kinematics with the cosine joint map (Sec. III-A.3), scaled per candidate
+ * by d_grad_loss [batch] FP64 when not NULL.  chains: host [n_arms]. */
+tk_status tk_soft_backward(const float* d_X, int32_t batch, const tk_chain* chains, const tk_mesh* meshes,
+                           int32_t n_arms, const tk_camera* cam, float sigma, const double* d_grad_loss,
+                           float* d_grad_X, void* d_ws, size_t ws_bytes, tk_stream s);
+
+/* The CMA-ES mean as an FP32 candidate: d_X[i] = offset_i + scale_i m_i. */
+tk_status tk_cmaes_mean_candidate(const void* d_state, int32_t n, int32_t lambda, float* d_X, tk_stream s);
+
+/* Zero an Adam state of dimension n (device, 8 (2n + 1) bytes: m, v, t). */
+tk_status tk_adam_reset(void* d_adam, int32_t n, tk_stream s);
+
+/* One Adam step (Kingma and Ba: m, v moments, bias correction) on the CMA-ES
+ * mean in the normalised space x (theta = offset + scale x), from d_grad_theta
+ * [n] FP32 = dL/dtheta at the mean (gradient in x = gradient in theta x
+ * scale).  Only the mean of the state changes. */
+tk_status tk_cmaes_adam(void* d_state, int32_t n, int32_t lambda, const float* d_grad_theta, void* d_adam,
+                        double lr, double beta1, double beta2, double eps, tk_stream s);
+
 /* ------------------------------------------------------- temporal filter */
 
 /* Constant-velocity Kalman filter of the per-frame estimates (Sec. III-A.4,

@@ -78,6 +78,8 @@ EXPORTS = [
     "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
+    "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
+    "tk_cmaes_adam",
 ]
 
 _lib = None
@@ -127,9 +129,18 @@ def lib():
         L.tk_kf_init.argtypes = [P, i32, P, P, P]
         L.tk_kf_step.argtypes = [P, i32, P, P, P, P]
         L.tk_cmaes_estimate.argtypes = [P, i32, i32, P, i32, P, P]
+        f32 = ctypes.c_float
+        L.tk_soft_workspace_bytes.restype = ctypes.c_size_t
+        L.tk_soft_workspace_bytes.argtypes = [i32, P, i32, P]
+        L.tk_soft_forward.argtypes = [P, i32, P, i32, P, f32, P, P, P, P, ctypes.c_size_t, P]
+        L.tk_soft_backward.argtypes = [P, i32, P, P, i32, P, f32, P, P, P, ctypes.c_size_t, P]
+        L.tk_cmaes_mean_candidate.argtypes = [P, i32, i32, P, P]
+        L.tk_adam_reset.argtypes = [P, i32, P]
+        L.tk_cmaes_adam.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
-                            "tk_raster_workspace_bytes", "tk_batch_table_bytes", "tk_kf_state_bytes"):
+                            "tk_raster_workspace_bytes", "tk_batch_table_bytes", "tk_kf_state_bytes",
+                            "tk_soft_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -381,6 +392,60 @@ def raster_workspace(batch, meshes, device="cuda") -> torch.Tensor:
 
 def _ws(ws):
     return (None, 0) if ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+
+
+# ------------------------------------------------------------------ differentiable form
+
+def soft_workspace_bytes(batch, meshes, cam) -> int:
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    return int(lib().tk_soft_workspace_bytes(batch, arr, nm, ctypes.byref(c)))
+
+
+def soft_workspace(batch, meshes, cam, device="cuda") -> torch.Tensor:
+    """A 256-byte aligned device workspace for tk_soft_forward / tk_soft_backward."""
+    nb = soft_workspace_bytes(batch, meshes, cam)
+    if nb == 0:
+        raise TkError(TK_ERR_INVALID_ARGUMENT, "tk_soft_workspace_bytes: invalid shapes " + lib().tk_last_error().decode())
+    t = torch.empty(nb, dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def soft_forward(link_xf, batch, meshes, cam, sigma, target, loss, ws, S=None, stream=None):
+    """Soft silhouette loss [batch] FP64 (and S [batch, H, W] FP32) of the link transforms."""
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    wp, wb = _ws(ws)
+    _check(lib().tk_soft_forward(_ptr(link_xf), batch, arr, nm, ctypes.byref(c), float(sigma), _ptr(target),
+                                 _ptr(S), _ptr(loss), wp, wb, _stream(stream)))
+
+
+def soft_backward(X, batch, chains, meshes, cam, sigma, grad_X, ws, grad_loss=None, stream=None):
+    """dL/dtheta [batch, 9 n_arms] FP32 of the last soft_forward on ws (scaled by grad_loss [batch] FP64)."""
+    arr, nm = _meshes(meshes)
+    ch = (Chain * nm)(*[chain(x) for x in chains])
+    c = camera(cam)
+    wp, wb = _ws(ws)
+    _check(lib().tk_soft_backward(_ptr(X), batch, ch, arr, nm, ctypes.byref(c), float(sigma), _ptr(grad_loss),
+                                  _ptr(grad_X), wp, wb, _stream(stream)))
+
+
+def cmaes_mean_candidate(state, n, lam, X, stream=None):
+    _check(lib().tk_cmaes_mean_candidate(_ptr(state), n, lam, _ptr(X), _stream(stream)))
+
+
+def adam_alloc(n, device="cuda") -> torch.Tensor:
+    return torch.zeros(2 * n + 1, dtype=torch.float64, device=device)
+
+
+def adam_reset(adam, n, stream=None):
+    _check(lib().tk_adam_reset(_ptr(adam), n, _stream(stream)))
+
+
+def cmaes_adam(state, n, lam, grad_theta, adam, lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().tk_cmaes_adam(_ptr(state), n, lam, _ptr(grad_theta), _ptr(adam), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(stream)))
 
 
 def raster_silhouette(link_xf, batch, meshes, cam, masks, ws=None, stream=None):

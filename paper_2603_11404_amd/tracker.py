@@ -146,6 +146,32 @@ class Generation:
                       kp_ref=p.kp_ref if self.use_kp else None, lambda_app=self.lambda_app,
                       lambda_kp=self.lambda_kp, tau=self.tau, loss=self.loss)
 
+    def refine(self, steps=5, lr=0.1, sigma=1.0):
+        """Gradient refinement of the mean after a generation: `steps` Adam
+        steps (Kingma and Ba defaults, learning rate lr in the normalised
+        space, moments restarted for every call) on the soft-silhouette loss
+        of the mean, each one tk_cmaes_mean_candidate -> tk_fk_transform ->
+        tk_soft_forward -> tk_soft_backward -> tk_cmaes_adam.  Returns the
+        device FP64 loss of the last evaluated mean."""
+        p = self.p
+        if getattr(self, "_soft", None) is None or self._soft[0] != sigma:
+            d = p.device
+            self._soft = (sigma, tk.soft_workspace(1, p.meshes, p.cam, d),
+                          torch.empty(1, self.n, dtype=torch.float32, device=d),
+                          torch.empty(1, p.n_arms, 4, 12, dtype=torch.float32, device=d),
+                          torch.empty(1, dtype=torch.float64, device=d),
+                          torch.empty(1, self.n, dtype=torch.float32, device=d),
+                          tk.adam_alloc(self.n, d))
+        _, ws, X1, xf1, loss1, g1, adam = self._soft
+        tk.adam_reset(adam, self.n)
+        for _ in range(steps):
+            tk.cmaes_mean_candidate(self.state, self.n, self.lam, X1)
+            tk.fk_transform(X1, 1, p.n_arms, p.chains, xf1)
+            tk.soft_forward(xf1, 1, p.meshes, p.cam, sigma, p.target, loss1, ws)
+            tk.soft_backward(X1, 1, p.chains, p.meshes, p.cam, sigma, g1, ws)
+            tk.cmaes_adam(self.state, self.n, self.lam, g1, adam, lr)
+        return loss1
+
     def step_plain(self):
         """Unbatched baseline: the same kernels launched once per candidate (batch = 1)."""
         p = self.p

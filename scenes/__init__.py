@@ -403,6 +403,9 @@ def workload(name: str) -> dict:
         meshes = [instrument_mesh(64, 150, 6, 4), instrument_mesh(100, 170, 7, 5, jaw_scale=1.3, box_scale=1.2)]
         return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),
                     lam=512, gens=30, frames=1, index=2, n_blocks=2)
+    if name == "soft640":        # differentiable form: 49544 tris, 640x480, 256 candidates, sigma = 1 px
+        return dict(mesh=instrument_mesh(100, 240, 8, 6), cam=camera(640, 480), lam=256, gens=30, frames=1,
+                    index=4, sigma=1.0)
     raise KeyError(name)
 
 
