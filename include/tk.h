@@ -42,6 +42,9 @@ extern "C" {
 
 typedef struct ihipStream_t* tk_stream; /* same type as hipStream_t */
 
+/* Flag bit of the loss kind: the two-tip keypoint term of Eq. kpts_loss. */
+#define TK_KP_TWO_TIPS 16
+
 typedef enum {
     TK_OK = 0,
     TK_ERR_INVALID_ARGUMENT = 1,
@@ -257,6 +260,12 @@ tk_status tk_raster_stats(const float* d_link_xf, int32_t batch, const tk_mesh* 
  * the keypoint term of every arm (Eq. kpts_loss extended to the 4 chain
  * keypoints: (|p_j - r_j| - tau)_+ for the shaft and wrist keypoints, the
  * better of the two jaw-tip assignments, and the tip-midpoint term).
+ * kind | TK_KP_TWO_TIPS takes Eq. kpts_loss as printed instead: the two jaw
+ * tips (keypoints 2, 3) under the better assignment plus their midpoint, and
+ * no keypoint term for an arm unless its two reference tips are finite and
+ * distinct (the paper evaluates the term only for exactly two detections).
+ * The kind argument of tk_cmaes_tell, tk_cmaes_tell_ask and tk_problem takes
+ * the same values.
  * d_counts [batch][2] from tk_mask_loss, d_target_count: device int32 |M|,
  * d_kp [batch][n_arms][4][2], d_kp_ref [n_arms][4][2], d_loss [batch] FP64. */
 tk_status tk_compose_loss(const int32_t* d_counts, int32_t batch, const int32_t* d_target_count, int32_t kind,

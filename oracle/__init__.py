@@ -87,6 +87,8 @@ def lib():
         L.tko_mask_loss.argtypes = [i64, i64, i64, i32, d]
         L.tko_kp_loss.restype = d
         L.tko_kp_loss.argtypes = [P, P, d]
+        L.tko_kp_loss_tips.restype = d
+        L.tko_kp_loss_tips.argtypes = [P, P, d]
         L.tko_eval_batch.argtypes = [P, i32, i32, P, P, P, P, P, P, i32]
         L.tko_max_threads.restype = i32
         L.tko_fk_jacobian.argtypes = [P, P, P]
@@ -201,6 +203,13 @@ def kp_loss(kp, ref, tau=0.0) -> float:
     kp = np.ascontiguousarray(kp, dtype=np.float64)
     ref = np.ascontiguousarray(ref, dtype=np.float64)
     return lib().tko_kp_loss(_p(kp), _p(ref), float(tau))
+
+
+def kp_loss_tips(kp, ref, tau=0.0) -> float:
+    """Keypoint loss of Eq. (8) on the two tool tips (keypoints 2, 3)."""
+    kp = np.ascontiguousarray(kp, dtype=np.float64)
+    ref = np.ascontiguousarray(ref, dtype=np.float64)
+    return lib().tko_kp_loss_tips(_p(kp), _p(ref), float(tau))
 
 
 def render(theta_arms, chains, meshes, cam) -> np.ndarray:

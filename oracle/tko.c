@@ -258,6 +258,23 @@ double tko_kp_loss(const double kp[4][2], const double ref[4][2], double tau) {
     return fixed + tips + pos(dist2(mp, mr) - tau);
 }
 
+/* Eq. (8) as printed, on the two tool tips (keypoints 2, 3): the better of the
+ * two assignments of the detected tips plus the tip-midpoint term, each as
+ * (distance - tau)_+; 0 unless exactly two distinct reference tips exist
+ * (both finite and not the same point). */
+double tko_kp_loss_tips(const double kp[4][2], const double ref[4][2], double tau) {
+    if (!(isfinite(ref[2][0]) && isfinite(ref[2][1]) && isfinite(ref[3][0]) && isfinite(ref[3][1])))
+        return 0.0;
+    if (ref[2][0] == ref[3][0] && ref[2][1] == ref[3][1]) return 0.0;
+    double keep = pos(dist2(kp[2], ref[2]) - tau) + pos(dist2(kp[3], ref[3]) - tau);
+    double swap = pos(dist2(kp[2], ref[3]) - tau) + pos(dist2(kp[3], ref[2]) - tau);
+    double tips = keep < swap ? keep : swap;
+    if (isnan(keep) || isnan(swap)) tips = NAN;
+    double mp[2] = {0.5 * (kp[2][0] + kp[3][0]), 0.5 * (kp[2][1] + kp[3][1])};
+    double mr[2] = {0.5 * (ref[2][0] + ref[3][0]), 0.5 * (ref[2][1] + ref[3][1])};
+    return tips + pos(dist2(mp, mr) - tau);
+}
+
 /* ---- whole-candidate evaluation (CPU baseline) ---- */
 int32_t tko_max_threads(void) {
 #ifdef _OPENMP

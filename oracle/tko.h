@@ -66,6 +66,11 @@ double tko_mask_loss(int64_t a, int64_t i, int64_t m, int32_t kind, double lambd
  * as (distance - tau)_+ in pixels. */
 double tko_kp_loss(const double kp[4][2], const double ref[4][2], double tau);
 
+/* Keypoint loss of Eq. (8) on the two tool tips (keypoints 2 and 3) only:
+ * min over the two assignments of the sum of (distance - tau)_+ plus the
+ * tip-midpoint term; 0 unless the two reference tips are finite and distinct. */
+double tko_kp_loss_tips(const double kp[4][2], const double ref[4][2], double tau);
+
 /* Whole candidate evaluation used for the CPU baseline:
  * for b in [0, batch): theta[b][n_arms*9] -> FK -> project/snap -> raster (OR of
  * the arms' meshes) -> counts[b][2] = {|S|, |S and M|}.  Runs the candidates

@@ -148,11 +148,14 @@ __device__ __forceinline__ double kp_dist(const float* p, const float* r) {
 //   kind 1: (a + m - 2i) + lambda_app |a - m|;
 // plus lambda_kp times the keypoint term of every arm when kp is given: the
 // shaft and wrist keypoints' (|p - r| - tau)_+, the better assignment of the
-// two jaw tips, and the tip midpoint.  kp: this candidate's [n_arms][4][2].
+// two jaw tips, and the tip midpoint; with the TK_KP_TWO_TIPS bit in kind,
+// Eq. (8) as printed instead: the two jaw tips and their midpoint only, and no
+// term for an arm whose two reference tips are not finite and distinct.
+// kp: this candidate's [n_arms][4][2].
 __device__ __forceinline__ double compose_loss_one(int64_t a_cnt, int64_t inter, int64_t m, const float* kp,
                                                    const float* kp_ref, const LossArgs& la) {
     double L;
-    if (la.kind == 0) {
+    if ((la.kind & 15) == 0) {
         const int64_t uni = a_cnt + m - inter;
         L = uni == 0 ? 0.0 : 1.0 - double(inter) / double(uni);
     } else {
@@ -162,7 +165,13 @@ __device__ __forceinline__ double compose_loss_one(int64_t a_cnt, int64_t inter,
         for (int arm = 0; arm < la.n_arms; arm++) {
             const float* p = kp + arm * 8;
             const float* r = kp_ref + arm * 8;
-            const double fixed = pos_part(kp_dist(p + 0, r + 0) - la.tau) + pos_part(kp_dist(p + 2, r + 2) - la.tau);
+            const bool two_tips = (la.kind & TK_KP_TWO_TIPS) != 0;
+            if (two_tips && !(isfinite(r[4]) && isfinite(r[5]) && isfinite(r[6]) && isfinite(r[7]) &&
+                              !(r[4] == r[6] && r[5] == r[7])))
+                continue;
+            const double fixed = two_tips ? 0.0
+                                          : pos_part(kp_dist(p + 0, r + 0) - la.tau) +
+                                                pos_part(kp_dist(p + 2, r + 2) - la.tau);
             const double keep = pos_part(kp_dist(p + 4, r + 4) - la.tau) + pos_part(kp_dist(p + 6, r + 6) - la.tau);
             const double swap = pos_part(kp_dist(p + 4, r + 6) - la.tau) + pos_part(kp_dist(p + 6, r + 4) - la.tau);
             double tips = keep < swap ? keep : swap;

@@ -69,7 +69,8 @@ tk_status make_fk_args(const tk_chain* chains, int32_t n_arms, const tk_camera* 
 
 tk_status make_loss_args(int32_t batch, int32_t kind, double lambda_app, const float* d_kp, const float* d_kp_ref,
                          int32_t n_arms, double lambda_kp, double tau, LossArgs* la) {
-    TK_REQUIRE(kind == 0 || kind == 1, "kind = %d must be 0 (1 - IoU) or 1 (render loss)", kind);
+    TK_REQUIRE((kind & ~TK_KP_TWO_TIPS) == 0 || (kind & ~TK_KP_TWO_TIPS) == 1,
+               "kind = %d must be 0 (1 - IoU) or 1 (render loss), optionally | TK_KP_TWO_TIPS", kind);
     TK_REQUIRE(std::isfinite(lambda_app) && std::isfinite(lambda_kp) && std::isfinite(tau), "non-finite weights");
     TK_REQUIRE((d_kp == nullptr) == (d_kp_ref == nullptr), "kp and kp_ref must both be given or both NULL");
     TK_REQUIRE(d_kp == nullptr || (n_arms >= 1 && n_arms <= kMaxArms), "n_arms = %d outside 1..%d", n_arms,

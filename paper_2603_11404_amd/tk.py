@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "TK_OK", 1: "TK_ERR_INVALID_ARGUMENT", 2: "TK_ERR_UNSUPPORTED
                 3: "TK_ERR_WORKSPACE_TOO_SMALL", 4: "TK_ERR_DEVICE"}
 
 LOSS_IOU, LOSS_RENDER = 0, 1
+KP_TWO_TIPS = 16            # flag bit of the loss kind: the two-tip keypoint term of Eq. (8)
 
 
 class TkError(RuntimeError):

@@ -290,6 +290,77 @@ def trajectory(rng: np.random.Generator, cam: Camera, n_frames: int) -> np.ndarr
     return out
 
 
+def hermite_trajectory(rng: np.random.Generator, cam: Camera, n_frames: int, n_waypoints: int = 20) -> np.ndarray:
+    """Seeded trajectory [n_frames, 9] in the manner of the paper's synthetic
+    set (Sec. IV, synthetic dataset): feasible waypoints (a bounded random walk
+    from a true pose: look-at angles, translation inside the view and the
+    depth band, joints across their range) joined by cubic Hermite splines
+    with Catmull-Rom tangents, plus temporally correlated Ornstein-Uhlenbeck
+    noise, then smoothed by a zero-phase first-order low-pass filter."""
+    w = np.empty((n_waypoints, N_PARAMS))
+    w[0] = true_pose(rng, cam)
+    side = 1.0 if w[0, 0] > math.pi else -1.0
+    for k in range(1, n_waypoints):
+        p = w[k - 1].copy()
+        p[0:3] += rng.uniform(-0.15, 0.15, 3)
+        p[3:6] += rng.uniform(-0.008, 0.008, 3)
+        p[6:9] = [rng.uniform(-0.8, 0.8), rng.uniform(-0.8, 0.8), rng.uniform(0.3, 0.8)]
+        p[0] = math.pi + side * min(max(side * (p[0] - math.pi), 0.35), 0.8)
+        p[2] = min(max(p[2], -0.8), 0.8)
+        p[5] = min(max(p[5], 0.08), 0.15)
+        p[3] = min(max(p[3], -0.25 * p[5] * cam.width / cam.fx), 0.25 * p[5] * cam.width / cam.fx)
+        p[4] = min(max(p[4], -0.25 * p[5] * cam.height / cam.fy), 0.25 * p[5] * cam.height / cam.fy)
+        w[k] = p
+    tang = np.empty_like(w)
+    tang[1:-1] = 0.5 * (w[2:] - w[:-2])
+    tang[0], tang[-1] = w[1] - w[0], w[-1] - w[-2]
+    out = np.empty((n_frames, N_PARAMS))
+    for t in range(n_frames):
+        sp = t * (n_waypoints - 1) / max(n_frames - 1, 1)
+        k = min(int(sp), n_waypoints - 2)
+        u = sp - k
+        h00, h10 = 2 * u ** 3 - 3 * u ** 2 + 1, u ** 3 - 2 * u ** 2 + u
+        h01, h11 = -2 * u ** 3 + 3 * u ** 2, u ** 3 - u ** 2
+        out[t] = h00 * w[k] + h10 * tang[k] + h01 * w[k + 1] + h11 * tang[k + 1]
+    # Ornstein-Uhlenbeck noise (mean reversion 0.1 per frame)
+    amp = np.array([0.002, 0.002, 0.002, 0.0002, 0.0002, 0.0002, 0.005, 0.005, 0.005])
+    ou = np.zeros(N_PARAMS)
+    for t in range(n_frames):
+        ou = ou - 0.1 * ou + amp * rng.normal(size=N_PARAMS)
+        out[t] += ou
+    # zero-phase low-pass: first-order smoothing forward, then backward
+    a = 0.3
+    for order in (range(1, n_frames), range(n_frames - 2, -1, -1)):
+        step = 1 if order.step == 1 else -1
+        for t in order:
+            out[t] = a * out[t] + (1 - a) * out[t - step]
+    return out
+
+
+def perturb_mask(rng: np.random.Generator, image: np.ndarray) -> np.ndarray:
+    """Segmentation errors in the manner of the paper's synthetic set: a random
+    dilation or erosion (1-2 steps of a 3x3 element, or none), then 2-6 disc
+    blobs of radius 2-5 px centred on boundary pixels, each added or cut."""
+    from scipy import ndimage
+
+    img = np.asarray(image, dtype=bool)
+    op = rng.choice(3, p=[0.4, 0.4, 0.2])
+    it = int(rng.integers(1, 3))
+    if op == 0:
+        img = ndimage.binary_dilation(img, iterations=it)
+    elif op == 1:
+        img = ndimage.binary_erosion(img, iterations=it)
+    edge = np.argwhere(img ^ ndimage.binary_erosion(img))
+    if len(edge):
+        yy, xx = np.mgrid[0:img.shape[0], 0:img.shape[1]]
+        for _ in range(int(rng.integers(2, 7))):
+            cy, cx = edge[rng.integers(len(edge))]
+            r = rng.uniform(2.0, 5.0)
+            disc = (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+            img = img | disc if rng.random() < 0.5 else img & ~disc
+    return img
+
+
 # --------------------------------------------------------------------------
 # Mask layout helpers (bit ly*8+lx of word [y/8][x/8]) and corruptions
 # --------------------------------------------------------------------------
@@ -403,6 +474,10 @@ def workload(name: str) -> dict:
         meshes = [instrument_mesh(64, 150, 6, 4), instrument_mesh(100, 170, 7, 5, jaw_scale=1.3, box_scale=1.2)]
         return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),
                     lam=512, gens=30, frames=1, index=2, n_blocks=2)
+    if name == "synth700":       # the paper's synthetic-set shape: 700x493, N = 70, Hermite/OU trajectory,
+        # dilation / erosion / edge-blob masks, two-tip keypoint term
+        return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(700, 493), lam=70, gens=30, frames=200,
+                    index=5, filter=FILTER_TRACK)
     if name == "soft640":        # differentiable form: 49544 tris, 640x480, 256 candidates, sigma = 1 px
         return dict(mesh=instrument_mesh(100, 240, 8, 6), cam=camera(640, 480), lam=256, gens=30, frames=1,
                     index=4, sigma=1.0)

@@ -129,3 +129,41 @@ def test_compose_loss_matches_oracle():
     T.compose_loss(z, 1, tz, 0, loss[:1])
     torch.cuda.synchronize()
     assert float(loss[0]) == 0.0
+
+
+def test_compose_loss_two_tip_keypoint_term_matches_oracle():
+    """kind | TK_KP_TWO_TIPS: Eq. (8) on the two tips, against the oracle,
+    including references with a missing or a coincident tip (term skipped)."""
+    T = tk()
+    rng = np.random.default_rng(8)
+    B = 200
+    a = rng.integers(100, 50000, B)
+    i = (a * rng.random(B)).astype(np.int64)
+    m = 20000
+    counts = torch.as_tensor(np.stack([a, i], 1).astype(np.int32), device=DEV)
+    tc = torch.tensor([m], dtype=torch.int32, device=DEV)
+    loss = torch.empty(B, dtype=torch.float64, device=DEV)
+    base = rng.uniform(0, 640, size=(4, 2))
+    refs = [base.copy(), base.copy(), base.copy()]
+    refs[1][3, 0] = np.nan                    # one tip not detected
+    refs[2][3] = refs[2][2]                   # the two tips coincide
+    kp = (base[None] + rng.normal(size=(B, 4, 2)) * 4).astype(np.float32)
+    kp[7, 2, 0] = np.nan
+    for ref_kp in refs:
+        for kind in (T.LOSS_IOU | T.KP_TWO_TIPS, T.LOSS_RENDER | T.KP_TWO_TIPS):
+            for lam_kp, tau in [(0.1, 0.0), (0.3, 2.0)]:
+                T.compose_loss(counts, B, tc, kind, loss, lambda_app=0.5,
+                               kp=torch.as_tensor(kp.reshape(B, 1, 4, 2), device=DEV),
+                               kp_ref=torch.as_tensor(ref_kp.astype(np.float32).reshape(1, 4, 2), device=DEV),
+                               n_arms=1, lambda_kp=lam_kp, tau=tau)
+                torch.cuda.synchronize()
+                got = loss.cpu().numpy()
+                for b in range(B):
+                    ref = oracle.mask_loss(a[b], i[b], m, kind & 15, 0.5) + lam_kp * oracle.kp_loss_tips(
+                        kp[b].astype(np.float64), ref_kp.astype(np.float32).astype(np.float64), tau)
+                    if math.isnan(ref):
+                        assert math.isnan(got[b])
+                    else:
+                        assert got[b] == pytest.approx(ref, rel=1e-12, abs=1e-12), (kind, lam_kp, b)
+    with pytest.raises(T.TkError):
+        T.compose_loss(counts, B, tc, 2, loss)

@@ -91,3 +91,45 @@ def test_keypoint_loss_properties():
     kp = ref.copy()
     kp[1] = [math.nan, math.nan]
     assert math.isnan(oracle.kp_loss(kp, ref))
+
+
+def test_two_tip_keypoint_loss_of_the_paper():
+    """Eq. (8) on the two tool tips: worked values, symmetry in the order of
+    the detected tips, the tau threshold, the midpoint term, and the skip rule
+    (no term unless two distinct reference tips exist)."""
+    import math
+    ref = np.array([[0.0, 0.0], [0.0, 0.0], [10.0, 20.0], [30.0, 20.0]])
+    kp = ref.copy()
+    assert oracle.kp_loss_tips(kp, ref) == 0.0
+    kp_sw = kp.copy()
+    kp_sw[[2, 3]] = kp[[3, 2]]                         # detections in the other order
+    assert oracle.kp_loss_tips(kp_sw, ref) == 0.0
+    # both tips moved by (3, 4): |v| = 5 each and for the midpoint
+    kp_v = kp.copy()
+    kp_v[2:] += [3.0, 4.0]
+    assert oracle.kp_loss_tips(kp_v, ref) == pytest.approx(15.0, abs=1e-12)
+    assert oracle.kp_loss_tips(kp_v, ref, tau=1.0) == pytest.approx(12.0, abs=1e-12)
+    assert oracle.kp_loss_tips(kp_v, ref, tau=6.0) == 0.0
+    # one tip moved by 6 along x: the tips term is 6, the midpoint moves by 3
+    kp_1 = kp.copy()
+    kp_1[3, 0] += 6.0
+    assert oracle.kp_loss_tips(kp_1, ref) == pytest.approx(9.0, abs=1e-12)
+    # the better assignment is taken: tips crossed over and shifted
+    kp_x = kp.copy()
+    kp_x[2], kp_x[3] = ref[3] + [0.0, 1.0], ref[2] + [0.0, 1.0]
+    assert oracle.kp_loss_tips(kp_x, ref) == pytest.approx(2.0 + 1.0, abs=1e-12)
+    # shaft and wrist keypoints play no part
+    kp_o = kp_v.copy()
+    kp_o[0:2] += 100.0
+    assert oracle.kp_loss_tips(kp_o, ref) == oracle.kp_loss_tips(kp_v, ref)
+    # skip rule: a missing or a coincident reference tip
+    ref_nan = ref.copy()
+    ref_nan[3, 1] = math.nan
+    assert oracle.kp_loss_tips(kp_v, ref_nan) == 0.0
+    ref_same = ref.copy()
+    ref_same[3] = ref[2]
+    assert oracle.kp_loss_tips(kp_v, ref_same) == 0.0
+    # a candidate tip behind the camera (NaN) makes the loss NaN (ranked last)
+    kp_nan = kp.copy()
+    kp_nan[2, 0] = math.nan
+    assert math.isnan(oracle.kp_loss_tips(kp_nan, ref))

@@ -66,3 +66,24 @@ def test_occluder_covers_requested_fraction():
     frac = img[y0:y1, x0:x1].sum() / img.sum()
     assert 0.1 <= phi <= 0.3 and frac >= phi
     assert scenes.apply_occluder(img, rect).sum() == img.sum() - img[y0:y1, x0:x1].sum()
+
+
+def test_hermite_trajectory_is_seeded_bounded_and_smooth():
+    cam = scenes.camera(700, 493)
+    a = scenes.hermite_trajectory(scenes.rng_for(5, scenes.SUB_TRAJ), cam, 300)
+    b = scenes.hermite_trajectory(scenes.rng_for(5, scenes.SUB_TRAJ), cam, 300)
+    assert np.array_equal(a, b) and a.shape == (300, 9)
+    assert a[:, 5].min() > 0.07 and a[:, 5].max() < 0.16          # depth band (plus the OU noise)
+    d2 = np.abs(np.diff(a, 2, axis=0))
+    assert d2[:, 3:6].max() < 2e-3 and d2[:, 0:3].max() < 0.02      # no jumps after the low-pass
+
+
+def test_perturb_mask_only_changes_pixels_near_the_boundary():
+    from scipy import ndimage
+    img = np.zeros((120, 160), bool)
+    img[30:90, 40:120] = True
+    for seed in range(8):
+        out = scenes.perturb_mask(np.random.default_rng(seed), img)
+        changed = out ^ img
+        near = ndimage.binary_dilation(img ^ ndimage.binary_erosion(img), iterations=8)
+        assert not np.any(changed & ~near), seed
