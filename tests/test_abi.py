@@ -64,3 +64,37 @@ def test_filter_argument_errors_launch_nothing():
     p = tk.kf_params(**good, lo=0.5, hi=1.0)          # x0 = 0 outside the clamp limits
     assert tk.lib().tk_kf_init(fake, 3, np.zeros(3).ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), None) == 1
     assert tk.lib().tk_kf_step(fake, 0, fake, None, None, None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtk.so not built")
+def test_soft_and_adam_argument_errors_launch_nothing():
+    """Sizes and argument checks of the differentiable form run on the host
+    before any launch (fake device addresses are never dereferenced)."""
+    import numpy as np
+    import scenes
+    from paper_2603_11404_amd import tk
+    L = tk.lib()
+    wl = scenes.workload("soft640")
+    m = wl["mesh"]
+    fake = 1 << 20
+    meshes = (tk.Mesh * 1)(tk.Mesh(m.n_vertices, m.n_triangles, fake, fake, fake))
+    cam = tk.camera(wl["cam"])
+    nb = L.tk_soft_workspace_bytes(256, meshes, 1, ctypes.byref(cam))
+    # corners, face records, tile lists (32 per face), big list, G, partials
+    assert nb >= 256 * (m.n_vertices * 16 + m.n_triangles * (48 + 32 * 4 + 4) + 640 * 480 * 4)
+    assert L.tk_soft_workspace_bytes(512, meshes, 1, ctypes.byref(cam)) > nb
+    big = tk.camera(scenes.camera(2048, 2048))
+    assert L.tk_soft_workspace_bytes(1, meshes, 1, ctypes.byref(big)) == 0       # over 16384 tiles
+    assert L.tk_soft_workspace_bytes(1, meshes, 3, ctypes.byref(cam)) == 0       # three arms
+    p = ctypes.c_void_p(fake)
+    assert L.tk_soft_forward(p, 1, meshes, 1, ctypes.byref(cam), ctypes.c_float(0.0), p, None, p, p,
+                             ctypes.c_size_t(nb), None) == tk.TK_ERR_INVALID_ARGUMENT
+    assert L.tk_soft_forward(p, 1, meshes, 1, ctypes.byref(big), ctypes.c_float(1.0), p, None, p, p,
+                             ctypes.c_size_t(nb), None) == tk.TK_ERR_UNSUPPORTED
+    assert L.tk_soft_forward(p, 256, meshes, 1, ctypes.byref(cam), ctypes.c_float(1.0), p, None, p, p,
+                             ctypes.c_size_t(nb - 1), None) == tk.TK_ERR_WORKSPACE_TOO_SMALL
+    assert L.tk_soft_forward(p, 256, meshes, 1, ctypes.byref(cam), ctypes.c_float(1.0), p, None, p,
+                             ctypes.c_void_p(fake + 8), ctypes.c_size_t(nb + 64), None) == tk.TK_ERR_INVALID_ARGUMENT
+    assert L.tk_adam_reset(p, 0, None) == tk.TK_ERR_INVALID_ARGUMENT
+    for lr, b1, b2, eps in [(0.0, 0.9, 0.999, 1e-8), (0.1, 1.0, 0.999, 1e-8), (0.1, 0.9, 0.999, 0.0)]:
+        assert L.tk_cmaes_adam(p, 9, 16, p, p, lr, b1, b2, eps, None) == tk.TK_ERR_INVALID_ARGUMENT
