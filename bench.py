@@ -421,11 +421,11 @@ def batch_leg(dev, count=64, gens=10):
 
 
 def synth700_leg(dev):
-    """The paper's synthetic-set shape: one instrument at 700x493, N = 70
-    candidates, 30 generations per frame over a 200-frame Hermite/OU
-    trajectory whose masks are dilated / eroded and blobbed, loss 1 - IoU +
-    0.1 x the two-tip keypoint term of Eq. (8), joint readings with 2-degree
-    noise, Kalman-filtered estimates."""
+    """The paper's synthetic-set protocol: one instrument at 700x493, N = 70
+    candidates, 3 iterations per frame (c_mu raised x2, sigma0 0.5) over a
+    200-frame Hermite/OU trajectory whose masks are dilated / eroded and
+    blobbed, loss 1 - IoU + 0.1 x the two-tip keypoint term of Eq. (8), joint
+    readings with 2-degree noise, Kalman-filtered estimates."""
     import torch
 
     import scenes
@@ -448,7 +448,8 @@ def synth700_leg(dev):
     est0 = traj[0] + scale * rng_q.normal(size=9)
     gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU | tk.KP_TWO_TIPS, lambda_kp=0.1)
     trk = tracker.Tracker(gen, scale, G, scenes.BASE_SEED + wl["index"] + 1000 * scenes.SUB_CMAES,
-                          filt=wl["filter"])
+                          filt=wl["filter"], sigma0=wl["sigma0"], c_m_scale=wl["c_m_scale"],
+                          c_mu_scale=wl["c_mu_scale"])
     trk.start(est0)
     res = []
     torch.cuda.synchronize()
@@ -460,8 +461,10 @@ def synth700_leg(dev):
         res.append(trk.end_frame())
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    out = {"workload": f"{mesh.n_triangles} tris, {cam.width}x{cam.height}, lambda={lam}, {G} gens x {F} frames, "
-                       "Hermite/OU trajectory, dilated/eroded/blobbed masks, 1-IoU + 0.1 two-tip keypoints",
+    out = {"workload": f"{mesh.n_triangles} tris, {cam.width}x{cam.height}, lambda={lam}, {G} gens x {F} frames "
+                       "(c_mu x2, sigma0 0.5), Hermite/OU trajectory, dilated/eroded/blobbed masks, "
+                       "1-IoU + 0.1 two-tip keypoints",
+           "ms_per_frame": wall * 1e3 / F,
            "ms_per_generation": wall * 1e3 / (F * G), "candidate_evals_per_s": lam * F * G / wall}
     for key, name in (("z", "raw"), ("theta", "filtered")):
         e = tracker.pose_errors(prob, np.stack([r[key] for r in res]), traj)

@@ -67,6 +67,8 @@ __global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a)
         S.hdr->lambda = lam;
         S.hdr->mu = mu;
         S.hdr->n_blocks = a.n_blocks;
+        S.hdr->denom_gen = -1;
+        S.hdr->denom = 0.0;
     }
     __syncthreads();
     for (int i = tid; i < lam; i += blockDim.x) {
@@ -198,6 +200,31 @@ __device__ __forceinline__ bool jacobi_rotation2(double a_ii, double a_pp, doubl
     return rot1 || rot2;
 }
 
+// Quotient of small non-negative integers (a < 2^13, 1 <= b <= 2^10): an FP32
+// reciprocal estimate within one of the quotient, then an exact integer
+// correction each way (checked exhaustively over that range).
+__device__ __forceinline__ int div_small(int a, int b) {
+    int q = int(float(a) * __builtin_amdgcn_rcpf(float(b)));
+    q += (q + 1) * b <= a ? 1 : 0;
+    q -= q * b > a ? 1 : 0;
+    return q;
+}
+
+// Row i of entry e of the upper triangle of an m x m matrix stored row by row
+// (row i holds m - i entries, starting at i m - i (i - 1) / 2): the root of
+// the quadratic as an estimate, then an exact correction each way.
+__device__ __forceinline__ int tri_row(int e, int m) {
+    const float b = float(2 * m + 1);
+    int i = int(0.5f * (b - sqrtf(fmaxf(b * b - 8.0f * float(e), 0.0f))));
+    auto start = [m](int r) { return r * m - (r * (r - 1)) / 2; };
+    i += (i + 1 < m && start(i + 1) <= e) ? 1 : 0;
+    i -= (i > 0 && start(i) > e) ? 1 : 0;
+    return i;
+}
+
+// Dynamic LDS of the update: the elite rows Y[mu][n].
+inline size_t update_lds_bytes(int n, int lam) { return sizeof(double) * size_t(n) * size_t(lam / 2); }
+
 // dynamic LDS: elite rows Y[mu][n].  The state is staged in LDS first so that
 // no loop below waits on global memory; sums over the elites are split into
 // fixed-order partial sums (deterministic).
@@ -236,8 +263,12 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     __shared__ double s_key[kMaxLambda];
     __shared__ int s_order[kMaxLambda];
     __shared__ double s_w[kMaxLambda / 2];
-    __shared__ double s_A[kMaxN * kMaxN], s_V[kMaxN * kMaxN], s_T[kMaxN * kMaxN];
-    __shared__ double s_B[kMaxN * kMaxN], s_C[kMaxN * kMaxN];
+    // 16-byte aligned: the Jacobi loop reads them as pairs of adjacent entries
+    __shared__ __align__(16) double s_A[kMaxN * kMaxN];
+    __shared__ __align__(16) double s_V[kMaxN * kMaxN];
+    __shared__ __align__(16) double s_T[kMaxN * kMaxN];
+    __shared__ double s_B[kMaxN * kMaxN];
+    __shared__ __align__(16) double s_C[kMaxN * kMaxN];
     __shared__ double s_part[kParts * kMaxN * (kMaxN + 1) / 2];
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
     __shared__ double s_scal[4];
@@ -269,6 +300,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         s_B[e] = S.B[e];
         s_C[e] = S.C[e];
     }
+
     if (tid < n) {
         s_pc[tid] = S.p_c[tid];
         s_ps[tid] = S.p_sigma[tid];
@@ -277,6 +309,10 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
     const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
     const int64_t gen = S.hdr->gen;
+    // the h_sigma denominator of this generation when the previous update
+    // cached it (same expression, same bits), else it is computed in step 3
+    const int64_t denom_gen = S.hdr->denom_gen;
+    const double denom_cached = S.hdr->denom;
     __syncthreads();
 
     // 1. ranking by (loss, index), NaN as +inf: rank = number of keys ordered
@@ -358,7 +394,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             double ss = 0.0;
             for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
             const double ps_norm = sqrt(ss);
-            const double denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
+            const double denom =
+                denom_gen == gen ? denom_cached : sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
             const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
             s_scal[0] = ps_norm;
             s_scal[1] = h;
@@ -444,6 +481,12 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     //   - writes its entry of A' = J^T A J (mirrored) and two entries of
     //     V' = V J into the other buffer, at the next round's positions (with
     //     no rotation this only moves the indices).
+    if (tid == kWave64) {
+        // while wave 0 runs the eigendecomposition: the next generation's
+        // h_sigma denominator, cached in the state with its generation
+        S.hdr->denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 2)));
+        S.hdr->denom_gen = gen + 1;
+    }
     if (tid < kWave64) {
         const int m = nb + (nb & 1);
         const int k1 = m - 1;                      // rounds per sweep
@@ -459,45 +502,44 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         };
         // positional layout: index l of block b starts at position l
         for (int e = tid; e < n_blocks * mm; e += kWave64) {
-            const int b = e / mm, i = (e % mm) / m, j = e % m;
+            const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
             const int gi = b * nb + i, gj = b * nb + j;
             s_A[e] = (i < nb && j < nb) ? 0.5 * (s_T[gi * n + gj] + s_T[gj * n + gi]) : 0.0;
         }
         for (int e = tid; e < n_v; e += kWave64) {
-            const int b = e / (nb * m), r = (e % (nb * m)) / m, j = e % m;
+            const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
             s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
         }
         constexpr int kASlots = AS;
         static_assert(VS == 2 * AS, "two V entries per A entry");
         const int na_slots = (n_a + kWave64 - 1) / kWave64;
-        // Fixed offsets of a lane's A entry (i, j), i <= j, of block b: the
-        // entry, its partner entries, the operands of the rotations of
-        // positions i and j, and its two targets.  The lane also updates two
-        // V entries, in columns i and j: row j - i of column i and row
+        // A lane holds the entry (i, j), i <= j, of block b of A, and two V
+        // entries, in columns i and j: row j - i of column i and row
         // m - j + i of column j (when < nb), which covers rows 0..m of every
-        // column exactly once over a block's entries.
-        int a_ij[kASlots], a_ipj[kASlots], a_pij[kASlots], a_pipj[kASlots];
-        int a_ii[kASlots], a_jj[kASlots], a_qi[kASlots], a_qj[kASlots], a_iq[kASlots], a_jq[kASlots];
+        // column exactly once over a block's entries.  What it reads comes in
+        // aligned pairs of adjacent columns (c & ~1, c | 1) of one row, at
+        // fixed offsets (in doubles, all even since m is even): rows i and
+        // i^1 at columns j&~1 (its entry and the partner entries), rows i,
+        // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
+        // rotations), and the two V rows at i&~1 and j&~1; it writes its
+        // entry (mirrored) and its V entries at their next positions.
+        int a_rij[kASlots], a_rpj[kASlots], a_ri[kASlots], a_rqi[kASlots], a_rj[kASlots], a_rqj[kASlots];
         int a_w1[kASlots], a_w2[kASlots];
-        int v0_r[kASlots], v0_rp[kASlots], v0_w[kASlots], v1_r[kASlots], v1_rp[kASlots], v1_w[kASlots];
+        int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
         bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
     #pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
             const int e = min(tid + kWave64 * sl, n_a - 1);
-            const int b = e / ntri_m;
-            int i = 0, rem = e - b * ntri_m;
-            while (rem >= m - i) { rem -= m - i; i++; }
-            const int j = i + rem, base = b * mm, vbase = b * nb * m;
-            a_ij[sl] = base + i * m + j;
-            a_ipj[sl] = base + i * m + (j ^ 1);
-            a_pij[sl] = base + (i ^ 1) * m + j;
-            a_pipj[sl] = base + (i ^ 1) * m + (j ^ 1);
-            a_ii[sl] = base + i * m + i;
-            a_jj[sl] = base + j * m + j;
-            a_qi[sl] = base + (i ^ 1) * m + (i ^ 1);
-            a_qj[sl] = base + (j ^ 1) * m + (j ^ 1);
-            a_iq[sl] = base + i * m + (i ^ 1);
-            a_jq[sl] = base + j * m + (j ^ 1);
+            const int b = div_small(e, ntri_m), eb = e - b * ntri_m;
+            const int i = tri_row(eb, m);
+            const int j = i + eb - (i * m - (i * (i - 1)) / 2), base = b * mm, vbase = b * nb * m;
+            const int ie = i & ~1, je = j & ~1;
+            a_rij[sl] = base + i * m + je;
+            a_rpj[sl] = base + (i ^ 1) * m + je;
+            a_ri[sl] = base + i * m + ie;
+            a_rqi[sl] = base + (i ^ 1) * m + ie;
+            a_rj[sl] = base + j * m + je;
+            a_rqj[sl] = base + (j ^ 1) * m + je;
             a_w1[sl] = base + move(i) * m + move(j);
             a_w2[sl] = base + move(j) * m + move(i);
             a_ok[sl] = tid + kWave64 * sl < n_a;
@@ -507,11 +549,9 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             const int r0 = j - i, r1 = m - j + i;
             v0_ok[sl] = a_ok[sl] && r0 < nb;
             v1_ok[sl] = a_ok[sl] && r1 < nb;
-            v0_r[sl] = vbase + min(r0, nb - 1) * m + i;
-            v0_rp[sl] = vbase + min(r0, nb - 1) * m + (i ^ 1);
+            v0_r[sl] = vbase + min(r0, nb - 1) * m + ie;
             v0_w[sl] = vbase + min(r0, nb - 1) * m + move(i);
-            v1_r[sl] = vbase + min(r1, nb - 1) * m + j;
-            v1_rp[sl] = vbase + min(r1, nb - 1) * m + (j ^ 1);
+            v1_r[sl] = vbase + min(r1, nb - 1) * m + je;
             v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
         double* Acur = s_A;
@@ -532,18 +572,28 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
                 if (sl < na_slots) {
-                    x_ij[sl] = Acur[a_ij[sl]];
-                    x_ipj[sl] = Acur[a_ipj[sl]];
-                    x_pij[sl] = Acur[a_pij[sl]];
-                    x_pipj[sl] = Acur[a_pipj[sl]];
-                    d_i[sl] = Acur[a_ii[sl]];
-                    d_j[sl] = Acur[a_jj[sl]];
-                    const double q_i = Acur[a_qi[sl]], q_j = Acur[a_qj[sl]];
-                    const double o_i = Acur[a_iq[sl]], o_j = Acur[a_jq[sl]];
-                    y0[sl] = Vcur[v0_r[sl]];
-                    y0p[sl] = Vcur[v0_rp[sl]];
-                    y1[sl] = Vcur[v1_r[sl]];
-                    y1p[sl] = Vcur[v1_rp[sl]];
+                    auto pair = [](const double* base, int off) {
+                        return *reinterpret_cast<const double2*>(base + off);
+                    };
+                    const double2 rij = pair(Acur, a_rij[sl]), rpj = pair(Acur, a_rpj[sl]);
+                    const double2 ri = pair(Acur, a_ri[sl]), rqi = pair(Acur, a_rqi[sl]);
+                    const double2 rj = pair(Acur, a_rj[sl]), rqj = pair(Acur, a_rqj[sl]);
+                    const double2 v0 = pair(Vcur, v0_r[sl]), v1 = pair(Vcur, v1_r[sl]);
+                    const bool ie = a_ei[sl], je = a_ej[sl];
+                    x_ij[sl] = je ? rij.x : rij.y;
+                    x_ipj[sl] = je ? rij.y : rij.x;
+                    x_pij[sl] = je ? rpj.x : rpj.y;
+                    x_pipj[sl] = je ? rpj.y : rpj.x;
+                    d_i[sl] = ie ? ri.x : ri.y;            // A(i, i)
+                    const double o_i = ie ? ri.y : ri.x;   // A(i, i^1)
+                    const double q_i = ie ? rqi.y : rqi.x; // A(i^1, i^1)
+                    d_j[sl] = je ? rj.x : rj.y;
+                    const double o_j = je ? rj.y : rj.x;
+                    const double q_j = je ? rqj.y : rqj.x;
+                    y0[sl] = ie ? v0.x : v0.y;             // V(r0, i), V(r0, i^1)
+                    y0p[sl] = ie ? v0.y : v0.x;
+                    y1[sl] = je ? v1.x : v1.y;
+                    y1p[sl] = je ? v1.y : v1.x;
                     rot |= jacobi_rotation2(d_i[sl], q_i, o_i, a_ei[sl], d_j[sl], q_j, o_j, a_ej[sl], a_ok[sl],
                                             &ci[sl], &si[sl], &cj[sl], &sj[sl]);
                 }
@@ -582,10 +632,11 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         // which ignores NaN like a running fmax from 0), B = V
         double ev = 0.0;
         if (tid < n) {
-            int p = tid % nb;
+            const int tb = div_small(tid, nb);
+            int p = tid - tb * nb;
             for (int r = 0; r < moved; r++) p = move(p);
             s_pos[tid] = p;
-            ev = Acur[(tid / nb) * mm + p * m + p];
+            ev = Acur[tb * mm + p * m + p];
         }
         double emax = tid < n ? fmax(0.0, ev) : 0.0;
         for (int off = kWave64 / 2; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off));
@@ -605,8 +656,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         }
         wave_sync();
         for (int e = tid; e < nn; e += kWave64) {
-            const int i = e / n, j = e % n, b = i / nb;
-            const double v = b == j / nb ? Vcur[b * nb * m + (i - b * nb) * m + s_pos[j]] : 0.0;
+            const int i = div_small(e, n), j = e - i * n, b = div_small(i, nb);
+            const double v = b == div_small(j, nb) ? Vcur[b * nb * m + (i - b * nb) * m + s_pos[j]] : 0.0;
             S.B[e] = v;
             s_B[e] = v;
         }
@@ -718,7 +769,7 @@ tk_status batch_launch_tell(const tk_problem* problems, int32_t n, const void* d
         for (int i = 0; i < n; i++) {
             if ((problems[i].n > 9) != bool(large)) continue;
             L.prob[L.count++] = i;
-            lds = std::max(lds, sizeof(double) * size_t(problems[i].lambda / 2) * size_t(problems[i].n));
+            lds = std::max(lds, update_lds_bytes(problems[i].n, problems[i].lambda));
             if (L.count == kMaxBatch)
                 if (tk_status st = flush()) return st;
         }
@@ -809,7 +860,7 @@ tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double
     clear_error();
     if (tk_status st = check_state(d_state, n, lambda)) return st;
     TK_REQUIRE(d_loss != nullptr, "loss is NULL");
-    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    const size_t lds = update_lds_bytes(n, lambda);
     // Jacobi entries inside the blocks number at most n(n+1)/2 (upper
     // triangle) and n^2 (all), whatever the block count: for n <= 9 they fit
     // one and two per lane of a wave, for n <= 18 three and six.
@@ -841,7 +892,7 @@ tk_status tk_cmaes_tell(void* d_state, int32_t n, int32_t lambda, const int32_t*
     ta.kp = d_kp;
     ta.kp_ref = d_kp_ref;
     ta.loss = d_loss;
-    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    const size_t lds = update_lds_bytes(n, lambda);
     if (n <= 9) {
         hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true, false>), dim3(1), dim3(1024), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);
@@ -876,7 +927,7 @@ tk_status tk_cmaes_tell_ask(void* d_state, int32_t n, int32_t lambda, const int3
     ta.X = d_X;
     ta.link_xf = d_link_xf;
     ta.kp_next = d_kp_next;
-    const size_t lds = sizeof(double) * size_t(lambda / 2) * size_t(n);
+    const size_t lds = update_lds_bytes(n, lambda);
     if (n <= 9) {
         hipLaunchKernelGGL((cmaes_update_kernel<1, 2, 1024, true, true>), dim3(1), dim3(1024), lds,
                            reinterpret_cast<hipStream_t>(s), d_state, n, lambda, nullptr, ta);

@@ -465,12 +465,22 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
     const uint64_t seed = S.hdr->seed;
     const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
     const int groups = (n + 3) / 4;
+    // the state this lane needs after the draw, loaded first so that the
+    // loads overlap the random-number arithmetic (the fences below would
+    // otherwise hold them back)
+    double mean_l = 0.0, off_l = 0.0, scale_l = 0.0;
+    if (lane < n) {
+        mean_l = S.mean[lane];
+        off_l = S.offset[lane];
+        scale_l = S.scale[lane];
+    }
+    const double sigma = *S.sigma;
     for (int e = lane; e < n * n; e += kWave) s_BD[e] = S.B[e] * S.D[e % n];
     if (lane < 2 * groups) draw_normal_pair(key0, key1, gen, b, lane >> 1, lane & 1, s_z + 2 * lane);
     wave_sync();
     if (lane < n) {
         double y;
-        const float x = candidate_coord(s_BD, s_z, n, lane, S.mean[lane], *S.sigma, S.offset[lane], S.scale[lane], &y);
+        const float x = candidate_coord(s_BD, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y);
         S.Z[size_t(b) * n + lane] = s_z[lane];
         S.Y[size_t(b) * n + lane] = y;
         a.X[size_t(b) * n + lane] = x;

@@ -40,8 +40,11 @@ struct StateHeader {               // first 64 bytes of the blob
     int32_t flags;
     int32_t magic;
     int32_t n, lambda, mu, n_blocks;
-    int32_t pad[6];
+    int64_t denom_gen;             // generation g of the cached h_sigma denominator (-1: none)
+    double denom;                  // sqrt(1 - (1 - c_sigma)^(2 (g + 1))) for g = denom_gen
+    int32_t pad[2];
 };
+static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
 constexpr int32_t kStateMagic = 0x544b4345;  // "ECKT"
 
 __host__ __device__ inline void cmaes_layout(int32_t n, int32_t lam, tk_cmaes_layout* L) {

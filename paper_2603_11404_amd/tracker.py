@@ -245,10 +245,12 @@ class Tracker:
     Estimates in the filter's coordinates hold joint angles q; CMA-ES runs on
     the unconstrained joint coordinates qhat (the cosine map of Sec. III-A.3).
     warm_start: "filter" starts frame t+1 from the filtered estimate of frame
-    t, "predict" from its constant-velocity prediction."""
+    t, "predict" from its constant-velocity prediction.  sigma0 and the
+    learning-rate multipliers (c_m_scale, c_mu_scale) set up CMA-ES at every
+    frame (the paper raises c_m and c_mu above their defaults without values)."""
 
     def __init__(self, gen: Generation, scale, gens_per_frame: int, seed0: int, filt: dict | None = None,
-                 warm_start: str = "filter"):
+                 warm_start: str = "filter", sigma0: float = 1.0, c_m_scale: float = 1.0, c_mu_scale: float = 1.0):
         assert warm_start in ("filter", "predict")
         self.gen, self.p = gen, gen.p
         self.n = gen.n
@@ -256,6 +258,7 @@ class Tracker:
         self.G = int(gens_per_frame)
         self.seed0 = int(seed0)
         self.warm_start = warm_start
+        self.sigma0, self.c_m_scale, self.c_mu_scale = float(sigma0), float(c_m_scale), float(c_mu_scale)
         d = self.p.device
         self.out = torch.empty(3, self.n, dtype=torch.float64, device=d)   # z, theta, theta_next
         self.kf = None
@@ -302,7 +305,8 @@ class Tracker:
             r = np.asarray(readings, np.float64).reshape(self.p.n_arms, 3)
             for a in range(self.p.n_arms):
                 mean[9 * a + 6:9 * a + 9] = r[a]
-        self.gen.init(np.zeros(self.n), 1.0, mean, self.scale, self.seed0 + f)
+        self.gen.init(np.zeros(self.n), self.sigma0, mean, self.scale, self.seed0 + f, c_m_scale=self.c_m_scale,
+                      c_mu_scale=self.c_mu_scale)
 
     def end_frame(self) -> dict:
         """Measurement, filter step and the per-frame copy to the host:

@@ -15,9 +15,11 @@ from paper_2603_11404_amd import soft, tk, tracker
 
 pytestmark = pytest.mark.gpu
 
-S_ATOL = 1e-4          # FP32 projection and transcendental functions against FP64
-LOSS_RTOL = 1e-4
-GRAD_RTOL = 1e-3       # norm-wise, FP32 sums of FP32 terms against FP64
+# FP32 projection, transcendental functions and sums against FP64; measured
+# maxima over 36 candidate / sigma cases: 7e-6, 5e-7 and 5.3e-5
+S_ATOL = 2e-5
+LOSS_RTOL = 5e-6
+GRAD_RTOL = 2e-4       # norm-wise
 
 
 def _problem(meshes, chains, cam, truth, dev):
