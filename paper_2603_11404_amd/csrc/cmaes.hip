@@ -155,49 +155,35 @@ __device__ __forceinline__ void wave_sync() {
 // which only sets the angle, and two for the normalisation, so that c and s
 // are orthogonal to working precision, at a fraction of the latency of the
 // correctly rounded square root and division.
-// Column i of the symmetric Schur rotation of the pair (p, q) = (min, max)
-// of (i, pi): J(i, i) = c and J(pi, i) = s', with s' = -s for i = p and +s
-// for i = q, where tan(theta) = t zeroes the (p, q) entry of J^T A J:
+// The symmetric Schur rotation of the pair (p, q) = (2P, 2P+1), from its 2x2
+// diagonal block: J(p, p) = J(q, q) = c, J(q, p) = s'_p = -s, J(p, q) =
+// s'_q = +s, where tan(theta) = t zeroes the (p, q) entry of J^T A J:
 //   t = 2 a_pq sign(d) / (|d| + sqrt(d^2 + 4 a_pq^2)),  d = a_qq - a_pp.
 // Written without a division: with w = |d| + sqrt(d^2 + 4 a_pq^2),
 // c = w / sqrt(w^2 + 4 a_pq^2) and s = 2 a_pq sign(d) / sqrt(w^2 + 4 a_pq^2).
 // The pair is rotated only when a_pq^2 > 1e-30 |a_pp a_qq|, i.e. when
-// |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|); otherwise (c, s') = (1, 0).
-// Both members of a pair evaluate the same operands in the same order, so
-// they agree bit for bit.
-// Two such columns (positions i and j of one entry) are computed step by step
-// in lockstep so that their dependent FP64 chains overlap.
-__device__ __forceinline__ bool jacobi_rotation2(double a_ii, double a_pp, double a_ip, bool i_is_p, double a_jj,
-                                                 double a_qq, double a_jq, bool j_is_p, bool paired, double* ci,
-                                                 double* si, double* cj, double* sj) {
-    const double app1 = i_is_p ? a_ii : a_pp, aqq1 = i_is_p ? a_pp : a_ii;
-    const double app2 = j_is_p ? a_jj : a_qq, aqq2 = j_is_p ? a_qq : a_jj;
-    const double d1 = aqq1 - app1, d2 = aqq2 - app2;
-    const double p1 = a_ip * a_ip, p2 = a_jq * a_jq;
-    const double q1 = 4.0 * p1, q2 = 4.0 * p2;
-    const double x1 = fma(d1, d1, q1), x2 = fma(d2, d2, q2);
-    const double hx1 = -0.5 * x1, hx2 = -0.5 * x2;
-    double r1 = __builtin_amdgcn_rsq(x1), r2 = __builtin_amdgcn_rsq(x2);
-    r1 = r1 * fma(hx1 * r1, r1, 1.5);
-    r2 = r2 * fma(hx2 * r2, r2, 1.5);
-    const double w1 = fma(x1, r1, fabs(d1)), w2 = fma(x2, r2, fabs(d2));
-    const double y1 = fma(w1, w1, q1), y2 = fma(w2, w2, q2);
-    const double hy1 = -0.5 * y1, hy2 = -0.5 * y2;
-    double t1 = __builtin_amdgcn_rsq(y1), t2 = __builtin_amdgcn_rsq(y2);
-    t1 = t1 * fma(hy1 * t1, t1, 1.5);
-    t2 = t2 * fma(hy2 * t2, t2, 1.5);
-    t1 = t1 * fma(hy1 * t1, t1, 1.5);
-    t2 = t2 * fma(hy2 * t2, t2, 1.5);
-    const double c1 = w1 * t1, c2 = w2 * t2;
-    const double sn1 = (d1 >= 0.0 ? 2.0 * a_ip : -2.0 * a_ip) * t1;
-    const double sn2 = (d2 >= 0.0 ? 2.0 * a_jq : -2.0 * a_jq) * t2;
-    const bool rot1 = paired && a_ip != 0.0 && p1 > 1e-30 * fabs(app1 * aqq1);
-    const bool rot2 = paired && a_jq != 0.0 && p2 > 1e-30 * fabs(app2 * aqq2);
-    *ci = rot1 ? c1 : 1.0;
-    *si = rot1 ? (i_is_p ? -sn1 : sn1) : 0.0;
-    *cj = rot2 ? c2 : 1.0;
-    *sj = rot2 ? (j_is_p ? -sn2 : sn2) : 0.0;
-    return rot1 || rot2;
+// |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|); otherwise (c, s) = (1, 0).
+__device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq, bool paired, double* c_out,
+                                              double* sn_out) {
+    const double d = aqq - app;
+    const double p2 = apq * apq;
+    const double q = 4.0 * p2;
+    const double x = fma(d, d, q);
+    const double hx = -0.5 * x;
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(hx * r, r, 1.5);
+    const double w = fma(x, r, fabs(d));
+    const double y = fma(w, w, q);
+    const double hy = -0.5 * y;
+    double t = __builtin_amdgcn_rsq(y);
+    t = t * fma(hy * t, t, 1.5);
+    t = t * fma(hy * t, t, 1.5);
+    const double c = w * t;
+    const double sn = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * t;
+    const bool rot = paired && apq != 0.0 && p2 > 1e-30 * fabs(app * aqq);
+    *c_out = rot ? c : 1.0;
+    *sn_out = rot ? sn : 0.0;
+    return rot;
 }
 
 // Quotient of small non-negative integers (a < 2^13, 1 <= b <= 2^10): an FP32
@@ -471,14 +457,16 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     // which every two indices of a block meet once per m - 1 rounds and the
     // layout returns to the start.  The rotated A and V are written straight
     // into their next positions, so every lane reads and writes the same LDS
-    // addresses in every round and computes them once.  Per round, every lane
-    // holding an upper-triangle entry (i, j) of A:
-    //   - reads the entries it needs and computes the rotations of positions
-    //     i and j itself (no exchange between lanes);
-    //   - when nothing rotates anywhere, tests its entry against the rotation
-    //     threshold; if no pair exceeds it the iteration has converged
-    //     (another sweep would rotate nothing);
-    //   - writes its entry of A' = J^T A J (mirrored) and two entries of
+    // addresses in every round and computes them once.  Per round:
+    //   - lane t < n_blocks m computes the rotation of the pair holding
+    //     position t from the pair's 2x2 diagonal block;
+    //   - every lane holding an upper-triangle entry (i, j) of A takes the
+    //     rotations of positions i and j from those lanes (cross-lane
+    //     shuffles) and reads its entry's 2x2 neighbourhood and its V entries;
+    //   - when nothing rotates anywhere, it tests its entry against the
+    //     rotation threshold; if no pair exceeds it the iteration has
+    //     converged (another sweep would rotate nothing);
+    //   - it writes its entry of A' = J^T A J (mirrored) and two entries of
     //     V' = V J into the other buffer, at the next round's positions (with
     //     no rotation this only moves the indices).
     if (tid == kWave64) {
@@ -523,7 +511,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
         // rotations), and the two V rows at i&~1 and j&~1; it writes its
         // entry (mirrored) and its V entries at their next positions.
-        int a_rij[kASlots], a_rpj[kASlots], a_ri[kASlots], a_rqi[kASlots], a_rj[kASlots], a_rqj[kASlots];
+        int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
         int a_w1[kASlots], a_w2[kASlots];
         int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
         bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
@@ -536,10 +524,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             const int ie = i & ~1, je = j & ~1;
             a_rij[sl] = base + i * m + je;
             a_rpj[sl] = base + (i ^ 1) * m + je;
-            a_ri[sl] = base + i * m + ie;
-            a_rqi[sl] = base + (i ^ 1) * m + ie;
-            a_rj[sl] = base + j * m + je;
-            a_rqj[sl] = base + (j ^ 1) * m + je;
+            a_li[sl] = b * m + i;               // the lanes holding the rotations of positions i and j
+            a_lj[sl] = b * m + j;
             a_w1[sl] = base + move(i) * m + move(j);
             a_w2[sl] = base + move(j) * m + move(i);
             a_ok[sl] = tid + kWave64 * sl < n_a;
@@ -561,41 +547,44 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         wave_sync();
         const int max_rounds = kMaxSweeps * k1;
         int moved = 0;                             // rounds applied (index moves) modulo k1
+        // lane t < n_blocks m computes the rotation of the pair holding position
+        // t, from the pair's 2x2 diagonal block (rows 2P, 2P+1 at column 2P)
+        const int n_pos = n_blocks * m;
+        const int t_pos = min(tid, n_pos - 1);
+        const int t_b = div_small(t_pos, m), t_p = t_pos - t_b * m, t_2P = t_p & ~1;
+        const int t_rp = t_b * mm + t_2P * m + t_2P, t_rq = t_rp + m;
+        const bool t_even = (t_p & 1) == 0;
         for (int it = 0; it < max_rounds; it++) {
-            // every lane reads its operands and computes the rotations of its
-            // two positions itself (the two members of a pair, and every lane
-            // needing the same position, get the same bits)
-            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots], d_i[kASlots], d_j[kASlots];
+            auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
+            const double2 bp = pair(Acur, t_rp), bq = pair(Acur, t_rq);
+            double c_t, sn_t;
+            const bool rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
+            const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
+            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
             double ci[kASlots], si[kASlots], cj[kASlots], sj[kASlots];
             double y0[kASlots], y0p[kASlots], y1[kASlots], y1p[kASlots];
-            bool rot = false;
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
                 if (sl < na_slots) {
-                    auto pair = [](const double* base, int off) {
-                        return *reinterpret_cast<const double2*>(base + off);
-                    };
                     const double2 rij = pair(Acur, a_rij[sl]), rpj = pair(Acur, a_rpj[sl]);
-                    const double2 ri = pair(Acur, a_ri[sl]), rqi = pair(Acur, a_rqi[sl]);
-                    const double2 rj = pair(Acur, a_rj[sl]), rqj = pair(Acur, a_rqj[sl]);
                     const double2 v0 = pair(Vcur, v0_r[sl]), v1 = pair(Vcur, v1_r[sl]);
                     const bool ie = a_ei[sl], je = a_ej[sl];
                     x_ij[sl] = je ? rij.x : rij.y;
                     x_ipj[sl] = je ? rij.y : rij.x;
                     x_pij[sl] = je ? rpj.x : rpj.y;
                     x_pipj[sl] = je ? rpj.y : rpj.x;
-                    d_i[sl] = ie ? ri.x : ri.y;            // A(i, i)
-                    const double o_i = ie ? ri.y : ri.x;   // A(i, i^1)
-                    const double q_i = ie ? rqi.y : rqi.x; // A(i^1, i^1)
-                    d_j[sl] = je ? rj.x : rj.y;
-                    const double o_j = je ? rj.y : rj.x;
-                    const double q_j = je ? rqj.y : rqj.x;
                     y0[sl] = ie ? v0.x : v0.y;             // V(r0, i), V(r0, i^1)
                     y0p[sl] = ie ? v0.y : v0.x;
                     y1[sl] = je ? v1.x : v1.y;
                     y1p[sl] = je ? v1.y : v1.x;
-                    rot |= jacobi_rotation2(d_i[sl], q_i, o_i, a_ei[sl], d_j[sl], q_j, o_j, a_ej[sl], a_ok[sl],
-                                            &ci[sl], &si[sl], &cj[sl], &sj[sl]);
+                    // the rotations of positions i and j from the lanes that computed them;
+                    // s' = -sn for the first position of a pair, +sn for the second
+                    ci[sl] = __shfl(c_t, a_li[sl]);
+                    const double sni = __shfl(sn_t, a_li[sl]);
+                    cj[sl] = __shfl(c_t, a_lj[sl]);
+                    const double snj = __shfl(sn_t, a_lj[sl]);
+                    si[sl] = sni == 0.0 ? 0.0 : (ie ? -sni : sni);
+                    sj[sl] = snj == 0.0 ? 0.0 : (je ? -snj : snj);
                 }
             }
             if (__ballot(rot) == 0ull) {
@@ -605,7 +594,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 for (int sl = 0; sl < kASlots; sl++) {
                     if (sl < na_slots) {
                         const double aij = x_ij[sl];
-                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(d_i[sl] * d_j[sl]);
+                        const double d_i = __shfl(dd_t, a_li[sl]), d_j = __shfl(dd_t, a_lj[sl]);
+                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(d_i * d_j);
                     }
                 }
                 if (__ballot(open) == 0ull) break;
