@@ -260,6 +260,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     __shared__ double s_scal[4];
     __shared__ double s_mean[kMaxN];
     __shared__ int s_pos[kMaxN];          // final Jacobi position of each index
+    __shared__ double s_sink[2 * kWave64];   // target of the V stores of lanes with no V entry
 
     StateView S = state_view(blob, n, lam);
     const int tid = threadIdx.x;
@@ -522,8 +523,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             const int i = tri_row(eb, m);
             const int j = i + eb - (i * m - (i * (i - 1)) / 2), base = b * mm, vbase = b * nb * m;
             const int ie = i & ~1, je = j & ~1;
-            a_rij[sl] = base + i * m + je;
-            a_rpj[sl] = base + (i ^ 1) * m + je;
+            a_rij[sl] = base + ie * m + je;           // rows 2P, 2P+1 of the entry's 2x2 block
+            a_rpj[sl] = base + (ie + 1) * m + je;
             a_li[sl] = b * m + i;               // the lanes holding the rotations of positions i and j
             a_lj[sl] = b * m + j;
             a_w1[sl] = base + move(i) * m + move(j);
@@ -560,31 +561,24 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             double c_t, sn_t;
             const bool rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
             const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
-            double x_ij[kASlots], x_ipj[kASlots], x_pij[kASlots], x_pipj[kASlots];
-            double ci[kASlots], si[kASlots], cj[kASlots], sj[kASlots];
-            double y0[kASlots], y0p[kASlots], y1[kASlots], y1p[kASlots];
+            // column t of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
+            const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
+            double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
+            double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots];
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
                 if (sl < na_slots) {
-                    const double2 rij = pair(Acur, a_rij[sl]), rpj = pair(Acur, a_rpj[sl]);
-                    const double2 v0 = pair(Vcur, v0_r[sl]), v1 = pair(Vcur, v1_r[sl]);
-                    const bool ie = a_ei[sl], je = a_ej[sl];
-                    x_ij[sl] = je ? rij.x : rij.y;
-                    x_ipj[sl] = je ? rij.y : rij.x;
-                    x_pij[sl] = je ? rpj.x : rpj.y;
-                    x_pipj[sl] = je ? rpj.y : rpj.x;
-                    y0[sl] = ie ? v0.x : v0.y;             // V(r0, i), V(r0, i^1)
-                    y0p[sl] = ie ? v0.y : v0.x;
-                    y1[sl] = je ? v1.x : v1.y;
-                    y1p[sl] = je ? v1.y : v1.x;
-                    // the rotations of positions i and j from the lanes that computed them;
-                    // s' = -sn for the first position of a pair, +sn for the second
-                    ci[sl] = __shfl(c_t, a_li[sl]);
-                    const double sni = __shfl(sn_t, a_li[sl]);
-                    cj[sl] = __shfl(c_t, a_lj[sl]);
-                    const double snj = __shfl(sn_t, a_lj[sl]);
-                    si[sl] = sni == 0.0 ? 0.0 : (ie ? -sni : sni);
-                    sj[sl] = snj == 0.0 ? 0.0 : (je ? -snj : snj);
+                    // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1), the
+                    // two V rows at columns 2P and 2Q, and the rotation columns u, w
+                    // of positions i and j from the lanes that hold them
+                    blk0[sl] = pair(Acur, a_rij[sl]);
+                    blk1[sl] = pair(Acur, a_rpj[sl]);
+                    vr0[sl] = pair(Vcur, v0_r[sl]);
+                    vr1[sl] = pair(Vcur, v1_r[sl]);
+                    u0[sl] = __shfl(col0_t, a_li[sl]);
+                    u1[sl] = __shfl(col1_t, a_li[sl]);
+                    w0[sl] = __shfl(col0_t, a_lj[sl]);
+                    w1[sl] = __shfl(col1_t, a_lj[sl]);
                 }
             }
             if (__ballot(rot) == 0ull) {
@@ -593,7 +587,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     #pragma unroll
                 for (int sl = 0; sl < kASlots; sl++) {
                     if (sl < na_slots) {
-                        const double aij = x_ij[sl];
+                        const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
+                        const double aij = a_ej[sl] ? row.x : row.y;
                         const double d_i = __shfl(dd_t, a_li[sl]), d_j = __shfl(dd_t, a_lj[sl]);
                         open |= a_off[sl] && aij * aij > 1e-30 * fabs(d_i * d_j);
                     }
@@ -602,15 +597,20 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             }
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
-                if (sl < na_slots && a_ok[sl]) {
-                    const double u0 = fma(cj[sl], x_ij[sl], sj[sl] * x_ipj[sl]);
-                    const double u1 = fma(cj[sl], x_pij[sl], sj[sl] * x_pipj[sl]);
-                    const double v = fma(ci[sl], u0, si[sl] * u1);
+                if (sl < na_slots) {
+                    // A'(i, j) = u^T B w; a lane past the last entry recomputes the
+                    // last entry, so its duplicate stores write the same value
+                    const double r0 = fma(w0[sl], blk0[sl].x, w1[sl] * blk0[sl].y);
+                    const double r1 = fma(w0[sl], blk1[sl].x, w1[sl] * blk1[sl].y);
+                    const double v = fma(u0[sl], r0, u1[sl] * r1);
                     Anext[a_w1[sl]] = v;
                     Anext[a_w2[sl]] = v;
+                    // V'(r, i) = V(r, 2P) u0 + V(r, 2P+1) u1, likewise at column j
+                    double* d0 = v0_ok[sl] ? Vnext + v0_w[sl] : s_sink + tid;
+                    double* d1 = v1_ok[sl] ? Vnext + v1_w[sl] : s_sink + kWave64 + tid;
+                    *d0 = fma(u0[sl], vr0[sl].x, u1[sl] * vr0[sl].y);
+                    *d1 = fma(w0[sl], vr1[sl].x, w1[sl] * vr1[sl].y);
                 }
-                if (sl < na_slots && v0_ok[sl]) Vnext[v0_w[sl]] = fma(ci[sl], y0[sl], si[sl] * y0p[sl]);
-                if (sl < na_slots && v1_ok[sl]) Vnext[v1_w[sl]] = fma(cj[sl], y1[sl], sj[sl] * y1p[sl]);
             }
             wave_sync();
             double* t = Acur; Acur = Anext; Anext = t;
