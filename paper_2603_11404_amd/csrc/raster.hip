@@ -507,6 +507,103 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
     for (int e = lane; e < n_arms * 48; e += kWave) a.link_xf_out[size_t(b) * n_arms * 48 + e] = s_M[e];
 }
 
+// ---------------------------------------------------------------- triangle chunks
+
+// Triangle chunks hold 64 triangles, one per lane, numbered over the meshes:
+// chunks 0 .. C0 - 1 are mesh 0's, the next ones mesh 1's; C >= 1 chunks in
+// all.  A chunk number past the last chunk stands for the last chunk, and a
+// lane past its mesh's last triangle for that triangle: every load below is
+// in bounds without a branch (a load in a branch makes the compiler wait for
+// it at the branch's end), and `live` marks the lanes whose triangle counts.
+struct ChunkLane {
+    bool second;   // the chunk is mesh 1's
+    int t;         // triangle of the lane in its mesh (clamped)
+    bool live;
+};
+
+__device__ __forceinline__ ChunkLane chunk_lane(const MeshK& m0, const MeshK& m1, int C0, int C, int c, int lane) {
+    const int cc = max(min(c, C - 1), 0);
+    const bool second = cc >= C0;
+    const int t = (cc - (second ? C0 : 0)) * kWave + lane;
+    const int T = second ? m1.n_triangles : m0.n_triangles;
+    return {second, min(t, T - 1), c < C && t < T};
+}
+
+// Vertex indices of lane `lane`'s triangle in chunk c.
+__device__ __forceinline__ void load_chunk_indices(const MeshK& m0, const MeshK& m1, int C0, int C, int c, int lane,
+                                                   int32_t* idx) {
+    const ChunkLane cl = chunk_lane(m0, m1, C0, C, c, lane);
+    const int32_t* tri = (cl.second ? m1.triangles : m0.triangles) + 3 * size_t(cl.t);
+    idx[0] = tri[0];
+    idx[1] = tri[1];
+    idx[2] = tri[2];
+}
+
+// The three vertices of a lane's triangle: snapped points read from the
+// workspace, or model-space positions and link-transform offsets to be
+// projected when the chunk is rasterised.
+template <bool FROM_SNAPPED>
+struct ChunkVerts;
+template <>
+struct ChunkVerts<true> {
+    int32_t X[3], Y[3];
+    bool live;
+};
+template <>
+struct ChunkVerts<false> {
+    float vx[3], vy[3], vz[3];
+    int off[3];
+    bool live;
+};
+
+// The vertices of lane `lane`'s triangle in chunk c, from the indices that
+// load_chunk_indices read for the same chunk (valid vertex indices of the
+// chunk's mesh in every lane).
+template <bool FS>
+__device__ __forceinline__ void gather_chunk(const RasterArgs& a, const MeshK& m0, const MeshK& m1, int C0, int C,
+                                             int b, int c, int lane, const int32_t* idx, ChunkVerts<FS>& g) {
+    const ChunkLane cl = chunk_lane(m0, m1, C0, C, c, lane);
+    g.live = cl.live;
+    if constexpr (FS) {
+        const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
+                           (size_t(b) * a.meshes.total_vertices + (cl.second ? m1.vertex_offset : m0.vertex_offset));
+        for (int k = 0; k < 3; k++) {
+            const int2 p = snap[idx[k]];
+            g.X[k] = p.x;
+            g.Y[k] = p.y;
+        }
+    } else {
+        const float* V = cl.second ? m1.vertices : m0.vertices;
+        const uint8_t* L = cl.second ? m1.vertex_link : m0.vertex_link;
+        for (int k = 0; k < 3; k++) {
+            const float* p = V + size_t(idx[k]) * 3;
+            g.vx[k] = p[0];
+            g.vy[k] = p[1];
+            g.vz[k] = p[2];
+            g.off[k] = (cl.second ? 48 : 0) + 12 * int(L[idx[k]]);
+        }
+    }
+}
+
+// Snapped points of a gathered chunk (INT32_MIN columns outside the meshes).
+template <bool FS>
+__device__ __forceinline__ void chunk_snapped(const ChunkVerts<FS>& g, const float* s_M, const CamK& cam, int32_t* X,
+                                              int32_t* Y) {
+    if constexpr (FS) {
+        for (int k = 0; k < 3; k++) {
+            X[k] = g.live ? g.X[k] : INT32_MIN;
+            Y[k] = g.live ? g.Y[k] : 0;
+        }
+    } else {
+        for (int k = 0; k < 3; k++) {
+            X[k] = INT32_MIN;
+            Y[k] = 0;
+        }
+        if (g.live)
+            for (int k = 0; k < 3; k++) project_snap(s_M + g.off[k], g.vx[k], g.vy[k], g.vz[k], cam, X[k], Y[k]);
+    }
+}
+
 // One workgroup rasterises candidate b of the problem described by a.
 template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
 __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
@@ -515,12 +612,28 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     __shared__ WaveQueues s_queue[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
+    __shared__ int32_t s_next_chunk;
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int lx = lane & 7, ly = lane >> 3;
     const CamK& cam = a.cam;
     const int words = cam.words_x * cam.words_y;
     WaveQueues& Q = s_queue[wave];
+
+    const int TV = a.meshes.total_vertices;
+    const MeshK& m0 = a.meshes.m[0];
+    const MeshK& m1 = a.meshes.m[1];
+    const bool two = a.meshes.n_meshes > 1;
+    const bool pretransform = FROM_SNAPPED && a.pretransform;
+    // triangles in chunks of 64 (one per lane), numbered over the meshes
+    const int C0 = (m0.n_triangles + kWave - 1) / kWave;
+    const int C = two ? C0 + (m1.n_triangles + kWave - 1) / kWave : C0;
+    // wave w starts with chunks w and NW + w; it claims each later chunk from
+    // an LDS counter two chunks ahead of the one it rasterises (indices two
+    // ahead, vertex gathers one ahead), so all waves finish within about one
+    // chunk of each other whatever the mix of triangle sizes
+    int c_cur = wave, c_nxt = wave + NW;
+    if (tid == 0) s_next_chunk = 2 * NW;
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
     if (a.ask) {
@@ -530,17 +643,24 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
     }
     __syncthreads();
-    if (FROM_SNAPPED && a.pretransform) {
+    // the vertex indices of the wave's first two chunks
+    int32_t idx_cur[3], idx_nxt[3];   // read only for chunks < C
+    if (C > 0) {   // no triangles at all: nothing to load
+        load_chunk_indices(m0, m1, C0, C, c_cur, lane, idx_cur);
+        load_chunk_indices(m0, m1, C0, C, c_nxt, lane, idx_nxt);
+    }
+    if (pretransform) {
         // transform, project and snap every vertex of this candidate once into the workspace
-        int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * a.meshes.total_vertices;
-        for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
-            const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
-            for (int v = tid; v < mesh.n_vertices; v += NT) {
-                const float* p = mesh.vertices + size_t(v) * 3;
-                int32_t X, Y;
-                project_snap(s_M + mi * 48 + 12 * mesh.vertex_link[v], p[0], p[1], p[2], cam, X, Y);
-                out[mesh.vertex_offset + v] = make_int2(X, Y);
-            }
+        int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * TV;
+        for (int gv = tid; gv < TV; gv += NT) {
+            const bool second = two && gv >= m1.vertex_offset;
+            const int v = gv - (second ? m1.vertex_offset : m0.vertex_offset);
+            const float* p = (second ? m1.vertices : m0.vertices) + size_t(v) * 3;
+            // the link transforms in s_M: 48 floats per mesh, 12 per link
+            const int off = (second ? 48 : 0) + 12 * int((second ? m1.vertex_link : m0.vertex_link)[v]);
+            int32_t X, Y;
+            project_snap(s_M + off, p[0], p[1], p[2], cam, X, Y);
+            out[gv] = make_int2(X, Y);
         }
         __syncthreads();
     }
@@ -549,46 +669,27 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     // (head, tail) and task counts (queued, done) of the narrow and wide queues
     int n_head = 0, n_tail = 0, n_queued = 0, n_done = 0;
     int w_head = 0, w_tail = 0, w_queued = 0, w_done = 0;
-    for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
-        const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
-        const float* M = s_M + mi * 48;
-        const int T = mesh.n_triangles;
-        const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
-                           (size_t(b) * a.meshes.total_vertices + mesh.vertex_offset);
-        // indices of this lane's first triangle; later chunks are prefetched one iteration ahead
-        int t = wave * kWave + lane;
-        int32_t idx[3] = {0, 0, 0};
-        if (t < T)
-            for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * t + k];
-        for (int base = wave * kWave; base < T; base += NT) {
-            t = base + lane;
-            const bool live = t < T;
-            int32_t X[3] = {INT32_MIN, INT32_MIN, INT32_MIN}, Y[3] = {0, 0, 0};
-            float vx[3], vy[3], vz[3];
-            int link[3];
-            if (live) {
-                for (int k = 0; k < 3; k++) {
-                    if (FROM_SNAPPED) {
-                        const int2 p = snap[idx[k]];
-                        X[k] = p.x;
-                        Y[k] = p.y;
-                    } else {
-                        const float* v = mesh.vertices + size_t(idx[k]) * 3;
-                        vx[k] = v[0];
-                        vy[k] = v[1];
-                        vz[k] = v[2];
-                        link[k] = mesh.vertex_link[idx[k]];
-                    }
-                }
-            }
-            // prefetch the next chunk's indices while this chunk is processed
-            const int tn = t + NT;
-            if (tn < T)
-                for (int k = 0; k < 3; k++) idx[k] = mesh.triangles[3 * tn + k];
-            if (!FROM_SNAPPED && live)
-                for (int k = 0; k < 3; k++) project_snap(M + 12 * link[k], vx[k], vy[k], vz[k], cam, X[k], Y[k]);
+    ChunkVerts<FROM_SNAPPED> g_cur;
+    if (c_cur < C) gather_chunk(a, m0, m1, C0, C, b, c_cur, lane, idx_cur, g_cur);
+    while (c_cur < C) {
+        // the claim's result is read after the triangle setup below, which
+        // covers its LDS round trip (this file is compiled without the
+        // compiler's atomic optimizer, which would wait for it right here)
+        int claim;   // read in lane 0 only
+        if (lane == 0) claim = atomicAdd(&s_next_chunk, 1);
+        ChunkVerts<FROM_SNAPPED> g_nxt;
+        gather_chunk(a, m0, m1, C0, C, b, c_nxt, lane, idx_nxt, g_nxt);
+        int c_new;
+        {
+            const bool live = g_cur.live;
+            int32_t X[3], Y[3];
+            chunk_snapped(g_cur, s_M, cam, X, Y);
             TriRec rec;
             const bool valid = live && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
+            // claims exceed every chunk the wave holds (the counter starts at
+            // 2 NW); the max keeps each wave's chunk numbers increasing regardless
+            c_new = max(__builtin_amdgcn_readlane(claim, 0), c_nxt + 1);
+            load_chunk_indices(m0, m1, C0, C, c_new, lane, idx_nxt);
             const bool near = valid && (rec.flags & kNear);
             const bool narrow = near && is_narrow(rec.box_x);
             const bool wide = near && !narrow;
@@ -660,6 +761,9 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
                 cover_big(br, lx, ly, lane, s_mask, cam.words_x);
             }
         }
+        g_cur = g_nxt;
+        c_cur = c_nxt;
+        c_nxt = c_new;
     }
     // the last partial rounds
     if (n_queued > n_done)
@@ -851,7 +955,10 @@ constexpr size_t kLdsLimit = 160 * 1024;
 
 template <int NT>
 constexpr size_t static_lds() {
-    return sizeof(WaveQueues) * (NT / kWave) + sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (NT / kWave);
+    // queues, transforms, count partials and the chunk counter (padded to 8
+    // bytes: the 64-bit words of the dynamic mask follow)
+    return sizeof(WaveQueues) * (NT / kWave) + sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (NT / kWave) +
+           sizeof(int64_t);
 }
 
 template <bool FS, bool WM, bool CN, int NT>
@@ -859,12 +966,22 @@ tk_status launch_raster_nt(const RasterArgs& a, size_t lds, hipStream_t s, const
     auto kern = raster_kernel<FS, WM, CN, NT>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
+    static size_t static_bytes = 0;
     std::call_once(once, [&] {
-        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsLimit - static_lds<NT>()));
+        // the LDS budget of the image mask assumes the kernel's static LDS is at most static_lds<NT>()
+        hipFuncAttributes fa{};
+        attr_err = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern));
+        static_bytes = fa.sharedSizeBytes;
+        if (attr_err == hipSuccess)
+            attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           int(kLdsLimit - static_lds<NT>()));
     });
     if (attr_err != hipSuccess)
         return fail(TK_ERR_DEVICE, "%s: cannot raise the dynamic LDS limit: %s", what, hipGetErrorString(attr_err));
+    if (static_bytes > static_lds<NT>())
+        return fail(TK_ERR_DEVICE, "%s: kernel has %zu bytes of static LDS, the launch assumes at most %zu", what,
+                    static_bytes, static_lds<NT>());
     hipLaunchKernelGGL(kern, dim3(a.batch), dim3(NT), lds, s, a);
     return check_launch(what);
 }
