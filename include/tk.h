@@ -114,6 +114,9 @@ typedef struct {
     int64_t C, B;       /* [n][n]; B columns are eigenvectors, D their sqrt eigenvalues */
     int64_t Z, Y;       /* [lambda][n] last draws z and y = B D z */
     int64_t order;      /* int32 [lambda] ranking of the last update */
+    int64_t z_gen;      /* int64 generation g whose draws Z holds for every candidate (-1: none);
+                         * an update draws the next generation's z while it runs its
+                         * eigendecomposition, and the ask-eval form then reads them */
 } tk_cmaes_layout;
 
 /* Size in bytes of a state blob for dimension n (1..18) and population

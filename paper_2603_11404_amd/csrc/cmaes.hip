@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a)
         S.hdr->n_blocks = a.n_blocks;
         S.hdr->denom_gen = -1;
         S.hdr->denom = 0.0;
+        S.hdr->z_gen = -1;
     }
     __syncthreads();
     for (int i = tid; i < lam; i += blockDim.x) {
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
         S.Z[k * n + i] = s_z[kk][i];
         S.Y[k * n + i] = y;
     }
+    if (blockIdx.x == 0 && tid == 0) S.hdr->z_gen = int64_t(gen);   // Z: this generation's draws once all blocks end
 }
 
 // ---------------------------------------------------------------- update
@@ -475,6 +477,27 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         // h_sigma denominator, cached in the state with its generation
         S.hdr->denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 2)));
         S.hdr->denom_gen = gen + 1;
+        S.hdr->z_gen = gen + 1;   // the loop below has written Z when the kernel ends
+    }
+    if (tid >= kWave64 && ((tid / kWave64) & 3) != 0) {
+        // meanwhile the waves that do not share wave 0's SIMD (under the
+        // usual round-robin placement) draw the next generation's z, exactly
+        // as a sampler would: they depend on the seed and generation only
+        constexpr int NW = NT / kWave64;
+        const int w = tid / kWave64;
+        const int li = (w - 1 - w / 4) * kWave64 + (tid & (kWave64 - 1));
+        const int stride = ((NW - 1) - (NW - 1) / 4) * kWave64;
+        const uint32_t gnext = uint32_t(gen + 1);
+        const uint64_t seed = S.hdr->seed;
+        const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
+        const int groups = (n + 3) / 4;
+        for (int task = li; task < lam * groups; task += stride) {
+            const int k = div_small(task, groups), j = task - k * groups;
+            double z[4];
+            draw_normals(key0, key1, gnext, k, j, z);
+            for (int t = 0; t < 4; t++)
+                if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
+        }
     }
     if (tid < kWave64) {
         const int m = nb + (nb & 1);
@@ -659,18 +682,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     //    generation, y = B D z, x = m + sigma y, theta = offset + scale x), then
     //    the forward kinematics of every candidate and arm
     __syncthreads();
-    const uint32_t gnext = uint32_t(gen + 1);
-    const uint64_t seed = S.hdr->seed;
-    const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
-    const int groups = (n + 3) / 4;
+    // (z of the next generation were drawn during the eigendecomposition)
     for (int e = tid; e < nn; e += NT) s_T[e] = s_B[e] * s_D[e % n];
-    for (int task = tid; task < lam * groups; task += NT) {
-        const int k = task / groups, j = task % groups;
-        double z[4];
-        draw_normals(key0, key1, gnext, k, j, z);
-        for (int t = 0; t < 4; t++)
-            if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
-    }
     __syncthreads();
     const double sigma_next = s_scal[3];
     for (int task = tid; task < lam * n; task += NT) {

@@ -454,34 +454,43 @@ struct RasterArgs {
 // generation is drawn exactly as the sample kernel draws it (same generator,
 // same B D product and arithmetic), written to X and the state's Z and Y, and
 // its forward kinematics (same device function as the FK kernel) goes to the
-// LDS transforms s_M and to link_xf_out / kp.  scratch: >= 2.9 KB of LDS.
+// LDS transforms s_M and to link_xf_out / kp.  When the state already holds
+// this generation's z (drawn by the previous update), they are read instead
+// of drawn.  scratch: >= 2.9 KB of LDS.
 __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
     const int n = a.n;
     StateView S = state_view(a.state, n, a.lam);
     double* s_BD = reinterpret_cast<double*>(scratch);              // [n][n]
     double* s_z = s_BD + kMaxN * kMaxN;                              // [n + 3]
     float* s_X = reinterpret_cast<float*>(s_z + kMaxN + 3);         // [n]
-    const uint32_t gen = uint32_t(S.hdr->gen);
+    const int64_t gen64 = S.hdr->gen;
+    const bool drawn = S.hdr->z_gen == gen64;
+    const uint32_t gen = uint32_t(gen64);
     const uint64_t seed = S.hdr->seed;
     const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
     const int groups = (n + 3) / 4;
     // the state this lane needs after the draw, loaded first so that the
     // loads overlap the random-number arithmetic (the fences below would
     // otherwise hold them back)
-    double mean_l = 0.0, off_l = 0.0, scale_l = 0.0;
+    double mean_l = 0.0, off_l = 0.0, scale_l = 0.0, z_l = 0.0;
     if (lane < n) {
         mean_l = S.mean[lane];
         off_l = S.offset[lane];
         scale_l = S.scale[lane];
+        z_l = S.Z[size_t(b) * n + lane];   // used when drawn
     }
     const double sigma = *S.sigma;
     for (int e = lane; e < n * n; e += kWave) s_BD[e] = S.B[e] * S.D[e % n];
-    if (lane < 2 * groups) draw_normal_pair(key0, key1, gen, b, lane >> 1, lane & 1, s_z + 2 * lane);
+    if (drawn) {
+        if (lane < n) s_z[lane] = z_l;
+    } else if (lane < 2 * groups) {
+        draw_normal_pair(key0, key1, gen, b, lane >> 1, lane & 1, s_z + 2 * lane);
+    }
     wave_sync();
     if (lane < n) {
         double y;
         const float x = candidate_coord(s_BD, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y);
-        S.Z[size_t(b) * n + lane] = s_z[lane];
+        if (!drawn) S.Z[size_t(b) * n + lane] = s_z[lane];
         S.Y[size_t(b) * n + lane] = y;
         a.X[size_t(b) * n + lane] = x;
         s_X[lane] = x;

@@ -42,9 +42,10 @@ struct StateHeader {               // first 64 bytes of the blob
     int32_t n, lambda, mu, n_blocks;
     int64_t denom_gen;             // generation g of the cached h_sigma denominator (-1: none)
     double denom;                  // sqrt(1 - (1 - c_sigma)^(2 (g + 1))) for g = denom_gen
-    int32_t pad[2];
+    int64_t z_gen;                 // generation whose draws Z holds for every candidate (-1: none)
 };
 static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
+static_assert(offsetof(StateHeader, z_gen) == 56, "z_gen offset in the layout");
 constexpr int32_t kStateMagic = 0x544b4345;  // "ECKT"
 
 __host__ __device__ inline void cmaes_layout(int32_t n, int32_t lam, tk_cmaes_layout* L) {
@@ -52,6 +53,7 @@ __host__ __device__ inline void cmaes_layout(int32_t n, int32_t lam, tk_cmaes_la
     L->gen = 0;
     L->seed = 8;
     L->flags = 16;
+    L->z_gen = 56;
     o = 64;
     auto take = [&o](int64_t bytes) {
         int64_t r = o;

@@ -64,7 +64,7 @@ class CmaesParams(ctypes.Structure):
 
 _LAYOUT_FIELDS = ["total_bytes", "gen", "seed", "flags", "sigma", "c_sigma", "d_sigma", "c_c", "c1", "c_mu", "c_m",
                   "mu_eff", "chi_n", "h_sigma", "weights", "mean", "p_sigma", "p_c", "offset", "scale", "D", "C",
-                  "B", "Z", "Y", "order"]
+                  "B", "Z", "Y", "order", "z_gen"]
 
 
 class CmaesLayout(ctypes.Structure):
@@ -343,6 +343,7 @@ def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:
            ("sigma", "c_sigma", "d_sigma", "c_c", "c1", "c_mu", "c_m", "mu_eff", "chi_n", "h_sigma")}
     out["gen"] = int(raw[L["gen"]:L["gen"] + 8].view(np.int64)[0])
     out["flags"] = int(raw[L["flags"]:L["flags"] + 4].view(np.int32)[0])
+    out["z_gen"] = int(raw[L["z_gen"]:L["z_gen"] + 8].view(np.int64)[0])
     out["weights"] = f64(L["weights"], lam)
     for name in ("mean", "p_sigma", "p_c", "offset", "scale", "D"):
         out[name] = f64(L[name], n)
@@ -359,11 +360,15 @@ def cmaes_write(state: torch.Tensor, n: int, lam: int, **fields):
     a given B, D).  Synchronous host-to-device copies."""
     L = cmaes_layout(n, lam)
     for name, val in fields.items():
-        if name == "gen":
+        if name in ("gen", "z_gen"):
             arr = np.array([int(val)], np.int64).view(np.uint8)
         else:
             arr = np.ascontiguousarray(val, np.float64).reshape(-1).view(np.uint8)
         state[L[name]:L[name] + arr.size].copy_(torch.from_numpy(arr.copy()).to(state.device))
+    if "Z" in fields and "z_gen" not in fields:
+        # the written z are not the draws of a known generation
+        arr = np.array([-1], np.int64).view(np.uint8)
+        state[L["z_gen"]:L["z_gen"] + 8].copy_(torch.from_numpy(arr.copy()).to(state.device))
 
 
 # ------------------------------------------------------------------ fitness path

@@ -127,3 +127,28 @@ def test_ask_eval_argument_errors():
         tk.cmaes_ask_eval(a.state, a.n, a.lam, prob.chains, prob.meshes, prob.cam, prob.target, a.X, a.xf, a.counts,
                           ws=small_ws)
     assert e.value.status == tk.TK_ERR_WORKSPACE_TOO_SMALL
+
+
+@pytest.mark.parametrize("n_arms,lam", [(1, 64), (2, 48)])
+def test_update_predraws_the_next_generation(n_arms, lam):
+    """An update draws the next generation's z while it decomposes C and
+    records that generation in the state (z_gen): the sampler draws the same
+    bits for it, and an ask-eval launch that reads the drawn z produces the
+    same candidates, counts and state as one that draws them itself."""
+    prob, (a, b) = _setup(n_arms, lam, tk.LOSS_IOU, 0.1)
+    for gen in range(4):
+        tk.cmaes_write(b.state, b.n, b.lam, z_gen=-1)      # b draws in its ask-eval prologue
+        a.ask_eval_tell()
+        b.ask_eval_tell()
+        torch.cuda.synchronize()
+        for name in ("X", "xf", "counts", "loss", "state"):
+            assert torch.equal(_bits(getattr(a, name)), _bits(getattr(b, name))), (gen, name)
+        va = tk.cmaes_view(a.state, a.n, a.lam)
+        assert va["z_gen"] == va["gen"] == gen + 1
+        # the sampler's draws of that generation are the same bits
+        c = a.state.clone()
+        tk.cmaes_write(c, a.n, a.lam, z_gen=-1)
+        X = torch.empty_like(a.X)
+        tk.cmaes_sample(c, a.n, a.lam, X)
+        torch.cuda.synchronize()
+        assert np.array_equal(tk.cmaes_view(c, a.n, a.lam)["Z"].view(np.uint64), va["Z"].view(np.uint64)), gen
