@@ -320,8 +320,19 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 double kj[8];
 #pragma unroll
                 for (int u = 0; u < 8; u++) kj[u] = s_key[j + u];
+                // a block wholly before k counts ties, one wholly after does not;
+                // only the block holding k needs the index (the condition is
+                // the same across most of a wave, so one side is skipped)
+                if (j + 8 <= k) {
 #pragma unroll
-                for (int u = 0; u < 8; u++) r += int(kj[u] < key) | (int(kj[u] == key) & int(j + u < k));
+                    for (int u = 0; u < 8; u++) r += int(kj[u] <= key);
+                } else if (j > k) {
+#pragma unroll
+                    for (int u = 0; u < 8; u++) r += int(kj[u] < key);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; u++) r += int(kj[u] < key) | (int(kj[u] == key) & int(j + u < k));
+                }
             }
             if (part == 0) {
                 for (int j = lam & ~7; j < lam; j++) {
