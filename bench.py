@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 # sha256 of the kernel sources they were taken on; the figure is reported only
 # while the sources are unchanged.
 RASTER_TRAFFIC = {"bytes_per_launch": 45968093.2,
+                  # SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x 4 waves per SIMD, same sources
+                  "valu_busy": 0.923,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
@@ -41,13 +43,17 @@ RASTER_TRAFFIC = {"bytes_per_launch": 45968093.2,
                   "sha256": "f5aaba210dff0806554d76050539466870753e9eefba2ea3ce5c8fb5e51f673f"}
 
 
-def raster_traffic():
+def raster_profile_valid():
     import hashlib
     h = hashlib.sha256()
     for p in RASTER_TRAFFIC["sources"]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
-    return RASTER_TRAFFIC["bytes_per_launch"] if h.hexdigest() == RASTER_TRAFFIC["sha256"] else None
+    return h.hexdigest() == RASTER_TRAFFIC["sha256"]
+
+
+def raster_traffic():
+    return RASTER_TRAFFIC["bytes_per_launch"] if raster_profile_valid() else None
 
 
 def log(msg):
@@ -217,6 +223,29 @@ def main():
         tracking["truth_jitter_mm"] = jitter_mm(truth)
         log(f"tracking over {len(frames_log)} frames: raw {tracking['raw']}, filtered {tracking['filtered']}")
 
+    # ---------------------------------------------------------------- per-generation distribution
+    # each of 300 generations (after 10 untimed ones) bracketed by its own
+    # events: median, p10 and p90 of the two-launch generation
+    state["frame"] = -1
+    for s in range(10):
+        run_step(s)
+    pairs_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(300)]
+    for i, (ea, eb) in enumerate(pairs_ev):
+        s = 10 + i
+        if s % G == 0:
+            end_frame()
+            start_frame((s // G) % F, s)
+        ea.record()
+        ask_eval()
+        tell()
+        eb.record()
+    torch.cuda.synchronize()
+    gen_us = np.array([ea.elapsed_time(eb) * 1e3 for ea, eb in pairs_ev])
+    generation_us = {"median": float(np.median(gen_us)), "p10": float(np.percentile(gen_us, 10)),
+                     "p90": float(np.percentile(gen_us, 90)), "generations": len(gen_us)}
+    log(f"per generation (events around each): median {generation_us['median']:.1f} us, "
+        f"p10 {generation_us['p10']:.1f}, p90 {generation_us['p90']:.1f}")
+
     # ---------------------------------------------------------------- work per fused launch
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     acc = np.zeros(4)
@@ -257,6 +286,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
                      "frac": achieved / peak_ops, "traffic": raster_traffic(),
                      "traffic_unit": "B per launch",
+                     "valu_busy": RASTER_TRAFFIC["valu_busy"] if raster_profile_valid() else None,
                      "kernel": "raster_kernel<true,false,true,1024> (tk_cmaes_ask_eval: draw, FK, raster, "
                                "counts; with workspace)",
                      "kernel_us": float(fused_ms.mean() * 1e3),
@@ -264,6 +294,7 @@ def main():
                                                                  "kept": kept,
                                                                  "box_pixels": box_px, "block_pairs": pairs}},
         "fitness_evals_per_s": lam / (fused_ms.mean() * 1e-3),
+        "generation_us": generation_us,
         "tracking": tracking,
     }
 
@@ -295,6 +326,7 @@ def main():
         out["graph_ms_per_step"] = graph_ms
         out["plain_ms_per_step"] = plain_ms
         out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
+        out["small320"] = small_leg(dev, with_cpu=not args.no_cpu_baseline)
         out["bimanual960"] = bimanual_leg(dev)
         out["batch64"] = batch_leg(dev)
         out["soft640"] = soft_leg(dev)
@@ -305,6 +337,76 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, mesh, cam, chain, traj, flips, readings, est0, lam)
 
     print(json.dumps(out), flush=True)
+
+
+def small_leg(dev, with_cpu=True, solves=20):
+    """The small plain-method configuration: one 1980-triangle instrument,
+    320x240, lambda = 16, 20-generation solves from a perturbed start, loss
+    1 - IoU against the render with 1% pixel flips.  GPU: the two launches of
+    each generation bracketed by events, over `solves` solves after two
+    untimed ones.  CPU: the oracle runs one whole 20-generation solve on one
+    host thread and on all of them."""
+    import torch
+
+    import oracle
+    from oracle import cmaes
+    import scenes
+    from paper_2603_11404_amd import tk, tracker
+
+    wl = scenes.workload("small")
+    mesh, cam, lam, G = wl["mesh"], wl["cam"], wl["lam"], wl["gens"]
+    chain = scenes.chain()
+    rng = scenes.rng_for(wl["index"], scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    flips = scenes.image_to_words(np.isin(np.arange(cam.width * cam.height), scenes.flip_indices(
+        scenes.rng_for(wl["index"], scenes.SUB_FLIPS), cam.width, cam.height)).reshape(cam.height, cam.width))
+    prob = tracker.Problem([mesh], [chain], cam, dev)
+    clean = prob.render(torch.as_tensor(truth[None].astype(np.float32), device=dev))[0]
+    prob.set_target(clean ^ torch.as_tensor(flips.view(np.int64), device=dev))
+    gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU)
+    rng_m = scenes.rng_for(wl["index"], scenes.SUB_CMAES)
+    starts = [truth + scenes.DEFAULT_SCALE * rng_m.normal(size=9) for _ in range(solves + 2)]
+    times, err_mm = [], []
+    for r, mean0 in enumerate(starts):
+        gen.init(np.zeros(9), 1.0, mean0, scenes.DEFAULT_SCALE, scenes.BASE_SEED + r)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(G)]
+        for ea, eb in ev:
+            ea.record()
+            gen.ask_eval_tell()
+            eb.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            times += [ea.elapsed_time(eb) * 1e3 for ea, eb in ev]
+            est = mean0 + scenes.DEFAULT_SCALE * tk.cmaes_view(gen.state, 9, lam)["mean"]   # physical mean
+            err_mm.append(float(np.linalg.norm(est[3:6] - truth[3:6]) * 1e3))
+    t = np.array(times)
+    out = {"workload": "small: one 1980-triangle instrument, 320x240, lambda=16, 9-D, 20-generation solves, "
+                       "loss 1-IoU, 1% pixel flips",
+           "gpu_us_per_generation": {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)),
+                                     "p90": float(np.percentile(t, 90)), "generations": len(t)},
+           "gpu_evals_per_s": lam / (float(np.median(t)) * 1e-6),
+           "final_trans_err_mm_median": float(np.median(err_mm))}
+    log(f"small320: {np.median(t):.1f} us per generation (p10 {np.percentile(t, 10):.1f}, "
+        f"p90 {np.percentile(t, 90):.1f}) over {len(t)} generations")
+    if with_cpu:
+        target = oracle.render(truth, [chain], [mesh], cam) ^ flips
+        m_cnt = oracle.counts(target, target, cam.width, cam.height)[2]
+        cpu = {}
+        for label, threads in (("one_thread", 1), ("all_threads", oracle.max_threads())):
+            es = cmaes.CMAES(9, lam, np.zeros(9), 1.0, starts[2], scenes.DEFAULT_SCALE, scenes.BASE_SEED + 2)
+            t0 = time.perf_counter()
+            for _ in range(G):
+                theta = es.sample().astype(np.float32).astype(np.float64)
+                cnt = oracle.eval_batch(theta, [chain], [mesh], cam, target, n_threads=threads)
+                es.update(np.array([oracle.mask_loss(cnt[k, 0], cnt[k, 1], m_cnt, 0) for k in range(lam)]))
+            el = time.perf_counter() - t0
+            cpu[label] = {"threads": threads, "ms_per_generation": el * 1e3 / G, "evals_per_s": G * lam / el}
+        cpu["sample"] = f"one whole {G}-generation solve of the oracle per thread count"
+        cpu["cpu"] = _cpu_model()
+        out["cpu_oracle"] = cpu
+        log(f"small320 oracle: {cpu['one_thread']['ms_per_generation']:.2f} ms per generation on 1 thread, "
+            f"{cpu['all_threads']['ms_per_generation']:.2f} on {cpu['all_threads']['threads']}")
+    return out
 
 
 def bimanual_leg(dev, gens=100):
