@@ -60,24 +60,22 @@ __device__ __forceinline__ void fk_pose(const float* __restrict__ th, const Chai
 }
 
 // Link l: 0 shaft (T_0 = I), 1 wrist Rx(q1), 2 / 3 jaws Rx(q1) Tr(0, 0, d) Ry(q2 +- q3 / 2).
+// One form for every link, M = T_r^c [Rx(q1) | Tr(0, 0, d)] Ry(phi), with
+// q1 = 0 for the shaft, d = 0 below the jaws and phi = 0 below them: the
+// factors are then exact identities (products with 1 and 0, sums with 0), so
+// every link gets the bits of its own formula (up to the sign of zeros), and
+// lanes holding different links take one path instead of three.
 __device__ __forceinline__ void fk_link(int l, const FkPose& P, const ChainK& ch, float* __restrict__ M) {
-    const float s1 = P.s1, c1 = P.c1;
-    if (l == 0) {
-#pragma unroll
-        for (int e = 0; e < 12; e++) M[e] = P.T[e];
-    } else if (l == 1) {
-        const float pitch[12] = {1, 0, 0, 0, 0, c1, -s1, 0, 0, s1, c1, 0};
-        aff_mul(P.T, pitch, M);
-    } else {
-        const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * ch.d, 0, s1, c1, c1 * ch.d};
-        float TY[12];
-        aff_mul(P.T, yaw_origin, TY);
-        const float phi = l == 2 ? P.q[1] + 0.5f * P.q[2] : P.q[1] - 0.5f * P.q[2];
-        float sp, cp;
-        sincosf(phi, &sp, &cp);
-        const float ry[12] = {cp, 0, sp, 0, 0, 1, 0, 0, -sp, 0, cp, 0};
-        aff_mul(TY, ry, M);
-    }
+    const float s1 = l >= 1 ? P.s1 : 0.0f, c1 = l >= 1 ? P.c1 : 1.0f;
+    const float d = l >= 2 ? ch.d : 0.0f;
+    const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * d, 0, s1, c1, c1 * d};
+    float TY[12];
+    aff_mul(P.T, yaw_origin, TY);
+    const float phi = l == 2 ? P.q[1] + 0.5f * P.q[2] : l == 3 ? P.q[1] - 0.5f * P.q[2] : 0.0f;
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    const float ry[12] = {cp, 0, sp, 0, 0, 1, 0, 0, -sp, 0, cp, 0};
+    aff_mul(TY, ry, M);
 }
 
 // Element j (0..3) of four values, chosen without indexing (a per-lane index

@@ -194,9 +194,16 @@ __device__ __forceinline__ int task_windows(int box_x) { return ((box_x >> 16) -
 __device__ __forceinline__ int task_bands(int box_y) { return ((box_y >> 16) - (box_y & 0xffff)) / 4 + 1; }
 
 // Narrow near triangles (box at most 2 columns wide, most of a fine mesh's
-// slivers) get their own tasks: the 2 box columns times 8 pixel rows.
+// slivers) get their own tasks: the 2 box columns times kNarrowRows pixel rows.
 __device__ __forceinline__ bool is_narrow(int box_x) { return (box_x >> 16) - (box_x & 0xffff) <= 1; }
-__device__ __forceinline__ int narrow_tasks(int box_y) { return ((box_y >> 16) - (box_y & 0xffff)) / 8 + 1; }
+// Rows per narrow task.  Narrow boxes of a fine mesh are mostly 1-6 rows tall
+// (about 90% at most 4 on the 640x480 instrument, a longer tail at 960x540):
+// 6-row tasks leave fewer idle rows than 8-row ones without the extra tasks
+// that 4-row ones need for the taller boxes.
+constexpr int kNarrowRows = 6;
+__device__ __forceinline__ int narrow_tasks(int box_y) {
+    return ((box_y >> 16) - (box_y & 0xffff)) / kNarrowRows + 1;
+}
 
 // ORs an 8x8 pixel block, bit 8r + c = pixel (xa + c, ya + r), into the (at
 // most 2 x 2) mask words it overlaps.  Only pixels inside the image may be set.
@@ -288,36 +295,37 @@ __device__ __forceinline__ void cover_window(const int4 q0, const int4 q1, int k
 }
 
 // One lane rasterises task k of a narrow near triangle: columns px0 and
-// px0 + 1 (the second only if inside the box) over pixel rows py0 + 8k ..
-// py0 + 8k + 7, with incremental 32-bit edge functions (all 8 rows lie within
-// 7 pixels of the box, where near triangles' edge functions are exact in 32
-// bits).  Each column's rows are collected with v_alignbit, clipped to the
-// box, spread to the block layout and ORed into the mask words.
+// px0 + 1 (the second only if inside the box) over the kNarrowRows pixel rows
+// from py0 + kNarrowRows k, with incremental 32-bit edge functions (all rows
+// lie within kNarrowRows - 1 pixels of the box, where near triangles' edge
+// functions are exact in 32 bits).  Each column's rows are collected with
+// v_alignbit, clipped to the box, spread to the block layout and ORed into
+// the mask words.
 __device__ __forceinline__ void cover_narrow(const int4 q0, const int4 q1, int k, unsigned long long* __restrict__ s_mask,
                                              int words_x) {
     const int px0 = q0.w & 0xffff, px1 = q0.w >> 16;
     const int py0 = q1.w & 0xffff, py1 = q1.w >> 16;
-    const int ya = py0 + 8 * k;
+    const int ya = py0 + kNarrowRows * k;
     const int32_t e0[3] = {q0.x, q0.y, q0.z};
     const int32_t dxs[3] = {rec_dx(q1.x), rec_dx(q1.y), rec_dx(q1.z)}, dys[3] = {rec_dy(q1.x), rec_dy(q1.y), rec_dy(q1.z)};
     uint32_t A[3], B[3], E[3];
     for (int e = 0; e < 3; e++) {
         A[e] = 0u - (uint32_t(dys[e]) << 8);          // one column to the right
         B[e] = uint32_t(dxs[e]) << 8;                 // one row down
-        E[e] = uint32_t(e0[e] + __mul24(dxs[e] << 8, 8 * k + 7));   // bottom row of the window
+        E[e] = uint32_t(e0[e] + __mul24(dxs[e] << 8, kNarrowRows * k + kNarrowRows - 1));   // bottom row of the window
     }
     // alignbit shifts the flags left and brings the new sign bit in at bit 0:
     // walking the rows bottom-up leaves row ya + r at bit r
     uint32_t neg0 = 0u, neg1 = 0u;
 #pragma unroll
-    for (int row = 7; row >= 0; row--) {
+    for (int row = kNarrowRows - 1; row >= 0; row--) {
         neg0 = __builtin_amdgcn_alignbit(neg0, E[0] | E[1] | E[2], 31);
         neg1 = __builtin_amdgcn_alignbit(neg1, (E[0] + A[0]) | (E[1] + A[1]) | (E[2] + A[2]), 31);
         E[0] -= B[0];
         E[1] -= B[1];
         E[2] -= B[2];
     }
-    const uint32_t rowmask = 0xFFu >> (7 - min(py1 - ya, 7));
+    const uint32_t rowmask = (0xFFu >> (8 - kNarrowRows)) >> (kNarrowRows - 1 - min(py1 - ya, kNarrowRows - 1));
     const uint32_t m0 = ~neg0 & rowmask;
     const uint32_t m1 = px1 > px0 ? ~neg1 & rowmask : 0u;
     const unsigned long long bits = spread_column(m0) | (spread_column(m1) << 1);
@@ -504,11 +512,13 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
         const ChainK ch = arm == 0 ? a.fk.ch[0] : a.fk.ch[1];
         FkPose P;
         fk_pose(s_X + 9 * arm, ch, P);
+        float M[12];
+        fk_link(lane < 8 ? part : select4(part, ch.kp_link[0], ch.kp_link[1], ch.kp_link[2], ch.kp_link[3]), P, ch,
+                M);
         if (lane < 8) {
-            fk_link(part, P, ch, s_M + 48 * arm + 12 * part);
+#pragma unroll
+            for (int e = 0; e < 12; e++) s_M[48 * arm + 12 * part + e] = M[e];
         } else {
-            float M[12];
-            fk_link(select4(part, ch.kp_link[0], ch.kp_link[1], ch.kp_link[2], ch.kp_link[3]), P, ch, M);
             fk_keypoint(M, ch, part, a.fk.cam, a.kp + (size_t(b) * n_arms + arm) * 8 + 2 * part);
         }
     }
@@ -703,7 +713,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             const bool narrow = near && is_narrow(rec.box_x);
             const bool wide = near && !narrow;
             // lane tasks: 8-column windows x 4-row bands (at most 5 x 9) for wide
-            // boxes, 8-row windows (at most 5) for narrow ones; both counts in one
+            // boxes, kNarrowRows-row windows (at most 6) for narrow ones; both counts in one
             // wave scan, wide in the low and narrow in the high 16 bits
             const int cnt_w = wide ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
             const int cnt_n = narrow ? narrow_tasks(rec.box_y) : 0;
