@@ -310,7 +310,46 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     int lg = 0;
     while (lg < 4 && (lam << (lg + 1)) <= NT) lg++;
     const int G = 1 << lg;
-    for (int base = 0; base < (lam << lg); base += NT) {   // same trip count in every lane
+    if (G == 1) {
+        // 2 lambda > NT: counting would cost lambda^2 tests at one lane per
+        // candidate.  Sort the (key, index) pairs instead with a bitonic
+        // network over P = 2^ceil(log2 lambda) slots; the padding slots hold
+        // +inf keys with indices >= lambda, so they sort last.  Pair t of a
+        // stage with stride s joins slots i = 2 s floor(t / s) + t mod s and
+        // i + s: for s <= 64 a wave's pairs stay within its own 128 slots
+        // (P / 2 <= NT, one pair per thread), so only the wider strides need
+        // the workgroup barrier.
+        int P = 1;
+        while (P < lam) P <<= 1;
+        for (int i = tid; i < P; i += NT) {
+            if (i >= lam) s_key[i] = INFINITY;
+            s_order[i] = i;
+        }
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                if (stride > 64) __syncthreads();
+                const int t = tid;
+                if (t < (P >> 1)) {
+                    const int ls = __builtin_ctz(stride);
+                    const int i = ((t >> ls) << (ls + 1)) + (t & (stride - 1)), j = i + stride;
+                    const double ka = s_key[i], kb = s_key[j];
+                    const int ia = s_order[i], ib = s_order[j];
+                    const bool a_after = ka > kb || (ka == kb && ia > ib);
+                    if (a_after == ((i & size) == 0)) {   // ascending blocks have bit `size` of i clear
+                        s_key[i] = kb;
+                        s_key[j] = ka;
+                        s_order[i] = ib;
+                        s_order[j] = ia;
+                    }
+                }
+                if (stride > 64) __syncthreads(); else wave_sync();
+            }
+        }
+        __syncthreads();
+        for (int r = tid; r < lam; r += NT) S.order[r] = s_order[r];
+    }
+    for (int base = 0; base < (G == 1 ? 0 : (lam << lg)); base += NT) {   // same trip count in every lane
         const int t = base + tid;
         const int k = t >> lg, part = t & (G - 1);
         int r = 0;
