@@ -70,7 +70,7 @@ def test_sample_matches_oracle_given_state(n, lam, nb):
         np.testing.assert_allclose(Xg, theta.astype(np.float32), rtol=2e-7, atol=1e-7)
 
 
-@pytest.mark.parametrize("n,lam,nb", [(9, 16, 1), (9, 256, 1), (18, 512, 2), (18, 64, 1)])
+@pytest.mark.parametrize("n,lam,nb", [(9, 16, 1), (9, 256, 1), (18, 512, 2), (18, 64, 1), (9, 1024, 1), (18, 1024, 2)])
 def test_update_matches_oracle_given_state(n, lam, nb):
     T = tk()
     es, st = _pair(n, lam, n_blocks=nb)
