@@ -186,6 +186,7 @@ struct WaveQueues {
     int32_t nstart[kNarrowRing];
     int4 wa[kWideRing], wb[kWideRing];
     int32_t wstart[kWideRing];
+    int32_t mark[64];      // per round: where each queued triangle's tasks start
 };
 
 // Lane tasks of a near triangle: 8-column windows times 4-row bands, both
@@ -242,6 +243,17 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
     x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+// Inclusive prefix maximum over the 64 lanes (same pattern; absent sources give -1).
+__device__ __forceinline__ int wave_inclusive_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));   // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));   // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));   // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));   // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));   // row_bcast:31 into rows 2, 3
     return x;
 }
 
@@ -401,24 +413,29 @@ __device__ __forceinline__ unsigned long long valid_bits(int wx, int wy, const C
 // ---------------------------------------------------------------- task rounds
 
 // Runs lane tasks done .. done + count - 1 (count <= 64, task done + i on lane
-// i) of a queue whose triangles occupy running slots tail .. head - 1.  Each
-// lane finds its triangle by binary search over the queued first-task numbers.
-// Returns the running slot of the triangle that holds task done + 64 (the new
-// tail after a full round).
+// i) of a queue whose triangles occupy running slots tail .. head - 1 (the
+// triangle at tail holds task done).  Lane l marks, in the wave's mark row,
+// the lane where triangle tail + l's tasks begin within the round (tail's own
+// at lane 0; first-task numbers increase, so marks never collide); a prefix
+// maximum over the lanes then gives each lane the last triangle starting at or
+// before its task.  Returns the running slot of the triangle that holds task
+// done + 64 (the new tail after a full round).
 template <int RING, bool NARROW>
 __device__ __forceinline__ int run_round(const int4* __restrict__ qa, const int4* __restrict__ qb,
-                                         const int32_t* __restrict__ qstart, int tail, int head, int done, int count,
-                                         int lane, unsigned long long* __restrict__ s_mask, int words_x) {
+                                         const int32_t* __restrict__ qstart, int32_t* __restrict__ mark, int tail,
+                                         int head, int done, int count, int lane,
+                                         unsigned long long* __restrict__ s_mask, int words_x) {
     const int q = done + lane;
     int next = tail;
+    mark[lane] = -1;
+    wave_sync();
+    if (lane < head - tail) {
+        const int rel = qstart[(tail + lane) & (RING - 1)] - done;
+        if (rel < kWave) mark[max(rel, 0)] = lane;
+    }
+    wave_sync();
+    const int lo = wave_inclusive_max(mark[lane]);   // slot tail + lo starts at or before task q
     if (lane < count) {
-        const int m = head - tail;
-        int lo = 0;   // qstart of slot tail + lo is <= q
-#pragma unroll
-        for (int step = RING / 2; step > 0; step >>= 1) {
-            const int i = lo + step;
-            if (i < m && qstart[(tail + i) & (RING - 1)] <= q) lo = i;
-        }
         const int slot = (tail + lo) & (RING - 1);
         const int k = q - qstart[slot];
         const int4 a = qa[slot], b = qb[slot];
@@ -723,7 +740,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             const int n_new = __popcll(nmask), w_new = __popcll(wmask);
             // the wide ring drains its pending tasks (fewer than 64) before it would overflow
             if (w_head - w_tail + w_new > kWideRing) {
-                run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, w_queued - w_done, lane,
+                run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane,
                                             s_mask, cam.words_x);
                 w_done = w_queued;
                 w_tail = w_head;
@@ -750,12 +767,12 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             w_queued += total & 0xffff;
             wave_sync();   // queued records written by other lanes are read below
             while (n_queued - n_done >= kWave) {
-                n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, n_tail, n_head, n_done, kWave, lane,
+                n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, kWave, lane,
                                                       s_mask, cam.words_x);
                 n_done += kWave;
             }
             while (w_queued - w_done >= kWave) {
-                w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, kWave, lane,
+                w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, kWave, lane,
                                                      s_mask, cam.words_x);
                 w_done += kWave;
             }
@@ -786,10 +803,10 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     }
     // the last partial rounds
     if (n_queued > n_done)
-        run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, n_tail, n_head, n_done, n_queued - n_done, lane, s_mask,
+        run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, n_queued - n_done, lane, s_mask,
                                      cam.words_x);
     if (w_queued > w_done)
-        run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, w_tail, w_head, w_done, w_queued - w_done, lane, s_mask,
+        run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane, s_mask,
                                     cam.words_x);
     __syncthreads();
 
