@@ -133,6 +133,24 @@ tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* 
                         const double* offset, const double* scale, const tk_cmaes_params* p,
                         uint64_t seed, tk_stream s);
 
+/* Initialise a state blob for the next frame at an estimate that is already
+ * in device memory, so a frame loop needs no host round trip (Sec. III-A: each
+ * frame starts from the previous frame's estimate; Sec. III-A.3: cosine joint
+ * map).  d_est: device FP64 [n], n = 9 n_arms, in the temporal filter's
+ * coordinates (pose, then joint angles q per arm), e.g. the theta or
+ * theta_next output of tk_kf_step.  The offset of each coordinate is
+ * d_est[i] for the pose and the inverse cosine map of the clamped joint angle
+ * (limits from chains, host [n_arms]) for the joints; where readings (host
+ * [n_arms][3] unconstrained joint coordinates, may be NULL) are given they
+ * replace the joint offsets.  Otherwise as tk_cmaes_init with mean0 = 0:
+ * sigma = sigma0, scale (host [n]), C = B = I, D = 1, paths 0, g = 0, seed,
+ * p (may be NULL).  d_est is read by the launched kernel, in stream order.
+ * Errors: TK_ERR_INVALID_ARGUMENT on sizes, NULL pointers, non-finite scale or
+ * readings, joint limits with lb >= ub; nothing is launched then. */
+tk_status tk_cmaes_init_at(void* d_state, int32_t n, int32_t lambda, const double* d_est, const tk_chain* chains,
+                           int32_t n_arms, const double* readings, double sigma0, const double* scale,
+                           const tk_cmaes_params* p, uint64_t seed, tk_stream s);
+
 /* Replace the mean (normalised space, host [n]) without touching sigma, C or
  * the paths (warm start from the previous frame, Sec. III-A). */
 tk_status tk_cmaes_set_mean(void* d_state, int32_t n, int32_t lambda, const double* mean, tk_stream s);

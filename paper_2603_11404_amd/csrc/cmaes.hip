@@ -22,7 +22,21 @@ struct InitArgs {
     double sigma0, c_m_scale, c_mu_scale, c1_scale;
     uint64_t seed;
     int32_t n, lambda, n_blocks;
+    // offset from a device estimate in the filter's coordinates (when est is
+    // set): coordinates in joint_mask are joint angles, encoded by the inverse
+    // cosine map with limits lb/ub; those in reading_mask keep offset[]
+    const double* est;
+    double lb[kMaxN], ub[kMaxN];
+    uint32_t joint_mask, reading_mask;
 };
+
+// Inverse cosine map (Sec. III-A.3): a joint angle q, clamped to [lb, ub], to
+// the unconstrained coordinate in [lb, ub].
+__device__ __forceinline__ double encode_joint(double q, double lb, double ub) {
+    q = fmin(fmax(q, lb), ub);
+    const double c = fmin(fmax(1.0 - 2.0 * (q - lb) / (ub - lb), -1.0), 1.0);
+    return lb + (ub - lb) / kPi * acos(c);
+}
 
 __global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a) {
     StateView S = state_view(blob, a.n, a.lambda);
@@ -78,7 +92,10 @@ __global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a)
     }
     for (int i = tid; i < n; i += blockDim.x) {
         S.mean[i] = a.mean0[i];
-        S.offset[i] = a.offset[i];
+        double off = a.offset[i];
+        if (a.est != nullptr && !((a.reading_mask >> i) & 1u))
+            off = ((a.joint_mask >> i) & 1u) ? encode_joint(a.est[i], a.lb[i], a.ub[i]) : a.est[i];
+        S.offset[i] = off;
         S.scale[i] = a.scale[i];
         S.p_sigma[i] = 0.0;
         S.p_c[i] = 0.0;
@@ -854,22 +871,10 @@ tk_status tk_cmaes_layout_get(int32_t n, int32_t lambda, tk_cmaes_layout* out) {
 }
 
 
-tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
-                        const double* offset, const double* scale, const tk_cmaes_params* p, uint64_t seed,
-                        tk_stream s) {
-    clear_error();
-    if (tk_status st = check_state(d_state, n, lambda)) return st;
-    TK_REQUIRE(mean0 && offset && scale, "mean0/offset/scale must be host arrays of n doubles");
+// The scalar settings shared by both initialisations.
+static tk_status init_settings(InitArgs& a, int32_t n, int32_t lambda, double sigma0, const tk_cmaes_params* p,
+                               uint64_t seed) {
     TK_REQUIRE(sigma0 > 0.0 && std::isfinite(sigma0), "sigma0 must be finite and > 0");
-    InitArgs a;
-    std::memset(&a, 0, sizeof a);
-    for (int i = 0; i < n; i++) {
-        TK_REQUIRE(std::isfinite(mean0[i]) && std::isfinite(offset[i]) && std::isfinite(scale[i]),
-                   "non-finite mean0/offset/scale[%d]", i);
-        a.mean0[i] = mean0[i];
-        a.offset[i] = offset[i];
-        a.scale[i] = scale[i];
-    }
     a.sigma0 = sigma0;
     a.c_m_scale = p ? p->c_m_scale : 1.0;
     a.c_mu_scale = p ? p->c_mu_scale : 1.0;
@@ -880,6 +885,61 @@ tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* 
     a.seed = seed;
     a.n = n;
     a.lambda = lambda;
+    return TK_OK;
+}
+
+tk_status tk_cmaes_init_at(void* d_state, int32_t n, int32_t lambda, const double* d_est, const tk_chain* chains,
+                           int32_t n_arms, const double* readings, double sigma0, const double* scale,
+                           const tk_cmaes_params* p, uint64_t seed, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(d_est && chains && scale, "d_est / chains / scale is NULL");
+    TK_REQUIRE(n_arms >= 1 && n_arms <= kMaxArms && n == 9 * n_arms, "n = %d must be 9 x n_arms (n_arms = %d)", n,
+               n_arms);
+    InitArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (tk_status st = init_settings(a, n, lambda, sigma0, p, seed)) return st;
+    a.est = d_est;
+    for (int i = 0; i < n; i++) {
+        TK_REQUIRE(std::isfinite(scale[i]), "non-finite scale[%d]", i);
+        a.scale[i] = scale[i];
+    }
+    for (int arm = 0; arm < n_arms; arm++) {
+        for (int j = 0; j < 3; j++) {
+            const int i = 9 * arm + 6 + j;
+            const double lb = chains[arm].q_lb[j], ub = chains[arm].q_ub[j];
+            TK_REQUIRE(std::isfinite(lb) && std::isfinite(ub) && lb < ub, "arm %d joint %d: limits must satisfy lb < ub",
+                       arm, j);
+            a.lb[i] = lb;
+            a.ub[i] = ub;
+            a.joint_mask |= 1u << i;
+            if (readings) {
+                TK_REQUIRE(std::isfinite(readings[3 * arm + j]), "non-finite reading of arm %d joint %d", arm, j);
+                a.offset[i] = readings[3 * arm + j];
+                a.reading_mask |= 1u << i;
+            }
+        }
+    }
+    hipLaunchKernelGGL(cmaes_init_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(s), d_state, a);
+    return check_launch("tk_cmaes_init_at");
+}
+
+tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
+                        const double* offset, const double* scale, const tk_cmaes_params* p, uint64_t seed,
+                        tk_stream s) {
+    clear_error();
+    if (tk_status st = check_state(d_state, n, lambda)) return st;
+    TK_REQUIRE(mean0 && offset && scale, "mean0/offset/scale must be host arrays of n doubles");
+    InitArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (tk_status st = init_settings(a, n, lambda, sigma0, p, seed)) return st;
+    for (int i = 0; i < n; i++) {
+        TK_REQUIRE(std::isfinite(mean0[i]) && std::isfinite(offset[i]) && std::isfinite(scale[i]),
+                   "non-finite mean0/offset/scale[%d]", i);
+        a.mean0[i] = mean0[i];
+        a.offset[i] = offset[i];
+        a.scale[i] = scale[i];
+    }
     hipLaunchKernelGGL(cmaes_init_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(s), d_state, a);
     return check_launch("tk_cmaes_init");
 }

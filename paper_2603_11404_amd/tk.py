@@ -73,7 +73,8 @@ class CmaesLayout(ctypes.Structure):
 
 EXPORTS = [
     "tk_status_string", "tk_last_error", "tk_version",
-    "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_set_mean", "tk_cmaes_sample",
+    "tk_cmaes_state_bytes", "tk_cmaes_layout_get", "tk_cmaes_init", "tk_cmaes_init_at", "tk_cmaes_set_mean",
+    "tk_cmaes_sample",
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
     "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
@@ -103,6 +104,7 @@ def lib():
         L.tk_cmaes_state_bytes.argtypes = [i32, i32]
         L.tk_cmaes_layout_get.argtypes = [i32, i32, P]
         L.tk_cmaes_init.argtypes = [P, i32, i32, P, f64, P, P, P, u64, P]
+        L.tk_cmaes_init_at.argtypes = [P, i32, i32, P, P, i32, P, f64, P, P, u64, P]
         L.tk_cmaes_set_mean.argtypes = [P, i32, i32, P, P]
         L.tk_cmaes_sample.argtypes = [P, i32, i32, P, P]
         L.tk_cmaes_update.argtypes = [P, i32, i32, P, P]
@@ -238,6 +240,23 @@ def cmaes_init(state, n, lam, mean0, sigma0, offset, scale, seed, c_m_scale=1.0,
     _check(lib().tk_cmaes_init(_ptr(state), n, lam, m.ctypes.data_as(ctypes.c_void_p), float(sigma0),
                                o.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p),
                                ctypes.byref(p), int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))
+
+
+def cmaes_init_at(state, n, lam, est, chains, readings, sigma0, scale, seed, c_m_scale=1.0, c_mu_scale=1.0,
+                  c1_scale=1.0, n_blocks=1, stream=None):
+    """cmaes_init with mean0 = 0 and the offset taken on the device from est
+    (device FP64 [n], filter coordinates: pose, joint angles), the joint
+    angles encoded by the inverse cosine map; readings (host [n_arms, 3]
+    unconstrained joint coordinates, or None) replace the joint offsets."""
+    n_arms = len(chains)
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    r = None if readings is None else np.ascontiguousarray(readings, np.float64).reshape(-1)
+    sc = np.ascontiguousarray(scale, np.float64)
+    p = CmaesParams(c_m_scale, c_mu_scale, c1_scale, n_blocks)
+    _check(lib().tk_cmaes_init_at(_ptr(state), n, lam, _ptr(est), ch, n_arms,
+                                  r.ctypes.data_as(ctypes.c_void_p) if r is not None else None, float(sigma0),
+                                  sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))
 
 
 def cmaes_set_mean(state, n, lam, mean, stream=None):

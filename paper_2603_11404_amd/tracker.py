@@ -238,9 +238,11 @@ class Tracker:
     Generation.ask_eval_tell()); end_frame() turns the CMA-ES mean into the
     filter's measurement (tk_cmaes_estimate: physical pose and joint angles)
     and filters it on the device (tk_kf_step: constant-velocity predict,
-    update, joint clamp).  One FP64 copy of 3 x n values per frame brings the
-    raw and filtered estimates to the host, where they also seed the next
-    frame.  With filt=None the raw estimate is passed through.
+    update, joint clamp).  The next frame starts from the filtered estimate
+    where it lies, in device memory (tk_cmaes_init_at); one asynchronous FP64
+    copy of 3 x n values per frame brings the raw and filtered estimates to
+    pinned host memory, read by collect() (end_frame() waits for its own
+    frame).  With filt=None the raw estimate is passed through.
 
     Estimates in the filter's coordinates hold joint angles q; CMA-ES runs on
     the unconstrained joint coordinates qhat (the cosine map of Sec. III-A.3).
@@ -262,6 +264,8 @@ class Tracker:
         d = self.p.device
         self.out = torch.empty(3, self.n, dtype=torch.float64, device=d)   # z, theta, theta_next
         self.kf = None
+        self.d_row = None     # row of self.out that starts the next frame (None: start from self.est)
+        self.pending = []     # pinned host copies of self.out, one per frame not yet collected
         if filt is not None:
             arms = self.p.n_arms
             tile = lambda a: np.tile(np.asarray(a, np.float64), arms)
@@ -291,15 +295,24 @@ class Tracker:
     def start(self, est0):
         """Restart tracking from est0 (CMA-ES coordinates, [n]); restarts the filter."""
         self.est = np.array(est0, dtype=np.float64)
+        self.d_row = None
         if self.kf is not None:
             x0 = np.clip(self._to_angles(self.est), self.params.lo[:self.n], self.params.hi[:self.n])
             tk.kf_init(self.kf, self.n, x0, self.params)
 
     def begin_frame(self, f: int, target=None, kp_ref=None, readings=None):
         """Observation of frame f (target words / keypoints, optional) and CMA-ES
-        initialisation; readings: joint readings qhat [n_arms, 3] or None."""
+        initialisation; readings: joint readings qhat [n_arms, 3] or None.  After
+        an end of frame the start is read on the device (tk_cmaes_init_at), so
+        the frame loop needs no host round trip; after start() it is est0."""
         if target is not None:
             self.p.set_target(target, kp_ref)
+        if self.d_row is not None:
+            r = None if readings is None else np.asarray(readings, np.float64).reshape(self.p.n_arms, 3)
+            tk.cmaes_init_at(self.gen.state, self.n, self.gen.lam, self.out[self.d_row], self.p.chains, r,
+                             self.sigma0, self.scale, self.seed0 + f, c_m_scale=self.c_m_scale,
+                             c_mu_scale=self.c_mu_scale)
+            return
         mean = self.est.copy()
         if readings is not None:
             r = np.asarray(readings, np.float64).reshape(self.p.n_arms, 3)
@@ -308,19 +321,39 @@ class Tracker:
         self.gen.init(np.zeros(self.n), self.sigma0, mean, self.scale, self.seed0 + f, c_m_scale=self.c_m_scale,
                       c_mu_scale=self.c_mu_scale)
 
-    def end_frame(self) -> dict:
-        """Measurement, filter step and the per-frame copy to the host:
-        {"z": raw estimate, "theta": filtered estimate} in the filter's coordinates."""
+    def end_frame_async(self):
+        """Measurement and filter step on the device, then an asynchronous copy
+        of (raw, filtered, predicted) estimates into pinned host memory; the
+        next begin_frame starts from the device copy.  No synchronisation."""
         g = self.gen
         tk.cmaes_estimate(g.state, self.n, g.lam, self.p.chains, self.out[0])
         if self.kf is not None:
             tk.kf_step(self.kf, self.n, self.out[0], self.out[1], self.out[2])
-        host = self.out.cpu().numpy()
-        z = host[0].copy()
-        th = host[1].copy() if self.kf is not None else z.copy()
-        nxt = host[2] if self.kf is not None and self.warm_start == "predict" else th
-        self.est = self._to_qhat(nxt)
-        return {"z": z, "theta": th}
+        host = torch.empty(3, self.n, dtype=torch.float64, pin_memory=True)
+        host.copy_(self.out, non_blocking=True)
+        self.pending.append(host)
+        self.d_row = 0 if self.kf is None else (2 if self.warm_start == "predict" else 1)
+
+    def collect(self) -> list:
+        """Waits for the frames ended since the last collect and returns their
+        {"z": raw estimate, "theta": filtered estimate} in the filter's coordinates."""
+        torch.cuda.synchronize(self.p.device)
+        out = []
+        for host in self.pending:
+            h = host.numpy()
+            z = h[0].copy()
+            th = h[1].copy() if self.kf is not None else z.copy()
+            out.append({"z": z, "theta": th})
+        if self.pending:
+            h = self.pending[-1].numpy()
+            self.est = self._to_qhat(h[self.d_row] if self.d_row is not None else h[0])
+        self.pending = []
+        return out
+
+    def end_frame(self) -> dict:
+        """end_frame_async() and collect() of this frame: {"z", "theta"}."""
+        self.end_frame_async()
+        return self.collect()[-1]
 
 
 def pose_errors(problem: Problem, est, truth) -> dict:

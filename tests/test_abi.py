@@ -98,3 +98,31 @@ def test_soft_and_adam_argument_errors_launch_nothing():
     assert L.tk_adam_reset(p, 0, None) == tk.TK_ERR_INVALID_ARGUMENT
     for lr, b1, b2, eps in [(0.0, 0.9, 0.999, 1e-8), (0.1, 1.0, 0.999, 1e-8), (0.1, 0.9, 0.999, 0.0)]:
         assert L.tk_cmaes_adam(p, 9, 16, p, p, lr, b1, b2, eps, None) == tk.TK_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libtk.so not built")
+def test_init_at_argument_errors_launch_nothing():
+    """tk_cmaes_init_at checks sizes, pointers, readings and joint limits on
+    the host before any launch (fake device addresses are never dereferenced)."""
+    import numpy as np
+    import scenes
+    from paper_2603_11404_amd import tk
+    L = tk.lib()
+    p = ctypes.c_void_p(1 << 20)
+    good = tk.chain(scenes.chain())
+    ch = (tk.Chain * 2)(good, good)
+    sc = np.ones(18)
+    par = tk.CmaesParams(1.0, 1.0, 1.0, 1)
+
+    def call(n=18, est=p, chains=ch, n_arms=2, readings=None, sigma0=1.0):
+        r = None if readings is None else np.ascontiguousarray(readings, np.float64).ctypes.data_as(ctypes.c_void_p)
+        return L.tk_cmaes_init_at(p, n, 16, est, chains, n_arms, r, sigma0, sc.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(par), 1, None)
+    bad = tk.chain(scenes.chain())
+    bad.q_lb[1], bad.q_ub[1] = 0.5, 0.5
+    assert call(n=9) == tk.TK_ERR_INVALID_ARGUMENT                      # n != 9 x n_arms
+    assert call(est=None) == tk.TK_ERR_INVALID_ARGUMENT
+    assert call(readings=[0, 0, np.nan, 0, 0, 0]) == tk.TK_ERR_INVALID_ARGUMENT
+    assert call(chains=(tk.Chain * 2)(good, bad)) == tk.TK_ERR_INVALID_ARGUMENT
+    assert call(sigma0=0.0) == tk.TK_ERR_INVALID_ARGUMENT
+    assert call(n_arms=3, n=27) == tk.TK_ERR_INVALID_ARGUMENT           # more arms than supported

@@ -146,3 +146,34 @@ def test_tracker_filters_its_raw_estimates():
     gen.ask_eval_tell()
     r = raw.end_frame()
     np.testing.assert_array_equal(r["theta"], r["z"])
+
+
+@pytest.mark.parametrize("with_readings", [False, True])
+def test_init_at_device_estimate_matches_host_init(with_readings):
+    """tk_cmaes_init_at reads the start on the device (pose as given, joint
+    angles through the inverse cosine map, clamped to the limits; readings
+    replace the joint offsets) and gives the state that tk_cmaes_init gives
+    from the same offset built on the host."""
+    dev = torch.device("cuda:0")
+    chains = [scenes.chain(), scenes.chain(1.3)]
+    n, lam = 18, 32
+    rng = np.random.default_rng(3)
+    est = rng.normal(size=n) * 0.3
+    est[6:9] = [chains[0].q_ub[0] + 0.2, 0.1, chains[0].q_lb[2] - 0.1]     # two joints beyond their limits
+    readings = rng.normal(size=(2, 3)) * 0.2 if with_readings else None
+    offset = est.copy()
+    for a, ch in enumerate(chains):
+        offset[9 * a + 6:9 * a + 9] = readings[a] if with_readings else tracker.encode_joints(est[9 * a + 6:9 * a + 9], ch)
+    scale = np.tile(scenes.DEFAULT_SCALE, 2)
+    s1, s2 = tk.cmaes_alloc(n, lam, dev), tk.cmaes_alloc(n, lam, dev)
+    tk.cmaes_init(s1, n, lam, np.zeros(n), 0.7, offset, scale, 11, n_blocks=2)
+    tk.cmaes_init_at(s2, n, lam, torch.as_tensor(est, device=dev), chains, readings, 0.7, scale, 11, n_blocks=2)
+    torch.cuda.synchronize()
+    v1, v2 = tk.cmaes_view(s1, n, lam), tk.cmaes_view(s2, n, lam)
+    pose = [i for i in range(n) if i % 9 < 6]
+    assert np.array_equal(v1["offset"][pose], v2["offset"][pose])
+    np.testing.assert_allclose(v2["offset"], v1["offset"], rtol=1e-14, atol=1e-15)
+    if with_readings:
+        assert np.array_equal(v1["offset"], v2["offset"])
+    for key in ("mean", "scale", "C", "B", "D", "p_sigma", "p_c", "weights", "sigma", "gen", "z_gen"):
+        assert np.array_equal(np.asarray(v1[key]), np.asarray(v2[key])), key
