@@ -117,6 +117,19 @@ def test_raster_two_meshes_union_and_empty():
     empty = scenes.Mesh(m1.vertices, np.zeros((0, 3), np.int32), m1.vertex_link, {})
     got = gpu_raster_from_snapped(np.stack(sn)[:, :m1.n_vertices], [empty], cam)
     assert not got.any()
+    # beside a mesh that has triangles, either arm may be the empty one
+    # (triangle chunks are numbered over both meshes)
+    s1 = np.stack(sn)[:, :m1.n_vertices]
+    s2 = np.stack(sn)[:, m1.n_vertices:]
+    only2 = [oracle_mask_from_snapped(*oracle_snapped(th2[k], ch, m2, cam), m2, cam) for k in range(3)]
+    only1 = [oracle_mask_from_snapped(*oracle_snapped(th1[k], ch, m1, cam), m1, cam) for k in range(3)]
+    empty2 = scenes.Mesh(m2.vertices, np.zeros((0, 3), np.int32), m2.vertex_link, {})
+    got = gpu_raster_from_snapped(np.concatenate([s1, s2], axis=1), [empty, m2], cam)
+    for k in range(3):
+        np.testing.assert_array_equal(got[k], only2[k])
+    got = gpu_raster_from_snapped(np.concatenate([s1, s2], axis=1), [m1, empty2], cam)
+    for k in range(3):
+        np.testing.assert_array_equal(got[k], only1[k])
 
 
 def test_mask_counts_bit_exact():
