@@ -647,29 +647,32 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         const bool t_even = (t_p & 1) == 0;
         for (int it = 0; it < max_rounds; it++) {
             auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
+            // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1) and the
+            // two V rows at columns 2P and 2Q do not depend on this round's
+            // rotations: they are read first, with no branch (every slot's
+            // offsets are valid; slots past the last entry repeat it)
+            double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
+    #pragma unroll
+            for (int sl = 0; sl < kASlots; sl++) {
+                blk0[sl] = pair(Acur, a_rij[sl]);
+                blk1[sl] = pair(Acur, a_rpj[sl]);
+                vr0[sl] = pair(Vcur, v0_r[sl]);
+                vr1[sl] = pair(Vcur, v1_r[sl]);
+            }
             const double2 bp = pair(Acur, t_rp), bq = pair(Acur, t_rq);
             double c_t, sn_t;
             const bool rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
             const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
             // column t of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
             const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
-            double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
+            // the rotation columns u, w of positions i and j from the lanes that hold them
             double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots];
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
-                if (sl < na_slots) {
-                    // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1), the
-                    // two V rows at columns 2P and 2Q, and the rotation columns u, w
-                    // of positions i and j from the lanes that hold them
-                    blk0[sl] = pair(Acur, a_rij[sl]);
-                    blk1[sl] = pair(Acur, a_rpj[sl]);
-                    vr0[sl] = pair(Vcur, v0_r[sl]);
-                    vr1[sl] = pair(Vcur, v1_r[sl]);
-                    u0[sl] = __shfl(col0_t, a_li[sl]);
-                    u1[sl] = __shfl(col1_t, a_li[sl]);
-                    w0[sl] = __shfl(col0_t, a_lj[sl]);
-                    w1[sl] = __shfl(col1_t, a_lj[sl]);
-                }
+                u0[sl] = __shfl(col0_t, a_li[sl]);
+                u1[sl] = __shfl(col1_t, a_li[sl]);
+                w0[sl] = __shfl(col0_t, a_lj[sl]);
+                w1[sl] = __shfl(col1_t, a_lj[sl]);
             }
             if (__ballot(rot) == 0ull) {
                 // nothing rotates in this round: stop if no pair exceeds the threshold
