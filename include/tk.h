@@ -217,6 +217,21 @@ tk_status tk_snap_vertices(const float* d_link_xf, int32_t batch, const tk_mesh*
  * candidate (batch * total vertices * 8); 0 on invalid arguments. */
 size_t tk_raster_workspace_bytes(int32_t batch, const tk_mesh* meshes, int32_t n_meshes);
 
+/* Claim order of a mesh's triangles for the raster entry points (the silhouette
+ * S of Sec. III-A.2 is an OR over triangles, so any order renders the same
+ * mask).  HOST pointers, no device call: vertices [n_vertices][3] and
+ * triangles [n_triangles][3] as in tk_mesh; triangles_out [n_triangles][3]
+ * (caller-owned, must not overlap triangles) receives the same triangles in
+ * blocks of 64 cut from the end of the list, the full blocks by decreasing
+ * summed model-space area, then the short block of the first n_triangles mod
+ * 64 triangles.  The raster kernels claim 64-triangle chunks in list order, so
+ * a mesh stored this way is rasterised costly chunks first, and the waves end
+ * close together.  Errors: TK_ERR_INVALID_ARGUMENT on sizes, NULL pointers,
+ * overlap or a vertex index outside [0, n_vertices); triangles_out is then
+ * not written. */
+tk_status tk_mesh_chunk_order(const float* vertices, int32_t n_vertices, const int32_t* triangles,
+                              int32_t n_triangles, int32_t* triangles_out);
+
 /* Binary silhouette S (Sec. III-A.2: S in {0,1}^{H x W}) of every candidate:
  * OR over the n_meshes arms (one mesh per arm, link transforms from
  * d_link_xf[batch][n_meshes][4][12]) of the exact integer coverage with the

@@ -664,11 +664,13 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     // triangles in chunks of 64 (one per lane), numbered over the meshes
     const int C0 = (m0.n_triangles + kWave - 1) / kWave;
     const int C = two ? C0 + (m1.n_triangles + kWave - 1) / kWave : C0;
-    // wave w starts with chunks w and NW + w; it claims each later chunk from
-    // an LDS counter two chunks ahead of the one it rasterises (indices two
-    // ahead, vertex gathers one ahead), so all waves finish within about one
-    // chunk of each other whatever the mix of triangle sizes
-    int c_cur = wave, c_nxt = wave + NW;
+    // wave w starts with chunks w and 2 NW - 1 - w (the first chunk of one
+    // wave pairs with the last of the first 2 NW, so that, when a mesh lists
+    // its costly chunks first, the costliest pairs with the cheapest); it
+    // claims each later chunk from an LDS counter two chunks ahead of the one
+    // it rasterises (indices two ahead, vertex gathers one ahead), so all
+    // waves finish within about one chunk of each other
+    int c_cur = wave, c_nxt = 2 * NW - 1 - wave;
     if (tid == 0) s_next_chunk = 2 * NW;
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;

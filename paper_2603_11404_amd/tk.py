@@ -81,7 +81,7 @@ EXPORTS = [
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
-    "tk_cmaes_adam",
+    "tk_cmaes_adam", "tk_mesh_chunk_order",
 ]
 
 _lib = None
@@ -140,6 +140,7 @@ def lib():
         L.tk_cmaes_mean_candidate.argtypes = [P, i32, i32, P, P]
         L.tk_adam_reset.argtypes = [P, i32, P]
         L.tk_cmaes_adam.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, P]
+        L.tk_mesh_chunk_order.argtypes = [P, i32, P, i32, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
                             "tk_raster_workspace_bytes", "tk_batch_table_bytes", "tk_kf_state_bytes",
@@ -188,12 +189,30 @@ def chain(ch) -> Chain:
     return c
 
 
-class DeviceMesh:
-    """Mesh arrays resident on the device plus the tk_mesh view of them."""
+def mesh_chunk_order(vertices, triangles) -> np.ndarray:
+    """tk_mesh_chunk_order on host arrays: the same triangles [T, 3] int32 in
+    the raster kernels' claim order (costly 64-triangle blocks first)."""
+    v = np.ascontiguousarray(vertices, np.float32)
+    t = np.ascontiguousarray(triangles, np.int32)
+    out = np.empty_like(t)
+    _check(lib().tk_mesh_chunk_order(v.ctypes.data, int(v.shape[0]), t.ctypes.data, int(t.shape[0]),
+                                     out.ctypes.data))
+    return out
 
-    def __init__(self, mesh, device="cuda"):
+
+class DeviceMesh:
+    """Mesh arrays resident on the device plus the tk_mesh view of them.
+
+    With chunk_order (the default) the triangles are stored in the order of
+    tk_mesh_chunk_order, which renders the same silhouette and lets the raster
+    kernels claim their costly chunks first."""
+
+    def __init__(self, mesh, device="cuda", chunk_order=True):
+        tris = np.ascontiguousarray(mesh.triangles, np.int32)
+        if chunk_order and tris.shape[0]:
+            tris = mesh_chunk_order(mesh.vertices, tris)
         self.vertices = torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float32), device=device)
-        self.triangles = torch.as_tensor(np.ascontiguousarray(mesh.triangles, np.int32), device=device)
+        self.triangles = torch.as_tensor(tris, device=device)
         self.vertex_link = torch.as_tensor(np.ascontiguousarray(mesh.vertex_link, np.uint8), device=device)
         self.n_vertices = int(self.vertices.shape[0])
         self.n_triangles = int(self.triangles.shape[0])

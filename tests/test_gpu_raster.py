@@ -267,3 +267,27 @@ def test_invalid_arguments_raise_without_launch():
     with pytest.raises(T.TkError) as e:
         T.raster_silhouette(xf, 2, [mesh], cam, masks, small_ws)
     assert e.value.status == 3
+
+
+@pytest.mark.parametrize("name", ["small", "track640"])
+def test_claim_order_renders_the_same_masks(name):
+    """The same snapped vertices rasterised from the mesh as given and from its
+    tk_mesh_chunk_order copy: identical masks, equal to the oracle's (which
+    reads the triangles as given)."""
+    T = tk()
+    wl = scenes.workload(name)
+    mesh, cam = wl["mesh"], wl["cam"]
+    rng = np.random.default_rng(300 + wl["index"])
+    th = candidates(rng, cam, 12, spread=3.0)
+    sns, fls = zip(*[oracle_snapped(t, scenes.chain(), mesh, cam) for t in th])
+    sn = torch.as_tensor(np.ascontiguousarray(np.stack(sns), np.int32), device=DEV)
+    got = []
+    for order in (False, True):
+        dm = T.DeviceMesh(mesh, DEV, chunk_order=order)
+        masks = torch.full((len(th), *T.words_shape(cam)), -1, dtype=torch.int64, device=DEV)
+        T.raster_from_snapped(sn, len(th), [dm], cam, masks)
+        torch.cuda.synchronize()
+        got.append(i64_to_words(masks.cpu().numpy()))
+    np.testing.assert_array_equal(got[0], got[1])
+    for k in range(len(th)):
+        np.testing.assert_array_equal(got[1][k], oracle_mask_from_snapped(sns[k], fls[k], mesh, cam))
