@@ -38,11 +38,11 @@ struct FkPose {
     float s1, c1;  // sin, cos of q1
 };
 
-__device__ __forceinline__ void fk_pose(const float* __restrict__ th, const ChainK& ch, FkPose& P) {
-    float sa, ca, sb, cb, sg, cg;
-    sincosf(th[0], &sa, &ca);
-    sincosf(th[1], &sb, &cb);
-    sincosf(th[2], &sg, &cg);
+// The pose from its trigonometric inputs: sines and cosines of the angles
+// alpha, beta, gamma (th[0..2]), the decoded joints q and sin, cos of q1.
+__device__ __forceinline__ void fk_pose_from(const float* __restrict__ th, float sa, float ca, float sb, float cb,
+                                             float sg, float cg, const float* __restrict__ q, float s1, float c1,
+                                             FkPose& P) {
     // R = Ry(gamma) Rx(alpha) Rz(beta)
     const float RyRx[9] = {cg, sg * sa, sg * ca, 0.0f, ca, -sa, -sg, cg * sa, cg * ca};
 #pragma unroll
@@ -55,8 +55,28 @@ __device__ __forceinline__ void fk_pose(const float* __restrict__ th, const Chai
     P.T[7] = th[4];
     P.T[11] = th[5];
 #pragma unroll
-    for (int j = 0; j < 3; j++) P.q[j] = decode_joint(th[6 + j], ch.lb[j], ch.ub[j]);
-    sincosf(P.q[0], &P.s1, &P.c1);
+    for (int j = 0; j < 3; j++) P.q[j] = q[j];
+    P.s1 = s1;
+    P.c1 = c1;
+}
+
+__device__ __forceinline__ void fk_pose(const float* __restrict__ th, const ChainK& ch, FkPose& P) {
+    float sa, ca, sb, cb, sg, cg;
+    sincosf(th[0], &sa, &ca);
+    sincosf(th[1], &sb, &cb);
+    sincosf(th[2], &sg, &cg);
+    float q[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) q[j] = decode_joint(th[6 + j], ch.lb[j], ch.ub[j]);
+    float s1, c1;
+    sincosf(q[0], &s1, &c1);
+    fk_pose_from(th, sa, ca, sb, cb, sg, cg, q, s1, c1, P);
+}
+
+// Angle phi of link l's last factor Ry(phi): q2 + q3 / 2 and q2 - q3 / 2 for
+// the jaws, 0 below them.
+__device__ __forceinline__ float fk_link_phi(int l, const float* __restrict__ q) {
+    return l == 2 ? q[1] + 0.5f * q[2] : l == 3 ? q[1] - 0.5f * q[2] : 0.0f;
 }
 
 // Link l: 0 shaft (T_0 = I), 1 wrist Rx(q1), 2 / 3 jaws Rx(q1) Tr(0, 0, d) Ry(q2 +- q3 / 2).
@@ -64,18 +84,23 @@ __device__ __forceinline__ void fk_pose(const float* __restrict__ th, const Chai
 // q1 = 0 for the shaft, d = 0 below the jaws and phi = 0 below them: the
 // factors are then exact identities (products with 1 and 0, sums with 0), so
 // every link gets the bits of its own formula (up to the sign of zeros), and
-// lanes holding different links take one path instead of three.
-__device__ __forceinline__ void fk_link(int l, const FkPose& P, const ChainK& ch, float* __restrict__ M) {
+// lanes holding different links take one path instead of three.  sp, cp:
+// sin and cos of fk_link_phi(l, P.q).
+__device__ __forceinline__ void fk_link_from(int l, const FkPose& P, const ChainK& ch, float sp, float cp,
+                                             float* __restrict__ M) {
     const float s1 = l >= 1 ? P.s1 : 0.0f, c1 = l >= 1 ? P.c1 : 1.0f;
     const float d = l >= 2 ? ch.d : 0.0f;
     const float yaw_origin[12] = {1, 0, 0, 0, 0, c1, -s1, -s1 * d, 0, s1, c1, c1 * d};
     float TY[12];
     aff_mul(P.T, yaw_origin, TY);
-    const float phi = l == 2 ? P.q[1] + 0.5f * P.q[2] : l == 3 ? P.q[1] - 0.5f * P.q[2] : 0.0f;
-    float sp, cp;
-    sincosf(phi, &sp, &cp);
     const float ry[12] = {cp, 0, sp, 0, 0, 1, 0, 0, -sp, 0, cp, 0};
     aff_mul(TY, ry, M);
+}
+
+__device__ __forceinline__ void fk_link(int l, const FkPose& P, const ChainK& ch, float* __restrict__ M) {
+    float sp, cp;
+    sincosf(fk_link_phi(l, P.q), &sp, &cp);
+    fk_link_from(l, P, ch, sp, cp, M);
 }
 
 // Element j (0..3) of four values, chosen without indexing (a per-lane index

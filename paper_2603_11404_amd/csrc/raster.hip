@@ -188,6 +188,7 @@ struct WaveQueues {
     int32_t wstart[kWideRing];
     int32_t mark[64];      // per round: where each queued triangle's tasks start
 };
+static_assert(sizeof(WaveQueues) >= 3328, "the ask prologue borrows wave 0's queues as 3.2 KB of scratch");
 
 // Lane tasks of a near triangle: 8-column windows times 4-row bands, both
 // starting at the box's top-left pixel.
@@ -481,13 +482,22 @@ struct RasterArgs {
 // its forward kinematics (same device function as the FK kernel) goes to the
 // LDS transforms s_M and to link_xf_out / kp.  When the state already holds
 // this generation's z (drawn by the previous update), they are read instead
-// of drawn.  scratch: >= 2.9 KB of LDS.
+// of drawn.  scratch: >= 3.2 KB of LDS.
 __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
     const int n = a.n;
     StateView S = state_view(a.state, n, a.lam);
     double* s_BD = reinterpret_cast<double*>(scratch);              // [n][n]
     double* s_z = s_BD + kMaxN * kMaxN;                              // [n + 3]
     float* s_X = reinterpret_cast<float*>(s_z + kMaxN + 3);         // [n]
+    float* s_trig = s_X + kMaxN;                                     // [2][16]
+    ChainK* s_ch = reinterpret_cast<ChainK*>(s_trig + 32);          // [kMaxArms]
+    // the chains' parameters copied to LDS by one lane: the lanes below select
+    // their arm's fields from LDS instead of holding both chains in scalar
+    // registers through the whole prologue (which the kernel would spill)
+    if (lane == 0) {
+        s_ch[0] = a.fk.ch[0];
+        s_ch[1] = a.fk.ch[1];
+    }
     const int64_t gen64 = S.hdr->gen;
     const bool drawn = S.hdr->z_gen == gen64;
     const uint32_t gen = uint32_t(gen64);
@@ -512,26 +522,65 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
         draw_normal_pair(key0, key1, gen, b, lane >> 1, lane & 1, s_z + 2 * lane);
     }
     wave_sync();
+    // the candidate's coordinates stay in registers until the end: a global
+    // store issued here would make the forward kinematics below wait for it
+    double y_l = 0.0, z_out = 0.0;
+    float x_l = 0.0f;
     if (lane < n) {
-        double y;
-        const float x = candidate_coord(s_BD, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y);
-        if (!drawn) S.Z[size_t(b) * n + lane] = s_z[lane];
-        S.Y[size_t(b) * n + lane] = y;
-        a.X[size_t(b) * n + lane] = x;
-        s_X[lane] = x;
+        x_l = candidate_coord(s_BD, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y_l);
+        z_out = s_z[lane];
+        s_X[lane] = x_l;
     }
     wave_sync();
-    // forward kinematics spread over lanes: (arm, link) on lanes 0 .. 4 n_arms - 1,
-    // (arm, keypoint) on lanes 8 .. 8 + 4 n_arms - 1
+    // forward kinematics in three lane-parallel levels, so that the chain of
+    // dependent trigonometric evaluations is two long instead of five; each
+    // value comes from the same call with the same argument as in fk_pose and
+    // fk_link, so the transforms carry the same bits as the FK kernel's.
+    // s_trig per arm: sin, cos of alpha, beta, gamma [0..5], q1..q3 [6..8],
+    // sin, cos of q1 [9, 10] and of the jaw angles phi+ [11, 12], phi- [13, 14].
     const int n_arms = a.fk.n_arms;
+    {
+        const int arm = lane >> 3, k = lane & 7;   // level 1: lane (arm, k), k < 6
+        if (arm < n_arms && k < 6) {
+            const float* th = s_X + 9 * arm;
+            float* t = s_trig + 16 * arm;
+            if (k < 3) {
+                float sn, cs;
+                sincosf(th[k], &sn, &cs);
+                t[2 * k] = sn;
+                t[2 * k + 1] = cs;
+            } else {
+                const int j = k - 3;
+                t[6 + j] = decode_joint(th[6 + j], s_ch[arm].lb[j], s_ch[arm].ub[j]);
+            }
+        }
+    }
+    wave_sync();
+    {
+        const int arm = lane >> 3, k = lane & 7;   // level 2: q1 (k = 0), phi+ (k = 1), phi- (k = 2)
+        if (arm < n_arms && k < 3) {
+            float* t = s_trig + 16 * arm;
+            float sn, cs;
+            sincosf(k == 0 ? t[6] : fk_link_phi(k + 1, t + 6), &sn, &cs);
+            t[9 + 2 * k] = sn;
+            t[10 + 2 * k] = cs;
+        }
+    }
+    wave_sync();
+    // level 3: (arm, link) on lanes 0 .. 4 n_arms - 1, (arm, keypoint) on
+    // lanes 8 .. 8 + 4 n_arms - 1
     const int arm = (lane & 7) >> 2, part = lane & 3;
     if ((lane < 8 && arm < n_arms) || (lane >= 8 && lane < 16 && arm < n_arms && a.kp)) {
-        const ChainK ch = arm == 0 ? a.fk.ch[0] : a.fk.ch[1];
+        const ChainK& ch = s_ch[arm];
+        const float* t = s_trig + 16 * arm;
         FkPose P;
-        fk_pose(s_X + 9 * arm, ch, P);
+        fk_pose_from(s_X + 9 * arm, t[0], t[1], t[2], t[3], t[4], t[5], t + 6, t[9], t[10], P);
+        const int l = lane < 8 ? part : select4(part, ch.kp_link[0], ch.kp_link[1], ch.kp_link[2], ch.kp_link[3]);
+        // sin, cos of fk_link_phi(l): phi+ for link 2, phi- for link 3, phi = 0 below (sin 0 = 0, cos 0 = 1)
+        const float sp = l == 2 ? t[11] : l == 3 ? t[13] : 0.0f;
+        const float cp = l == 2 ? t[12] : l == 3 ? t[14] : 1.0f;
         float M[12];
-        fk_link(lane < 8 ? part : select4(part, ch.kp_link[0], ch.kp_link[1], ch.kp_link[2], ch.kp_link[3]), P, ch,
-                M);
+        fk_link_from(l, P, ch, sp, cp, M);
         if (lane < 8) {
 #pragma unroll
             for (int e = 0; e < 12; e++) s_M[48 * arm + 12 * part + e] = M[e];
@@ -540,6 +589,11 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
         }
     }
     wave_sync();
+    if (lane < n) {
+        if (!drawn) S.Z[size_t(b) * n + lane] = z_out;
+        S.Y[size_t(b) * n + lane] = y_l;
+        a.X[size_t(b) * n + lane] = x_l;
+    }
     for (int e = lane; e < n_arms * 48; e += kWave) a.link_xf_out[size_t(b) * n_arms * 48 + e] = s_M[e];
 }
 
