@@ -419,34 +419,97 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         s_part[part * n + i] = acc;
     }
     __syncthreads();
-    if (tid < n) {
-        double acc = 0.0;
-        for (int part = 0; part < kParts; part++) acc += s_part[part * n + tid];
-        s_yw[tid] = acc;
-        s_mean[tid] = S.mean[tid] + c_m * sigma * acc;
-        S.mean[tid] = s_mean[tid];
-    }
-    __syncthreads();
-    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
-    if (tid < n) {
-        double acc = 0.0;
-        for (int j = 0; j < n; j++) acc += s_B[j * n + tid] * s_yw[j];
-        s_t[tid] = acc / s_D[tid];
-    }
-    __syncthreads();
-    if (tid < n) {
-        double acc = 0.0;
-        for (int j = 0; j < n; j++) acc += s_B[tid * n + j] * s_t[j];
-        s_ps[tid] = (1.0 - cs) * s_ps[tid] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
-        S.p_sigma[tid] = s_ps[tid];
-    }
-    __syncthreads();
+    // The mean, the paths and sigma (through step 3) are short chains on a
+    // single wave: wave 1 runs them with wave-level synchronisation, while
+    // wave 0 sets up the per-lane layout of the eigendecomposition (step 5),
+    // which depends on n and the block structure only.
+    const int m = nb + (nb & 1);
+    const int k1 = m - 1;                      // rounds per sweep
+    const int mm = m * m;
+    const int ntri_m = m * (m + 1) / 2;
+    const int n_a = n_blocks * ntri_m;         // upper-triangle entries of the blocks
+    const int n_v = n_blocks * nb * m;         // V entries of the blocks
+    auto move = [m](int p) {                   // position of an index in the next round
+        if (m == 2 || p == 0) return p;
+        if (p == 2) return 1;
+        if (p & 1) return p + 2 <= m - 1 ? p + 2 : m - 2;
+        return p - 2;
+    };
+    constexpr int kASlots = AS;
+    static_assert(VS == 2 * AS, "two V entries per A entry");
+    const int na_slots = (n_a + kWave64 - 1) / kWave64;
+    // A lane holds the entry (i, j), i <= j, of block b of A, and two V
+    // entries, in columns i and j: row j - i of column i and row
+    // m - j + i of column j (when < nb), which covers rows 0..m of every
+    // column exactly once over a block's entries.  What it reads comes in
+    // aligned pairs of adjacent columns (c & ~1, c | 1) of one row, at
+    // fixed offsets (in doubles, all even since m is even): rows i and
+    // i^1 at columns j&~1 (its entry and the partner entries), rows i,
+    // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
+    // rotations), and the two V rows at i&~1 and j&~1; it writes its
+    // entry (mirrored) and its V entries at their next positions.
+    int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
+    int a_w1[kASlots], a_w2[kASlots];
+    int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
+    bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
     if (tid < kWave64) {
+    #pragma unroll
+        for (int sl = 0; sl < kASlots; sl++) {
+            const int e = min(tid + kWave64 * sl, n_a - 1);
+            const int b = div_small(e, ntri_m), eb = e - b * ntri_m;
+            const int i = tri_row(eb, m);
+            const int j = i + eb - (i * m - (i * (i - 1)) / 2), base = b * mm, vbase = b * nb * m;
+            const int ie = i & ~1, je = j & ~1;
+            a_rij[sl] = base + ie * m + je;           // rows 2P, 2P+1 of the entry's 2x2 block
+            a_rpj[sl] = base + (ie + 1) * m + je;
+            a_li[sl] = b * m + i;               // the lanes holding the rotations of positions i and j
+            a_lj[sl] = b * m + j;
+            a_w1[sl] = base + move(i) * m + move(j);
+            a_w2[sl] = base + move(j) * m + move(i);
+            a_ok[sl] = tid + kWave64 * sl < n_a;
+            a_off[sl] = a_ok[sl] && i != j;
+            a_ei[sl] = (i & 1) == 0;
+            a_ej[sl] = (j & 1) == 0;
+            const int r0 = j - i, r1 = m - j + i;
+            v0_ok[sl] = a_ok[sl] && r0 < nb;
+            v1_ok[sl] = a_ok[sl] && r1 < nb;
+            v0_r[sl] = vbase + min(r0, nb - 1) * m + ie;
+            v0_w[sl] = vbase + min(r0, nb - 1) * m + move(i);
+            v1_r[sl] = vbase + min(r1, nb - 1) * m + je;
+            v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
+        }
+    }
+    static_assert(NT >= 2 * kWave64, "wave 1 runs the paths while wave 0 sets up the eigendecomposition");
+    const int t1 = tid - kWave64;              // lane within wave 1
+    const bool on_w1 = (tid >> 6) == 1;
+    if (on_w1 && t1 < n) {
+        double acc = 0.0;
+        for (int part = 0; part < kParts; part++) acc += s_part[part * n + t1];
+        s_yw[t1] = acc;
+        s_mean[t1] = S.mean[t1] + c_m * sigma * acc;
+        S.mean[t1] = s_mean[t1];
+    }
+    wave_sync();
+    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
+    if (on_w1 && t1 < n) {
+        double acc = 0.0;
+        for (int j = 0; j < n; j++) acc += s_B[j * n + t1] * s_yw[j];
+        s_t[t1] = acc / s_D[t1];
+    }
+    wave_sync();
+    if (on_w1 && t1 < n) {
+        double acc = 0.0;
+        for (int j = 0; j < n; j++) acc += s_B[t1 * n + j] * s_t[j];
+        s_ps[t1] = (1.0 - cs) * s_ps[t1] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
+        S.p_sigma[t1] = s_ps[t1];
+    }
+    wave_sync();
+    if (on_w1) {
         // sum of the recombination weights: strided partial sums, then a fixed butterfly
         double sw = 0.0;
-        for (int r = tid; r < mu; r += kWave64) sw += s_w[r];
+        for (int r = t1; r < mu; r += kWave64) sw += s_w[r];
         for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
-        if (tid == 0) {
+        if (t1 == 0) {
             double ss = 0.0;
             for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
             const double ps_norm = sqrt(ss);
@@ -464,9 +527,9 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     }
     __syncthreads();
     const double h_sigma = s_scal[1], sum_w = s_scal[2];
-    if (tid < n) {
-        s_pc[tid] = (1.0 - cc) * s_pc[tid] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[tid];
-        S.p_c[tid] = s_pc[tid];
+    if (on_w1 && t1 < n) {
+        s_pc[t1] = (1.0 - cc) * s_pc[t1] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[t1];
+        S.p_c[t1] = s_pc[t1];
     }
 
     // 4. covariance: rank-one + rank-mu (upper triangle, partial sums), symmetric, block-masked
@@ -567,18 +630,6 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         }
     }
     if (tid < kWave64) {
-        const int m = nb + (nb & 1);
-        const int k1 = m - 1;                      // rounds per sweep
-        const int mm = m * m;
-        const int ntri_m = m * (m + 1) / 2;
-        const int n_a = n_blocks * ntri_m;         // upper-triangle entries of the blocks
-        const int n_v = n_blocks * nb * m;         // V entries of the blocks
-        auto move = [m](int p) {                   // position of an index in the next round
-            if (m == 2 || p == 0) return p;
-            if (p == 2) return 1;
-            if (p & 1) return p + 2 <= m - 1 ? p + 2 : m - 2;
-            return p - 2;
-        };
         // positional layout: index l of block b starts at position l
         for (int e = tid; e < n_blocks * mm; e += kWave64) {
             const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
@@ -588,48 +639,6 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         for (int e = tid; e < n_v; e += kWave64) {
             const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
             s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
-        }
-        constexpr int kASlots = AS;
-        static_assert(VS == 2 * AS, "two V entries per A entry");
-        const int na_slots = (n_a + kWave64 - 1) / kWave64;
-        // A lane holds the entry (i, j), i <= j, of block b of A, and two V
-        // entries, in columns i and j: row j - i of column i and row
-        // m - j + i of column j (when < nb), which covers rows 0..m of every
-        // column exactly once over a block's entries.  What it reads comes in
-        // aligned pairs of adjacent columns (c & ~1, c | 1) of one row, at
-        // fixed offsets (in doubles, all even since m is even): rows i and
-        // i^1 at columns j&~1 (its entry and the partner entries), rows i,
-        // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
-        // rotations), and the two V rows at i&~1 and j&~1; it writes its
-        // entry (mirrored) and its V entries at their next positions.
-        int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
-        int a_w1[kASlots], a_w2[kASlots];
-        int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
-        bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
-    #pragma unroll
-        for (int sl = 0; sl < kASlots; sl++) {
-            const int e = min(tid + kWave64 * sl, n_a - 1);
-            const int b = div_small(e, ntri_m), eb = e - b * ntri_m;
-            const int i = tri_row(eb, m);
-            const int j = i + eb - (i * m - (i * (i - 1)) / 2), base = b * mm, vbase = b * nb * m;
-            const int ie = i & ~1, je = j & ~1;
-            a_rij[sl] = base + ie * m + je;           // rows 2P, 2P+1 of the entry's 2x2 block
-            a_rpj[sl] = base + (ie + 1) * m + je;
-            a_li[sl] = b * m + i;               // the lanes holding the rotations of positions i and j
-            a_lj[sl] = b * m + j;
-            a_w1[sl] = base + move(i) * m + move(j);
-            a_w2[sl] = base + move(j) * m + move(i);
-            a_ok[sl] = tid + kWave64 * sl < n_a;
-            a_off[sl] = a_ok[sl] && i != j;
-            a_ei[sl] = (i & 1) == 0;
-            a_ej[sl] = (j & 1) == 0;
-            const int r0 = j - i, r1 = m - j + i;
-            v0_ok[sl] = a_ok[sl] && r0 < nb;
-            v1_ok[sl] = a_ok[sl] && r1 < nb;
-            v0_r[sl] = vbase + min(r0, nb - 1) * m + ie;
-            v0_w[sl] = vbase + min(r0, nb - 1) * m + move(i);
-            v1_r[sl] = vbase + min(r1, nb - 1) * m + je;
-            v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
         double* Acur = s_A;
         double* Anext = s_T;
