@@ -158,3 +158,116 @@ def test_update_matches_paper_equation_in_theta_form():
         np.testing.assert_allclose(es.C, 0.5 * (Sigma + Sigma.T), rtol=0, atol=1e-13)
         checked += 1
     assert checked >= 3
+
+
+# ---------------------------------------------------------------- random selection
+#
+# Under selection that ignores the candidates (the loss a seeded random
+# permutation, drawn independently of the samples), the update of Eq. (3)-(4)
+# with Hansen's step-size and path rules must be unbiased: the tutorial builds
+# every rule so that, without selection pressure, E[m'] = m, E[C'] = C, the
+# conjugate path p_sigma keeps the distribution N(0, I) whatever C is, and
+# E[ln sigma'] = ln sigma.  These facts follow from the mathematics alone
+# (y_i:lambda are then i.i.d. N(0, C), z_i:lambda i.i.d. N(0, I)), so they pin
+# the sampling square root, the weights, C^(-1/2) in the path, the path
+# normalisations and the covariance learning rates without restating them.
+# A non-isotropic C (eigenvalues 1 .. 100, rotated) makes a C^(+1/2) for
+# C^(-1/2) slip, a missing sqrt(mu_eff) or a wrong weight sum visible.
+
+N_TRIALS = 3000
+
+
+def _fixed_state(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.linspace(1.0, 100.0, n)
+    return Q, ev, Q @ np.diag(ev) @ Q.T
+
+
+def _random_selection_trials(n, lam, p_sigma_stationary, p_c_stationary, seed=123):
+    Q, ev, C = _fixed_state(n, seed)
+    Lc = np.linalg.cholesky(C)
+    rng = np.random.default_rng(seed + 1)
+    m0 = rng.normal(size=n)
+    sigma0 = 0.3
+    out = {"dm": [], "ps": [], "C": [], "dlogs": []}
+    for t in range(N_TRIALS):
+        es = cmaes.CMAES(n, lam, m0, sigma0, np.zeros(n), np.ones(n), seed=1000 + t)
+        es.C, es.B, es.D = C.copy(), Q.copy(), np.sqrt(ev)
+        es.g = 1000                          # h_sigma's start-up correction has died out
+        es.p_sigma = rng.normal(size=n) if p_sigma_stationary else np.zeros(n)
+        es.p_c = Lc @ rng.normal(size=n) if p_c_stationary else np.zeros(n)
+        es.sample()
+        es.update(rng.permutation(lam).astype(np.float64))   # selection blind to the samples
+        out["dm"].append((es.m - m0) / (es.k["c_m"] * sigma0))
+        out["ps"].append(es.p_sigma.copy())
+        out["C"].append(es.C.copy())
+        out["dlogs"].append(math.log(es.sigma / sigma0))
+    return {k: np.array(v) for k, v in out.items()}, C, es.k
+
+
+def _cov_bound(S, N):
+    """5 standard errors of the sample covariance of N Gaussian draws with covariance S."""
+    d = np.sqrt(np.diag(S))
+    return 5.0 * np.sqrt((np.outer(d, d) ** 2 + S ** 2) / N)
+
+
+@pytest.mark.parametrize("lam", [16, 70])
+def test_random_selection_mean_step_has_covariance_C_over_mu_eff(lam):
+    """m' - m = c_m sigma y_w with y_w ~ N(0, C / mu_eff): zero mean and
+    mu_eff * Cov = C (pins y = B D z and the normalised weights)."""
+    n = 9
+    r, C, k = _random_selection_trials(n, lam, False, False)
+    dm = r["dm"]
+    se = np.sqrt(np.diag(C) / k["mu_eff"] / N_TRIALS)
+    assert np.all(np.abs(dm.mean(0)) <= 5.0 * se)
+    cov = k["mu_eff"] * np.cov(dm.T)
+    assert np.all(np.abs(cov - C) <= _cov_bound(C, N_TRIALS))
+
+
+@pytest.mark.parametrize("lam", [16, 70])
+def test_random_selection_conjugate_path_is_isotropic(lam):
+    """From p_sigma = 0, p_sigma' = sqrt(c_s (2 - c_s) mu_eff) C^(-1/2) y_w has
+    covariance c_s (2 - c_s) I for any C; from a stationary N(0, I) draw it
+    stays N(0, I)."""
+    n = 9
+    r, _, k = _random_selection_trials(n, lam, False, False)
+    cs = k["c_sigma"]
+    cov = np.cov(r["ps"].T) / (cs * (2.0 - cs))
+    assert np.all(np.abs(cov - np.eye(n)) <= _cov_bound(np.eye(n), N_TRIALS))
+    r2, _, _ = _random_selection_trials(n, lam, True, False, seed=321)
+    cov2 = np.cov(r2["ps"].T)
+    assert np.all(np.abs(cov2 - np.eye(n)) <= _cov_bound(np.eye(n), N_TRIALS))
+    assert np.all(np.abs(r2["ps"].mean(0)) <= 5.0 / math.sqrt(N_TRIALS))
+
+
+@pytest.mark.parametrize("lam", [16, 70])
+def test_random_selection_covariance_is_unbiased(lam):
+    """With p_c in its stationary law N(0, C) and p_sigma = 0 (so h_sigma = 1),
+    E[C'] = C: the rank-one and rank-mu terms replace exactly what the decay
+    (1 - c_1 - c_mu sum w) removes."""
+    n = 9
+    r, C, k = _random_selection_trials(n, lam, False, True)
+    mean_C = r["C"].mean(0)
+    d = np.sqrt(np.diag(C))
+    per_trial_var = (k["c_mu"] ** 2 / k["mu_eff"] + k["c1"] ** 2) * (np.outer(d, d) ** 2 + C ** 2)
+    assert np.all(np.abs(mean_C - C) <= 5.0 * np.sqrt(per_trial_var / N_TRIALS))
+    # the bound is tight enough to see a dropped rank-one term (its mean is c_1 C)
+    # or a decay off by c_1
+    assert 5.0 * np.sqrt(per_trial_var.max() / N_TRIALS) < 0.5 * k["c1"] * np.abs(C).max()
+
+
+def test_random_selection_log_step_size_has_zero_drift():
+    """With p_sigma stationary, ||p_sigma'|| is chi-distributed with n degrees of
+    freedom, so E[ln sigma' - ln sigma] = (c_s / d_s)(E chi_n / chi_n_approx - 1),
+    which is below 1e-4 for n = 9 (E chi_n = sqrt 2 Gamma((n+1)/2) / Gamma(n/2))."""
+    n, lam = 9, 16
+    r, _, k = _random_selection_trials(n, lam, True, False, seed=77)
+    e_chi = math.sqrt(2.0) * math.exp(math.lgamma((n + 1) / 2.0) - math.lgamma(n / 2.0))
+    drift = k["c_sigma"] / k["d_sigma"] * (e_chi / k["chi_n"] - 1.0)
+    assert abs(drift) < 1e-4
+    d = r["dlogs"]
+    assert abs(d.mean() - drift) <= 5.0 * d.std() / math.sqrt(N_TRIALS)
+    # and the spread is that of a chi variable scaled by c_s / (d_s chi_n)
+    chi_var = n - e_chi ** 2
+    np.testing.assert_allclose(d.std(), k["c_sigma"] / k["d_sigma"] * math.sqrt(chi_var) / k["chi_n"], rtol=0.1)
