@@ -118,8 +118,11 @@ def main():
         .reshape(cam.height, cam.width)) for _ in range(F)])
     targets = clean ^ torch.as_tensor(flips.view(np.int64), device=dev)
     rng_q = scenes.rng_for(wl["index"], scenes.SUB_CMAES)
-    q_true = tracker.decode_joints(traj[:, 6:9], chain)
-    readings = tracker.encode_joints(q_true + rng_q.normal(size=q_true.shape) * math.radians(2.0), chain)
+    # joint readings: the true joint angles (device cosine map) plus 2-degree
+    # noise, back in the unconstrained coordinates
+    noisy = tracker.joint_angles(prob, traj)
+    noisy[:, 6:9] += rng_q.normal(size=(F, 3)) * math.radians(2.0)
+    readings = tracker.joint_coordinates(prob, noisy)[:, 6:9]
     est0 = traj[0] + scale * rng_q.normal(size=9)
     torch.cuda.synchronize()
 
@@ -558,8 +561,9 @@ def synth700_leg(dev):
     targets = torch.as_tensor(np.stack([scenes.image_to_words(scenes.perturb_mask(rng_m, im)) for im in clean])
                               .view(np.int64), device=dev)
     rng_q = scenes.rng_for(wl["index"], scenes.SUB_CMAES)
-    q_true = tracker.decode_joints(traj[:, 6:9], chain)
-    readings = tracker.encode_joints(q_true + rng_q.normal(size=q_true.shape) * math.radians(2.0), chain)
+    noisy = tracker.joint_angles(prob, traj)
+    noisy[:, 6:9] += rng_q.normal(size=(F, 3)) * math.radians(2.0)
+    readings = tracker.joint_coordinates(prob, noisy)[:, 6:9]
     est0 = traj[0] + scale * rng_q.normal(size=9)
     gen = tracker.Generation(prob, lam, loss_kind=tk.LOSS_IOU | tk.KP_TWO_TIPS, lambda_kp=0.1)
     trk = tracker.Tracker(gen, scale, G, scenes.BASE_SEED + wl["index"] + 1000 * scenes.SUB_CMAES,

@@ -280,24 +280,13 @@ class Tracker:
             self.kf = tk.kf_alloc(self.n, d)
         self.est = None
 
-    def _to_angles(self, theta) -> np.ndarray:
-        out = np.array(theta, dtype=np.float64)
-        for a, ch in enumerate(self.p.chains):
-            out[9 * a + 6:9 * a + 9] = decode_joints(out[9 * a + 6:9 * a + 9], ch)
-        return out
-
-    def _to_qhat(self, theta) -> np.ndarray:
-        out = np.array(theta, dtype=np.float64)
-        for a, ch in enumerate(self.p.chains):
-            out[9 * a + 6:9 * a + 9] = encode_joints(out[9 * a + 6:9 * a + 9], ch)
-        return out
-
     def start(self, est0):
-        """Restart tracking from est0 (CMA-ES coordinates, [n]); restarts the filter."""
+        """Restart tracking from est0 (CMA-ES coordinates, [n]); restarts the
+        filter at est0 with its joints as angles (cosine map on the device)."""
         self.est = np.array(est0, dtype=np.float64)
         self.d_row = None
         if self.kf is not None:
-            x0 = np.clip(self._to_angles(self.est), self.params.lo[:self.n], self.params.hi[:self.n])
+            x0 = np.clip(joint_angles(self.p, self.est)[0], self.params.lo[:self.n], self.params.hi[:self.n])
             tk.kf_init(self.kf, self.n, x0, self.params)
 
     def begin_frame(self, f: int, target=None, kp_ref=None, readings=None):
@@ -344,9 +333,6 @@ class Tracker:
             z = h[0].copy()
             th = h[1].copy() if self.kf is not None else z.copy()
             out.append({"z": z, "theta": th})
-        if self.pending:
-            h = self.pending[-1].numpy()
-            self.est = self._to_qhat(h[self.d_row] if self.d_row is not None else h[0])
         self.pending = []
         return out
 
@@ -359,39 +345,84 @@ class Tracker:
 def pose_errors(problem: Problem, est, truth) -> dict:
     """Per-frame pose errors of estimates est [F, n] (filter coordinates: pose
     and joint angles) against truth [F, n] (CMA-ES coordinates, qhat joints),
-    per arm: rotation (geodesic angle between the two shaft rotations, degrees,
-    from the device forward kinematics), translation (m) and mean absolute
-    joint-angle error (degrees)."""
+    per arm, after resolving the instrument's two-fold ambiguity as Sec. IV
+    prescribes: a roll of the shaft by pi with the wrist and jaw-mean angles
+    negated, (beta + pi, -q1, -q2, q3), renders the same silhouette (the jaws
+    trade places), so of the truth and that equivalent the one whose roll
+    beta is closer to the estimate's (wrapped absolute difference) is scored.
+    Returns rotation (geodesic angle between the two shaft rotations,
+    degrees, from the device forward kinematics), translation (m), mean
+    absolute joint-angle error (degrees) and, per frame and arm, whether the
+    equivalent was taken ("flipped")."""
     est = np.asarray(est, np.float64)
     truth = np.asarray(truth, np.float64)
-    F = est.shape[0]
-    th = torch.as_tensor(np.concatenate([est, truth]).astype(np.float32), device=problem.device)
+    F, arms = est.shape[0], problem.n_arms
+    q_truth = joint_angles(problem, truth)                     # joints as angles (device cosine map)
+    ref, flipped = symmetric_reference(est, q_truth, arms)
+    # rotations of the shaft link from the device forward kinematics (only the
+    # pose enters the shaft's transform, so the rows' joint angles, which the
+    # forward kinematics would read as unconstrained coordinates, do not matter)
+    th = torch.as_tensor(np.concatenate([est, ref]).astype(np.float32), device=problem.device)
     R = problem.transforms(th)[:, :, 0, :, :3].double().cpu().numpy()      # [2F, arms, 3, 3]
     # angle = 2 asin(|R_a - R_b|_F / (2 sqrt 2)): well conditioned for small angles
-    diff = np.linalg.norm((R[:F] - R[F:]).reshape(F, problem.n_arms, 9), axis=-1)
+    diff = np.linalg.norm((R[:F] - R[F:]).reshape(F, arms, 9), axis=-1)
     rot = np.degrees(2.0 * np.arcsin(np.minimum(diff / (2.0 * np.sqrt(2.0)), 1.0)))
-    out = {"rot_deg": rot, "trans_m": np.zeros((F, problem.n_arms)), "joint_deg": np.zeros((F, problem.n_arms))}
-    for a, ch in enumerate(problem.chains):
+    out = {"rot_deg": rot, "trans_m": np.zeros((F, arms)), "joint_deg": np.zeros((F, arms)), "flipped": flipped}
+    for a in range(arms):
         s = slice(9 * a, 9 * a + 9)
-        out["trans_m"][:, a] = np.linalg.norm(est[:, s][:, 3:6] - truth[:, s][:, 3:6], axis=1)
-        q_true = np.stack([decode_joints(t[6:9], ch) for t in truth[:, s]])
-        out["joint_deg"][:, a] = np.degrees(np.abs(est[:, s][:, 6:9] - q_true).mean(axis=1))
+        out["trans_m"][:, a] = np.linalg.norm(est[:, s][:, 3:6] - ref[:, s][:, 3:6], axis=1)
+        out["joint_deg"][:, a] = np.degrees(np.abs(est[:, s][:, 6:9] - ref[:, s][:, 6:9]).mean(axis=1))
     return out
 
 
-# ------------------------------------------------------------------ host-side set-up helpers
+def symmetric_reference(est, q_truth, n_arms):
+    """The scoring reference of every frame and arm (Sec. IV): the truth
+    q_truth [F, n] (filter coordinates) or its equivalent (beta + pi, -q1,
+    -q2, q3), whichever has the roll beta closer to the estimate's, with
+    angles compared modulo 2 pi (ties keep the truth).  Returns (ref [F, n],
+    flipped [F, n_arms] bool)."""
+    est = np.asarray(est, np.float64)
+    ref = np.array(q_truth, dtype=np.float64, copy=True)
+    flipped = np.zeros((ref.shape[0], n_arms), dtype=bool)
+    wrap = lambda a: np.abs(np.remainder(a + np.pi, 2.0 * np.pi) - np.pi)
+    for a in range(n_arms):
+        o = 9 * a
+        alt = ref[:, o:o + 9].copy()
+        alt[:, 1] += np.pi
+        alt[:, 6:8] *= -1.0
+        flip = wrap(est[:, o + 1] - alt[:, 1]) < wrap(est[:, o + 1] - ref[:, o + 1])
+        ref[flip, o:o + 9] = alt[flip]
+        flipped[:, a] = flip
+    return ref, flipped
 
-def decode_joints(qhat, chain) -> np.ndarray:
-    """Cosine map of Sec. III-A.3 (unconstrained qhat -> q in [lb, ub]) on the
-    host, for building initial means from joint readings; the per-generation
-    decode runs inside tk_fk_transform."""
-    lb, ub = np.asarray(chain.q_lb), np.asarray(chain.q_ub)
-    return lb + (ub - lb) / 2.0 * (1.0 - np.cos(np.pi * (np.asarray(qhat) - lb) / (ub - lb)))
+
+# ------------------------------------------------------------------ joint coordinates on the device
+
+def joint_angles(problem: Problem, theta) -> np.ndarray:
+    """Rows theta [F, n] of CMA-ES coordinates (unconstrained joints qhat) as
+    filter coordinates (joint angles q in the limits): the cosine map of Sec.
+    III-A.3 evaluated by the device (tk_cmaes_estimate of a state whose
+    offset is the row).  For set-up and evaluation, not for the frame loop."""
+    theta = np.atleast_2d(np.asarray(theta, np.float64))
+    n = 9 * problem.n_arms
+    state = tk.cmaes_alloc(n, 2, problem.device)
+    z = torch.empty(theta.shape[0], n, dtype=torch.float64, device=problem.device)
+    for f, row in enumerate(theta):
+        tk.cmaes_init(state, n, 2, np.zeros(n), 1.0, row, np.ones(n), 0)
+        tk.cmaes_estimate(state, n, 2, problem.chains, z[f])
+    return z.cpu().numpy()
 
 
-def encode_joints(q, chain) -> np.ndarray:
-    """Inverse cosine map (Sec. III-A.3): a joint reading q, clamped to its
-    limits, to the unconstrained coordinate in [lb, ub]."""
-    lb, ub = np.asarray(chain.q_lb), np.asarray(chain.q_ub)
-    q = np.clip(np.asarray(q, dtype=np.float64), lb, ub)
-    return lb + (ub - lb) / np.pi * np.arccos(np.clip(1.0 - 2.0 * (q - lb) / (ub - lb), -1.0, 1.0))
+def joint_coordinates(problem: Problem, q_theta) -> np.ndarray:
+    """The inverse: rows q_theta [F, n] with joint angles (clamped to their
+    limits) back to CMA-ES coordinates, by the device's inverse cosine map
+    (tk_cmaes_init_at reads them as the offset of a state)."""
+    q_theta = np.atleast_2d(np.asarray(q_theta, np.float64))
+    n = 9 * problem.n_arms
+    state = tk.cmaes_alloc(n, 2, problem.device)
+    d = torch.as_tensor(q_theta, device=problem.device)
+    out = np.empty_like(q_theta)
+    for f in range(q_theta.shape[0]):
+        tk.cmaes_init_at(state, n, 2, d[f], problem.chains, None, 1.0, np.ones(n), 0)
+        out[f] = tk.cmaes_view(state, n, 2)["offset"]
+    return out

@@ -126,7 +126,7 @@ def test_tracker_filters_its_raw_estimates():
     hi = np.array([np.inf] * 6 + list(chain.q_ub))
     ms, vs = filt["meas_std"], filt["vel_std"]
     x0 = traj[0].copy()
-    x0[6:9] = tracker.decode_joints(x0[6:9], chain)
+    x0[6:9] = [oracle.decode(x0[6 + j], chain.q_lb[j], chain.q_ub[j]) for j in range(3)]
     ref = KalmanCV.diagonal(x0, ms ** 2, (5 * vs) ** 2, filt["pos_std"] ** 2, vs ** 2, ms ** 2, filt["dt"], lo, hi)
     for f in range(F):
         trk.begin_frame(f, targets[f], kps[f])
@@ -163,7 +163,11 @@ def test_init_at_device_estimate_matches_host_init(with_readings):
     readings = rng.normal(size=(2, 3)) * 0.2 if with_readings else None
     offset = est.copy()
     for a, ch in enumerate(chains):
-        offset[9 * a + 6:9 * a + 9] = readings[a] if with_readings else tracker.encode_joints(est[9 * a + 6:9 * a + 9], ch)
+        if with_readings:
+            offset[9 * a + 6:9 * a + 9] = readings[a]
+        else:   # the inverse cosine map of the joint angles clamped to their limits
+            q = np.clip(est[9 * a + 6:9 * a + 9], ch.q_lb, ch.q_ub)
+            offset[9 * a + 6:9 * a + 9] = [oracle.encode(q[j], ch.q_lb[j], ch.q_ub[j]) for j in range(3)]
     scale = np.tile(scenes.DEFAULT_SCALE, 2)
     s1, s2 = tk.cmaes_alloc(n, lam, dev), tk.cmaes_alloc(n, lam, dev)
     tk.cmaes_init(s1, n, lam, np.zeros(n), 0.7, offset, scale, 11, n_blocks=2)
