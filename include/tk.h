@@ -280,6 +280,27 @@ tk_status tk_cmaes_ask_eval(void* d_state, int32_t n, int32_t lambda, const tk_c
                             float* d_link_xf, float* d_kp, int32_t* d_counts, void* d_ws, size_t ws_bytes,
                             tk_stream s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch and results as tk_cmaes_ask_eval with a workspace, but the
+ * snapped-vertex workspace is a static array inside the library, one per
+ * device, of TK_NOALLOC_SCRATCH_BYTES (allocated when the library's code
+ * object is loaded on a device and held until the process ends; its address
+ * is looked up on the first call on each device).  The call allocates
+ * nothing.  Requires lambda * (sum of the meshes' n_vertices) * 8 <=
+ * TK_NOALLOC_SCRATCH_BYTES (e.g. 256 candidates of a 10k-vertex mesh), else
+ * TK_ERR_UNSUPPORTED and nothing is launched.  Every call on a device uses
+ * that device's one array: calls whose launches overlap on one device (other
+ * streams, other threads) race and give undefined counts; calls ordered on a
+ * stream are fine.  The kernel writes every entry it reads before reading it,
+ * so nothing needs clearing between calls.  Other arguments and errors as for
+ * tk_cmaes_ask_eval. */
+#define TK_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+tk_status tk_cmaes_ask_eval_noalloc(void* d_state, int32_t n, int32_t lambda, const tk_chain* chains,
+                                    int32_t n_arms, const tk_mesh* meshes, const tk_camera* cam,
+                                    const uint64_t* d_target, float* d_X, float* d_link_xf, float* d_kp,
+                                    int32_t* d_counts, tk_stream s);
+
 /* Workload statistics of a raster launch over the same inputs (for
  * measurement, not on the hot path): d_stats[4] uint64 = {triangles kept,
  * pixel centres inside the kept triangles' clamped boxes, (triangle, 8x8

@@ -1123,6 +1123,64 @@ tk_status attach_workspace(RasterArgs* a, void* d_ws, size_t ws_bytes, const cha
     return TK_OK;
 }
 
+// Arguments of the ask-eval launch (workspace not yet attached).
+tk_status ask_eval_args(void* d_state, int32_t n, int32_t lambda, const tk_chain* chains, int32_t n_arms,
+                        const tk_mesh* meshes, const tk_camera* cam, const uint64_t* d_target, float* d_X,
+                        float* d_link_xf, float* d_kp, int32_t* d_counts, RasterArgs* a) {
+    TK_REQUIRE(d_state != nullptr && (reinterpret_cast<uintptr_t>(d_state) & 255) == 0,
+               "state must be a 256-byte aligned device pointer");
+    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
+    TK_REQUIRE(n_arms >= 1 && n_arms <= kMaxArms && n == 9 * n_arms, "n = %d must be 9 x n_arms (n_arms = %d)", n,
+               n_arms);
+    if (tk_status st = common_raster_checks(lambda, meshes, n_arms, cam, a)) return st;
+    TK_REQUIRE(d_X && d_link_xf && d_target && d_counts, "X / link_xf / target / counts is NULL");
+    if (tk_status st = make_fk_args(chains, n_arms, cam, &a->fk)) return st;
+    a->fk.batch = lambda;
+    a->ask = 1;
+    a->n = n;
+    a->lam = lambda;
+    a->state = d_state;
+    a->X = d_X;
+    a->link_xf_out = d_link_xf;
+    a->kp = d_kp;
+    a->target = reinterpret_cast<const unsigned long long*>(d_target);
+    a->counts = d_counts;
+    return TK_OK;
+}
+
+// ---------------------------------------------------------------- static scratch of the allocation-free entry point
+
+// The snapped-vertex workspace of tk_cmaes_ask_eval_noalloc: one array per
+// device, allocated when the code object is loaded and held until the process
+// ends.  Host code never uses this name as an address (on the host it is a
+// stand-in symbol); it uses the device address that hipGetSymbolAddress
+// returns, queried once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[TK_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (queried on the first
+// call on that device).
+tk_status noalloc_scratch(void** out, const char* what) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(TK_ERR_DEVICE, "%s: hipGetDevice: %s", what, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TK_ERR_UNSUPPORTED, "%s: device %d beyond %d", what, dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(TK_ERR_DEVICE, "%s: hipGetSymbolAddress of the static scratch on device %d: %s", what, dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TK_OK;
+}
+
 }  // namespace
 
 size_t batch_raster_entry_bytes() { return sizeof(RasterArgs); }
@@ -1283,29 +1341,35 @@ tk_status tk_cmaes_ask_eval(void* d_state, int32_t n, int32_t lambda, const tk_c
                             float* d_link_xf, float* d_kp, int32_t* d_counts, void* d_ws, size_t ws_bytes,
                             tk_stream s) {
     clear_error();
-    TK_REQUIRE(d_state != nullptr && (reinterpret_cast<uintptr_t>(d_state) & 255) == 0,
-               "state must be a 256-byte aligned device pointer");
-    TK_REQUIRE(lambda >= 2 && lambda <= kMaxLambda, "lambda = %d outside 2..%d", lambda, kMaxLambda);
-    TK_REQUIRE(n_arms >= 1 && n_arms <= kMaxArms && n == 9 * n_arms, "n = %d must be 9 x n_arms (n_arms = %d)", n,
-               n_arms);
     RasterArgs a;
-    if (tk_status st = common_raster_checks(lambda, meshes, n_arms, cam, &a)) return st;
-    TK_REQUIRE(d_X && d_link_xf && d_target && d_counts, "X / link_xf / target / counts is NULL");
-    if (tk_status st = make_fk_args(chains, n_arms, cam, &a.fk)) return st;
-    a.fk.batch = lambda;
-    a.ask = 1;
-    a.n = n;
-    a.lam = lambda;
-    a.state = d_state;
-    a.X = d_X;
-    a.link_xf_out = d_link_xf;
-    a.kp = d_kp;
-    a.target = reinterpret_cast<const unsigned long long*>(d_target);
-    a.counts = d_counts;
+    if (tk_status st = ask_eval_args(d_state, n, lambda, chains, n_arms, meshes, cam, d_target, d_X, d_link_xf, d_kp,
+                                     d_counts, &a))
+        return st;
     if (tk_status st = attach_workspace(&a, d_ws, ws_bytes, "tk_cmaes_ask_eval")) return st;
     if (a.pretransform)
         return launch_raster<true, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_cmaes_ask_eval");
     return launch_raster<false, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_cmaes_ask_eval");
+}
+
+tk_status tk_cmaes_ask_eval_noalloc(void* d_state, int32_t n, int32_t lambda, const tk_chain* chains,
+                                    int32_t n_arms, const tk_mesh* meshes, const tk_camera* cam,
+                                    const uint64_t* d_target, float* d_X, float* d_link_xf, float* d_kp,
+                                    int32_t* d_counts, tk_stream s) {
+    clear_error();
+    RasterArgs a;
+    if (tk_status st = ask_eval_args(d_state, n, lambda, chains, n_arms, meshes, cam, d_target, d_X, d_link_xf, d_kp,
+                                     d_counts, &a))
+        return st;
+    const size_t need = tk_raster_workspace_bytes(lambda, meshes, n_arms);
+    if (need > TK_NOALLOC_SCRATCH_BYTES)
+        return fail(TK_ERR_UNSUPPORTED,
+                    "tk_cmaes_ask_eval_noalloc: %d candidates x %d vertices need %zu bytes of scratch, the "
+                    "library's static scratch holds %zu (use tk_cmaes_ask_eval with a workspace)",
+                    lambda, a.meshes.total_vertices, need, size_t(TK_NOALLOC_SCRATCH_BYTES));
+    void* ws = nullptr;
+    if (tk_status st = noalloc_scratch(&ws, "tk_cmaes_ask_eval_noalloc")) return st;
+    if (tk_status st = attach_workspace(&a, ws, TK_NOALLOC_SCRATCH_BYTES, "tk_cmaes_ask_eval_noalloc")) return st;
+    return launch_raster<true, false, true>(a, reinterpret_cast<hipStream_t>(s), "tk_cmaes_ask_eval_noalloc");
 }
 
 tk_status tk_snap_vertices(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,

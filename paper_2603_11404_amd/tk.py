@@ -78,6 +78,7 @@ EXPORTS = [
     "tk_cmaes_update", "tk_fk_transform", "tk_snap_vertices", "tk_raster_silhouette", "tk_raster_from_snapped",
     "tk_mask_loss", "tk_mask_popcount", "tk_eval_fused", "tk_compose_loss", "tk_raster_stats",
     "tk_raster_workspace_bytes", "tk_cmaes_tell_ask", "tk_cmaes_tell", "tk_cmaes_ask_eval",
+    "tk_cmaes_ask_eval_noalloc",
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
@@ -122,6 +123,7 @@ def lib():
         L.tk_cmaes_tell_ask.argtypes = [P, i32, i32, P, P, i32, f64, P, P, f64, f64, P, P, i32, P, P, P, P, P]
         L.tk_cmaes_tell.argtypes = [P, i32, i32, P, P, i32, f64, P, P, i32, f64, f64, P, P]
         L.tk_cmaes_ask_eval.argtypes = [P, i32, i32, P, i32, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.tk_cmaes_ask_eval_noalloc.argtypes = [P, i32, i32, P, i32, P, P, P, P, P, P, P, P]
         L.tk_batch_table_bytes.restype = ctypes.c_size_t
         L.tk_batch_table_bytes.argtypes = [i32]
         L.tk_batch_describe.argtypes = [P, i32, P, ctypes.c_size_t]
@@ -322,6 +324,21 @@ def cmaes_ask_eval(state, n, lam, chains, meshes, cam, target, X, link_xf, count
     wp, wb = _ws(ws)
     _check(lib().tk_cmaes_ask_eval(_ptr(state), n, lam, ch, n_arms, arr, ctypes.byref(c), _ptr(target), _ptr(X),
                                    _ptr(link_xf), _ptr(kp), _ptr(counts), wp, wb, _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024   # TK_NOALLOC_SCRATCH_BYTES
+
+
+def cmaes_ask_eval_noalloc(state, n, lam, chains, meshes, cam, target, X, link_xf, counts, kp=None, stream=None):
+    """cmaes_ask_eval with the library's static per-device scratch as its
+    workspace: the call allocates nothing (lam x total vertices x 8 bytes
+    must fit NOALLOC_SCRATCH_BYTES; overlapping calls on one device race)."""
+    n_arms = len(chains)
+    ch = (Chain * n_arms)(*[chain(c) for c in chains])
+    arr, nm = _meshes(meshes)
+    c = camera(cam)
+    _check(lib().tk_cmaes_ask_eval_noalloc(_ptr(state), n, lam, ch, n_arms, arr, ctypes.byref(c), _ptr(target),
+                                           _ptr(X), _ptr(link_xf), _ptr(kp), _ptr(counts), _stream(stream)))
 
 
 KF_MAX_N = 18
