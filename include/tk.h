@@ -69,12 +69,24 @@ typedef struct { float fx, fy, cx, cy; int32_t width, height; float z_near; } tk
  *   vertices [n_vertices][3] float32, metres, in the frame of their link;
  *   triangles [n_triangles][3] int32 vertex indices (either winding);
  *   vertex_link [n_vertices] uint8 in 0..3 (shaft, wrist, jaw+, jaw-).
- * 0 <= n_triangles <= 16M, 1 <= n_vertices <= 16M. */
+ * 0 <= n_triangles <= 16M, 1 <= n_vertices <= 16M.
+ * closed: 1 asserts that the triangles form a closed, consistently oriented
+ * surface -- every directed edge a->b occurs as often as b->a, which
+ * tk_mesh_closed checks on the host -- else 0.  For such a mesh the raster
+ * entry points that snap through a workspace draw only the triangles of
+ * positive signed area in the snapped image plane whenever no vertex of the
+ * mesh fails the near plane: those cover exactly the pixel centres that all
+ * triangles cover (the signed count of covering triangles at a centre,
+ * taken at the infinitesimally shifted point that the top-left rule amounts
+ * to, is the winding number of an empty boundary: zero), so the silhouette
+ * is identical.  A wrong 1 gives wrong silhouettes. */
 typedef struct {
     int32_t n_vertices, n_triangles;
     const float* vertices;
     const int32_t* triangles;
     const uint8_t* vertex_link;
+    int32_t closed;
+    int32_t reserved;   /* 0 */
 } tk_mesh;
 
 /* Kinematic chain of one instrument (Sec. III-A.3 and Fig. 2: end-effector
@@ -231,6 +243,28 @@ size_t tk_raster_workspace_bytes(int32_t batch, const tk_mesh* meshes, int32_t n
  * not written. */
 tk_status tk_mesh_chunk_order(const float* vertices, int32_t n_vertices, const int32_t* triangles,
                               int32_t n_triangles, int32_t* triangles_out);
+
+/* Whether a triangle list (HOST [n_triangles][3], indices in [0, n_vertices))
+ * is a closed, consistently oriented surface: *closed = 1 when every
+ * directed edge a->b occurs exactly as often as b->a (edges of a repeated
+ * vertex are ignored), else 0 -- the value tk_mesh.closed asserts.
+ * Errors: TK_ERR_INVALID_ARGUMENT on sizes, NULL pointers or indices out of
+ * range; *closed is then not written. */
+tk_status tk_mesh_closed(const int32_t* triangles, int32_t n_triangles, int32_t n_vertices, int32_t* closed);
+
+/* Plane order of a mesh's triangles (HOST pointers, no device call; same
+ * silhouette in any order): triangles_out [n_triangles][3] receives the
+ * triangles sorted by their supporting plane in model space -- the link of
+ * their first vertex, the direction of the unit normal (2-degree polar bands,
+ * then 0.01-degree azimuth bins), then the plane's offset (0.1 micrometre
+ * bins); ties keep list order; degenerate triangles last in their link.
+ * Coplanar triangles of one link project with the same orientation in every
+ * pose, so 64-triangle chunks of this order are mostly wholly back-facing or
+ * wholly front-facing, and the one-sided raster path (tk_mesh.closed) skips
+ * back-facing chunks as a whole.  Apply before tk_mesh_chunk_order, which
+ * moves whole 64-triangle blocks.  Errors as for tk_mesh_chunk_order. */
+tk_status tk_mesh_plane_order(const float* vertices, const uint8_t* vertex_link, int32_t n_vertices,
+                              const int32_t* triangles, int32_t n_triangles, int32_t* triangles_out);
 
 /* Binary silhouette S (Sec. III-A.2: S in {0,1}^{H x W}) of every candidate:
  * OR over the n_meshes arms (one mesh per arm, link transforms from

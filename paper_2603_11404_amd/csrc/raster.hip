@@ -638,6 +638,7 @@ template <>
 struct ChunkVerts<true> {
     int32_t X[3], Y[3];
     bool live;
+    bool second;   // the triangle is mesh 1's
 };
 template <>
 struct ChunkVerts<false> {
@@ -655,6 +656,7 @@ __device__ __forceinline__ void gather_chunk(const RasterArgs& a, const MeshK& m
     const ChunkLane cl = chunk_lane(m0, m1, C0, C, c, lane);
     g.live = cl.live;
     if constexpr (FS) {
+        g.second = cl.second;
         const int2* snap = reinterpret_cast<const int2*>(a.snapped) +
                            (size_t(b) * a.meshes.total_vertices + (cl.second ? m1.vertex_offset : m0.vertex_offset));
         for (int k = 0; k < 3; k++) {
@@ -702,7 +704,8 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     __shared__ WaveQueues s_queue[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
-    __shared__ int32_t s_next_chunk;
+    // [0] next chunk to claim; [1] bit m: a vertex of mesh m failed the near plane
+    __shared__ int32_t s_ctl[2];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int lx = lane & 7, ly = lane >> 3;
@@ -725,7 +728,10 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     // it rasterises (indices two ahead, vertex gathers one ahead), so all
     // waves finish within about one chunk of each other
     int c_cur = wave, c_nxt = 2 * NW - 1 - wave;
-    if (tid == 0) s_next_chunk = 2 * NW;
+    if (tid == 0) {
+        s_ctl[0] = 2 * NW;
+        s_ctl[1] = 0;
+    }
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
     if (a.ask) {
@@ -744,6 +750,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     if (pretransform) {
         // transform, project and snap every vertex of this candidate once into the workspace
         int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * TV;
+        int culled = 0;   // bit m: one of this lane's vertices of mesh m failed the near plane
         for (int gv = tid; gv < TV; gv += NT) {
             const bool second = two && gv >= m1.vertex_offset;
             const int v = gv - (second ? m1.vertex_offset : m0.vertex_offset);
@@ -751,11 +758,21 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             // the link transforms in s_M: 48 floats per mesh, 12 per link
             const int off = (second ? 48 : 0) + 12 * int((second ? m1.vertex_link : m0.vertex_link)[v]);
             int32_t X, Y;
-            project_snap(s_M + off, p[0], p[1], p[2], cam, X, Y);
+            const bool ok = project_snap(s_M + off, p[0], p[1], p[2], cam, X, Y);
+            culled |= ok ? 0 : (second ? 2 : 1);
             out[gv] = make_int2(X, Y);
         }
+        const unsigned long long c0 = __ballot(culled & 1), c1 = __ballot(culled & 2);
+        if (lane == 0 && (c0 | c1)) atomicOr(&s_ctl[1], (c0 ? 1 : 0) | (c1 ? 2 : 0));
         __syncthreads();
     }
+    // One-sided drawing: a closed mesh none of whose vertices failed the near
+    // plane is rasterised from its triangles of positive signed area only --
+    // the same pixel centres as all of its triangles (tk_mesh.closed).  Only
+    // with the pre-transform is the near-plane test known before the set-up.
+    const int near_culled = pretransform ? s_ctl[1] : 3;
+    const bool one0 = m0.closed && !(near_culled & 1);
+    const bool one1 = two && m1.closed && !(near_culled & 2);
 
     // queue state, the same in every lane of the wave: running slot counts
     // (head, tail) and task counts (queued, done) of the narrow and wide queues
@@ -768,89 +785,103 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
         // covers its LDS round trip (this file is compiled without the
         // compiler's atomic optimizer, which would wait for it right here)
         int claim;   // read in lane 0 only
-        if (lane == 0) claim = atomicAdd(&s_next_chunk, 1);
+        if (lane == 0) claim = atomicAdd(&s_ctl[0], 1);
         ChunkVerts<FROM_SNAPPED> g_nxt;
         gather_chunk(a, m0, m1, C0, C, b, c_nxt, lane, idx_nxt, g_nxt);
         int c_new;
         {
-            const bool live = g_cur.live;
             int32_t X[3], Y[3];
             chunk_snapped(g_cur, s_M, cam, X, Y);
+            bool keep = g_cur.live;
+            if constexpr (FROM_SNAPPED) {
+                // back-facing (or degenerate) triangles of a one-sided mesh cover nothing new
+                if (g_cur.second ? one1 : one0) {
+                    const int64_t area2 = (int64_t(X[1]) - X[0]) * (int64_t(Y[2]) - Y[0]) -
+                                          (int64_t(Y[1]) - Y[0]) * (int64_t(X[2]) - X[0]);
+                    keep = keep && area2 > 0;
+                }
+            }
+            // a chunk with nothing to draw (wholly back-facing in a plane-ordered
+            // mesh) skips the set-up and queueing with one uniform branch
+            const bool any = __ballot(keep) != 0ull;
             TriRec rec;
-            const bool valid = live && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
+            bool valid = false;
+            if (any) valid = keep && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
             // claims exceed every chunk the wave holds (the counter starts at
             // 2 NW); the max keeps each wave's chunk numbers increasing regardless
             c_new = max(__builtin_amdgcn_readlane(claim, 0), c_nxt + 1);
             load_chunk_indices(m0, m1, C0, C, c_new, lane, idx_nxt);
-            const bool near = valid && (rec.flags & kNear);
-            const bool narrow = near && is_narrow(rec.box_x);
-            const bool wide = near && !narrow;
-            // lane tasks: 8-column windows x 4-row bands (at most 5 x 9) for wide
-            // boxes, kNarrowRows-row windows (at most 6) for narrow ones; both counts in one
-            // wave scan, wide in the low and narrow in the high 16 bits
-            const int cnt_w = wide ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
-            const int cnt_n = narrow ? narrow_tasks(rec.box_y) : 0;
-            const int incl = wave_inclusive_sum(cnt_w | (cnt_n << 16));
-            const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-            const unsigned long long nmask = __ballot(narrow), wmask = __ballot(wide);
-            const int n_new = __popcll(nmask), w_new = __popcll(wmask);
-            // the wide ring drains its pending tasks (fewer than 64) before it would overflow
-            if (w_head - w_tail + w_new > kWideRing) {
-                run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane,
-                                            s_mask, cam.words_x);
-                w_done = w_queued;
-                w_tail = w_head;
-            }
-            if (narrow || wide) {
-                const NearRec r = pack_near(rec);
-                const unsigned long long m = narrow ? nmask : wmask;
-                const int rank = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
-                if (narrow) {
-                    const int slot = (n_head + rank) & (kNarrowRing - 1);
-                    Q.na[slot] = r.a;
-                    Q.nb[slot] = r.b;
-                    Q.nstart[slot] = n_queued + (incl >> 16) - cnt_n;
-                } else {
-                    const int slot = (w_head + rank) & (kWideRing - 1);
-                    Q.wa[slot] = r.a;
-                    Q.wb[slot] = r.b;
-                    Q.wstart[slot] = w_queued + (incl & 0xffff) - cnt_w;
+            if (any) {
+                const bool near = valid && (rec.flags & kNear);
+                const bool narrow = near && is_narrow(rec.box_x);
+                const bool wide = near && !narrow;
+                // lane tasks: 8-column windows x 4-row bands (at most 5 x 9) for wide
+                // boxes, kNarrowRows-row windows (at most 6) for narrow ones; both counts in one
+                // wave scan, wide in the low and narrow in the high 16 bits
+                const int cnt_w = wide ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;
+                const int cnt_n = narrow ? narrow_tasks(rec.box_y) : 0;
+                const int incl = wave_inclusive_sum(cnt_w | (cnt_n << 16));
+                const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                const unsigned long long nmask = __ballot(narrow), wmask = __ballot(wide);
+                const int n_new = __popcll(nmask), w_new = __popcll(wmask);
+                // the wide ring drains its pending tasks (fewer than 64) before it would overflow
+                if (w_head - w_tail + w_new > kWideRing) {
+                    run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane,
+                                                s_mask, cam.words_x);
+                    w_done = w_queued;
+                    w_tail = w_head;
                 }
-            }
-            n_head += n_new;
-            n_queued += total >> 16;
-            w_head += w_new;
-            w_queued += total & 0xffff;
-            wave_sync();   // queued records written by other lanes are read below
-            while (n_queued - n_done >= kWave) {
-                n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, kWave, lane,
-                                                      s_mask, cam.words_x);
-                n_done += kWave;
-            }
-            while (w_queued - w_done >= kWave) {
-                w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, kWave, lane,
-                                                     s_mask, cam.words_x);
-                w_done += kWave;
-            }
-            // triangles needing 64-bit edge functions or big boxes: the whole wave
-            // on one triangle at a time, its record broadcast from its lane
-            unsigned long long todo = __ballot(valid && !near);
-            while (todo) {
-                const int j = __builtin_ctzll(todo);
-                todo &= todo - 1;
-                TriRec br;
+                if (narrow || wide) {
+                    const NearRec r = pack_near(rec);
+                    const unsigned long long m = narrow ? nmask : wmask;
+                    const int rank = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                    if (narrow) {
+                        const int slot = (n_head + rank) & (kNarrowRing - 1);
+                        Q.na[slot] = r.a;
+                        Q.nb[slot] = r.b;
+                        Q.nstart[slot] = n_queued + (incl >> 16) - cnt_n;
+                    } else {
+                        const int slot = (w_head + rank) & (kWideRing - 1);
+                        Q.wa[slot] = r.a;
+                        Q.wb[slot] = r.b;
+                        Q.wstart[slot] = w_queued + (incl & 0xffff) - cnt_w;
+                    }
+                }
+                n_head += n_new;
+                n_queued += total >> 16;
+                w_head += w_new;
+                w_queued += total & 0xffff;
+                wave_sync();   // queued records written by other lanes are read below
+                while (n_queued - n_done >= kWave) {
+                    n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, kWave, lane,
+                                                          s_mask, cam.words_x);
+                    n_done += kWave;
+                }
+                while (w_queued - w_done >= kWave) {
+                    w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, kWave, lane,
+                                                         s_mask, cam.words_x);
+                    w_done += kWave;
+                }
+                // triangles needing 64-bit edge functions or big boxes: the whole wave
+                // on one triangle at a time, its record broadcast from its lane
+                unsigned long long todo = __ballot(valid && !near);
+                while (todo) {
+                    const int j = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    TriRec br;
 #pragma unroll
-                for (int e = 0; e < 3; e++) {
-                    br.e0lo[e] = __builtin_amdgcn_readlane(rec.e0lo[e], j);
-                    br.e0hi[e] = __builtin_amdgcn_readlane(rec.e0hi[e], j);
-                    br.dx[e] = __builtin_amdgcn_readlane(rec.dx[e], j);
-                    br.dy[e] = __builtin_amdgcn_readlane(rec.dy[e], j);
+                    for (int e = 0; e < 3; e++) {
+                        br.e0lo[e] = __builtin_amdgcn_readlane(rec.e0lo[e], j);
+                        br.e0hi[e] = __builtin_amdgcn_readlane(rec.e0hi[e], j);
+                        br.dx[e] = __builtin_amdgcn_readlane(rec.dx[e], j);
+                        br.dy[e] = __builtin_amdgcn_readlane(rec.dy[e], j);
+                    }
+                    br.box_x = __builtin_amdgcn_readlane(rec.box_x, j);
+                    br.box_y = __builtin_amdgcn_readlane(rec.box_y, j);
+                    br.flags = __builtin_amdgcn_readlane(rec.flags, j);
+                    br.pad = 0;
+                    cover_big(br, lx, ly, lane, s_mask, cam.words_x);
                 }
-                br.box_x = __builtin_amdgcn_readlane(rec.box_x, j);
-                br.box_y = __builtin_amdgcn_readlane(rec.box_y, j);
-                br.flags = __builtin_amdgcn_readlane(rec.flags, j);
-                br.pad = 0;
-                cover_big(br, lx, ly, lane, s_mask, cam.words_x);
             }
         }
         g_cur = g_nxt;
@@ -963,12 +994,28 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 __global__ __launch_bounds__(256) void stats_kernel(RasterArgs a, unsigned long long* __restrict__ stats) {
     const int b = blockIdx.y;
     __shared__ unsigned long long s_acc[4];
+    __shared__ int s_culled;   // bit m: a vertex of mesh m fails the near plane
     if (threadIdx.x < 4) s_acc[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) s_culled = 0;
+    __syncthreads();
+    for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
+        const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];
+        const float* M = a.link_xf + (size_t(b) * a.meshes.n_meshes + mi) * 48;
+        bool any = false;
+        for (int v = threadIdx.x; v < mesh.n_vertices; v += blockDim.x) {
+            const float* p = mesh.vertices + size_t(v) * 3;
+            int32_t X, Y;
+            any |= !project_snap(M + 12 * mesh.vertex_link[v], p[0], p[1], p[2], a.cam, X, Y);
+        }
+        if (any) atomicOr(&s_culled, 1 << mi);
+    }
     __syncthreads();
     unsigned long long kept = 0, pix = 0, pairs = 0, huge = 0;
     for (int mi = 0; mi < a.meshes.n_meshes; mi++) {
         const MeshK mesh = mi == 0 ? a.meshes.m[0] : a.meshes.m[1];   // selected, not indexed: no private copy of the arguments
         const float* M = a.link_xf + (size_t(b) * a.meshes.n_meshes + mi) * 48;
+        // the triangles the one-sided path of the workspace forms draws
+        const bool one = mesh.closed && !((s_culled >> mi) & 1);
         for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < mesh.n_triangles; t += gridDim.x * blockDim.x) {
             int32_t X[3], Y[3];
             for (int k = 0; k < 3; k++) {
@@ -976,6 +1023,8 @@ __global__ __launch_bounds__(256) void stats_kernel(RasterArgs a, unsigned long 
                 const float* p = mesh.vertices + size_t(v) * 3;
                 project_snap(M + 12 * mesh.vertex_link[v], p[0], p[1], p[2], a.cam, X[k], Y[k]);
             }
+            if (one && (int64_t(X[1]) - X[0]) * (int64_t(Y[2]) - Y[0]) - (int64_t(Y[1]) - Y[0]) * (int64_t(X[2]) - X[0]) <= 0)
+                continue;
             TriRec r;
             if (!setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], a.cam, r)) continue;
             kept++;

@@ -100,9 +100,11 @@ tk_status validate_meshes(const tk_mesh* meshes, int32_t n_meshes, MeshSet* out)
         out->m[i].n_vertices = m.n_vertices;
         out->m[i].n_triangles = m.n_triangles;
         out->m[i].vertex_offset = static_cast<int32_t>(total);
+        TK_REQUIRE(m.closed == 0 || m.closed == 1, "mesh %d: closed = %d must be 0 or 1", i, m.closed);
+        out->m[i].closed = m.closed;
         total += m.n_vertices;
     }
-    for (int i = n_meshes; i < kMaxArms; i++) out->m[i] = MeshK{nullptr, nullptr, nullptr, 0, 0, 0};
+    for (int i = n_meshes; i < kMaxArms; i++) out->m[i] = MeshK{nullptr, nullptr, nullptr, 0, 0, 0, 0};
     TK_REQUIRE(total <= (1 << 24), "too many vertices in total");
     out->total_vertices = static_cast<int32_t>(total);
     return TK_OK;

@@ -129,6 +129,7 @@ struct MeshK {
     const int32_t* triangles;
     const uint8_t* vertex_link;
     int32_t n_vertices, n_triangles, vertex_offset;  // offset into concatenated snapped arrays
+    int32_t closed;                                  // tk_mesh.closed
 };
 
 struct MeshSet {

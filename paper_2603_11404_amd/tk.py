@@ -38,7 +38,8 @@ class Camera(ctypes.Structure):
 
 class Mesh(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
-                ("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p), ("vertex_link", ctypes.c_void_p)]
+                ("vertices", ctypes.c_void_p), ("triangles", ctypes.c_void_p), ("vertex_link", ctypes.c_void_p),
+                ("closed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Chain(ctypes.Structure):
@@ -82,7 +83,7 @@ EXPORTS = [
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
-    "tk_cmaes_adam", "tk_mesh_chunk_order",
+    "tk_cmaes_adam", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order",
 ]
 
 _lib = None
@@ -143,6 +144,8 @@ def lib():
         L.tk_adam_reset.argtypes = [P, i32, P]
         L.tk_cmaes_adam.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, P]
         L.tk_mesh_chunk_order.argtypes = [P, i32, P, i32, P]
+        L.tk_mesh_closed.argtypes = [P, i32, i32, P]
+        L.tk_mesh_plane_order.argtypes = [P, P, i32, P, i32, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
                             "tk_raster_workspace_bytes", "tk_batch_table_bytes", "tk_kf_state_bytes",
@@ -202,17 +205,41 @@ def mesh_chunk_order(vertices, triangles) -> np.ndarray:
     return out
 
 
+def mesh_closed(triangles, n_vertices) -> bool:
+    """tk_mesh_closed: whether the triangle list is a closed, consistently
+    oriented surface (every directed edge matched by its reverse)."""
+    t = np.ascontiguousarray(triangles, np.int32)
+    out = ctypes.c_int32(-1)
+    _check(lib().tk_mesh_closed(t.ctypes.data if t.size else None, int(t.shape[0]), int(n_vertices),
+                                ctypes.byref(out)))
+    return bool(out.value)
+
+
+def mesh_plane_order(vertices, vertex_link, triangles) -> np.ndarray:
+    """tk_mesh_plane_order on host arrays: the same triangles grouped by their
+    supporting plane."""
+    v = np.ascontiguousarray(vertices, np.float32)
+    l = np.ascontiguousarray(vertex_link, np.uint8)
+    t = np.ascontiguousarray(triangles, np.int32)
+    out = np.empty_like(t)
+    _check(lib().tk_mesh_plane_order(v.ctypes.data, l.ctypes.data, int(v.shape[0]), t.ctypes.data, int(t.shape[0]),
+                                     out.ctypes.data))
+    return out
+
+
 class DeviceMesh:
     """Mesh arrays resident on the device plus the tk_mesh view of them.
 
-    With chunk_order (the default) the triangles are stored in the order of
-    tk_mesh_chunk_order, which renders the same silhouette and lets the raster
-    kernels claim their costly chunks first."""
+    With chunk_order (the default) the triangles are stored grouped by plane
+    (tk_mesh_plane_order) and then in the claim order of tk_mesh_chunk_order:
+    the same silhouette, with mostly one-orientation chunks claimed costly
+    ones first.  closed is what tk_mesh_closed reports for the triangles."""
 
     def __init__(self, mesh, device="cuda", chunk_order=True):
         tris = np.ascontiguousarray(mesh.triangles, np.int32)
         if chunk_order and tris.shape[0]:
-            tris = mesh_chunk_order(mesh.vertices, tris)
+            tris = mesh_chunk_order(mesh.vertices, mesh_plane_order(mesh.vertices, mesh.vertex_link, tris))
+        self.closed = mesh_closed(tris, mesh.n_vertices)
         self.vertices = torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float32), device=device)
         self.triangles = torch.as_tensor(tris, device=device)
         self.vertex_link = torch.as_tensor(np.ascontiguousarray(mesh.vertex_link, np.uint8), device=device)
@@ -221,7 +248,8 @@ class DeviceMesh:
 
     def struct(self) -> Mesh:
         return Mesh(self.n_vertices, self.n_triangles, self.vertices.data_ptr(),
-                    self.triangles.data_ptr() if self.n_triangles else None, self.vertex_link.data_ptr())
+                    self.triangles.data_ptr() if self.n_triangles else None, self.vertex_link.data_ptr(),
+                    int(self.closed), 0)
 
 
 def _meshes(meshes):

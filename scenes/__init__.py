@@ -82,6 +82,30 @@ def _quad_grid(p0, du, dv, nu, nv):
     return verts, tris
 
 
+def _weld(verts, tris, tol=1e-9):
+    """Merges vertices closer than tol (the same point reached along two face
+    grids) into the first of them; returns (vertices, triangles)."""
+    from scipy.spatial import cKDTree
+    n = len(verts)
+    rep = np.arange(n)
+    for i, j in sorted(cKDTree(verts).query_pairs(tol)):
+        ri, rj = rep[i], rep[j]
+        while rep[ri] != ri:
+            ri = rep[ri]
+        while rep[rj] != rj:
+            rj = rep[rj]
+        rep[max(ri, rj)] = min(ri, rj)
+    for i in range(n):
+        r = i
+        while rep[r] != r:
+            r = rep[r]
+        rep[i] = r
+    keep = np.unique(rep)
+    new_index = np.full(n, -1)
+    new_index[keep] = np.arange(len(keep))
+    return verts[keep], new_index[rep][tris]
+
+
 def _tri_subdiv(p0, p1, p2, m):
     """Split triangle p0 p1 p2 into m*m congruent triangles."""
     p0, p1, p2 = (np.asarray(a, dtype=np.float64) for a in (p0, p1, p2))
@@ -105,14 +129,17 @@ def instrument_mesh(segments=32, rings=28, box_div=3, wedge_div=1,
 
     Link frames: the end-effector (robot) frame sits at the wrist-pitch axis
     with z pointing distally (paper Fig. 2 caption, Sec. III-A).
-      * shaft (link 0): open cylinder r = 4 mm on z in [-0.302, -0.002];
-        `segments` around, `rings` interior rings -> 2*segments*(rings+1) tris.
+      * shaft (link 0): cylinder r = 4 mm on z in [-0.302, -0.002] closed by
+        two end discs; `segments` around, `rings` interior rings ->
+        2*segments*(rings+1) side tris + 2*segments cap tris.
       * wrist (link 1): box x, y in +-3.5 mm (x box_scale), z in [-0.002, 0.009];
         each face split box_div x box_div -> 12*box_div^2 tris.
       * jaws (links 2, 3): triangular prisms in the jaw frames, base half-width
         2.5 mm, length 14 mm (x jaw_scale), y in +-2 mm; jaw+ in x >= 0, jaw-
         mirrored -> 16*wedge_div^2 tris.
-    Vertices are emitted sorted by link.
+    Vertices are emitted sorted by link.  Each part is a closed surface with
+    outward-consistent winding: its face grids share (welded) vertices, so
+    every edge a->b of a triangle appears exactly as often as b->a.
     """
     parts = []  # (verts, tris, link)
 
@@ -133,6 +160,14 @@ def instrument_mesh(segments=32, rings=28, box_div=3, wedge_div=1,
             d = (i + 1) * segments + j
             tris.append((a, b, c))
             tris.append((a, c, d))
+    # end discs: a fan about a centre vertex at each end, wound so that each
+    # rim edge runs opposite to the side triangle sharing it
+    lo, hi = len(verts), len(verts) + 1
+    top = (nz - 1) * segments
+    for j in range(segments):
+        tris.append((lo, (j + 1) % segments, j))
+        tris.append((hi, top + j, top + (j + 1) % segments))
+    verts = np.concatenate([verts, [[0.0, 0.0, z0], [0.0, 0.0, z1]]])
     parts.append((verts, np.array(tris, dtype=np.int64), LINK_SHAFT))
 
     # wrist box
@@ -152,7 +187,7 @@ def instrument_mesh(segments=32, rings=28, box_div=3, wedge_div=1,
         v, t = _quad_grid(p0, du, dv, k, k)
         bt.append(t + sum(len(x) for x in bv))
         bv.append(v)
-    parts.append((np.concatenate(bv), np.concatenate(bt), LINK_WRIST))
+    parts.append((*_weld(np.concatenate(bv), np.concatenate(bt)), LINK_WRIST))
 
     # jaws
     w = 0.0025 * jaw_scale
@@ -169,16 +204,16 @@ def instrument_mesh(segments=32, rings=28, box_div=3, wedge_div=1,
         def add(v, t):
             wt.append(t + sum(len(x) for x in wv))
             wv.append(v)
-        # two caps at y = -hy, +hy
-        for y in (-hy, hy):
-            add(*_tri_subdiv(xyz(A, y), xyz(B, y), xyz(C, y), m))
+        # two caps at y = -hy, +hy, wound opposite ways (each against the sides it meets)
+        add(*_tri_subdiv(xyz(A, -hy), xyz(C, -hy), xyz(B, -hy), m))
+        add(*_tri_subdiv(xyz(A, hy), xyz(B, hy), xyz(C, hy), m))
         # three rectangular sides
         for P, Q in ((A, B), (B, C), (C, A)):
             p0 = xyz(P, -hy)
             du = np.subtract(xyz(Q, -hy), p0)
             dv = (0.0, 2 * hy, 0.0)
             add(*_quad_grid(p0, du, dv, m, m))
-        parts.append((np.concatenate(wv), np.concatenate(wt), link))
+        parts.append((*_weld(np.concatenate(wv), np.concatenate(wt)), link))
 
     all_v, all_t, all_l = [], [], []
     off = 0
@@ -200,7 +235,7 @@ def mesh_for_triangles(n_tris: int, jaw_scale=1.0, box_scale=1.0) -> Mesh:
         s, k, m = 32, 3, 1
     else:
         s, k, m = 64, 6, 4
-    rest = n_tris - 12 * k * k - 16 * m * m
+    rest = n_tris - 12 * k * k - 16 * m * m - 2 * s
     rings = max(0, int(round(rest / (2 * s))) - 1)
     return instrument_mesh(s, rings, k, m, jaw_scale, box_scale)
 

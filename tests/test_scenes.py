@@ -5,10 +5,13 @@ import scenes
 
 
 def test_mesh_triangle_counts():
+    # shaft sides 2 s (r + 1) and end discs 2 s, box 12 k^2, jaws 16 m^2
     m = scenes.instrument_mesh(32, 28, 3, 1)
-    assert m.n_triangles == 2 * 32 * 29 + 12 * 9 + 16 == 1980
+    assert m.n_triangles == 2 * 32 * 29 + 2 * 32 + 12 * 9 + 16 == 2044
     m2 = scenes.instrument_mesh(64, 150, 6, 4)
-    assert m2.n_triangles == 2 * 64 * 151 + 12 * 36 + 16 * 16
+    assert m2.n_triangles == 2 * 64 * 151 + 2 * 64 + 12 * 36 + 16 * 16 == 20144
+    # welded face grids: shaft rings + 2 disc centres, box surface grid, jaw prisms
+    assert m.n_vertices == 32 * 30 + 2 + (6 * 3 * 3 + 2) + 2 * 6
     for mesh in (m, m2, scenes.mesh_for_triangles(35000, 1.3, 1.2), scenes.mesh_for_triangles(3000)):
         assert mesh.triangles.min() >= 0 and mesh.triangles.max() < mesh.n_vertices
         assert np.all(np.diff(mesh.vertex_link.astype(int)) >= 0)       # sorted by link
