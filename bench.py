@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Throughput of the batched CMA-ES silhouette-fitness path on one MI355X.
 
-Workload (single-instrument tracking, 640x480): 20016-triangle procedural
-instrument, lambda = 256 candidates of 9 parameters, loss = 1 - IoU + 0.1 x
+Workload (single-instrument tracking, 640x480): 20144-triangle procedural
+closed instrument, lambda = 256 candidates of 9 parameters, loss = 1 - IoU + 0.1 x
 keypoint reprojection term, 30 CMA-ES generations per frame over a seeded
 100-frame trajectory with 1% pixel-flip noise in the targets and 2-degree
 noise on the joint readings.  A step is one generation: sample -> FK ->
@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 RASTER_TRAFFIC = {"bytes_per_launch": 44879892.7,
                   # SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x 4 waves per SIMD, same sources
                   "valu_busy": 0.972,
+                  # LDS bytes and instructions per launch (SQ LDS counters), same sources
+                  "lds_bytes": None, "lds_insts": None,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
@@ -185,18 +187,13 @@ def main():
     torch.cuda.synchronize()
     drain()
     log(f"warm-up done ({args.warmup} generations)")
-    # the raster kernel is timed on every EVENT_EVERY-th generation of the timed
-    # region (events on the launch stream around its launch)
-    EVENT_EVERY = 8
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(0, args.steps, EVENT_EVERY)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     state["log"] = True
     w0 = time.perf_counter()
     t_start.record()
     for i in range(args.steps):
-        run_step(args.warmup + i, evs[i // EVENT_EVERY] if i % EVENT_EVERY == 0 else None)
+        run_step(args.warmup + i)
         if (i + 1) % 500 == 0:
             log(f"timed generations queued: {i + 1}/{args.steps}")
     t_end.record()
@@ -204,14 +201,20 @@ def main():
     wall = time.perf_counter() - w0
     gpu_ms = t_start.elapsed_time(t_end)
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
-    fused_ms = np.array([a.elapsed_time(b) for a, b in evs])
     if (args.warmup + args.steps) % G == 0:
         end_frame()                                   # the last timed frame is complete
     state["log"] = None
     drain()
     frames_log, state["logged"] = state["logged"], []
-    log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events; "
-        f"ask-eval avg {fused_ms.mean() * 1e3:.1f} us over {len(fused_ms)} sampled launches")
+    g0, g1 = args.warmup, args.warmup + args.steps - 1
+    frames_timed = sorted({(s // G) % F for s in range(g0, g1 + 1)})
+    timed_region = {"generations": [g0, g1], "frames_touched": len(frames_timed),
+                    "first_frame": (g0 // G) % F, "frame_starts_timed": sum(1 for s in range(g0, g1 + 1) if s % G == 0),
+                    "note": f"generations {g0}..{g1} of the {G}-generation-per-frame loop over {F} frames "
+                            f"(frame index wraps); the per-frame filter step, CMA-ES restart and result copy "
+                            f"run inside the timed region at every frame start it contains"}
+    log(f"timed: {args.steps} generations in {wall:.3f} s wall / {gpu_ms:.1f} ms GPU events "
+        f"({timed_region['frame_starts_timed']} frame starts inside)")
 
     # pose errors of the frames completed in the timed region (raw CMA-ES
     # estimates and temporally filtered ones) against the trajectory
@@ -261,7 +264,36 @@ def main():
     log(f"per generation (events around each): median {generation_us['median']:.1f} us, "
         f"p10 {generation_us['p10']:.1f}, p90 {generation_us['p90']:.1f}")
 
-    # ---------------------------------------------------------------- work per fused launch
+    # ---------------------------------------------------------------- roofline of the ask-eval raster kernel
+    # (a) KT back-to-back launches of the benchmarked ask-eval kernel on the
+    # state of one generation (the launch is idempotent: it re-draws the same
+    # candidates), one event pair on the launch stream around all of them;
+    # (b) events around each of KS single launches, each followed by the tell
+    # of its generation as in the loop (median)
+    KT, KS = 200, 100
+    state["frame"] = -1
+    for s in range(3):
+        run_step(s)
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(10):
+        ask_eval()
+    ka.record()
+    for _ in range(KT):
+        ask_eval()
+    kb.record()
+    torch.cuda.synchronize()
+    kernel_us = ka.elapsed_time(kb) * 1e3 / KT
+    single = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(KS)]
+    for i, (ea, eb) in enumerate(single):
+        run_step(3 + i, events=(ea, eb))
+    torch.cuda.synchronize()
+    drain()
+    single_us = np.array([ea.elapsed_time(eb) * 1e3 for ea, eb in single])
+    log(f"ask-eval kernel: {kernel_us:.1f} us per launch over {KT} back-to-back launches; "
+        f"{np.median(single_us):.1f} us median of {KS} single event-bracketed launches")
+
+    # work per launch from tk_raster_stats on the same inputs (the triangles the
+    # kernel draws: one orientation of a closed mesh, culling applied)
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     acc = np.zeros(4)
     n_st = 0
@@ -274,13 +306,19 @@ def main():
     kept, box_px, pairs, huge = acc / n_st
     tri_all = lam * mesh.n_triangles
     vert_all = lam * mesh.n_vertices
-    # algorithmic integer/FP32 lane operations of one launch (see the roofline notes in the design doc):
-    # 22 per vertex transform + snap, 10 per triangle cull test, 40 per kept triangle set-up,
-    # 5 per pixel centre tested inside a kept triangle's box (3 edge functions, combine, test)
-    ops = 22.0 * vert_all + 10.0 * tri_all + 40.0 * kept + 5.0 * box_px
+    # per-unit costs of the method's own units (survey of the path): 25 FP32
+    # operations per vertex transform and projection, 40 integer operations per
+    # triangle set-up, 3 edge functions x 8 operations per pixel centre tested
+    # inside a drawn triangle's clamped box
+    ops = 25.0 * vert_all + 40.0 * tri_all + 24.0 * box_px
+    # the finer count of the design doc: 22 per vertex, 10 per triangle cull test,
+    # 40 per kept triangle set-up, 5 per tested pixel centre
+    ops_fine = 22.0 * vert_all + 10.0 * tri_all + 40.0 * kept + 5.0 * box_px
     peak_ops = 256 * 64 * 2.4e9
-    achieved = ops / (fused_ms.mean() * 1e-3)
-    log(f"per launch: kept {kept:.0f} tris, {box_px:.0f} box pixels, {pairs:.0f} block pairs, {huge:.0f} wide")
+    achieved = ops / (kernel_us * 1e-6)
+    log(f"per launch: kept {kept:.0f} tris, {box_px:.0f} box pixels, {pairs:.0f} block pairs, {huge:.0f} wide; "
+        f"{ops:.3e} ops -> {achieved / 1e12:.2f} T ops/s ({achieved / peak_ops:.3f} of the ALU peak)")
+    peaks = measure_peaks(dev)
 
     out = {
         "metric": "candidate pose evals/sec (FK+raster+loss) at 640x480; ms per CMA-ES generation",
@@ -295,21 +333,33 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "track640: single-instrument tracking, procedural 20016-triangle instrument, "
-                               "640x480, lambda=256, 9-D, loss 1-IoU + 0.1 keypoints, 30 gens/frame, 100 frames",
+        "config": {"workload": f"track640: single-instrument tracking, procedural {mesh.n_triangles}-triangle "
+                               "closed instrument, 640x480, lambda=256, 9-D, loss 1-IoU + 0.1 keypoints, "
+                               "30 gens/frame, 100-frame trajectory",
                    "triangles": mesh.n_triangles, "width": cam.width, "height": cam.height, "lambda": lam,
-                   "dims": 9, "gens_per_frame": G, "frames": F},
+                   "dims": 9, "gens_per_frame": G, "frames": F, "timed_region": timed_region},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
                      "frac": achieved / peak_ops, "traffic": raster_traffic(),
                      "traffic_unit": "B per launch",
                      "valu_busy": RASTER_TRAFFIC["valu_busy"] if raster_profile_valid() else None,
+                     "lds": raster_lds(kernel_us, peaks),
+                     "constants_from_profiles": "traffic, valu_busy and lds counts are taken from the committed "
+                                                "rocprofv3 counter runs (profiles/) and reported only while the "
+                                                "kernel sources match the hash recorded there; null otherwise",
                      "kernel": "raster_kernel<true,false,true,1024> (tk_cmaes_ask_eval: draw, FK, raster, "
                                "counts; with workspace)",
-                     "kernel_us": float(fused_ms.mean() * 1e3),
-                     "ops_per_launch": ops, "units_per_launch": {"vertices": vert_all, "triangles": tri_all,
-                                                                 "kept": kept,
-                                                                 "box_pixels": box_px, "block_pairs": pairs}},
-        "fitness_evals_per_s": lam / (fused_ms.mean() * 1e-3),
+                     "kernel_us": kernel_us,
+                     "kernel_us_timing": f"mean of {KT} back-to-back launches (one event pair on the launch "
+                                         f"stream); median of {KS} single event-bracketed launches: "
+                                         f"{float(np.median(single_us)):.2f} us",
+                     "ops_per_launch": ops,
+                     "ops_formula": "25 per vertex + 40 per triangle + 24 per box pixel of a drawn triangle",
+                     "ops_fine_per_launch": ops_fine,
+                     "frac_fine": ops_fine / (kernel_us * 1e-6) / peak_ops,
+                     "units_per_launch": {"vertices": vert_all, "triangles": tri_all, "kept": kept,
+                                          "box_pixels": box_px, "block_pairs": pairs},
+                     "peaks_measured": peaks},
+        "fitness_evals_per_s": lam / (kernel_us * 1e-6),
         "generation_us": generation_us,
         "tracking": tracking,
     }
@@ -355,8 +405,61 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def measure_peaks(dev):
+    """Measured bandwidth roofs on this device: HBM by a streaming copy of
+    1 GiB (read + write bytes over the best of 5 runs), LDS by the loop of
+    conflict-free 128-bit reads and writes (2048 workgroups)."""
+    import torch
+
+    from paper_2603_11404_amd import tk
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tk.bench_copy(src, dst, nbytes)
+    best = 1e9
+    for _ in range(5):
+        a.record()
+        tk.bench_copy(src, dst, nbytes)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    hbm = 2.0 * nbytes / (best * 1e-3)
+    assert torch.equal(src, dst)
+    del src, dst
+    wgs, iters = 2048, 2048
+    out = torch.zeros(wgs, dtype=torch.int32, device=dev)
+    tk.bench_lds(wgs, 16, out)
+    best = 1e9
+    for _ in range(5):
+        a.record()
+        tk.bench_lds(wgs, iters, out)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    lds = wgs * iters * 256 * 128.0 / (best * 1e-3)
+    log(f"measured peaks: HBM copy {hbm / 1e9:.0f} GB/s, LDS {lds / 1e12:.1f} TB/s")
+    return {"hbm_GBps": hbm / 1e9, "hbm_spec_GBps": 8000.0, "lds_TBps": lds / 1e12,
+            "lds_spec_TBps": 256 * 128 * 2.4e9 / 1e12,
+            "method": "HBM: tk_bench_copy of 1 GiB (2 x bytes / time, best of 5); LDS: tk_bench_lds, "
+                      "2048 workgroups x 2048 iterations of 4 + 4 conflict-free 128-bit accesses per thread"}
+
+
+def raster_lds(kernel_us, peaks):
+    """LDS side of the raster kernel's roofline from the committed counter run
+    (LDS instructions per launch, with the bytes each moves), against the
+    measured LDS roof; None while the kernel sources differ from the profiled ones."""
+    if not raster_profile_valid() or RASTER_TRAFFIC.get("lds_bytes") is None:
+        return None
+    bps = RASTER_TRAFFIC["lds_bytes"] / (kernel_us * 1e-6)
+    return {"bytes_per_launch": RASTER_TRAFFIC["lds_bytes"], "achieved_TBps": bps / 1e12,
+            "peak_TBps": peaks["lds_TBps"], "frac": bps / (peaks["lds_TBps"] * 1e12),
+            "lds_instructions_per_launch": RASTER_TRAFFIC.get("lds_insts")}
+
+
 def small_leg(dev, with_cpu=True, solves=20):
-    """The small plain-method configuration: one 1980-triangle instrument,
+    """The small plain-method configuration: one 2044-triangle instrument,
     320x240, lambda = 16, 20-generation solves from a perturbed start, loss
     1 - IoU against the render with 1% pixel flips.  GPU: the two launches of
     each generation bracketed by events, over `solves` solves after two
@@ -396,7 +499,7 @@ def small_leg(dev, with_cpu=True, solves=20):
             est = mean0 + scenes.DEFAULT_SCALE * tk.cmaes_view(gen.state, 9, lam)["mean"]   # physical mean
             err_mm.append(float(np.linalg.norm(est[3:6] - truth[3:6]) * 1e3))
     t = np.array(times)
-    out = {"workload": "small: one 1980-triangle instrument, 320x240, lambda=16, 9-D, 20-generation solves, "
+    out = {"workload": f"small: one {mesh.n_triangles}-triangle instrument, 320x240, lambda=16, 9-D, 20-generation solves, "
                        "loss 1-IoU, 1% pixel flips",
            "gpu_us_per_generation": {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)),
                                      "p90": float(np.percentile(t, 90)), "generations": len(t)},
@@ -405,6 +508,8 @@ def small_leg(dev, with_cpu=True, solves=20):
     log(f"small320: {np.median(t):.1f} us per generation (p10 {np.percentile(t, 10):.1f}, "
         f"p90 {np.percentile(t, 90):.1f}) over {len(t)} generations")
     if with_cpu:
+        from threadpoolctl import threadpool_limits
+        _blas = threadpool_limits(1, "blas")    # the oracle's 9 x 9 numpy steps: no BLAS threads beside OpenMP
         target = oracle.render(truth, [chain], [mesh], cam) ^ flips
         m_cnt = oracle.counts(target, target, cam.width, cam.height)[2]
         cpu = {}
@@ -417,6 +522,7 @@ def small_leg(dev, with_cpu=True, solves=20):
                 es.update(np.array([oracle.mask_loss(cnt[k, 0], cnt[k, 1], m_cnt, 0) for k in range(lam)]))
             el = time.perf_counter() - t0
             cpu[label] = {"threads": threads, "ms_per_generation": el * 1e3 / G, "evals_per_s": G * lam / el}
+        _blas.restore_original_limits()
         cpu["sample"] = f"one whole {G}-generation solve of the oracle per thread count"
         cpu["cpu"] = _cpu_model()
         out["cpu_oracle"] = cpu
@@ -426,7 +532,7 @@ def small_leg(dev, with_cpu=True, solves=20):
 
 
 def bimanual_leg(dev, gens=100):
-    """Bi-manual workload: two uneven instruments (20016 + 35188 triangles),
+    """Bi-manual workload: two uneven instruments (20144 + 35388 triangles),
     960x540, lambda = 512, 18-D with a block-diagonal covariance, target with
     an occluding rectangle; generations of two launches (both arms in each),
     timed eagerly and as a replayed HIP graph."""
@@ -469,7 +575,8 @@ def bimanual_leg(dev, gens=100):
     graph_ms = a.elapsed_time(b) / gens
     best = min(eager_ms, graph_ms)
     log(f"bimanual960: {eager_ms * 1e3:.1f} us per generation eager, {graph_ms * 1e3:.1f} us graph replay")
-    return {"workload": "two instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D block-diagonal, occluder",
+    tris = " + ".join(str(m.n_triangles) for m in wl["meshes"])
+    return {"workload": f"two instruments ({tris} tris), 960x540, lambda=512, 18-D block-diagonal, occluder",
             "ms_per_generation": eager_ms, "graph_ms_per_generation": graph_ms,
             "candidate_evals_per_s": lam / (best * 1e-3), "generations": gens}
 
@@ -597,7 +704,7 @@ def synth700_leg(dev):
 def soft_leg(dev, reps=10):
     """Differentiable form: soft silhouette forward + backward (FK, projection,
     binning, soft raster, loss; face-major backward, FK Jacobian) of 256
-    candidates of a 49544-triangle instrument at 640x480, sigma = 1 px; and
+    candidates of a 49744-triangle instrument at 640x480, sigma = 1 px; and
     the refinement of one problem's CMA-ES mean by 5 Adam steps per generation."""
     import torch
 
@@ -672,6 +779,8 @@ def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):
     from oracle import cmaes
     import scenes
 
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1, "blas")              # the oracle's 9 x 9 numpy steps: no BLAS threads beside OpenMP
     log("cpu baseline: oracle on the host cores")
     target = oracle.render(traj[0], [chain], [mesh], cam) ^ flips[0]
     ref_kp = oracle.keypoints(oracle.fk(traj[0], chain), chain, cam)

@@ -343,6 +343,17 @@ tk_status tk_cmaes_ask_eval_noalloc(void* d_state, int32_t n, int32_t lambda, co
 tk_status tk_raster_stats(const float* d_link_xf, int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
                           const tk_camera* cam, uint64_t* d_stats, tk_stream s);
 
+/* Bandwidth microbenchmarks for the roofline denominators (measurement only,
+ * not on the fitness path).  tk_bench_copy: a streaming copy of bytes (a
+ * multiple of 16; 16-byte aligned device pointers) from d_src to d_dst --
+ * 2 * bytes of HBM traffic.  tk_bench_lds: `workgroups` workgroups of 256
+ * threads, each with 64 KB of LDS, run `iters` iterations of 4 conflict-free
+ * 128-bit LDS reads and 4 writes per thread (iters * 256 * 128 bytes per
+ * workgroup) and XOR their data into d_out[workgroup] (device uint32
+ * [workgroups], caller-cleared).  Errors: TK_ERR_INVALID_ARGUMENT. */
+tk_status tk_bench_copy(const void* d_src, void* d_dst, size_t bytes, tk_stream s);
+tk_status tk_bench_lds(int32_t workgroups, int32_t iters, uint32_t* d_out, tk_stream s);
+
 /* Loss composition in FP64 (Eq. objective and render_loss; Sec. IV):
  *   kind 0: 1 - IoU = 1 - i/(a + m - i)  (0 when the union is empty);
  *   kind 1: (a + m - 2i) + lambda_app*|a - m|  (sum of squared mask errors

@@ -83,7 +83,8 @@ EXPORTS = [
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
-    "tk_cmaes_adam", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order",
+    "tk_cmaes_adam", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order", "tk_bench_copy",
+    "tk_bench_lds",
 ]
 
 _lib = None
@@ -145,6 +146,8 @@ def lib():
         L.tk_cmaes_adam.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, P]
         L.tk_mesh_chunk_order.argtypes = [P, i32, P, i32, P]
         L.tk_mesh_closed.argtypes = [P, i32, i32, P]
+        L.tk_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
+        L.tk_bench_lds.argtypes = [i32, i32, P, P]
         L.tk_mesh_plane_order.argtypes = [P, P, i32, P, i32, P]
         for name in EXPORTS:
             if name not in ("tk_status_string", "tk_last_error", "tk_version", "tk_cmaes_state_bytes",
@@ -355,6 +358,16 @@ def cmaes_ask_eval(state, n, lam, chains, meshes, cam, target, X, link_xf, count
 
 
 NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024   # TK_NOALLOC_SCRATCH_BYTES
+
+
+def bench_copy(src, dst, nbytes, stream=None):
+    """tk_bench_copy: streaming copy of nbytes from src to dst (device tensors)."""
+    _check(lib().tk_bench_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
+
+
+def bench_lds(workgroups, iters, out, stream=None):
+    """tk_bench_lds: LDS read/write loop; out: device int32 [workgroups], cleared by the caller."""
+    _check(lib().tk_bench_lds(int(workgroups), int(iters), _ptr(out), _stream(stream)))
 
 
 def cmaes_ask_eval_noalloc(state, n, lam, chains, meshes, cam, target, X, link_xf, counts, kp=None, stream=None):

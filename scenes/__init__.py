@@ -505,7 +505,7 @@ def workload(name: str) -> dict:
     if name == "track640":       # 20k tris, 640x480, lambda=256, 30 gens x 100 frames
         return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(640, 480),
                     lam=256, gens=30, frames=100, index=1, filter=FILTER_TRACK)
-    if name == "bimanual960":    # two uneven instruments (20016 + 35188 tris), 960x540, lambda=512, 18-D
+    if name == "bimanual960":    # two uneven instruments (20144 + 35388 tris), 960x540, lambda=512, 18-D
         meshes = [instrument_mesh(64, 150, 6, 4), instrument_mesh(100, 170, 7, 5, jaw_scale=1.3, box_scale=1.2)]
         return dict(meshes=meshes, mesh=meshes[0], chains=[chain(), chain(jaw_scale=1.3)], cam=camera(960, 540),
                     lam=512, gens=30, frames=1, index=2, n_blocks=2)
@@ -514,7 +514,7 @@ def workload(name: str) -> dict:
         # Hermite/OU trajectory, dilation / erosion / edge-blob masks, two-tip keypoint term
         return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(700, 493), lam=70, gens=3, frames=200,
                     index=5, filter=FILTER_TRACK, sigma0=0.5, c_m_scale=1.0, c_mu_scale=2.0)
-    if name == "soft640":        # differentiable form: 49544 tris, 640x480, 256 candidates, sigma = 1 px
+    if name == "soft640":        # differentiable form: 49744 tris, 640x480, 256 candidates, sigma = 1 px
         return dict(mesh=instrument_mesh(100, 240, 8, 6), cam=camera(640, 480), lam=256, gens=30, frames=1,
                     index=4, sigma=1.0)
     raise KeyError(name)

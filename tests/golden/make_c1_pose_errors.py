@@ -1,5 +1,5 @@
 """Writes c1_pose_errors.json: final pose errors of 20-generation oracle
-solves of the small workload (one 1980-triangle instrument, 320x240, f = 400,
+solves of the small workload (one 2044-triangle instrument, 320x240, f = 400,
 lambda = 16, loss 1 - IoU against the render of a seeded true pose with 1 %
 of the pixels flipped), one solve per seed.  Calls only oracle/ (FP64 forward
 kinematics and projection, integer rasteriser, FP64 CMA-ES of Sec. III-A.1);
@@ -93,7 +93,7 @@ def main():
     rows = run(n)
     tr = np.array([r["trans_mm"] for r in rows])
     ro = np.array([r["rot_deg"] for r in rows])
-    doc = {"workload": "small: 1980-triangle instrument, 320x240, f=400, lambda=16, 20 generations, loss 1-IoU, "
+    doc = {"workload": "small: 2044-triangle instrument, 320x240, f=400, lambda=16, 20 generations, loss 1-IoU, "
                        "768 pixel flips",
            "generator": "tests/golden/make_c1_pose_errors.py (oracle only)",
            "solves": rows,

@@ -1,5 +1,5 @@
 """Bi-manual workload at full size (Sec. III-B): two uneven instruments
-(20016 and 35188 triangles), 960x540, lambda = 512, 18-D with a
+(20144 and 35388 triangles), 960x540, lambda = 512, 18-D with a
 block-diagonal covariance, both arms in one launch, target with an occluding
 rectangle over 10-30 % of the tools.
 
