@@ -504,7 +504,9 @@ typedef struct {
     int32_t threads;
 } tk_problem;
 
-/* Bytes of the device table of n_problems (0 if n_problems is outside 1..65536). */
+/* Bytes of the device table of n_problems (0 if n_problems is outside
+ * 1..65536): problem descriptors and the control words of the persistent
+ * launch. */
 size_t tk_batch_table_bytes(int32_t n_problems);
 
 /* Validates the problems and writes their device descriptors into the HOST
@@ -518,6 +520,22 @@ tk_status tk_batch_describe(const tk_problem* problems, int32_t n_problems, void
  * problems: the host array given to tk_batch_describe; d_table: its device
  * copy. */
 tk_status tk_batch_ask_eval(const tk_problem* problems, int32_t n_problems, const void* d_table, tk_stream s);
+
+/* tk_cmaes_ask_eval for every problem, with identical results, in one
+ * persistent launch per 128 problems (NEXT batching form: candidates of all
+ * problems, of any image size and mesh, in one launch): a resident grid of
+ * 1024-thread workgroups, one per compute unit, claims (problem, candidate)
+ * items from a counter in d_table, the problems ordered costliest per
+ * candidate first (image pixels x sqrt(triangles)); each item lays out its
+ * LDS for its image (mask, then per-wave task rings: 128 narrow slots for 16
+ * rasterising waves where they fit, else 64 slots for as many waves as fit).
+ * The problems' threads field is not used.  d_table: the device copy of the
+ * tk_batch_describe table, NOT const: its control words (zero in the
+ * described table) count the claims and are reset to zero by the launch's
+ * last workgroup, so launches on one table must not overlap.  Errors as for
+ * tk_batch_ask_eval; TK_ERR_UNSUPPORTED when an image leaves no LDS for one
+ * wave's queues (above about 1700 x 1000 pixels). */
+tk_status tk_batch_ask_eval_persistent(const tk_problem* problems, int32_t n_problems, void* d_table, tk_stream s);
 
 /* tk_cmaes_tell for every problem, with identical results: one workgroup per
  * problem, one launch per 128 problems (per covariance size class). */

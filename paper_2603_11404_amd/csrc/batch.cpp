@@ -1,7 +1,9 @@
 // Batched independent problems: table layout and the C entry points.
 //
 // Table (written on the host by tk_batch_describe, used from device memory):
-//   [n raster entries][pad to 256 bytes][n update entries]
+//   [n raster entries][pad to 256 bytes][n update entries][pad to 256 bytes]
+//   [control: one int32 pair per persistent launch of up to 128 problems,
+//    zero between launches]
 #include <cstring>
 
 #include "tk_internal.h"
@@ -12,6 +14,10 @@ namespace {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 size_t update_offset(int32_t n) { return align256(size_t(n) * batch_raster_entry_bytes()); }
+
+size_t control_offset(int32_t n) { return align256(update_offset(n) + size_t(n) * batch_update_entry_bytes()); }
+
+size_t control_bytes(int32_t n) { return align256(size_t(8) * ((n + kMaxBatch - 1) / kMaxBatch)); }
 
 tk_status check_batch(const tk_problem* problems, int32_t n_problems, const void* table) {
     TK_REQUIRE(problems != nullptr, "problems is NULL");
@@ -30,7 +36,7 @@ extern "C" {
 
 size_t tk_batch_table_bytes(int32_t n_problems) {
     if (n_problems < 1 || n_problems > 65536) return 0;
-    return update_offset(n_problems) + size_t(n_problems) * batch_update_entry_bytes();
+    return control_offset(n_problems) + control_bytes(n_problems);
 }
 
 tk_status tk_batch_describe(const tk_problem* problems, int32_t n_problems, void* h_table, size_t table_bytes) {
@@ -59,6 +65,13 @@ tk_status tk_batch_ask_eval(const tk_problem* problems, int32_t n_problems, cons
     clear_error();
     if (tk_status st = check_batch(problems, n_problems, d_table)) return st;
     return batch_launch_raster(problems, n_problems, d_table, reinterpret_cast<hipStream_t>(s));
+}
+
+tk_status tk_batch_ask_eval_persistent(const tk_problem* problems, int32_t n_problems, void* d_table, tk_stream s) {
+    clear_error();
+    if (tk_status st = check_batch(problems, n_problems, d_table)) return st;
+    int32_t* counters = reinterpret_cast<int32_t*>(static_cast<char*>(d_table) + control_offset(n_problems));
+    return batch_launch_persistent(problems, n_problems, d_table, counters, reinterpret_cast<hipStream_t>(s));
 }
 
 tk_status tk_batch_tell(const tk_problem* problems, int32_t n_problems, const void* d_table, tk_stream s) {

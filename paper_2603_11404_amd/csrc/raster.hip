@@ -21,8 +21,10 @@
 //   3. after a barrier the mask is written out and/or reduced against the
 //      target with popcounts.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "fitness_device.h"
 #include "sample_device.h"
@@ -180,8 +182,9 @@ __device__ __forceinline__ int32_t rec_dy(int32_t v) { return v >> 16; }
 // are pending, so rounds run with every lane busy whatever the mix of the
 // chunk.  The queues are rings indexed by running slot counts; start[] holds
 // each queued triangle's first task number (a running count of the wave's
-// tasks of that class).  The narrow ring never holds more than 63 pending plus
-// 64 new triangles; the wide ring is drained before it would overflow.
+// tasks of that class).  A ring is drained (its pending tasks, fewer than 64,
+// run as a partial round) before new triangles would overflow it; with 128
+// narrow slots that never happens (at most 63 pending plus 64 new).
 constexpr int kNarrowRing = 128;
 constexpr int kWideRing = 64;
 struct WaveQueues {
@@ -191,7 +194,33 @@ struct WaveQueues {
     int32_t wstart[kWideRing];
     int32_t mark[64];      // per round: where each queued triangle's tasks start
 };
-static_assert(sizeof(WaveQueues) >= 3328, "the ask prologue borrows wave 0's queues as 3.2 KB of scratch");
+
+// Bytes of one wave's queues with a narrow ring of nr slots (the layout of
+// WaveQueues with kNarrowRing = nr).
+__host__ __device__ constexpr int queue_bytes(int nr) { return nr * 36 + kWideRing * 36 + 64 * 4; }
+static_assert(queue_bytes(kNarrowRing) == sizeof(WaveQueues), "queue layout");
+static_assert(queue_bytes(64) >= 3328, "the ask prologue borrows wave 0's queues as 3.2 KB of scratch");
+
+// One wave's queues inside a block of LDS laid out as WaveQueues with a
+// narrow ring of nmask + 1 slots.
+struct QueueView {
+    int4 *na, *nb, *wa, *wb;
+    int32_t *nstart, *wstart, *mark;
+    int nmask;   // narrow ring slots - 1
+};
+
+__device__ __forceinline__ QueueView queue_view(char* base, int nr) {
+    QueueView q;
+    q.na = reinterpret_cast<int4*>(base);
+    q.nb = q.na + nr;
+    q.nstart = reinterpret_cast<int32_t*>(q.nb + nr);
+    q.wa = reinterpret_cast<int4*>(q.nstart + nr);
+    q.wb = q.wa + kWideRing;
+    q.wstart = reinterpret_cast<int32_t*>(q.wb + kWideRing);
+    q.mark = q.wstart + kWideRing;
+    q.nmask = nr - 1;
+    return q;
+}
 
 // Lane tasks of a near triangle: 8-column windows times 4-row bands, both
 // starting at the box's top-left pixel.
@@ -424,23 +453,23 @@ __device__ __forceinline__ unsigned long long valid_bits(int wx, int wy, const C
 // maximum over the lanes then gives each lane the last triangle starting at or
 // before its task.  Returns the running slot of the triangle that holds task
 // done + 64 (the new tail after a full round).
-template <int RING, bool NARROW>
+template <bool NARROW>
 __device__ __forceinline__ int run_round(const int4* __restrict__ qa, const int4* __restrict__ qb,
-                                         const int32_t* __restrict__ qstart, int32_t* __restrict__ mark, int tail,
-                                         int head, int done, int count, int lane,
+                                         const int32_t* __restrict__ qstart, int32_t* __restrict__ mark, int ring_mask,
+                                         int tail, int head, int done, int count, int lane,
                                          unsigned long long* __restrict__ s_mask, int words_x) {
     const int q = done + lane;
     int next = tail;
     mark[lane] = -1;
     wave_sync();
     if (lane < head - tail) {
-        const int rel = qstart[(tail + lane) & (RING - 1)] - done;
+        const int rel = qstart[(tail + lane) & ring_mask] - done;
         if (rel < kWave) mark[max(rel, 0)] = lane;
     }
     wave_sync();
     const int lo = wave_inclusive_max(mark[lane]);   // slot tail + lo starts at or before task q
     if (lane < count) {
-        const int slot = (tail + lo) & (RING - 1);
+        const int slot = (tail + lo) & ring_mask;
         const int k = q - qstart[slot];
         const int4 a = qa[slot], b = qb[slot];
         int ntask;
@@ -699,22 +728,32 @@ __device__ __forceinline__ void chunk_snapped(const ChunkVerts<FS>& g, const flo
     }
 }
 
-// One workgroup rasterises candidate b of the problem described by a.
-template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
-__device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
+// Where a workgroup's per-wave task queues live: `active` blocks of
+// queue_bytes(NR) bytes from base, one per rasterising wave (waves past them
+// help with the per-candidate phases only).
+struct QueueLayout {
+    char* base;
+    int active;   // rasterising waves, 1 .. NT / 64
+};
+
+// One workgroup rasterises candidate b of the problem described by a into the
+// image mask s_mask (LDS); NR narrow ring slots per wave (128, or 64 with
+// drains before overflow).
+template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT, int NR = kNarrowRing>
+__device__ __forceinline__ void raster_body(const RasterArgs& a, const int b, unsigned long long* __restrict__ s_mask,
+                                            const QueueLayout ql, const int tid) {
     constexpr int NW = NT / kWave;
-    extern __shared__ unsigned long long s_mask[];
-    __shared__ WaveQueues s_queue[NW];
     __shared__ float s_M[kMaxArms * 48];
     __shared__ int32_t s_red[2][NW];
     // [0] next chunk to claim; [1] bit m: a vertex of mesh m failed the near plane
     __shared__ int32_t s_ctl[2];
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
     const int lx = lane & 7, ly = lane >> 3;
     const CamK& cam = a.cam;
     const int words = cam.words_x * cam.words_y;
-    WaveQueues& Q = s_queue[wave];
+    const int NA = ql.active;
+    const QueueView Q = queue_view(ql.base + wave * queue_bytes(NR), NR);   // used by waves < NA only
 
     const int TV = a.meshes.total_vertices;
     const MeshK& m0 = a.meshes.m[0];
@@ -724,21 +763,21 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     // triangles in chunks of 64 (one per lane), numbered over the meshes
     const int C0 = (m0.n_triangles + kWave - 1) / kWave;
     const int C = two ? C0 + (m1.n_triangles + kWave - 1) / kWave : C0;
-    // wave w starts with chunks w and 2 NW - 1 - w (the first chunk of one
-    // wave pairs with the last of the first 2 NW, so that, when a mesh lists
+    // wave w starts with chunks w and 2 NA - 1 - w (the first chunk of one
+    // wave pairs with the last of the first 2 NA, so that, when a mesh lists
     // its costly chunks first, the costliest pairs with the cheapest); it
     // claims each later chunk from an LDS counter two chunks ahead of the one
     // it rasterises (indices two ahead, vertex gathers one ahead), so all
     // waves finish within about one chunk of each other
-    int c_cur = wave, c_nxt = 2 * NW - 1 - wave;
+    int c_cur = wave < NA ? wave : C, c_nxt = wave < NA ? 2 * NA - 1 - wave : C;
     if (tid == 0) {
-        s_ctl[0] = 2 * NW;
+        s_ctl[0] = 2 * NA;
         s_ctl[1] = 0;
     }
 
     for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
     if (a.ask) {
-        if (wave == 0) ask_candidate(a, b, lane, s_M, reinterpret_cast<char*>(&s_queue[0]));   // queue not in use yet
+        if (wave == 0) ask_candidate(a, b, lane, s_M, ql.base);   // wave 0's queues are not in use yet
     } else if (!FROM_SNAPPED || a.pretransform) {
         for (int i = tid; i < a.meshes.n_meshes * 48; i += NT)
             s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
@@ -811,7 +850,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
             bool valid = false;
             if (any) valid = keep && setup_triangle(X[0], Y[0], X[1], Y[1], X[2], Y[2], cam, rec);
             // claims exceed every chunk the wave holds (the counter starts at
-            // 2 NW); the max keeps each wave's chunk numbers increasing regardless
+            // 2 NA); the max keeps each wave's chunk numbers increasing regardless
             c_new = max(__builtin_amdgcn_readlane(claim, 0), c_nxt + 1);
             load_chunk_indices(m0, m1, C0, C, c_new, lane, idx_nxt);
             if (any) {
@@ -827,10 +866,16 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
                 const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
                 const unsigned long long nmask = __ballot(narrow), wmask = __ballot(wide);
                 const int n_new = __popcll(nmask), w_new = __popcll(wmask);
-                // the wide ring drains its pending tasks (fewer than 64) before it would overflow
+                // a ring drains its pending tasks (fewer than 64) before it would overflow
+                if (n_head - n_tail + n_new > Q.nmask + 1) {
+                    run_round<true>(Q.na, Q.nb, Q.nstart, Q.mark, Q.nmask, n_tail, n_head, n_done, n_queued - n_done,
+                                    lane, s_mask, cam.words_x);
+                    n_done = n_queued;
+                    n_tail = n_head;
+                }
                 if (w_head - w_tail + w_new > kWideRing) {
-                    run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane,
-                                                s_mask, cam.words_x);
+                    run_round<false>(Q.wa, Q.wb, Q.wstart, Q.mark, kWideRing - 1, w_tail, w_head, w_done,
+                                     w_queued - w_done, lane, s_mask, cam.words_x);
                     w_done = w_queued;
                     w_tail = w_head;
                 }
@@ -839,7 +884,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
                     const unsigned long long m = narrow ? nmask : wmask;
                     const int rank = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
                     if (narrow) {
-                        const int slot = (n_head + rank) & (kNarrowRing - 1);
+                        const int slot = (n_head + rank) & Q.nmask;
                         Q.na[slot] = r.a;
                         Q.nb[slot] = r.b;
                         Q.nstart[slot] = n_queued + (incl >> 16) - cnt_n;
@@ -856,13 +901,13 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
                 w_queued += total & 0xffff;
                 wave_sync();   // queued records written by other lanes are read below
                 while (n_queued - n_done >= kWave) {
-                    n_tail = run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, kWave, lane,
-                                                          s_mask, cam.words_x);
+                    n_tail = run_round<true>(Q.na, Q.nb, Q.nstart, Q.mark, Q.nmask, n_tail, n_head, n_done, kWave, lane,
+                                             s_mask, cam.words_x);
                     n_done += kWave;
                 }
                 while (w_queued - w_done >= kWave) {
-                    w_tail = run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, kWave, lane,
-                                                         s_mask, cam.words_x);
+                    w_tail = run_round<false>(Q.wa, Q.wb, Q.wstart, Q.mark, kWideRing - 1, w_tail, w_head, w_done, kWave,
+                                              lane, s_mask, cam.words_x);
                     w_done += kWave;
                 }
                 // triangles needing 64-bit edge functions or big boxes: the whole wave
@@ -893,11 +938,11 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
     }
     // the last partial rounds
     if (n_queued > n_done)
-        run_round<kNarrowRing, true>(Q.na, Q.nb, Q.nstart, Q.mark, n_tail, n_head, n_done, n_queued - n_done, lane, s_mask,
-                                     cam.words_x);
+        run_round<true>(Q.na, Q.nb, Q.nstart, Q.mark, Q.nmask, n_tail, n_head, n_done, n_queued - n_done, lane, s_mask,
+                        cam.words_x);
     if (w_queued > w_done)
-        run_round<kWideRing, false>(Q.wa, Q.wb, Q.wstart, Q.mark, w_tail, w_head, w_done, w_queued - w_done, lane, s_mask,
-                                    cam.words_x);
+        run_round<false>(Q.wa, Q.wb, Q.wstart, Q.mark, kWideRing - 1, w_tail, w_head, w_done, w_queued - w_done, lane,
+                         s_mask, cam.words_x);
     __syncthreads();
 
     int32_t cnt_s = 0, cnt_i = 0;
@@ -935,7 +980,10 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b) {
 
 template <bool FROM_SNAPPED, bool WRITE_MASK, bool COUNTS, int NT>
 __global__ __launch_bounds__(NT) void raster_kernel(RasterArgs a) {
-    raster_body<FROM_SNAPPED, WRITE_MASK, COUNTS, NT>(a, blockIdx.x);
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ WaveQueues s_queue[NT / kWave];
+    raster_body<FROM_SNAPPED, WRITE_MASK, COUNTS, NT>(
+        a, blockIdx.x, s_dyn, QueueLayout{reinterpret_cast<char*>(s_queue), NT / kWave}, threadIdx.x);
 }
 
 // Many problems in one launch: workgroups first[i] .. first[i + 1] - 1 draw
@@ -955,7 +1003,63 @@ __global__ __launch_bounds__(NT) void raster_batch_kernel(BatchLaunch L) {
     for (int step = kMaxBatch / 2; step > 0; step >>= 1)
         if (lo + step < L.count && L.first[lo + step] <= g) lo += step;
     const RasterArgs& a = L.table[L.prob[lo]];
-    raster_body<true, false, true, NT>(a, g - L.first[lo]);
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ WaveQueues s_queue[NT / kWave];
+    raster_body<true, false, true, NT>(a, g - L.first[lo], s_dyn,
+                                       QueueLayout{reinterpret_cast<char*>(s_queue), NT / kWave}, threadIdx.x);
+}
+
+// Persistent form: a grid of resident workgroups, each claiming (problem,
+// candidate) items from a device counter until all are taken.  Problem
+// prob[i] owns items first[i] .. first[i + 1] - 1, one per candidate; the host
+// lists the problems costliest per candidate first, so the last claims are
+// cheap (longest-first list scheduling over the whole batch).  Every item uses
+// the same 1024-thread workgroup with its own LDS layout: the image mask, then
+// NR narrow ring slots per wave for active[i] rasterising waves.  counter[0] is the next item and counter[1] the workgroups that have
+// finished; the last to finish resets both, so consecutive launches (and graph
+// replays) need no clearing.
+struct PersistLaunch {
+    const RasterArgs* table;
+    int32_t* counter;
+    int32_t count;
+    int32_t prob[kMaxBatch];
+    int32_t first[kMaxBatch + 1];
+    int32_t active[kMaxBatch];
+};
+
+template <int NT, int NR>
+__global__ __launch_bounds__(NT) void raster_persistent_kernel(PersistLaunch L) {
+    extern __shared__ unsigned long long s_dyn[];
+    __shared__ int32_t s_item;
+    const int total = L.first[L.count];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&L.counter[0], 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();   // every thread has read the claim before the next one overwrites it
+        if (item >= total) break;
+        int lo = 0;   // last i with first[i] <= item
+        for (int step = kMaxBatch / 2; step > 0; step >>= 1)
+            if (lo + step < L.count && L.first[lo + step] <= item) lo += step;
+        const RasterArgs& a = L.table[L.prob[lo]];
+        const size_t mask_bytes = (size_t(a.cam.words_x) * a.cam.words_y * 8 + 15) & ~size_t(15);
+        // the thread index passes through an empty asm statement each item, so
+        // that nothing derived from it is hoisted out of the loop and held in
+        // registers across the whole body
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        raster_body<true, false, true, NT, NR>(a, item - L.first[lo], s_dyn,
+                                               QueueLayout{reinterpret_cast<char*>(s_dyn) + mask_bytes, L.active[lo]},
+                                               tid);
+        __syncthreads();   // the item's last LDS reads are done before the next item clears the mask
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&L.counter[1], 1) == int(gridDim.x) - 1) {
+            L.counter[0] = 0;
+            L.counter[1] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- snapped vertices (debug / parity)
@@ -1301,7 +1405,95 @@ tk_status launch_raster_batch(const BatchLaunch& L, size_t lds, hipStream_t s) {
     return check_launch("tk_batch_ask_eval");
 }
 
+constexpr int kPersistThreads = 1024;
+// static LDS of the persistent kernel: transforms, count partials, control words, the claimed item
+constexpr size_t kPersistStatic = sizeof(float) * kMaxArms * 48 + sizeof(int32_t) * 2 * (kPersistThreads / kWave) +
+                                  sizeof(int64_t) + 16;
+constexpr size_t kPersistDynamic = kLdsLimit - kPersistStatic;
+
 }  // namespace
+
+// Rasterising waves of a problem's workgroup in the persistent kernel with nr
+// narrow ring slots per wave: as many as fit beside the image mask, at most 16.
+int persist_active(const CamK& cam, int nr) {
+    const size_t mask = (mask_lds_bytes(cam) + 15) & ~size_t(15);
+    if (mask >= kPersistDynamic) return 0;
+    return int(std::min<size_t>(kPersistThreads / kWave, (kPersistDynamic - mask) / queue_bytes(nr)));
+}
+
+template <int NR>
+tk_status launch_persistent(const PersistLaunch& L, int cus, hipStream_t s) {
+    auto kern = raster_persistent_kernel<kPersistThreads, NR>;
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    static size_t static_bytes = 0;
+    std::call_once(once, [&] {
+        hipFuncAttributes fa{};
+        err = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern));
+        static_bytes = fa.sharedSizeBytes;
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      int(kPersistDynamic));
+    });
+    if (err != hipSuccess)
+        return fail(TK_ERR_DEVICE, "tk_batch_ask_eval_persistent: kernel set-up: %s", hipGetErrorString(err));
+    if (static_bytes > kPersistStatic)
+        return fail(TK_ERR_DEVICE, "tk_batch_ask_eval_persistent: kernel has %zu bytes of static LDS, %zu assumed",
+                    static_bytes, kPersistStatic);
+    hipLaunchKernelGGL(kern, dim3(cus), dim3(kPersistThreads), kPersistDynamic, s, L);
+    return check_launch("tk_batch_ask_eval_persistent");
+}
+
+// All problems in one persistent launch per kMaxBatch problems, costliest
+// per candidate first (image pixels times the square root of the triangle
+// count as the estimate); 128 narrow ring slots when every image of the
+// launch leaves room for 16 such waves, else 64.  counters: device int32
+// pairs, one per launch.
+tk_status batch_launch_persistent(const tk_problem* problems, int32_t n, const void* d_entries, int32_t* d_counters,
+                                  hipStream_t s) {
+    static std::once_flag once;
+    static hipError_t dev_err = hipSuccess;
+    static int cus = 0;
+    std::call_once(once, [&] {
+        int dev = 0;
+        dev_err = hipGetDevice(&dev);
+        if (dev_err == hipSuccess) dev_err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    });
+    if (dev_err != hipSuccess || cus < 1)
+        return fail(TK_ERR_DEVICE, "tk_batch_ask_eval_persistent: device query: %s", hipGetErrorString(dev_err));
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; i++) {
+        const tk_problem& p = problems[i];
+        int64_t tris = 0;
+        for (int m = 0; m < p.n_arms; m++) tris += p.meshes[m].n_triangles;
+        cost[i] = double(p.cam.width) * p.cam.height * std::sqrt(double(tris) + 1000.0);
+        order[i] = i;
+        if (persist_active(make_cam(p.cam), 64) == 0)
+            return fail(TK_ERR_UNSUPPORTED, "tk_batch_ask_eval_persistent: problem %d: image %dx%d leaves no LDS for "
+                        "the task queues", i, p.cam.width, p.cam.height);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int base = 0, launch = 0; base < n; base += kMaxBatch, launch++) {
+        PersistLaunch L;
+        std::memset(&L, 0, sizeof L);
+        L.table = static_cast<const RasterArgs*>(d_entries);
+        L.counter = d_counters + 2 * launch;
+        L.count = std::min(kMaxBatch, n - base);
+        bool wide_rings = true;
+        for (int i = 0; i < L.count; i++)
+            wide_rings &= persist_active(make_cam(problems[order[base + i]].cam), kNarrowRing) == kPersistThreads / kWave;
+        for (int i = 0; i < L.count; i++) {
+            const tk_problem& p = problems[order[base + i]];
+            L.prob[i] = order[base + i];
+            L.first[i + 1] = L.first[i] + p.lambda;
+            L.active[i] = persist_active(make_cam(p.cam), wide_rings ? kNarrowRing : 64);
+        }
+        if (tk_status st = wide_rings ? launch_persistent<kNarrowRing>(L, cus, s) : launch_persistent<64>(L, cus, s))
+            return st;
+    }
+    return TK_OK;
+}
 
 // Problems grouped by workgroup size; one launch per group of at most kMaxBatch.
 tk_status batch_launch_raster(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s) {

@@ -170,6 +170,8 @@ size_t batch_update_entry_bytes();
 tk_status batch_describe_raster(const tk_problem& p, void* dst);
 tk_status batch_describe_update(const tk_problem& p, void* dst);
 tk_status batch_launch_raster(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s);
+tk_status batch_launch_persistent(const tk_problem* problems, int32_t n, const void* d_entries, int32_t* d_counters,
+                                  hipStream_t s);
 tk_status batch_launch_tell(const tk_problem* problems, int32_t n, const void* d_entries, hipStream_t s);
 
 tk_status validate_camera(const tk_camera* cam);

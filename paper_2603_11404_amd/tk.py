@@ -84,7 +84,7 @@ EXPORTS = [
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
     "tk_cmaes_adam", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order", "tk_bench_copy",
-    "tk_bench_lds",
+    "tk_bench_lds", "tk_batch_ask_eval_persistent",
 ]
 
 _lib = None
@@ -130,6 +130,7 @@ def lib():
         L.tk_batch_table_bytes.argtypes = [i32]
         L.tk_batch_describe.argtypes = [P, i32, P, ctypes.c_size_t]
         L.tk_batch_ask_eval.argtypes = [P, i32, P, P]
+        L.tk_batch_ask_eval_persistent.argtypes = [P, i32, P, P]
         L.tk_batch_tell.argtypes = [P, i32, P, P]
         L.tk_kf_state_bytes.restype = ctypes.c_size_t
         L.tk_kf_state_bytes.argtypes = [i32]
@@ -620,6 +621,10 @@ class Batch:
 
     def ask_eval(self, stream=None):
         _check(lib().tk_batch_ask_eval(self.problems, self.n, _ptr(self.table_view), _stream(stream)))
+
+    def ask_eval_persistent(self, stream=None):
+        """All problems' ask-eval in one persistent launch (per 128 problems)."""
+        _check(lib().tk_batch_ask_eval_persistent(self.problems, self.n, _ptr(self.table_view), _stream(stream)))
 
     def tell(self, stream=None):
         _check(lib().tk_batch_tell(self.problems, self.n, _ptr(self.table_view), _stream(stream)))
