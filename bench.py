@@ -738,14 +738,14 @@ def soft_leg(dev, reps=10):
     theta = torch.as_tensor((truth[None] + scenes.DEFAULT_SCALE[None] * rng.normal(size=(lam, 9))).astype(np.float32),
                             device=dev)
     xf = torch.empty(lam, 1, 4, 12, dtype=torch.float32, device=dev)
-    ws = tk.soft_workspace(lam, prob.meshes, cam, dev)
+    ws = tk.soft_workspace(lam, prob.soft_meshes, cam, dev)
     loss = torch.empty(lam, dtype=torch.float64, device=dev)
     g = torch.empty_like(theta)
 
     def fwd_bwd():
         tk.fk_transform(theta, lam, 1, prob.chains, xf)
-        tk.soft_forward(xf, lam, prob.meshes, cam, sigma, prob.target, loss, ws)
-        tk.soft_backward(theta, lam, prob.chains, prob.meshes, cam, sigma, g, ws)
+        tk.soft_forward(xf, lam, prob.soft_meshes, cam, sigma, prob.target, loss, ws)
+        tk.soft_backward(theta, lam, prob.chains, prob.soft_meshes, cam, sigma, g, ws)
 
     fwd_bwd()
     torch.cuda.synchronize()
@@ -754,9 +754,9 @@ def soft_leg(dev, reps=10):
     for _ in range(reps):
         a.record()
         tk.fk_transform(theta, lam, 1, prob.chains, xf)
-        tk.soft_forward(xf, lam, prob.meshes, cam, sigma, prob.target, loss, ws)
+        tk.soft_forward(xf, lam, prob.soft_meshes, cam, sigma, prob.target, loss, ws)
         b.record()
-        tk.soft_backward(theta, lam, prob.chains, prob.meshes, cam, sigma, g, ws)
+        tk.soft_backward(theta, lam, prob.chains, prob.soft_meshes, cam, sigma, g, ws)
         c.record()
         torch.cuda.synchronize()
         fwd_ms += a.elapsed_time(b) / reps
@@ -779,13 +779,24 @@ def soft_leg(dev, reps=10):
     torch.cuda.synchronize()
     plain_gen = a.elapsed_time(b) / gens
     refined_gen = b.elapsed_time(c) / gens
+    # the same generation + refinement recorded once into a HIP graph and replayed
+    gen.capture(refine=(5, 0.1, sigma))
+    gen.replay()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(gens):
+        gen.replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph_gen = a.elapsed_time(b) / gens
     log(f"soft640: forward {fwd_ms:.2f} ms + backward {bwd_ms:.2f} ms for {lam} candidates; generation "
-        f"{plain_gen:.3f} ms, with 5 Adam steps on the mean {refined_gen:.3f} ms")
+        f"{plain_gen:.3f} ms, with 5 Adam steps on the mean {refined_gen:.3f} ms ({graph_gen:.3f} ms as a graph)")
     return {"workload": f"{mesh.n_triangles} tris, {cam.width}x{cam.height}, {lam} candidates, sigma {sigma} px",
             "forward_ms": fwd_ms, "backward_ms": bwd_ms,
             "candidate_grads_per_s": lam / ((fwd_ms + bwd_ms) * 1e-3),
             "generation_ms": plain_gen, "generation_with_refine_ms": refined_gen,
-            "refine_steps_per_generation": 5}
+            "generation_with_refine_graph_ms": graph_gen,
+            "refine_ms": refined_gen - plain_gen, "refine_steps_per_generation": 5}
 
 
 def cpu_baseline(seconds, mesh, cam, chain, traj, flips, readings, est0, lam):

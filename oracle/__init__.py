@@ -94,6 +94,8 @@ def lib():
         L.tko_fk_jacobian.argtypes = [P, P, P]
         L.tko_soft.restype = d
         L.tko_soft.argtypes = [P, i32, P, P, P, d, P, P, P]
+        L.tko_soft_banded.restype = d
+        L.tko_soft_banded.argtypes = [P, i32, P, P, P, d, P, P, P]
         _lib = L
     return _lib
 
@@ -254,9 +256,11 @@ def fk_jacobian(theta, chain) -> np.ndarray:
     return out
 
 
-def soft(theta_arms, chains, meshes, cam, sigma, target=None, want_S=False, want_grad=False):
+def soft(theta_arms, chains, meshes, cam, sigma, target=None, want_S=False, want_grad=False, banded=False):
     """Soft silhouette loss L = sum_p (S - M)^2 of the arms at theta [n_arms*9]
-    (FP64); returns (L, S [H, W] or None, dL/dtheta [n_arms*9] or None)."""
+    (FP64); returns (L, S [H, W] or None, dL/dtheta [n_arms*9] or None).
+    banded=True evaluates the same definitions face-major over each face's
+    10-sigma box (tko_soft_banded), for large meshes."""
     theta = np.ascontiguousarray(theta_arms, dtype=np.float64).reshape(-1)
     n_arms = len(meshes)
     ch = (_Chain * n_arms)(*[_chain(c) for c in chains])
@@ -269,7 +273,8 @@ def soft(theta_arms, chains, meshes, cam, sigma, target=None, want_S=False, want
     tgt = None if target is None else np.ascontiguousarray(target, dtype=np.uint64)
     S = np.zeros((cam.height, cam.width)) if want_S else None
     g = np.zeros(9 * n_arms) if want_grad else None
-    L = lib().tko_soft(_p(theta), n_arms, ch, me, ctypes.byref(cm), float(sigma),
+    fn = lib().tko_soft_banded if banded else lib().tko_soft
+    L = fn(_p(theta), n_arms, ch, me, ctypes.byref(cm), float(sigma),
                        _p(tgt) if tgt is not None else None, _p(S) if S is not None else None,
                        _p(g) if g is not None else None)
     return float(L), S, g

@@ -95,6 +95,12 @@ void tko_fk_jacobian(const double theta[9], const tko_chain* ch, double dM[9][4]
 double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
                 const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad);
 
+/* The same S, loss and gradient evaluated face-major over each face's box
+ * grown by 10 sigma (tko_soft_banded in tko_soft.c): S and L are the same
+ * numbers as tko_soft's; the gradient agrees to rounding.  For large meshes. */
+double tko_soft_banded(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
+                       const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -223,10 +223,10 @@ static int mask_bit(const uint64_t* M, int32_t W, int32_t x, int32_t y) {
     return (int)((M[(y / 8) * bx + x / 8] >> ((y % 8) * 8 + x % 8)) & 1u);
 }
 
-double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
-                const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad) {
-    const int np = 9 * n_arms;
-    /* faces that take part, with their projected corners and corner Jacobians */
+/* The faces that take part, with their projected corners and corner
+ * Jacobians (in list order over the arms); *used receives their count. */
+static face_t* build_faces(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
+                           const tko_camera* cam, int32_t* used_out) {
     int32_t nf = 0;
     for (int a = 0; a < n_arms; a++) nf += meshes[a].n_triangles;
     face_t* F = (face_t*)malloc(sizeof(face_t) * (size_t)(nf > 0 ? nf : 1));
@@ -265,6 +265,27 @@ double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, co
             if (ok && area != 0.0 && isfinite(area)) F[used++] = f;
         }
     }
+    *used_out = used;
+    return F;
+}
+
+/* Whether pixel centre (px, py) lies in face f's box grown by 10 sigma (cut =
+ * -10 sigma): outside it the distance to the face exceeds 10 sigma. */
+static int in_band_box(const face_t* f, double cut, double px, double py) {
+    double lo_u = f->u[0], hi_u = f->u[0], lo_v = f->v[0], hi_v = f->v[0];
+    for (int c = 1; c < 3; c++) {
+        lo_u = fmin(lo_u, f->u[c]); hi_u = fmax(hi_u, f->u[c]);
+        lo_v = fmin(lo_v, f->v[c]); hi_v = fmax(hi_v, f->v[c]);
+    }
+    return !(px < lo_u + cut || px > hi_u - cut || py < lo_v + cut || py > hi_v - cut);
+}
+
+double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
+                const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad) {
+    const int np = 9 * n_arms;
+    /* faces that take part, with their projected corners and corner Jacobians */
+    int32_t used = 0;
+    face_t* F = build_faces(theta, n_arms, chains, meshes, cam, &used);
     const double s0 = sig(-10.0);
     const double cut = -10.0 * sigma;
     double loss = 0.0;
@@ -282,12 +303,7 @@ double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, co
             for (int32_t j = 0; j < used; j++) {
                 const face_t* f = &F[j];
                 /* outside the face's box grown by 10 sigma the distance exceeds 10 sigma */
-                double lo_u = f->u[0], hi_u = f->u[0], lo_v = f->v[0], hi_v = f->v[0];
-                for (int c = 1; c < 3; c++) {
-                    lo_u = fmin(lo_u, f->u[c]); hi_u = fmax(hi_u, f->u[c]);
-                    lo_v = fmin(lo_v, f->v[c]); hi_v = fmax(hi_v, f->v[c]);
-                }
-                if (px < lo_u + cut || px > hi_u - cut || py < lo_v + cut || py > hi_v - cut) continue;
+                if (!in_band_box(f, cut, px, py)) continue;
                 int ia, ib;
                 double t, nx, ny, sg;
                 const double d = signed_dist(f, px, py, &ia, &ib, &t, &nx, &ny, &sg);
@@ -324,11 +340,97 @@ double tko_soft(const double* theta, int32_t n_arms, const tko_chain* chains, co
             }
         }
     }
-    (void)idx;
     free(dd);
     free(dpd);
     free(pr);
     free(idx);
+    free(F);
+    return loss;
+}
+
+/* ---- the same silhouette, loss and gradient, face-major ----
+ *
+ * The definitions of tko_soft evaluated face by face over only the pixel
+ * centres of each face's box grown by 10 sigma (the same box test, applied
+ * inside a range one pixel wider than the box), so that meshes of tens of
+ * thousands of faces at 640 x 480 finish in seconds.  Faces are visited in
+ * ascending order, so each pixel multiplies its factors 1 - prob_j in the
+ * same order as tko_soft: S and the loss are the same numbers.  A factor that
+ * is exactly zero (prob = 1, deep inside a face) is counted instead of
+ * multiplied; the product over the other faces of the gradient is then the
+ * product of the non-zero factors divided by the face's own factor, or zero
+ * when another factor is zero (an identity of the product, with no division
+ * by zero). */
+double tko_soft_banded(const double* theta, int32_t n_arms, const tko_chain* chains, const tko_mesh* meshes,
+                       const tko_camera* cam, double sigma, const uint64_t* target, double* S_out, double* grad) {
+    const int np = 9 * n_arms;
+    const int32_t W = cam->width, H = cam->height;
+    int32_t used = 0;
+    face_t* F = build_faces(theta, n_arms, chains, meshes, cam, &used);
+    const double s0 = sig(-10.0);
+    const double cut = -10.0 * sigma;
+    double* prod = (double*)malloc(sizeof(double) * (size_t)W * H);       /* product of the non-zero factors */
+    int32_t* zeros = (int32_t*)calloc((size_t)W * H, sizeof(int32_t));   /* factors exactly zero */
+    double* wpix = (double*)malloc(sizeof(double) * (size_t)W * H);       /* 2 (S - M) */
+    for (size_t i = 0; i < (size_t)W * H; i++) prod[i] = 1.0;
+    if (grad)
+        for (int p = 0; p < np; p++) grad[p] = 0.0;
+    double loss = 0.0;
+    /* pass 0: the per-pixel products; pass 1 (gradient only): the chain rule */
+    for (int pass = 0; pass < (grad ? 2 : 1); pass++) {
+        for (int32_t j = 0; j < used; j++) {
+            const face_t* f = &F[j];
+            double lo_u = f->u[0], hi_u = f->u[0], lo_v = f->v[0], hi_v = f->v[0];
+            for (int c = 1; c < 3; c++) {
+                lo_u = fmin(lo_u, f->u[c]); hi_u = fmax(hi_u, f->u[c]);
+                lo_v = fmin(lo_v, f->v[c]); hi_v = fmax(hi_v, f->v[c]);
+            }
+            /* a pixel range one pixel wider than the grown box; the box test decides */
+            const double x0 = floor(lo_u + cut - 0.5) - 1.0, x1 = ceil(hi_u - cut - 0.5) + 1.0;
+            const double y0 = floor(lo_v + cut - 0.5) - 1.0, y1 = ceil(hi_v - cut - 0.5) + 1.0;
+            if (!(x1 >= 0.0 && y1 >= 0.0 && x0 <= W - 1 && y0 <= H - 1)) continue;
+            const int32_t xa = x0 < 0.0 ? 0 : (int32_t)x0, xb = x1 > W - 1 ? W - 1 : (int32_t)x1;
+            const int32_t ya = y0 < 0.0 ? 0 : (int32_t)y0, yb = y1 > H - 1 ? H - 1 : (int32_t)y1;
+            for (int32_t y = ya; y <= yb; y++)
+                for (int32_t x = xa; x <= xb; x++) {
+                    const double px = x + 0.5, py = y + 0.5;
+                    if (!in_band_box(f, cut, px, py)) continue;
+                    int ia, ib;
+                    double t, nx, ny, sg;
+                    const double d = signed_dist(f, px, py, &ia, &ib, &t, &nx, &ny, &sg);
+                    if (d < cut) continue;
+                    const double sgm = sig(d / sigma);
+                    const double fac = 1.0 - (sgm - s0) / (1.0 - s0);
+                    const size_t q = (size_t)y * W + x;
+                    if (pass == 0) {
+                        if (fac == 0.0) zeros[q]++;
+                        else prod[q] *= fac;
+                        continue;
+                    }
+                    const int others_zero = zeros[q] - (fac == 0.0 ? 1 : 0) > 0;
+                    const double others = others_zero ? 0.0 : (fac == 0.0 ? prod[q] : prod[q] / fac);
+                    const double w = wpix[q] * others * (sgm * (1.0 - sgm) / (sigma * (1.0 - s0)));
+                    for (int p = 0; p < np; p++) {
+                        const double g = -(nx * ((1.0 - t) * f->du[ia][p] + t * f->du[ib][p]) +
+                                           ny * ((1.0 - t) * f->dv[ia][p] + t * f->dv[ib][p]));
+                        grad[p] += w * sg * g;
+                    }
+                }
+        }
+        if (pass == 0)
+            for (int32_t y = 0; y < H; y++)
+                for (int32_t x = 0; x < W; x++) {
+                    const size_t q = (size_t)y * W + x;
+                    const double S = 1.0 - (zeros[q] > 0 ? 0.0 : prod[q]);
+                    const double m = target ? (double)mask_bit(target, W, x, y) : 0.0;
+                    loss += (S - m) * (S - m);
+                    wpix[q] = 2.0 * (S - m);
+                    if (S_out) S_out[q] = S;
+                }
+    }
+    free(wpix);
+    free(zeros);
+    free(prod);
     free(F);
     return loss;
 }

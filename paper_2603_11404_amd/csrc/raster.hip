@@ -73,7 +73,15 @@ struct TriRec {
 static_assert(sizeof(TriRec) == 64, "record size");
 
 constexpr int32_t kWide = 1;            // flags bit: 64-bit edge functions
-constexpr int32_t kNear = 2;            // flags bit: every vertex within 32 px of the box origin (lane tasks)
+constexpr int32_t kNear = 2;            // flags bit: every vertex within 56 px of the box origin (lane tasks)
+
+// Near triangles have every vertex within kNearQ8 (56 pixels in Q8 units) of
+// their box origin.  Then every edge vector is below 2 kNearQ8 = 28672 (it
+// packs into 16 bits, and 256 times it fits the 24-bit multiplier), and every
+// edge function over the box and 7 pixels beyond it -- the pixel centres the
+// lane tasks evaluate -- is below 2 x 28672 x (28672 + 7 x 256) < 1.75e9 <
+// 2^31 in magnitude: exact in 32-bit modular arithmetic.
+constexpr int32_t kNearQ8 = 56 * 256;
 
 __device__ __forceinline__ int64_t rec_e0(const TriRec& r, int e) {
     return int64_t((uint64_t(uint32_t(r.e0hi[e])) << 32) | uint64_t(uint32_t(r.e0lo[e])));
@@ -92,15 +100,15 @@ __device__ __forceinline__ bool setup_triangle(int32_t x0, int32_t y0, int32_t x
     if (px0 > px1 || py0 > py1) return false;
     r.box_x = px0 | (px1 << 16);
     r.box_y = py0 | (py1 << 16);
-    // vertices relative to the box origin (Q8); near: all within 32 pixels of it
+    // vertices relative to the box origin (Q8); near: all within 56 pixels of it
     const int32_t ox = px0 << 8, oy = py0 << 8;
-    const bool near = (xmax - ox < (1 << 13)) & (xmin - ox >= -(1 << 13)) & (ymax - oy < (1 << 13)) &
-                      (ymin - oy >= -(1 << 13));
+    const bool near = (xmax - ox < kNearQ8) & (xmin - ox >= -kNearQ8) & (ymax - oy < kNearQ8) &
+                      (ymin - oy >= -kNearQ8);
     bool wide = false;
     if (near) {
-        // differences < 2^14, so all products fit the 24-bit multiplier and every
-        // edge function over the box (and 7 pixels beyond it) stays below 2^30 --
-        // exact in 32 bits; the high words are never read for near triangles
+        // differences < 2 kNearQ8, so all products fit the 24-bit multiplier and
+        // every edge function over the box (and 7 pixels beyond it) is exact in
+        // 32 bits (see kNearQ8); the high words are never read for near triangles
         int32_t rx[3] = {x0 - ox, x1 - ox, x2 - ox}, ry[3] = {y0 - oy, y1 - oy, y2 - oy};
         const int32_t area2 = __mul24(x1 - x0, y2 - y0) - __mul24(y1 - y0, x2 - x0);
         if (area2 == 0) return false;
@@ -857,7 +865,7 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b, un
                 const bool near = valid && (rec.flags & kNear);
                 const bool narrow = near && is_narrow(rec.box_x);
                 const bool wide = near && !narrow;
-                // lane tasks: 8-column windows x 4-row bands (at most 5 x 9) for wide
+                // lane tasks: 8-column windows x 4-row bands (at most 8 x 15) for wide
                 // boxes, kNarrowRows-row windows (at most 6) for narrow ones; both counts in one
                 // wave scan, wide in the low and narrow in the high 16 bits
                 const int cnt_w = wide ? task_windows(rec.box_x) * task_bands(rec.box_y) : 0;

@@ -40,7 +40,15 @@ constexpr int kSoftTile = 8;               // 8 x 8 pixels per tile, one wave
 constexpr int kSoftMaxTiles = 32;          // tiles per face in the tile lists
 constexpr int kSoftMaxTileCount = 16384;   // tiles per image (LDS counters)
 constexpr int kSoftBinThreads = 1024;
-constexpr int kSoftFaceBlock = 256;        // faces per backward workgroup
+constexpr int kSoftFaceBlock = 256;        // threads per backward workgroup
+constexpr int kSoftFaceLanes = 8;          // lanes per face in the backward pass
+constexpr int kSoftFacesPerBlock = kSoftFaceBlock / kSoftFaceLanes;
+           // waves per tile in the forward pass
+constexpr int kSoftWideBin = 64;           // from this batch on, one binning workgroup per candidate
+constexpr int kSoftBinGroups = 32;         // below it, binning workgroups per candidate
+constexpr int kSoftFwdChunkSmall = 64;     // faces of a tile list per forward work item, batch < kSoftWideBin
+constexpr int kSoftFwdChunkWide = 1024;    // the same from kSoftWideBin candidates on
+constexpr int kSoftReduceGroups = 16;      // workgroups summing the backward partials of one candidate
 constexpr int kSoftGrad = 48;              // dL/dM: 4 links x 12 entries
 constexpr double kFixScale = 4294967296.0; // 2^32
 constexpr float kBand = 10.0f;             // the band is d >= -10 sigma
@@ -54,8 +62,9 @@ struct FaceRec {              // 48 bytes
 static_assert(sizeof(FaceRec) == 48, "face record is 48 bytes");
 
 struct SoftLayout {
-    size_t verts, faces, tile_off, lists, big, big_n, G, tloss, part, total;
-    int32_t tiles_x, tiles_y, n_tiles, n_blocks;
+    size_t verts, faces, tile_off, tile_cnt, tile_tot, chunks, chunk_n, facc, done, lists, big, big_n, G, tloss, part,
+        gsum, total;
+    int32_t tiles_x, tiles_y, n_tiles, n_blocks, chunk_cap, fwd_chunk;
 };
 
 struct SoftArgs {
@@ -65,17 +74,24 @@ struct SoftArgs {
     int32_t block_offset[kMaxArms];    // first backward workgroup of each arm
     int32_t total_faces, batch;
     float sigma, inv_sigma;
-    int32_t tiles_x, tiles_y, n_tiles, n_blocks;
+    int32_t tiles_x, tiles_y, n_tiles, n_blocks, chunk_cap, fwd_chunk;
     // workspace
     float4* verts;        // [batch][V]
     FaceRec* faces;       // [batch][F]
     int32_t* tile_off;    // [batch][n_tiles + 1]
+    int32_t* tile_cnt;    // [batch][kSoftBinGroups][n_tiles] each binning workgroup's first slot in a tile list
+    int32_t* tile_tot;    // [batch][n_tiles] list lengths summed by the binning workgroups (both: batch < kSoftWideBin)
+    int2* chunks;         // [batch][chunk_cap] forward work items (tile, k): faces k * fwd_chunk... of its list
+    int32_t* chunk_n;     // [batch] work items
+    long long* facc;      // [batch][n_tiles][64] fixed-point sums of tiles split over several items
+    int32_t* done;        // [batch][n_tiles] items of a split tile finished
     int32_t* lists;       // [batch][F * kSoftMaxTiles]
     int32_t* big;         // [batch][F]
     int32_t* big_n;       // [batch]
     float* G;             // [batch][H * W]
     double* tloss;        // [batch][n_tiles]
     float* part;          // [batch][n_blocks][kSoftGrad]
+    double* gsum;         // [batch][kSoftReduceGroups][kMaxArms][kSoftGrad] sums of slices of the partials
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -87,7 +103,10 @@ SoftLayout soft_layout(int32_t batch, const MeshSet& ms, int32_t total_faces, in
     L.tiles_y = (H + kSoftTile - 1) / kSoftTile;
     L.n_tiles = L.tiles_x * L.tiles_y;
     L.n_blocks = 0;
-    for (int a = 0; a < ms.n_meshes; a++) L.n_blocks += (faces_per_arm[a] + kSoftFaceBlock - 1) / kSoftFaceBlock;
+    // each tile: one work item, or one per fwd_chunk faces of a longer list
+    L.fwd_chunk = batch < kSoftWideBin ? kSoftFwdChunkSmall : kSoftFwdChunkWide;
+    L.chunk_cap = int32_t(L.n_tiles + (size_t(total_faces) * kSoftMaxTiles + L.fwd_chunk - 1) / L.fwd_chunk);
+    for (int a = 0; a < ms.n_meshes; a++) L.n_blocks += (faces_per_arm[a] + kSoftFacesPerBlock - 1) / kSoftFacesPerBlock;
     const size_t B = size_t(batch), V = size_t(ms.total_vertices), F = size_t(total_faces);
     size_t o = 0;
     auto take = [&o](size_t bytes) {
@@ -98,12 +117,19 @@ SoftLayout soft_layout(int32_t batch, const MeshSet& ms, int32_t total_faces, in
     L.verts = take(B * V * sizeof(float4));
     L.faces = take(B * F * sizeof(FaceRec));
     L.tile_off = take(B * size_t(L.n_tiles + 1) * sizeof(int32_t));
+    L.tile_cnt = take(batch < kSoftWideBin ? B * kSoftBinGroups * size_t(L.n_tiles) * sizeof(int32_t) : 0);
+    L.tile_tot = take(batch < kSoftWideBin ? B * size_t(L.n_tiles) * sizeof(int32_t) : 0);
+    L.chunks = take(B * size_t(L.chunk_cap) * sizeof(int2));
+    L.chunk_n = take(B * sizeof(int32_t));
+    L.facc = take(B * size_t(L.n_tiles) * 64 * sizeof(long long));
+    L.done = take(B * size_t(L.n_tiles) * sizeof(int32_t));
     L.lists = take(B * F * kSoftMaxTiles * sizeof(int32_t));
     L.big = take(B * F * sizeof(int32_t));
     L.big_n = take(B * sizeof(int32_t));
     L.G = take(B * size_t(W) * size_t(H) * sizeof(float));
     L.tloss = take(B * size_t(L.n_tiles) * sizeof(double));
     L.part = take(B * size_t(L.n_blocks) * kSoftGrad * sizeof(float));
+    L.gsum = take(B * kSoftReduceGroups * kMaxArms * kSoftGrad * sizeof(double));
     L.total = o;
     return L;
 }
@@ -183,6 +209,11 @@ __global__ __launch_bounds__(256) void soft_vert_kernel(const float* __restrict_
 }
 
 __global__ __launch_bounds__(256) void soft_face_kernel(SoftArgs a) {
+    if (a.tile_tot) {   // clear what the multi-workgroup binning accumulates
+        const int b = blockIdx.y;
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.big_n[b] = 0;
+        for (int t = blockIdx.x * 256 + threadIdx.x; t < a.n_tiles; t += gridDim.x * 256) a.tile_tot[size_t(b) * a.n_tiles + t] = 0;
+    }
     const int32_t gf = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (gf >= a.total_faces) return;
@@ -290,6 +321,122 @@ __global__ __launch_bounds__(kSoftBinThreads) void soft_bin_kernel(SoftArgs a) {
     }
 }
 
+// Binning across workgroups for small batches (the single-workgroup form
+// above leaves most of the chip idle then): workgroup g of a candidate counts
+// the faces g * 256 + tid + k * kSoftBinGroups * 256 per tile in LDS and
+// reserves that many slots of each tile it touches by one atomic add on the
+// tile's total, which returns its first slot inside the tile's list; the plan
+// pass turns the totals into list offsets; the fill pass repeats the count with
+// LDS cursors from offset + first slot.  The order of the faces inside a tile
+// list depends on the order of those atomics; the forward pass sums integers,
+// so no result depends on it.  The face kernel clears big_n and the totals.
+__device__ __forceinline__ bool face_tiles(const FaceRec& r, int& tx0, int& tx1, int& ty0, int& ty1) {
+    tx0 = r.x0 / kSoftTile;
+    tx1 = r.x1 / kSoftTile;
+    ty0 = r.y0 / kSoftTile;
+    ty1 = r.y1 / kSoftTile;
+    return (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= kSoftMaxTiles;
+}
+
+__global__ __launch_bounds__(256) void soft_bin_count_kernel(SoftArgs a) {
+    __shared__ int32_t s_cnt[kSoftMaxTileCount];
+    const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int nt = a.n_tiles;
+    for (int t = tid; t < nt; t += 256) s_cnt[t] = 0;
+    __syncthreads();
+    const FaceRec* faces = a.faces + size_t(b) * a.total_faces;
+    for (int32_t f = g * 256 + tid; f < a.total_faces; f += kSoftBinGroups * 256) {
+        const FaceRec r = faces[f];
+        if (r.orient == 0.0f) continue;
+        int tx0, tx1, ty0, ty1;
+        if (!face_tiles(r, tx0, tx1, ty0, ty1)) {
+            a.big[size_t(b) * a.total_faces + atomicAdd(&a.big_n[b], 1)] = f;
+            continue;
+        }
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++) atomicAdd(&s_cnt[ty * a.tiles_x + tx], 1);
+    }
+    __syncthreads();
+    int32_t* first = a.tile_cnt + (size_t(b) * kSoftBinGroups + g) * nt;
+    int32_t* tot = a.tile_tot + size_t(b) * nt;
+    for (int t = tid; t < nt; t += 256)
+        if (s_cnt[t] > 0) first[t] = atomicAdd(&tot[t], s_cnt[t]);
+}
+
+__global__ __launch_bounds__(256) void soft_bin_fill_kernel(SoftArgs a) {
+    __shared__ int32_t s_cur[kSoftMaxTileCount];
+    const int g = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int nt = a.n_tiles;
+    // tiles this workgroup did not count hold stale first slots; they are not touched below
+    const int32_t* first = a.tile_cnt + (size_t(b) * kSoftBinGroups + g) * nt;
+    const int32_t* off = a.tile_off + size_t(b) * (nt + 1);
+    for (int t = tid; t < nt; t += 256) s_cur[t] = off[t] + first[t];
+    __syncthreads();
+    const FaceRec* faces = a.faces + size_t(b) * a.total_faces;
+    int32_t* lists = a.lists + size_t(b) * a.total_faces * kSoftMaxTiles;
+    for (int32_t f = g * 256 + tid; f < a.total_faces; f += kSoftBinGroups * 256) {
+        const FaceRec r = faces[f];
+        if (r.orient == 0.0f) continue;
+        int tx0, tx1, ty0, ty1;
+        if (!face_tiles(r, tx0, tx1, ty0, ty1)) continue;
+        for (int ty = ty0; ty <= ty1; ty++)
+            for (int tx = tx0; tx <= tx1; tx++) lists[atomicAdd(&s_cur[ty * a.tiles_x + tx], 1)] = f;
+    }
+}
+
+__device__ __forceinline__ int32_t fwd_items(int32_t n, int32_t chunk) { return n <= chunk ? 1 : (n + chunk - 1) / chunk; }
+
+// Plan of the forward pass, one workgroup per candidate: the list offsets of
+// the tiles (from the totals of the multi-workgroup binning when from_totals,
+// else already written by the single-workgroup binning) and the work items:
+// a tile whose list is longer than fwd_chunk faces is split into items of
+// fwd_chunk faces, whose sums meet in facc (cleared here) and are
+// finished by the last item to arrive (done, cleared here).
+__global__ __launch_bounds__(kSoftBinThreads) void soft_plan_kernel(SoftArgs a, int from_totals) {
+    __shared__ int32_t s_c[kSoftBinThreads], s_k[kSoftBinThreads];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int nt = a.n_tiles;
+    int32_t* off = a.tile_off + size_t(b) * (nt + 1);
+    const int32_t* tot = from_totals ? a.tile_tot + size_t(b) * nt : nullptr;
+    const int per = (nt + kSoftBinThreads - 1) / kSoftBinThreads;
+    const int c0 = min(tid * per, nt), c1 = min(c0 + per, nt);
+    int32_t sc = 0, sk = 0;
+    for (int t = c0; t < c1; t++) {
+        const int32_t n = from_totals ? tot[t] : off[t + 1] - off[t];
+        sc += n;
+        sk += fwd_items(n, a.fwd_chunk);
+    }
+    s_c[tid] = sc;
+    s_k[tid] = sk;
+    __syncthreads();
+    for (int o = 1; o < kSoftBinThreads; o <<= 1) {
+        const int32_t vc = tid >= o ? s_c[tid - o] : 0, vk = tid >= o ? s_k[tid - o] : 0;
+        __syncthreads();
+        s_c[tid] += vc;
+        s_k[tid] += vk;
+        __syncthreads();
+    }
+    int32_t rc = s_c[tid] - sc, rk = s_k[tid] - sk;
+    int2* items = a.chunks + size_t(b) * a.chunk_cap;
+    for (int t = c0; t < c1; t++) {
+        const int32_t n = from_totals ? tot[t] : off[t + 1] - off[t];
+        if (from_totals) off[t] = rc;
+        rc += n;
+        const int32_t k_n = fwd_items(n, a.fwd_chunk);
+        for (int32_t k = 0; k < k_n; k++) items[rk + k] = make_int2(t, k);
+        rk += k_n;
+        if (k_n > 1) {
+            a.done[size_t(b) * nt + t] = 0;
+            long long* acc = a.facc + (size_t(b) * nt + t) * 64;
+            for (int i = 0; i < 64; i++) acc[i] = 0;
+        }
+    }
+    if (tid == kSoftBinThreads - 1) {
+        if (from_totals) off[nt] = s_c[tid];
+        a.chunk_n[b] = s_k[tid];
+    }
+}
+
 // log(1 - prob) of one (pixel, face) pair in fixed point; 0 outside the band.
 __device__ __forceinline__ long long pair_log_fixed(const FaceRec& r, int px, int py, float inv_sigma) {
     if (px < r.x0 || px > r.x1 || py < r.y0 || py > r.y1) return 0;
@@ -300,27 +447,17 @@ __device__ __forceinline__ long long pair_log_fixed(const FaceRec& r, int px, in
     return llrint(double(term) * kFixScale);
 }
 
-__global__ __launch_bounds__(64) void soft_fwd_kernel(SoftArgs a, const uint64_t* __restrict__ target,
-                                                      float* __restrict__ S_out) {
-    const int t = blockIdx.x, b = blockIdx.y;
-    const int lane = threadIdx.x;
+// One wave per work item (tile, k) of the candidate, looping when the grid
+// is smaller than the item count; lane = pixel of the 8x8 tile, the wave adds
+// the fixed-point terms of faces k * fwd_chunk ... of the tile list (item 0
+// also of the big faces).  A tile of one item is finished at once; the items
+// of a longer list add their sums into facc, and the last to arrive finishes
+// the tile.  All sums are integers: the same bits in any order.
+__device__ __forceinline__ void fwd_finish(const SoftArgs& a, const uint64_t* __restrict__ target,
+                                           float* __restrict__ S_out, int b, int t, int lane, long long acc) {
     const int tx = t % a.tiles_x, ty = t / a.tiles_x;
     const int px = tx * kSoftTile + (lane & 7), py = ty * kSoftTile + (lane >> 3);
     const int W = a.cam.width, H = a.cam.height;
-    const FaceRec* faces = a.faces + size_t(b) * a.total_faces;
-    const int32_t* off = a.tile_off + size_t(b) * (a.n_tiles + 1);
-    const int32_t* lists = a.lists + size_t(b) * a.total_faces * kSoftMaxTiles;
-    long long acc = 0;
-    const int32_t e0 = off[t], e1 = off[t + 1];
-    for (int32_t e = e0; e < e1; e++) acc += pair_log_fixed(faces[lists[e]], px, py, a.inv_sigma);
-    const int32_t nb = a.big_n[b];
-    const int32_t* big = a.big + size_t(b) * a.total_faces;
-    const int x_lo = tx * kSoftTile, y_lo = ty * kSoftTile;
-    for (int32_t e = 0; e < nb; e++) {
-        const FaceRec r = faces[big[e]];
-        if (r.x1 < x_lo || r.x0 >= x_lo + kSoftTile || r.y1 < y_lo || r.y0 >= y_lo + kSoftTile) continue;
-        acc += pair_log_fixed(r, px, py, a.inv_sigma);
-    }
     const bool inimg = px < W && py < H;
     const double lsum = double(acc) / kFixScale;         // log(1 - S)
     const double one_minus_S = exp(lsum);
@@ -337,6 +474,62 @@ __global__ __launch_bounds__(64) void soft_fwd_kernel(SoftArgs a, const uint64_t
     }
     for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
     if (lane == 0) a.tloss[size_t(b) * a.n_tiles + t] = l;
+}
+
+// The read-only inputs come as separate restrict arguments: the kernel's own
+// stores then provably leave them alone, and their wave-uniform loads stay
+// scalar (face records in SGPRs) across the item loop.  The register bound
+// (8 waves per SIMD) keeps the constants of fwd_finish's FP64 exp / expm1
+// from being hoisted out of the loop into vector registers.
+__global__ __launch_bounds__(64, 8) void soft_fwd_kernel(SoftArgs a, const FaceRec* __restrict__ faces_all,
+                                                     const int32_t* __restrict__ lists_all,
+                                                     const int32_t* __restrict__ off_all,
+                                                     const int2* __restrict__ items_all,
+                                                     const int32_t* __restrict__ big_all,
+                                                     const uint64_t* __restrict__ target, float* __restrict__ S_out) {
+    const int b = blockIdx.y;
+    const int lane = threadIdx.x;
+    const FaceRec* __restrict__ faces = faces_all + size_t(b) * a.total_faces;
+    const int32_t* __restrict__ off = off_all + size_t(b) * (a.n_tiles + 1);
+    const int32_t* __restrict__ lists = lists_all + size_t(b) * a.total_faces * kSoftMaxTiles;
+    const int2* __restrict__ items = items_all + size_t(b) * a.chunk_cap;
+    const int32_t n_items = a.chunk_n[b];
+    const int32_t nb = a.big_n[b];
+    const int32_t* __restrict__ big = big_all + size_t(b) * a.total_faces;
+    for (int32_t c = blockIdx.x; c < n_items; c += gridDim.x) {
+        const int2 it = items[c];
+        const int t = it.x, k = it.y;
+        const int tx = t % a.tiles_x, ty = t / a.tiles_x;
+        const int px = tx * kSoftTile + (lane & 7), py = ty * kSoftTile + (lane >> 3);
+        const int32_t e0 = off[t], e1 = off[t + 1];
+        const int32_t k_n = fwd_items(e1 - e0, a.fwd_chunk);
+        const int32_t lo = e0 + k * a.fwd_chunk, hi = min(lo + a.fwd_chunk, e1);
+        long long acc = 0;
+        for (int32_t e = lo; e < hi; e++) acc += pair_log_fixed(faces[lists[e]], px, py, a.inv_sigma);
+        if (k == 0) {
+            const int x_lo = tx * kSoftTile, y_lo = ty * kSoftTile;
+            for (int32_t e = 0; e < nb; e++) {
+                const FaceRec r = faces[big[e]];
+                if (r.x1 < x_lo || r.x0 >= x_lo + kSoftTile || r.y1 < y_lo || r.y0 >= y_lo + kSoftTile) continue;
+                acc += pair_log_fixed(r, px, py, a.inv_sigma);
+            }
+        }
+        bool finish = true;
+        if (k_n > 1) {
+            long long* tacc = a.facc + (size_t(b) * a.n_tiles + t) * 64;
+            atomicAdd(reinterpret_cast<unsigned long long*>(tacc + lane), static_cast<unsigned long long>(acc));
+            __threadfence();
+            int last = 0;
+            if (lane == 0) last = atomicAdd(&a.done[size_t(b) * a.n_tiles + t], 1) == k_n - 1;
+            finish = __shfl(last, 0) != 0;
+            if (finish) {
+                __threadfence();
+                acc = static_cast<long long>(__hip_atomic_load(reinterpret_cast<unsigned long long*>(tacc + lane),
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+        if (finish) fwd_finish(a, target, S_out, b, t, lane, acc);
+    }
 }
 
 __global__ __launch_bounds__(256) void soft_loss_kernel(SoftArgs a, double* __restrict__ loss) {
@@ -363,66 +556,81 @@ __global__ __launch_bounds__(kSoftFaceBlock) void soft_bwd_face_kernel(SoftArgs 
     const int b = blockIdx.y;
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
+    // kSoftFaceLanes lanes per face: lane j of a group walks the band rows y0 + j, y0 + j + kSoftFaceLanes, ...
+    const int grp = tid / kSoftFaceLanes, j = tid % kSoftFaceLanes;
     const int arm = (a.ms.n_meshes > 1 && blk >= a.block_offset[1]) ? 1 : 0;
     const MeshK m = arm == 0 ? a.ms.m[0] : a.ms.m[1];
-    const int32_t lf = (blk - (arm == 0 ? 0 : a.block_offset[1])) * kSoftFaceBlock + tid;
+    const int32_t lf = (blk - (arm == 0 ? 0 : a.block_offset[1])) * kSoftFacesPerBlock + grp;
     const int32_t gf = (arm == 0 ? a.face_offset[0] : a.face_offset[1]) + lf;
     float acc[kSoftGrad];
 #pragma unroll
     for (int e = 0; e < kSoftGrad; e++) acc[e] = 0.0f;
-    if (lf < m.n_triangles) {
-        const FaceRec r = a.faces[size_t(b) * a.total_faces + gf];
-        float g0u = 0.0f, g0v = 0.0f, g1u = 0.0f, g1v = 0.0f, g2u = 0.0f, g2v = 0.0f;
-        if (r.orient != 0.0f) {
-            const int W = a.cam.width;
-            const float* Gm = a.G + size_t(b) * W * a.cam.height;
-            for (int py = r.y0; py <= r.y1; py++) {
-                for (int px = r.x0; px <= r.x1; px++) {
-                    const float G = Gm[size_t(py) * W + px];
-                    if (G == 0.0f) continue;
-                    const EdgeHit h = face_distance(r, px + 0.5f, py + 0.5f);
-                    const float x = h.d * a.inv_sigma;
-                    if (!(x >= -kBand)) continue;
-                    const float sg = 1.0f / (1.0f + expf(-x));
-                    // dL/dd = G sig(x); dd/d(corner a) = -sg n (1 - t), dd/d(corner b) = -sg n t
-                    const float w = -G * sg * h.sg;
-                    const float wa = w * (1.0f - h.t), wb = w * h.t;
-                    const int ia = h.ia, ib = ia == 2 ? 0 : ia + 1;
-                    const float ca0 = ia == 0 ? wa : (ib == 0 ? wb : 0.0f);
-                    const float ca1 = ia == 1 ? wa : (ib == 1 ? wb : 0.0f);
-                    const float ca2 = ia == 2 ? wa : (ib == 2 ? wb : 0.0f);
-                    g0u += ca0 * h.nx;
-                    g0v += ca0 * h.ny;
-                    g1u += ca1 * h.nx;
-                    g1v += ca1 * h.ny;
-                    g2u += ca2 * h.nx;
-                    g2v += ca2 * h.ny;
-                }
+    const bool has = lf < m.n_triangles;
+    FaceRec r;
+    if (has) r = a.faces[size_t(b) * a.total_faces + gf];
+    const bool live = has && r.orient != 0.0f;
+    float g0u = 0.0f, g0v = 0.0f, g1u = 0.0f, g1v = 0.0f, g2u = 0.0f, g2v = 0.0f;
+    if (live) {
+        const int W = a.cam.width;
+        const float* Gm = a.G + size_t(b) * W * a.cam.height;
+        for (int py = r.y0 + j; py <= r.y1; py += kSoftFaceLanes) {
+            for (int px = r.x0; px <= r.x1; px++) {
+                const float G = Gm[size_t(py) * W + px];
+                if (G == 0.0f) continue;
+                const EdgeHit h = face_distance(r, px + 0.5f, py + 0.5f);
+                const float x = h.d * a.inv_sigma;
+                if (!(x >= -kBand)) continue;
+                const float sg = 1.0f / (1.0f + expf(-x));
+                // dL/dd = G sig(x); dd/d(corner a) = -sg n (1 - t), dd/d(corner b) = -sg n t
+                const float w = -G * sg * h.sg;
+                const float wa = w * (1.0f - h.t), wb = w * h.t;
+                const int ia = h.ia, ib = ia == 2 ? 0 : ia + 1;
+                const float ca0 = ia == 0 ? wa : (ib == 0 ? wb : 0.0f);
+                const float ca1 = ia == 1 ? wa : (ib == 1 ? wb : 0.0f);
+                const float ca2 = ia == 2 ? wa : (ib == 2 ? wb : 0.0f);
+                g0u += ca0 * h.nx;
+                g0v += ca0 * h.ny;
+                g1u += ca1 * h.nx;
+                g1v += ca1 * h.ny;
+                g2u += ca2 * h.nx;
+                g2v += ca2 * h.ny;
             }
-            const float4* V = a.verts + size_t(b) * a.ms.total_vertices + m.vertex_offset;
+        }
+    }
+    // the face's corner gradients: butterfly over its lanes (fixed order; lane 0's sum is used)
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const float gu = c == 0 ? g0u : (c == 1 ? g1u : g2u);
-                const float gv = c == 0 ? g0v : (c == 1 ? g1v : g2v);
-                const int32_t vi = m.triangles[3 * lf + c];
-                const float4 p = V[vi];
-                const float iz = 1.0f / p.z;
-                // u = fx X / Z + cx: dL/dX = gu fx / Z, dL/dY = gv fy / Z,
-                // dL/dZ = -(gu (u - cx) + gv (v - cy)) / Z
-                const float gX = gu * a.cam.fx * iz, gY = gv * a.cam.fy * iz;
-                const float gZ = -(gu * (p.x - a.cam.cx) + gv * (p.y - a.cam.cy)) * iz;
-                const float h4[4] = {m.vertices[3 * vi], m.vertices[3 * vi + 1], m.vertices[3 * vi + 2], 1.0f};
-                const int l = m.vertex_link[vi];
+    for (int o = 1; o < kSoftFaceLanes; o <<= 1) {
+        g0u += __shfl_xor(g0u, o);
+        g0v += __shfl_xor(g0v, o);
+        g1u += __shfl_xor(g1u, o);
+        g1v += __shfl_xor(g1v, o);
+        g2u += __shfl_xor(g2u, o);
+        g2v += __shfl_xor(g2v, o);
+    }
+    if (live && j == 0) {
+        const float4* V = a.verts + size_t(b) * a.ms.total_vertices + m.vertex_offset;
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const float e0 = gX * h4[k], e1 = gY * h4[k], e2 = gZ * h4[k];
+        for (int c = 0; c < 3; c++) {
+            const float gu = c == 0 ? g0u : (c == 1 ? g1u : g2u);
+            const float gv = c == 0 ? g0v : (c == 1 ? g1v : g2v);
+            const int32_t vi = m.triangles[3 * lf + c];
+            const float4 p = V[vi];
+            const float iz = 1.0f / p.z;
+            // u = fx X / Z + cx: dL/dX = gu fx / Z, dL/dY = gv fy / Z,
+            // dL/dZ = -(gu (u - cx) + gv (v - cy)) / Z
+            const float gX = gu * a.cam.fx * iz, gY = gv * a.cam.fy * iz;
+            const float gZ = -(gu * (p.x - a.cam.cx) + gv * (p.y - a.cam.cy)) * iz;
+            const float h4[4] = {m.vertices[3 * vi], m.vertices[3 * vi + 1], m.vertices[3 * vi + 2], 1.0f};
+            const int l = m.vertex_link[vi];
 #pragma unroll
-                    for (int ll = 0; ll < 4; ll++) {
-                        if (l == ll) {
-                            acc[ll * 12 + k] += e0;
-                            acc[ll * 12 + 4 + k] += e1;
-                            acc[ll * 12 + 8 + k] += e2;
-                        }
+            for (int k = 0; k < 4; k++) {
+                const float e0 = gX * h4[k], e1 = gY * h4[k], e2 = gZ * h4[k];
+#pragma unroll
+                for (int ll = 0; ll < 4; ll++) {
+                    if (l == ll) {
+                        acc[ll * 12 + k] += e0;
+                        acc[ll * 12 + 4 + k] += e1;
+                        acc[ll * 12 + 8 + k] += e2;
                     }
                 }
             }
@@ -434,8 +642,8 @@ __global__ __launch_bounds__(kSoftFaceBlock) void soft_bwd_face_kernel(SoftArgs 
     // fixed-order tree over the lanes of each entry
     for (int o = kSoftFaceBlock / 2; o > 0; o >>= 1) {
         for (int idx = tid; idx < kSoftGrad * o; idx += kSoftFaceBlock) {
-            const int e = idx / o, j = idx % o;
-            s_acc[e][j] += s_acc[e][j + o];
+            const int e = idx / o, jj = idx % o;
+            s_acc[e][jj] += s_acc[e][jj + o];
         }
         __syncthreads();
     }
@@ -487,17 +695,44 @@ __device__ inline double dot34(const double* G, const double* A, const double* a
 // M_l = T_r^c(alpha, beta, gamma, x, y, z) T_l(q(qhat)):
 // T_r^c = [Ry(gamma) Rx(alpha) Rz(beta) | (x, y, z)], T_0 = I, T_1 = Rx(q1),
 // T_2,3 = [Rx(q1) Ry(q2 +- q3/2) | Rx(q1) (0, 0, d)], q = lb + (ub - lb)/2 (1 - cos(pi (qhat - lb)/(ub - lb))).
-__global__ __launch_bounds__(128) void soft_param_kernel(SoftArgs a, ParamArgs p) {
+constexpr int kParamThreads = 128;
+
+// Sums of the per-workgroup partials of dL/dM_l of one candidate in a fixed
+// order: workgroup g takes the g-th of kSoftReduceGroups contiguous slices of
+// each arm's rows; in it, wave w adds rows w, w + 4, ... with lane e on entry e
+// (coalesced 48-float rows), then the waves' sums are added in order.
+__global__ __launch_bounds__(256) void soft_reduce_kernel(SoftArgs a) {
+    __shared__ double s_w[4][kMaxArms * kSoftGrad];
+    const int g = blockIdx.x, b = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n_arms = a.ms.n_meshes;
+    for (int arm = 0; arm < n_arms; arm++) {
+        const int r0 = arm == 0 ? 0 : a.block_offset[1];
+        const int r1 = (arm == 0 && n_arms > 1) ? a.block_offset[1] : a.n_blocks;
+        const int k0 = r0 + int((long long)(r1 - r0) * g / kSoftReduceGroups);
+        const int k1 = r0 + int((long long)(r1 - r0) * (g + 1) / kSoftReduceGroups);
+        double s = 0.0;
+        if (lane < kSoftGrad) {
+            const float* row = a.part + size_t(b) * a.n_blocks * kSoftGrad + lane;
+#pragma unroll 4
+            for (int k = k0 + w; k < k1; k += 4) s += double(row[size_t(k) * kSoftGrad]);
+            s_w[w][arm * kSoftGrad + lane] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < n_arms * kSoftGrad)
+        a.gsum[(size_t(b) * kSoftReduceGroups + g) * kMaxArms * kSoftGrad + threadIdx.x] =
+            ((s_w[0][threadIdx.x] + s_w[1][threadIdx.x]) + s_w[2][threadIdx.x]) + s_w[3][threadIdx.x];
+}
+
+// Jacobian of the link transforms applied to the summed dL/dM_l.
+__global__ __launch_bounds__(kParamThreads) void soft_param_kernel(SoftArgs a, ParamArgs p) {
     __shared__ double s_g[kMaxArms][kSoftGrad];
     const int b = blockIdx.x, tid = threadIdx.x;
     const int n_arms = a.ms.n_meshes;
     if (tid < n_arms * kSoftGrad) {
-        const int arm = tid / kSoftGrad, e = tid % kSoftGrad;
-        const int k0 = arm == 0 ? 0 : a.block_offset[1];
-        const int k1 = (arm == 0 && n_arms > 1) ? a.block_offset[1] : a.n_blocks;
-        double s = 0.0;
-        for (int k = k0; k < k1; k++) s += double(a.part[(size_t(b) * a.n_blocks + k) * kSoftGrad + e]);
-        s_g[arm][e] = s;
+        double v = 0.0;
+        for (int g = 0; g < kSoftReduceGroups; g++) v += a.gsum[(size_t(b) * kSoftReduceGroups + g) * kMaxArms * kSoftGrad + tid];
+        s_g[tid / kSoftGrad][tid % kSoftGrad] = v;
     }
     __syncthreads();
     if (tid >= n_arms) return;
@@ -604,8 +839,10 @@ tk_status make_soft_shape(int32_t batch, const tk_mesh* meshes, int32_t n_meshes
     a->tiles_y = L->tiles_y;
     a->n_tiles = L->n_tiles;
     a->n_blocks = L->n_blocks;
+    a->chunk_cap = L->chunk_cap;
+    a->fwd_chunk = L->fwd_chunk;
     a->block_offset[0] = 0;
-    a->block_offset[1] = (fpa[0] + kSoftFaceBlock - 1) / kSoftFaceBlock;
+    a->block_offset[1] = (fpa[0] + kSoftFacesPerBlock - 1) / kSoftFacesPerBlock;
     return TK_OK;
 }
 
@@ -622,12 +859,19 @@ tk_status make_soft_args(int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
     a->verts = reinterpret_cast<float4*>(w + L->verts);
     a->faces = reinterpret_cast<FaceRec*>(w + L->faces);
     a->tile_off = reinterpret_cast<int32_t*>(w + L->tile_off);
+    a->tile_cnt = reinterpret_cast<int32_t*>(w + L->tile_cnt);
+    a->tile_tot = batch < kSoftWideBin ? reinterpret_cast<int32_t*>(w + L->tile_tot) : nullptr;
+    a->chunks = reinterpret_cast<int2*>(w + L->chunks);
+    a->chunk_n = reinterpret_cast<int32_t*>(w + L->chunk_n);
+    a->facc = reinterpret_cast<long long*>(w + L->facc);
+    a->done = reinterpret_cast<int32_t*>(w + L->done);
     a->lists = reinterpret_cast<int32_t*>(w + L->lists);
     a->big = reinterpret_cast<int32_t*>(w + L->big);
     a->big_n = reinterpret_cast<int32_t*>(w + L->big_n);
     a->G = reinterpret_cast<float*>(w + L->G);
     a->tloss = reinterpret_cast<double*>(w + L->tloss);
     a->part = reinterpret_cast<float*>(w + L->part);
+    a->gsum = reinterpret_cast<double*>(w + L->gsum);
     return TK_OK;
 }
 
@@ -658,10 +902,21 @@ tk_status tk_soft_forward(const float* d_link_xf, int32_t batch, const tk_mesh* 
     hipStream_t st = reinterpret_cast<hipStream_t>(s);
     hipLaunchKernelGGL(soft_vert_kernel, dim3((a.ms.total_vertices + 255) / 256, batch), dim3(256), 0, st, d_link_xf,
                        a);
-    if (a.total_faces > 0)
-        hipLaunchKernelGGL(soft_face_kernel, dim3((a.total_faces + 255) / 256, batch), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(soft_bin_kernel, dim3(batch), dim3(kSoftBinThreads), 0, st, a);
-    hipLaunchKernelGGL(soft_fwd_kernel, dim3(a.n_tiles, batch), dim3(64), 0, st, a, d_target, d_S);
+    const int face_blocks = (a.total_faces + 255) / 256;
+    hipLaunchKernelGGL(soft_face_kernel, dim3(face_blocks > 0 ? face_blocks : 1, batch), dim3(256), 0, st, a);
+    if (batch >= kSoftWideBin) {
+        hipLaunchKernelGGL(soft_bin_kernel, dim3(batch), dim3(kSoftBinThreads), 0, st, a);
+        hipLaunchKernelGGL(soft_plan_kernel, dim3(batch), dim3(kSoftBinThreads), 0, st, a, 0);
+    } else {
+        hipLaunchKernelGGL(soft_bin_count_kernel, dim3(kSoftBinGroups, batch), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(soft_plan_kernel, dim3(batch), dim3(kSoftBinThreads), 0, st, a, 1);
+        hipLaunchKernelGGL(soft_bin_fill_kernel, dim3(kSoftBinGroups, batch), dim3(256), 0, st, a);
+    }
+    // a wave per work item (an item per tile, and the extra items of split
+    // tiles), looping when a candidate has more items than the grid
+    const int fwd_groups = std::min(a.chunk_cap, 2 * a.n_tiles);
+    hipLaunchKernelGGL(soft_fwd_kernel, dim3(fwd_groups, batch), dim3(64), 0, st, a, a.faces, a.lists, a.tile_off,
+                       a.chunks, a.big, d_target, d_S);
     hipLaunchKernelGGL(soft_loss_kernel, dim3(batch), dim3(256), 0, st, a, d_loss);
     return check_launch("tk_soft_forward");
 }
@@ -692,7 +947,8 @@ tk_status tk_soft_backward(const float* d_X, int32_t batch, const tk_chain* chai
     hipStream_t st = reinterpret_cast<hipStream_t>(s);
     if (a.n_blocks > 0)
         hipLaunchKernelGGL(soft_bwd_face_kernel, dim3(a.n_blocks, batch), dim3(kSoftFaceBlock), 0, st, a);
-    hipLaunchKernelGGL(soft_param_kernel, dim3(batch), dim3(128), 0, st, a, p);
+    hipLaunchKernelGGL(soft_reduce_kernel, dim3(kSoftReduceGroups, batch), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(soft_param_kernel, dim3(batch), dim3(kParamThreads), 0, st, a, p);
     return check_launch("tk_soft_backward");
 }
 

@@ -234,15 +234,19 @@ def mesh_plane_order(vertices, vertex_link, triangles) -> np.ndarray:
 class DeviceMesh:
     """Mesh arrays resident on the device plus the tk_mesh view of them.
 
-    With chunk_order (the default) the triangles are stored grouped by plane
-    (tk_mesh_plane_order) and then in the claim order of tk_mesh_chunk_order:
-    the same silhouette, with mostly one-orientation chunks claimed costly
-    ones first.  closed is what tk_mesh_closed reports for the triangles."""
+    By default the triangles are stored grouped by plane (tk_mesh_plane_order)
+    and then in the claim order of tk_mesh_chunk_order: the same silhouette,
+    with mostly one-orientation chunks claimed costly ones first.  The soft
+    silhouette's face-major passes prefer neighbouring faces in neighbouring
+    lanes (plane_order=False keeps the list order inside the 64-triangle
+    blocks).  closed is what tk_mesh_closed reports for the triangles."""
 
-    def __init__(self, mesh, device="cuda", chunk_order=True):
+    def __init__(self, mesh, device="cuda", chunk_order=True, plane_order=True):
         tris = np.ascontiguousarray(mesh.triangles, np.int32)
+        if plane_order and tris.shape[0]:
+            tris = mesh_plane_order(mesh.vertices, mesh.vertex_link, tris)
         if chunk_order and tris.shape[0]:
-            tris = mesh_chunk_order(mesh.vertices, mesh_plane_order(mesh.vertices, mesh.vertex_link, tris))
+            tris = mesh_chunk_order(mesh.vertices, tris)
         self.closed = mesh_closed(tris, mesh.n_vertices)
         self.vertices = torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float32), device=device)
         self.triangles = torch.as_tensor(tris, device=device)

@@ -34,6 +34,9 @@ class Problem:
         assert len(meshes) == len(chains)
         self.device = torch.device(device)
         self.meshes = [tk.DeviceMesh(m, self.device) for m in meshes]
+        # the soft silhouette's copy: list order inside the claim-order blocks
+        # (its face-major passes want neighbouring faces in neighbouring lanes)
+        self.soft_meshes = [tk.DeviceMesh(m, self.device, plane_order=False) for m in meshes]
         self.chains = list(chains)
         self.cam = cam
         self.n_arms = len(meshes)
@@ -156,7 +159,7 @@ class Generation:
         p = self.p
         if getattr(self, "_soft", None) is None or self._soft[0] != sigma:
             d = p.device
-            self._soft = (sigma, tk.soft_workspace(1, p.meshes, p.cam, d),
+            self._soft = (sigma, tk.soft_workspace(1, p.soft_meshes, p.cam, d),
                           torch.empty(1, self.n, dtype=torch.float32, device=d),
                           torch.empty(1, p.n_arms, 4, 12, dtype=torch.float32, device=d),
                           torch.empty(1, dtype=torch.float64, device=d),
@@ -167,8 +170,8 @@ class Generation:
         for _ in range(steps):
             tk.cmaes_mean_candidate(self.state, self.n, self.lam, X1)
             tk.fk_transform(X1, 1, p.n_arms, p.chains, xf1)
-            tk.soft_forward(xf1, 1, p.meshes, p.cam, sigma, p.target, loss1, ws)
-            tk.soft_backward(X1, 1, p.chains, p.meshes, p.cam, sigma, g1, ws)
+            tk.soft_forward(xf1, 1, p.soft_meshes, p.cam, sigma, p.target, loss1, ws)
+            tk.soft_backward(X1, 1, p.chains, p.soft_meshes, p.cam, sigma, g1, ws)
             tk.cmaes_adam(self.state, self.n, self.lam, g1, adam, lr)
         return loss1
 
@@ -186,10 +189,16 @@ class Generation:
                             p.kp_ref if self.use_kp else None, p.n_arms, self.lambda_kp, self.tau)
         tk.cmaes_update(self.state, self.n, self.lam, self.loss)
 
-    def capture(self, fused=True):
+    def capture(self, fused=True, refine=None):
         """Record one generation (ask_eval_tell(), or step() with fused=False)
-        into a HIP graph, replayed by replay()."""
-        run = self.ask_eval_tell if fused else self.step
+        into a HIP graph, replayed by replay(); with refine = (steps, lr,
+        sigma) the graph also holds the refinement of the mean that follows it."""
+        gen = self.ask_eval_tell if fused else self.step
+
+        def run():
+            gen()
+            if refine is not None:
+                self.refine(*refine)
         s = torch.cuda.Stream(device=self.p.device)
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):

@@ -197,3 +197,80 @@ def test_soft_argument_errors():
     with pytest.raises(tk.TkError) as e:
         tk.soft_forward(xf, 1, prob.meshes, big, 1.0, prob.target, loss, ws)
     assert e.value.status == tk.TK_ERR_UNSUPPORTED
+
+
+def test_soft_full_size_candidates_match_banded_oracle():
+    """The differentiable form at its full size: the 49744-triangle instrument
+    at 640x480, sigma = 1 px, six candidates of a 256-candidate launch (the
+    batch the bench runs), against the oracle's face-major form of the same
+    definitions: S per pixel, the loss and dL/dtheta."""
+    dev = torch.device("cuda:0")
+    wl = scenes.workload("soft640")
+    mesh, cam, ch = wl["mesh"], wl["cam"], scenes.chain()
+    rng = scenes.rng_for(wl["index"], scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    prob, target = _problem([mesh], [ch], cam, truth, dev)
+    theta = (truth[None] + scenes.DEFAULT_SCALE[None] * rng.normal(size=(wl["lam"], 9))).astype(np.float32)
+    loss, S, g = _run(prob, theta, wl["sigma"], dev)
+    # FP32 projected corners are off by up to about 4 ulp of the image
+    # coordinates (6.1e-5 px near 640 px, four times the 160 px cases above),
+    # and S moves by at most 1 / (4 sigma) per pixel of distance
+    s_atol = 4.0 * float(np.spacing(np.float32(max(cam.width, cam.height)))) / (4.0 * wl["sigma"])
+    for b in (0, 1, 77, 128, 200, wl["lam"] - 1):
+        th64 = theta[b].astype(np.float64)
+        print(f"soft640 candidate {b}", flush=True)
+        L, So, go = oracle.soft(th64, [ch], [mesh], cam, wl["sigma"], target, want_S=True, want_grad=True,
+                                banded=True)
+        assert np.max(np.abs(S[b] - So)) <= s_atol, (b, np.max(np.abs(S[b] - So)), s_atol)
+        assert abs(loss[b] - L) <= LOSS_RTOL * max(L, 1.0), (b, loss[b], L)
+        assert np.linalg.norm(go) > 0
+        assert np.linalg.norm(g[b] - go) <= GRAD_RTOL * np.linalg.norm(go), (b, np.linalg.norm(g[b] - go) /
+                                                                              np.linalg.norm(go))
+
+
+def test_soft_binning_forms_agree_bitwise():
+    """Batches below 64 candidates bin across workgroups (LDS histograms and
+    per-workgroup fill cursors), larger ones with one workgroup per candidate;
+    the order of faces inside a tile list may differ, the forward sums are
+    integers and the backward is face-major, so loss and gradient agree bit
+    for bit."""
+    dev = torch.device("cuda:0")
+    wl = scenes.workload("track640")
+    cam, mesh, ch = wl["cam"], wl["mesh"], scenes.chain()
+    rng = scenes.rng_for(5, scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    prob, _ = _problem([mesh], [ch], cam, truth, dev)
+    theta = (truth[None] + scenes.DEFAULT_SCALE[None] * rng.normal(size=(64, 9))).astype(np.float32)
+    l64, _, g64 = _run(prob, theta, 1.0, dev, want_S=False)
+    for k0, k1 in [(0, 1), (3, 11), (20, 63)]:
+        l, _, g = _run(prob, theta[k0:k1], 1.0, dev, want_S=False)
+        np.testing.assert_array_equal(l, l64[k0:k1])
+        np.testing.assert_array_equal(g, g64[k0:k1])
+
+
+def test_generation_with_refinement_replays_as_a_graph():
+    """A generation followed by 5 Adam steps on the mean, recorded once into a
+    HIP graph and replayed, leaves the same state bit for bit as running it
+    eagerly on a twin, replay after replay, with eager work in between."""
+    dev = torch.device("cuda:0")
+    wl = scenes.workload("small")
+    cam, mesh, ch = wl["cam"], wl["mesh"], scenes.chain()
+    rng = scenes.rng_for(8, scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    prob, _ = _problem([mesh], [ch], cam, truth, dev)
+    start = truth + 0.5 * scenes.DEFAULT_SCALE * rng.normal(size=9)
+    gens = [tracker.Generation(prob, 16) for _ in range(2)]
+    for g in gens:
+        g.init(np.zeros(9), 1.0, start, scenes.DEFAULT_SCALE, 21)
+    g_eager, g_graph = gens
+    # capture() runs one warm-up generation + refinement before recording
+    g_graph.capture(refine=(5, 0.1, 1.0))
+    g_eager.ask_eval_tell()
+    g_eager.refine(5, 0.1, 1.0)
+    for _ in range(4):
+        g_graph.replay()
+        g_eager.ask_eval_tell()
+        loss = g_eager.refine(5, 0.1, 1.0)
+        torch.cuda.synchronize()
+        assert torch.equal(g_graph.state, g_eager.state)
+        assert torch.equal(g_graph._soft[4], loss)

@@ -142,3 +142,79 @@ def test_gradient_matches_central_differences_two_arms():
     target = oracle.render(truth, chains, meshes, cam)
     th = truth + np.tile(scenes.DEFAULT_SCALE, 2) * rng.normal(size=18) * 0.5
     _fd_check(th, chains, meshes, cam, target, np.tile(scenes.DEFAULT_SCALE, 2))
+
+
+# ---------------------------------------------------------------- face-major form
+
+def _banded_vs_literal(theta, chains, meshes, cam, sigma, target):
+    L1, S1, g1 = oracle.soft(theta, chains, meshes, cam, sigma, target, want_S=True, want_grad=True)
+    L2, S2, g2 = oracle.soft(theta, chains, meshes, cam, sigma, target, want_S=True, want_grad=True, banded=True)
+    return L1, S1, g1, L2, S2, g2
+
+
+@pytest.mark.parametrize("sigma", [1.0, 0.7])
+def test_banded_form_equals_the_literal_one(sigma):
+    """Face-major over each face's 10-sigma box: S and the loss are the same
+    numbers, the gradient the same to rounding (one and two arms)."""
+    rng = np.random.default_rng(21)
+    cam = scenes.camera(96, 72, f=110.0)
+    meshes = [scenes.instrument_mesh(12, 4, 1, 1), scenes.instrument_mesh(10, 3, 1, 1, jaw_scale=1.3)]
+    chains = [scenes.chain(), scenes.chain(1.3)]
+    for n_arms in (1, 2):
+        for _ in range(3):
+            th = np.concatenate([scenes.true_pose(rng, cam) for _ in range(n_arms)])
+            target = oracle.render(th + 0.3 * np.tile(scenes.DEFAULT_SCALE, n_arms), chains[:n_arms],
+                                   meshes[:n_arms], cam)
+            L1, S1, g1, L2, S2, g2 = _banded_vs_literal(th, chains[:n_arms], meshes[:n_arms], cam, sigma, target)
+            assert L1 == L2 and np.array_equal(S1, S2)
+            assert L1 > 0 and np.linalg.norm(g1) > 0
+            assert np.linalg.norm(g2 - g1) <= 1e-12 * np.linalg.norm(g1)
+
+
+def test_banded_form_with_factors_exactly_zero():
+    """Deep inside large faces the logistic is 1 in FP64 and the factor 1 - prob
+    is exactly zero: the product over the other faces must still follow the
+    definition (zero whenever another factor is zero)."""
+    cam, theta, mesh = plane_setup([[(4, 4), (60, 6), (8, 58)], [(10, 12), (58, 40), (30, 60)],
+                                    [(2, 30), (40, 2), (50, 50)]])
+    target = np.zeros(((cam.height + 7) // 8, (cam.width + 7) // 8), np.uint64)
+    target[2:5, 2:5] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    for sigma in (0.25, 0.5):
+        L1, S1, g1, L2, S2, g2 = _banded_vs_literal(theta, [scenes.chain()], [mesh], cam, sigma, target)
+        assert (S1 == 1.0).sum() > 100            # factors exactly zero occur
+        assert L1 == L2 and np.array_equal(S1, S2)
+        assert np.linalg.norm(g2 - g1) <= 1e-12 * max(np.linalg.norm(g1), 1e-300)
+
+
+def _fd_job(args):
+    th, k, h, scale = args
+    wl = scenes.workload("soft640")
+    mesh, cam, ch = wl["mesh"], wl["cam"], scenes.chain()
+    truth = scenes.true_pose(scenes.rng_for(wl["index"], scenes.SUB_POSE), cam)
+    target = oracle.render(truth, [ch], [mesh], cam)
+    e = np.zeros(9)
+    e[k] = h * scale[k]
+    lp, _, _ = oracle.soft(th + e, [ch], [mesh], cam, 1.0, target, banded=True)
+    lm, _, _ = oracle.soft(th - e, [ch], [mesh], cam, 1.0, target, banded=True)
+    return (lp - lm) / (2.0 * h * scale[k])
+
+
+@pytest.mark.slow
+def test_banded_gradient_matches_central_differences_at_full_size():
+    """The 49744-triangle instrument at 640x480, sigma = 1 px: the analytic
+    gradient of 16 seeded candidates equals central differences (h = 1e-4 in
+    the normalised coordinates) to 1e-3 relative, norm-wise."""
+    import multiprocessing as mp
+    wl = scenes.workload("soft640")
+    mesh, cam, ch = wl["mesh"], wl["cam"], scenes.chain()
+    rng = scenes.rng_for(wl["index"], scenes.SUB_POSE)
+    truth = scenes.true_pose(rng, cam)
+    target = oracle.render(truth, [ch], [mesh], cam)
+    cands = [truth + scenes.DEFAULT_SCALE * rng.normal(size=9) for _ in range(16)]
+    jobs = [(th, k, 1e-4, scenes.DEFAULT_SCALE) for th in cands for k in range(9)]
+    with mp.get_context("fork").Pool(min(8, mp.cpu_count())) as pool:
+        fd = np.array(pool.map(_fd_job, jobs)).reshape(16, 9)
+    for c, th in enumerate(cands):
+        _, _, g = oracle.soft(th, [ch], [mesh], cam, 1.0, target, want_grad=True, banded=True)
+        assert np.linalg.norm(g) > 0
+        assert np.linalg.norm(fd[c] - g) <= 1e-3 * np.linalg.norm(g), c
