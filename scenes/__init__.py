@@ -511,9 +511,11 @@ def workload(name: str) -> dict:
                     lam=512, gens=30, frames=1, index=2, n_blocks=2)
     if name == "synth700":       # the paper's synthetic-set protocol: 700x493, N = 70, 3 iterations per
         # frame with raised learning rates (c_mu x2, sigma0 0.5: a reading, the paper gives no values),
-        # Hermite/OU trajectory, dilation / erosion / edge-blob masks, two-tip keypoint term
-        return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(700, 493), lam=70, gens=3, frames=200,
-                    index=5, filter=FILTER_TRACK, sigma0=0.5, c_m_scale=1.0, c_mu_scale=2.0)
+        # 1000-frame Hermite/OU trajectory, dilation / erosion / edge-blob masks, the render loss (MSE +
+        # appearance) plus the two-tip keypoint term in pixels (weights: a reading, the paper gives none)
+        return dict(mesh=instrument_mesh(64, 150, 6, 4), cam=camera(700, 493), lam=70, gens=3, frames=1000,
+                    index=5, filter=FILTER_TRACK, sigma0=0.5, c_m_scale=1.0, c_mu_scale=2.0,
+                    lambda_app=1.0, lambda_kp=10.0, tau=2.0)
     if name == "soft640":        # differentiable form: 49744 tris, 640x480, 256 candidates, sigma = 1 px
         return dict(mesh=instrument_mesh(100, 240, 8, 6), cam=camera(640, 480), lam=256, gens=30, frames=1,
                     index=4, sigma=1.0)
