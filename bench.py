@@ -29,20 +29,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-# HBM bytes per launch of the dominant kernel from the two hardware-counter
-# passes (FETCH_SIZE, WRITE_SIZE) scaled by a copy kernel of known size, and the
-# sha256 of the kernel sources they were taken on; the figure is reported only
-# while the sources are unchanged.
-RASTER_TRAFFIC = {"bytes_per_launch": 44879892.7,
-                  # SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x 4 waves per SIMD, same sources
-                  "valu_busy": 0.972,
-                  # LDS bytes and instructions per launch (SQ LDS counters), same sources
-                  "lds_bytes": None, "lds_insts": None,
+# Counter figures of the dominant kernel from the committed rocprofv3 runs
+# (profiles/raster_kernel_track640.md), with the sha256 of the kernel sources
+# they were taken on; they are reported only while the sources are unchanged.
+#   bytes_per_launch: HBM bytes, FETCH_SIZE and WRITE_SIZE (two passes) scaled
+#     by what the same counters read for a copy of known size;
+#   valu_busy: SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x 4 waves per SIMD;
+#   lds_equiv_bytes: SQ_LDS_IDX_ACTIVE per launch times the bytes the LDS
+#     microbenchmark (tk_bench_lds) moves per unit of the same counter, i.e.
+#     the LDS occupancy expressed as bytes at the microbenchmark's rate;
+#   lds_insts, lds_bank_conflict_frac: SQ_INSTS_LDS per launch and
+#     SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.
+RASTER_TRAFFIC = {"bytes_per_launch": 44462505.1, "read_bytes": 23711544.3, "write_bytes": 20750960.8,
+                  "valu_busy": 0.904,
+                  "lds_equiv_bytes": 605250199.0, "lds_insts": 751416.0, "lds_bank_conflict_frac": 0.235,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
                               "paper_2603_11404_amd/csrc/sample_device.h"),
-                  "sha256": "4891a578d9ea4e498de286fdf858a85f7eaa21830f1caa38fde2dd600a47b754"}
+                  "sha256": "6882bdc5319c4eb65b3afd83b6e59e8f9f825a36186188ed70a6c788ddfab29c"}
 
 
 def raster_profile_valid():
@@ -70,6 +75,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall time budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph and plain-launch comparison loops")
+    ap.add_argument("--legs", default=None,
+                    help="comma-separated extra legs to run (small320, bimanual960, batch64, soft640, synth700); "
+                         "default: all of them unless --no-extras")
     ap.add_argument("--plain-gens", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain copy kernel over 256 MiB (reference for HBM byte counters)")
@@ -341,6 +349,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_ops / 1e12, "unit": "Tops/s",
                      "frac": achieved / peak_ops, "traffic": raster_traffic(),
                      "traffic_unit": "B per launch",
+                     "hbm_frac": (raster_traffic() / (kernel_us * 1e-6) / (peaks["hbm_GBps"] * 1e9)
+                                  if raster_traffic() is not None else None),
                      "valu_busy": RASTER_TRAFFIC["valu_busy"] if raster_profile_valid() else None,
                      "lds": raster_lds(kernel_us, peaks),
                      "constants_from_profiles": "traffic, valu_busy and lds counts are taken from the committed "
@@ -392,11 +402,15 @@ def main():
         out["graph_ms_per_step"] = graph_ms
         out["plain_ms_per_step"] = plain_ms
         out["batched_vs_plain"] = plain_ms / min(graph_ms, ms_per_step)
-        out["small320"] = small_leg(dev, with_cpu=not args.no_cpu_baseline)
-        out["bimanual960"] = bimanual_leg(dev)
-        out["batch64"] = batch_leg(dev)
-        out["soft640"] = soft_leg(dev)
-        out["synth700"] = synth700_leg(dev)
+    legs = {"small320": lambda: small_leg(dev, with_cpu=not args.no_cpu_baseline),
+            "bimanual960": lambda: bimanual_leg(dev), "batch64": lambda: batch_leg(dev),
+            "soft640": lambda: soft_leg(dev), "synth700": lambda: synth700_leg(dev)}
+    chosen = [] if args.no_extras and args.legs is None else \
+        (list(legs) if args.legs is None else [x for x in args.legs.split(",") if x])
+    for name in chosen:
+        if name not in legs:
+            raise SystemExit(f"unknown leg {name!r}; choose from {', '.join(legs)}")
+        out[name] = legs[name]()
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if not args.no_cpu_baseline:
@@ -447,15 +461,17 @@ def measure_peaks(dev):
 
 
 def raster_lds(kernel_us, peaks):
-    """LDS side of the raster kernel's roofline from the committed counter run
-    (LDS instructions per launch, with the bytes each moves), against the
-    measured LDS roof; None while the kernel sources differ from the profiled ones."""
-    if not raster_profile_valid() or RASTER_TRAFFIC.get("lds_bytes") is None:
+    """LDS side of the raster kernel's roofline from the committed counter run:
+    the LDS occupancy per launch (SQ_LDS_IDX_ACTIVE) expressed in bytes at the
+    rate of the LDS microbenchmark, over the kernel time, against the measured
+    LDS roof; None while the kernel sources differ from the profiled ones."""
+    if not raster_profile_valid() or RASTER_TRAFFIC.get("lds_equiv_bytes") is None:
         return None
-    bps = RASTER_TRAFFIC["lds_bytes"] / (kernel_us * 1e-6)
-    return {"bytes_per_launch": RASTER_TRAFFIC["lds_bytes"], "achieved_TBps": bps / 1e12,
+    bps = RASTER_TRAFFIC["lds_equiv_bytes"] / (kernel_us * 1e-6)
+    return {"equiv_bytes_per_launch": RASTER_TRAFFIC["lds_equiv_bytes"], "achieved_TBps": bps / 1e12,
             "peak_TBps": peaks["lds_TBps"], "frac": bps / (peaks["lds_TBps"] * 1e12),
-            "lds_instructions_per_launch": RASTER_TRAFFIC.get("lds_insts")}
+            "lds_instructions_per_launch": RASTER_TRAFFIC["lds_insts"],
+            "bank_conflict_frac": RASTER_TRAFFIC["lds_bank_conflict_frac"]}
 
 
 def small_leg(dev, with_cpu=True, solves=20):
@@ -650,13 +666,43 @@ def batch_leg(dev, count=64, gens=10):
     b.record()
     torch.cuda.synchronize()
     single_ms = a.elapsed_time(b) / 3
+    # ask-eval alone per resolution class: persistent launch of the class's
+    # problems against launching each of them
+    shapes = scenes.batch_problem_shapes(count)
+    classes = {}
+    for res in scenes.BATCH_RESOLUTIONS:
+        sel = [i for i, sh in enumerate(shapes) if (sh["width"], sh["height"]) == res]
+        if not sel:
+            continue
+        sub = tk.Batch([gens_[i].problem_struct(threads[i]) for i in sel], device=dev)
+        sub.ask_eval_persistent()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(5):
+            sub.ask_eval_persistent()
+        b.record()
+        torch.cuda.synchronize()
+        p_ms = a.elapsed_time(b) / 5
+        a.record()
+        for _ in range(3):
+            for i in sel:
+                g = gens_[i]
+                tk.cmaes_ask_eval(g.state, g.n, g.lam, g.p.chains, g.p.meshes, g.p.cam, g.p.target, g.X, g.xf,
+                                  g.counts, kp=g.kp, ws=g.ws)
+        b.record()
+        torch.cuda.synchronize()
+        s_ms = a.elapsed_time(b) / 3
+        classes[f"{res[0]}x{res[1]}"] = {"problems": len(sel), "persistent_ask_ms": p_ms, "per_problem_ask_ms": s_ms,
+                                         "ratio": s_ms / p_ms}
+    log("batch64 ask-eval per resolution (persistent vs per problem): " +
+        ", ".join(f"{k} {v['persistent_ask_ms']:.2f} vs {v['per_problem_ask_ms']:.2f} ms" for k, v in classes.items()))
     log(f"batch64: {persist_ms:.2f} ms per generation with the persistent launch, {batch_ms:.2f} ms with one "
         f"launch per workgroup size, {single_ms:.2f} ms launching each problem "
         f"({lam_total} candidates, {tri_total / 1e6:.0f} M candidate-triangles)")
     return {"workload": f"{count} problems, 320x240..1280x720, lambda 64..1024, 2k..50k tris, 1% flips",
             "candidates_per_generation": lam_total, "ms_per_generation": persist_ms,
             "candidate_evals_per_s": lam_total / (persist_ms * 1e-3), "per_problem_launches_ms": single_ms,
-            "batched_vs_per_problem": single_ms / persist_ms,
+            "batched_vs_per_problem": single_ms / persist_ms, "ask_eval_by_resolution": classes,
             "grouped_launches_ms": batch_ms, "grouped_vs_per_problem": single_ms / batch_ms,
             "workgroup_sizes": {str(t): threads.count(t) for t in sorted(set(threads))}}
 
