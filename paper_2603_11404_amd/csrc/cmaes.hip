@@ -160,6 +160,7 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
 
 constexpr int kWave64 = 64;
 constexpr int kMaxSweeps = 30;
+static_assert(kMaxSweeps % 2 == 0, "the Jacobi rounds run in pairs");
 
 // Orders this wave's LDS writes before its later LDS reads (single-wave phases).
 __device__ __forceinline__ void wave_sync() {
@@ -205,6 +206,53 @@ __device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq
     return rot;
 }
 
+// The rotations of two pairs at once, each with exactly the arithmetic of
+// pair_rotation, written step by step for both so that the two dependent
+// chains interleave in one wave's instruction stream.
+__device__ __forceinline__ void pair_rotation2(const double app[2], const double aqq[2], const double apq[2],
+                                               double c_out[2], double sn_out[2], bool rot_out[2]) {
+    double d[2], p2[2], q[2], x[2], hx[2], r[2], w[2], y[2], hy[2], t[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        d[k] = aqq[k] - app[k];
+        p2[k] = apq[k] * apq[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        q[k] = 4.0 * p2[k];
+        x[k] = fma(d[k], d[k], 4.0 * p2[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        hx[k] = -0.5 * x[k];
+        r[k] = __builtin_amdgcn_rsq(x[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) r[k] = r[k] * fma(hx[k] * r[k], r[k], 1.5);
+#pragma unroll
+    for (int k = 0; k < 2; k++) w[k] = fma(x[k], r[k], fabs(d[k]));
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        y[k] = fma(w[k], w[k], q[k]);
+        hy[k] = -0.5 * y[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) t[k] = __builtin_amdgcn_rsq(y[k]);
+#pragma unroll
+    for (int k = 0; k < 2; k++) t[k] = t[k] * fma(hy[k] * t[k], t[k], 1.5);
+#pragma unroll
+    for (int k = 0; k < 2; k++) t[k] = t[k] * fma(hy[k] * t[k], t[k], 1.5);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double c = w[k] * t[k];
+        const double sn = (d[k] >= 0.0 ? 2.0 * apq[k] : -2.0 * apq[k]) * t[k];
+        const bool rot = apq[k] != 0.0 && p2[k] > 1e-30 * fabs(app[k] * aqq[k]);
+        c_out[k] = rot ? c : 1.0;
+        sn_out[k] = rot ? sn : 0.0;
+        rot_out[k] = rot;
+    }
+}
+
 // Quotient of small non-negative integers (a < 2^13, 1 <= b <= 2^10): an FP32
 // reciprocal estimate within one of the quotient, then an exact integer
 // correction each way (checked exhaustively over that range).
@@ -225,6 +273,122 @@ __device__ __forceinline__ int tri_row(int e, int m) {
     i += (i + 1 < m && start(i + 1) <= e) ? 1 : 0;
     i -= (i > 0 && start(i) > e) ? 1 : 0;
     return i;
+}
+
+// ---- ranking by (loss, index): a 64-element bitonic sort in the registers of
+// one wave, then every element counts the elements ordered before it in the
+// other waves' sorted lists by binary search.  The order is a total order (no
+// two candidates share an index), so the result is the unique rank.
+
+// The ranking compares 64-bit integers: a loss maps to an integer whose
+// unsigned order is the order of the doubles (sign bit flipped for
+// non-negative values, every bit for negative ones), after -0 is made +0 and
+// NaN +inf, so that equal losses give equal integers.
+__device__ __forceinline__ uint64_t order_key(double v) {
+    v = (v != v) ? INFINITY : v + 0.0;
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    return b ^ ((b >> 63) ? ~0ull : (1ull << 63));
+}
+
+// (key, index) record of a sorted list in LDS, read as one 16-byte word.
+struct __align__(16) RankRec {
+    uint64_t key;
+    int32_t idx, pad;
+};
+
+// (ka, ia) ordered before (kb, ib), evaluated without branches.
+__device__ __forceinline__ bool ordered_before(uint64_t ka, int ia, uint64_t kb, int ib) {
+    return (ka < kb) | ((ka == kb) & (ia < ib));
+}
+
+// The value that lane (lane ^ S) holds, for S = 1 ... 32, without LDS: DPP
+// quad permutations for 1 and 2, row rotations for 4 and 8 (rotating a
+// 16-lane row by 8 is the exchange with lane ^ 8; by 4 and by 12 it reaches
+// lane ^ 4 for lanes with bit 2 set and clear), the gfx950 16- and 32-lane
+// swaps for 16 and 32.
+template <int S>
+__device__ __forceinline__ int lane_xor(int v, int lane) {
+    if constexpr (S == 1) {
+        return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (S == 2) {
+        return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (S == 4) {
+        const int a = __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false);
+        const int b = __builtin_amdgcn_mov_dpp(v, 0x12C, 0xF, 0xF, false);
+        return (lane & 4) ? a : b;
+    } else if constexpr (S == 8) {
+        return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (S == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? int(r[0]) : int(r[1]);
+    } else {
+        static_assert(S == 32, "lane exchange distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? int(r[0]) : int(r[1]);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ double lane_xor_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = uint32_t(lane_xor<S>(int(uint32_t(b)), lane));
+    const uint32_t hi = uint32_t(lane_xor<S>(int(uint32_t(uint64_t(b) >> 32)), lane));
+    return __longlong_as_double(static_cast<long long>((uint64_t(hi) << 32) | lo));
+}
+
+// Maximum over the wave (of values that are not NaN).
+__device__ __forceinline__ double wave_max_f64(double v, int lane) {
+    v = fmax(v, lane_xor_f64<32>(v, lane));
+    v = fmax(v, lane_xor_f64<16>(v, lane));
+    v = fmax(v, lane_xor_f64<8>(v, lane));
+    v = fmax(v, lane_xor_f64<4>(v, lane));
+    v = fmax(v, lane_xor_f64<2>(v, lane));
+    return fmax(v, lane_xor_f64<1>(v, lane));
+}
+
+// One compare-exchange stage of the bitonic network: lanes lane and
+// lane ^ STRIDE compare their (key, index); within blocks of SIZE lanes that
+// sort ascending (bit SIZE of the lane clear) the lower lane keeps the first
+// of the two, in descending blocks the second.
+template <int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_stage(uint64_t& key, int& idx, int lane) {
+    const uint32_t plo = uint32_t(lane_xor<STRIDE>(int(uint32_t(key)), lane));
+    const uint32_t phi = uint32_t(lane_xor<STRIDE>(int(uint32_t(key >> 32)), lane));
+    const uint64_t pk = (uint64_t(phi) << 32) | plo;
+    const int pi = lane_xor<STRIDE>(idx, lane);
+    const bool flip = ((lane & STRIDE) != 0) != ((lane & SIZE) != 0);
+    const bool keep = ordered_before(key, idx, pk, pi) != flip;
+    key = keep ? key : pk;
+    idx = keep ? idx : pi;
+}
+
+template <int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_merge(uint64_t& key, int& idx, int lane) {
+    bitonic_stage<SIZE, STRIDE>(key, idx, lane);
+    if constexpr (STRIDE > 1) bitonic_merge<SIZE, STRIDE / 2>(key, idx, lane);
+}
+
+// Sorts the wave's 64 (key, index) pairs ascending: lane l ends with the l-th.
+template <int SIZE = 64>
+__device__ __forceinline__ void wave_sort64(uint64_t& key, int& idx, int lane) {
+    if constexpr (SIZE > 2) wave_sort64<SIZE / 2>(key, idx, lane);
+    bitonic_merge<SIZE, SIZE / 2>(key, idx, lane);
+}
+
+// Number of records of each of four sorted 64-record lists ordered before
+// (key, idx): binary lifting over the answers 0 ... 64, the four searches
+// advancing together so that their LDS reads overlap.
+__device__ __forceinline__ void count_before64x4(const RankRec* const list[4], uint64_t key, int idx, int b[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) b[q] = 0;
+#pragma unroll
+    for (int s = 64; s >= 1; s >>= 1) {
+        RankRec e[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) e[q] = list[q][min(b[q] + s - 1, 63)];
+#pragma unroll
+        for (int q = 0; q < 4; q++) b[q] += ((b[q] + s <= 64) & ordered_before(e[q].key, e[q].idx, key, idx)) ? s : 0;
+    }
 }
 
 // Dynamic LDS of the update: the elite rows Y[mu][n].
@@ -265,8 +429,7 @@ template <int AS, int VS, int NT, bool COMPOSE, bool ASK>
 __device__ __forceinline__ void update_body(void* blob, const int n, const int lam, const double* __restrict__ loss,
                                             const TellAskArgs& ta) {
     extern __shared__ double s_elite[];  // [mu][n]
-    __shared__ double s_key[kMaxLambda];
-    __shared__ int s_order[kMaxLambda];
+    __shared__ RankRec s_rec[kMaxLambda];   // the waves' sorted lists of 64
     __shared__ double s_w[kMaxLambda / 2];
     // 16-byte aligned: the Jacobi loop reads them as pairs of adjacent entries
     __shared__ __align__(16) double s_A[kMaxN * kMaxN];
@@ -274,7 +437,9 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     __shared__ __align__(16) double s_T[kMaxN * kMaxN];
     __shared__ double s_B[kMaxN * kMaxN];
     __shared__ __align__(16) double s_C[kMaxN * kMaxN];
-    __shared__ double s_part[kParts * kMaxN * (kMaxN + 1) / 2];
+    __shared__ double s_part[kParts * kMaxN];                     // recombination partial sums
+    __shared__ double s_partc[kParts * kMaxN * (kMaxN + 1) / 2];  // rank-mu partial sums
+    __shared__ double s_X[kMaxN * kMaxN];                         // C' B
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
     __shared__ double s_scal[4];
     __shared__ double s_mean[kMaxN];
@@ -289,28 +454,69 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     const int nn = n * n;
     const int ntri = n * (n + 1) / 2;
 
-    // 0. stage losses and state
-    for (int k = tid; k < lam; k += NT) {
-        double v;
-        if (COMPOSE) {
-            v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
-                                 ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
-            if (ta.loss) ta.loss[k] = v;
-        } else {
-            v = loss[k];
+    // 0. stage the state, the losses and the candidates' y.  The state goes
+    //    through registers into LDS after the sort, so that its loads, the
+    //    count loads and the loss composition are in flight together.  Lane
+    //    tid holds candidates k = tid + r NT (r < R), i.e. entry `lane` of
+    //    list l = wave + r NW of 64 candidates, with their keys and rows of Y.
+    //    Keys past lambda are +inf, and their indices order them last.
+    constexpr int R = kMaxLambda / NT;
+    constexpr int NW = NT / kWave64;
+    constexpr int NMAX = AS == 1 ? 9 : kMaxN;   // n of the variant (n <= 9 uses AS = 1)
+    const int lane = tid & (kWave64 - 1), wave = tid / kWave64;
+    uint64_t kr[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int k = tid + r * NT;
+        double v = INFINITY;
+        if (k < lam) {
+            if (COMPOSE) {
+                v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
+                                     ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
+                if (ta.loss) ta.loss[k] = v;
+            } else {
+                v = loss[k];
+            }
         }
-        s_key[k] = (v != v) ? INFINITY : v;
+        kr[r] = order_key(v);
     }
-    for (int r = tid; r < mu; r += NT) s_w[r] = S.weights[r];
-    for (int e = tid; e < nn; e += NT) {
-        s_B[e] = S.B[e];
-        s_C[e] = S.C[e];
-    }
-
+    const double st_w = tid < mu ? S.weights[tid] : 0.0;
+    const double st_b = tid < nn ? S.B[tid] : 0.0;
+    const double st_c = tid < nn ? S.C[tid] : 0.0;
+    double st_pc = 0.0, st_ps = 0.0, st_d = 0.0;
     if (tid < n) {
-        s_pc[tid] = S.p_c[tid];
-        s_ps[tid] = S.p_sigma[tid];
-        s_D[tid] = S.D[tid];
+        st_pc = S.p_c[tid];
+        st_ps = S.p_sigma[tid];
+        st_d = S.D[tid];
+    }
+    double yr[R][NMAX];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int k = tid + r * NT;
+#pragma unroll
+        for (int i = 0; i < NMAX; i++) yr[r][i] = (k < lam && i < n) ? S.Y[size_t(k) * n + i] : 0.0;
+    }
+    // 1a. each wave sorts its lists of 64 (key, index) pairs in registers
+    //     (NaN ranks as +inf) and stores them in LDS
+    int ir[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int l = wave + r * NW;
+        ir[r] = tid + r * NT;
+        if (64 * l < lam) {   // uniform over the wave
+            wave_sort64(kr[r], ir[r], lane);
+            s_rec[64 * l + lane] = RankRec{kr[r], ir[r], 0};
+        }
+    }
+    if (tid < mu) s_w[tid] = st_w;
+    if (tid < nn) {
+        s_B[tid] = st_b;
+        s_C[tid] = st_c;
+    }
+    if (tid < n) {
+        s_pc[tid] = st_pc;
+        s_ps[tid] = st_ps;
+        s_D[tid] = st_d;
     }
     const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
     const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
@@ -321,92 +527,36 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     const double denom_cached = S.hdr->denom;
     __syncthreads();
 
-    // 1. ranking by (loss, index), NaN as +inf: rank = number of keys ordered
-    //    before.  G = 2^lg adjacent lanes share one candidate, each counting a
-    //    strided eighth-block subset of the keys, then a butterfly adds them.
-    int lg = 0;
-    while (lg < 4 && (lam << (lg + 1)) <= NT) lg++;
-    const int G = 1 << lg;
-    if (G == 1) {
-        // 2 lambda > NT: counting would cost lambda^2 tests at one lane per
-        // candidate.  Sort the (key, index) pairs instead with a bitonic
-        // network over P = 2^ceil(log2 lambda) slots; the padding slots hold
-        // +inf keys with indices >= lambda, so they sort last.  Pair t of a
-        // stage with stride s joins slots i = 2 s floor(t / s) + t mod s and
-        // i + s: for s <= 64 a wave's pairs stay within its own 128 slots
-        // (P / 2 <= NT, one pair per thread), so only the wider strides need
-        // the workgroup barrier.
-        int P = 1;
-        while (P < lam) P <<= 1;
-        for (int i = tid; i < P; i += NT) {
-            if (i >= lam) s_key[i] = INFINITY;
-            s_order[i] = i;
-        }
-        __syncthreads();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                if (stride > 64) __syncthreads();
-                const int t = tid;
-                if (t < (P >> 1)) {
-                    const int ls = __builtin_ctz(stride);
-                    const int i = ((t >> ls) << (ls + 1)) + (t & (stride - 1)), j = i + stride;
-                    const double ka = s_key[i], kb = s_key[j];
-                    const int ia = s_order[i], ib = s_order[j];
-                    const bool a_after = ka > kb || (ka == kb && ia > ib);
-                    if (a_after == ((i & size) == 0)) {   // ascending blocks have bit `size` of i clear
-                        s_key[i] = kb;
-                        s_key[j] = ka;
-                        s_order[i] = ib;
-                        s_order[j] = ia;
-                    }
-                }
-                if (stride > 64) __syncthreads(); else wave_sync();
+    // 1b. rank = position in the own sorted list + the number of records
+    //     ordered before it in each other list (four searches side by side).
+    //     The rank goes back to the lane that holds the candidate's row of Y
+    //     (a lane of the same wave), which writes it to the elite rows.
+    const int n_lists = (lam + 63) / 64;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int l = wave + r * NW;
+        if (64 * l < lam) {
+            const int idx = ir[r];
+            const uint64_t key = kr[r];
+            int rank = lane;
+            for (int l0 = 0; l0 < n_lists; l0 += 4) {   // uniform trip count
+                const RankRec* lists[4];
+                int b[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) lists[q] = s_rec + 64 * min(l0 + q, n_lists - 1);
+                count_before64x4(lists, key, idx, b);
+#pragma unroll
+                for (int q = 0; q < 4; q++) rank += (l0 + q >= n_lists || l0 + q == l) ? 0 : b[q];
+            }
+            if (idx < lam) S.order[rank] = idx;
+            // sorted lane -> the lane of candidate idx (idx mod 64): its rank
+            const int my_rank = __builtin_amdgcn_ds_permute(4 * (idx & (kWave64 - 1)), rank);
+            if (my_rank < mu && tid + r * NT < lam) {
+#pragma unroll
+                for (int i = 0; i < NMAX; i++)
+                    if (i < n) s_elite[my_rank * n + i] = yr[r][i];
             }
         }
-        __syncthreads();
-        for (int r = tid; r < lam; r += NT) S.order[r] = s_order[r];
-    }
-    for (int base = 0; base < (G == 1 ? 0 : (lam << lg)); base += NT) {   // same trip count in every lane
-        const int t = base + tid;
-        const int k = t >> lg, part = t & (G - 1);
-        int r = 0;
-        if (k < lam) {
-            const double key = s_key[k];
-            for (int j = part * 8; j + 8 <= lam; j += 8 * G) {
-                double kj[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) kj[u] = s_key[j + u];
-                // a block wholly before k counts ties, one wholly after does not;
-                // only the block holding k needs the index (the condition is
-                // the same across most of a wave, so one side is skipped)
-                if (j + 8 <= k) {
-#pragma unroll
-                    for (int u = 0; u < 8; u++) r += int(kj[u] <= key);
-                } else if (j > k) {
-#pragma unroll
-                    for (int u = 0; u < 8; u++) r += int(kj[u] < key);
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 8; u++) r += int(kj[u] < key) | (int(kj[u] == key) & int(j + u < k));
-                }
-            }
-            if (part == 0) {
-                for (int j = lam & ~7; j < lam; j++) {
-                    const double kj = s_key[j];
-                    r += int(kj < key) | (int(kj == key) & int(j < k));
-                }
-            }
-        }
-        for (int off = 1; off < G; off <<= 1) r += __shfl_xor(r, off);
-        if (k < lam && part == 0) {
-            s_order[r] = k;
-            S.order[r] = k;
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < mu * n; e += NT) {
-        const int r = e / n, i = e % n;
-        s_elite[e] = S.Y[s_order[r] * n + i];
     }
     __syncthreads();
 
@@ -450,6 +600,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     // entry (mirrored) and its V entries at their next positions.
     int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
     int a_w1[kASlots], a_w2[kASlots];
+    int a_dp[kASlots], a_dq[kASlots];      // diagonal blocks of the pairs of positions i and j
     int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
     bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
     if (tid < kWave64) {
@@ -464,6 +615,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             a_rpj[sl] = base + (ie + 1) * m + je;
             a_li[sl] = b * m + i;               // the lanes holding the rotations of positions i and j
             a_lj[sl] = b * m + j;
+            a_dp[sl] = base + ie * m + ie;
+            a_dq[sl] = base + je * m + je;
             a_w1[sl] = base + move(i) * m + move(j);
             a_w2[sl] = base + move(j) * m + move(i);
             a_ok[sl] = tid + kWave64 * sl < n_a;
@@ -479,36 +632,33 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
     }
-    static_assert(NT >= 2 * kWave64, "wave 1 runs the paths while wave 0 sets up the eigendecomposition");
+    static_assert(NT >= 4 * kWave64, "waves 1..3 have their own tasks while wave 0 sets up the eigendecomposition");
     const int t1 = tid - kWave64;              // lane within wave 1
     const bool on_w1 = (tid >> 6) == 1;
-    if (on_w1 && t1 < n) {
-        double acc = 0.0;
-        for (int part = 0; part < kParts; part++) acc += s_part[part * n + t1];
-        s_yw[t1] = acc;
-        s_mean[t1] = S.mean[t1] + c_m * sigma * acc;
-        S.mean[t1] = s_mean[t1];
-    }
-    wave_sync();
-    // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
-    if (on_w1 && t1 < n) {
-        double acc = 0.0;
-        for (int j = 0; j < n; j++) acc += s_B[j * n + t1] * s_yw[j];
-        s_t[t1] = acc / s_D[t1];
-    }
-    wave_sync();
-    if (on_w1 && t1 < n) {
-        double acc = 0.0;
-        for (int j = 0; j < n; j++) acc += s_B[t1 * n + j] * s_t[j];
-        s_ps[t1] = (1.0 - cs) * s_ps[t1] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
-        S.p_sigma[t1] = s_ps[t1];
-    }
-    wave_sync();
+    const int wv = tid >> 6;
     if (on_w1) {
-        // sum of the recombination weights: strided partial sums, then a fixed butterfly
-        double sw = 0.0;
-        for (int r = t1; r < mu; r += kWave64) sw += s_w[r];
-        for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
+        if (t1 < n) {
+            double acc = 0.0;
+            for (int part = 0; part < kParts; part++) acc += s_part[part * n + t1];
+            s_yw[t1] = acc;
+            s_mean[t1] = S.mean[t1] + c_m * sigma * acc;
+            S.mean[t1] = s_mean[t1];
+        }
+        wave_sync();
+        // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
+        if (t1 < n) {
+            double acc = 0.0;
+            for (int j = 0; j < n; j++) acc += s_B[j * n + t1] * s_yw[j];
+            s_t[t1] = acc / s_D[t1];
+        }
+        wave_sync();
+        if (t1 < n) {
+            double acc = 0.0;
+            for (int j = 0; j < n; j++) acc += s_B[t1 * n + j] * s_t[j];
+            s_ps[t1] = (1.0 - cs) * s_ps[t1] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
+            S.p_sigma[t1] = s_ps[t1];
+        }
+        wave_sync();
         if (t1 == 0) {
             double ss = 0.0;
             for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
@@ -518,49 +668,61 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
             s_scal[0] = ps_norm;
             s_scal[1] = h;
-            s_scal[2] = sw;
             *S.h_sigma = h;
             s_scal[3] = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
             *S.sigma = s_scal[3];
             S.hdr->gen = gen + 1;
         }
+        wave_sync();
+        if (t1 < n) {
+            s_pc[t1] = (1.0 - cc) * s_pc[t1] + s_scal[1] * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[t1];
+            S.p_c[t1] = s_pc[t1];
+        }
+    } else if (wv == 2) {
+        // sum of the recombination weights: strided partial sums, then a fixed butterfly
+        const int t2 = tid & (kWave64 - 1);
+        double sw = 0.0;
+        for (int r = t2; r < mu; r += kWave64) sw += s_w[r];
+        for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
+        if (t2 == 0) s_scal[2] = sw;
+    } else if (wv == 3) {
+        // V = B in the positional layout of the eigendecomposition (step 5):
+        // index l of block b starts at position l (the dummy column is zero)
+        for (int e = tid & (kWave64 - 1); e < n_v; e += kWave64) {
+            const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
+            s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
+        }
+    }
+    // 4a. (waves 2 and up, beside the paths) rank-mu partial sums of the
+    //     upper triangle, which do not depend on the paths
+    if (wv >= 2) {
+        for (int task = tid - 2 * kWave64; task < kParts * ntri; task += NT - 2 * kWave64) {
+            const int part = task / ntri, e = task - part * ntri;
+            const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
+            double acc = 0.0;
+#pragma unroll 4
+            for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
+            s_partc[part * ntri + e] = acc;
+        }
     }
     __syncthreads();
     const double h_sigma = s_scal[1], sum_w = s_scal[2];
-    if (on_w1 && t1 < n) {
-        s_pc[t1] = (1.0 - cc) * s_pc[t1] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[t1];
-        S.p_c[t1] = s_pc[t1];
-    }
 
-    // 4. covariance: rank-one + rank-mu (upper triangle, partial sums), symmetric, block-masked
-    for (int task = tid; task < kParts * ntri; task += NT) {
-        const int part = task / ntri, e = task % ntri;
-        int i = 0, rem = e;
-        while (rem >= n - i) { rem -= n - i; i++; }
-        const int j = i + rem;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
-        s_part[part * ntri + e] = acc;
-    }
-    __syncthreads();
+    // 4b. covariance: rank-one + rank-mu, symmetric, block-masked (into s_T)
     const double delta = (1.0 - h_sigma) * cc * (2.0 - cc);
     const double keep = 1.0 - c1 - cmu * sum_w;
     for (int e = tid; e < ntri; e += NT) {
-        int i = 0, rem = e;
-        while (rem >= n - i) { rem -= n - i; i++; }
-        const int j = i + rem;
+        const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
         double rmu = 0.0;
-        for (int part = 0; part < kParts; part++) rmu += s_part[part * ntri + e];
+        for (int part = 0; part < kParts; part++) rmu += s_partc[part * ntri + e];
         const double cij = keep * s_C[i * n + j] + c1 * (s_pc[i] * s_pc[j] + delta * s_C[i * n + j]) + cmu * rmu;
         const double cji = keep * s_C[j * n + i] + c1 * (s_pc[j] * s_pc[i] + delta * s_C[j * n + i]) + cmu * rmu;
         double v = 0.5 * (cij + cji);
         if (i / nb != j / nb) v = 0.0;   // block-diagonal covariance
-        s_A[i * n + j] = v;
-        s_A[j * n + i] = v;
+        s_T[i * n + j] = v;
+        s_T[j * n + i] = v;
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += NT) S.C[e] = s_A[e];
 
     // 5. Jacobi eigendecomposition, warm-started from the previous eigenvectors:
     //    A = B^T C B (nearly diagonal when C changed little), V = B; every
@@ -568,15 +730,26 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     for (int e = tid; e < nn; e += NT) {
         const int i = e / n, j = e % n;
         double t = 0.0;
-        for (int k = 0; k < n; k++) t += s_A[i * n + k] * s_B[k * n + j];
-        s_V[e] = t;                                   // C B (temporary)
+        for (int k = 0; k < n; k++) t += s_T[i * n + k] * s_B[k * n + j];
+        s_X[e] = t;                                   // C B
+        S.C[e] = s_T[e];
     }
     __syncthreads();
-    for (int e = tid; e < nn; e += NT) {
-        const int i = e / n, j = e % n;
-        double t = 0.0;
-        for (int k = 0; k < n; k++) t += s_B[k * n + i] * s_V[k * n + j];
-        s_T[e] = t;                                   // B^T C B
+    // A = B^T C B in the positional layout, symmetrised: 0.5 (A_ij + A_ji)
+    // from both products (each summed over k in order); dummy rows and columns zero
+    for (int e = tid; e < n_blocks * mm; e += NT) {
+        const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
+        double v = 0.0;
+        if (i < nb && j < nb) {
+            const int gi = b * nb + i, gj = b * nb + j;
+            double tij = 0.0, tji = 0.0;
+            for (int k = 0; k < n; k++) {
+                tij += s_B[k * n + gi] * s_X[k * n + gj];
+                tji += s_B[k * n + gj] * s_X[k * n + gi];
+            }
+            v = 0.5 * (tij + tji);
+        }
+        s_A[e] = v;
     }
     __syncthreads();
 
@@ -630,72 +803,73 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         }
     }
     if (tid < kWave64) {
-        // positional layout: index l of block b starts at position l
-        for (int e = tid; e < n_blocks * mm; e += kWave64) {
-            const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
-            const int gi = b * nb + i, gj = b * nb + j;
-            s_A[e] = (i < nb && j < nb) ? 0.5 * (s_T[gi * n + gj] + s_T[gj * n + gi]) : 0.0;
-        }
-        for (int e = tid; e < n_v; e += kWave64) {
-            const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
-            s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
-        }
-        double* Acur = s_A;
-        double* Anext = s_T;
-        double* Vcur = s_V;
-        double* Vnext = s_C;
-        wave_sync();
-        const int max_rounds = kMaxSweeps * k1;
+        const int max_rounds = kMaxSweeps * k1;   // even (kMaxSweeps is)
         int moved = 0;                             // rounds applied (index moves) modulo k1
-        // lane t < n_blocks m computes the rotation of the pair holding position
-        // t, from the pair's 2x2 diagonal block (rows 2P, 2P+1 at column 2P)
+        // (several entries per lane) lane t < n_blocks m computes the rotation
+        // of the pair holding position t, from the pair's 2x2 diagonal block
+        // (rows 2P, 2P+1 at column 2P)
         const int n_pos = n_blocks * m;
         const int t_pos = min(tid, n_pos - 1);
         const int t_b = div_small(t_pos, m), t_p = t_pos - t_b * m, t_2P = t_p & ~1;
         const int t_rp = t_b * mm + t_2P * m + t_2P, t_rq = t_rp + m;
         const bool t_even = (t_p & 1) == 0;
-        for (int it = 0; it < max_rounds; it++) {
-            auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
+        auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
+        // One round from (Ac, Vc) into (An, Vn); true when it found the
+        // iteration converged.  Every round rotates and moves the indices (with
+        // no rotation this only moves them); the test whether to stop follows
+        // the stores, so that it is not on the path from one round to the next.
+        auto jacobi_round = [&](const double* Ac, double* An, const double* Vc, double* Vn) -> bool {
             // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1) and the
-            // two V rows at columns 2P and 2Q do not depend on this round's
-            // rotations: they are read first, with no branch (every slot's
+            // two V rows at columns 2P and 2Q, read with no branch (every slot's
             // offsets are valid; slots past the last entry repeat it)
             double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
-                blk0[sl] = pair(Acur, a_rij[sl]);
-                blk1[sl] = pair(Acur, a_rpj[sl]);
-                vr0[sl] = pair(Vcur, v0_r[sl]);
-                vr1[sl] = pair(Vcur, v1_r[sl]);
+                blk0[sl] = pair(Ac, a_rij[sl]);
+                blk1[sl] = pair(Ac, a_rpj[sl]);
+                vr0[sl] = pair(Vc, v0_r[sl]);
+                vr1[sl] = pair(Vc, v1_r[sl]);
             }
-            const double2 bp = pair(Acur, t_rp), bq = pair(Acur, t_rq);
-            double c_t, sn_t;
-            const bool rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
-            const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
-            // column t of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
-            const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
-            // the rotation columns u, w of positions i and j from the lanes that hold them
-            double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots];
-    #pragma unroll
-            for (int sl = 0; sl < kASlots; sl++) {
-                u0[sl] = __shfl(col0_t, a_li[sl]);
-                u1[sl] = __shfl(col1_t, a_li[sl]);
-                w0[sl] = __shfl(col0_t, a_lj[sl]);
-                w1[sl] = __shfl(col1_t, a_lj[sl]);
-            }
-            if (__ballot(rot) == 0ull) {
-                // nothing rotates in this round: stop if no pair exceeds the threshold
-                bool open = false;
+            // the rotation columns u, w of positions i and j, and A(i, i), A(j, j)
+            double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots], di[kASlots], dj[kASlots];
+            bool rot;
+            if constexpr (AS == 1) {
+                // one entry per lane: the lane computes both rotations itself
+                // from the pairs' diagonal blocks (read with its other operands),
+                // with no exchange between lanes
+                const double2 p0 = pair(Ac, a_dp[0]), p1 = pair(Ac, a_dp[0] + m);
+                const double2 q0 = pair(Ac, a_dq[0]), q1 = pair(Ac, a_dq[0] + m);
+                const double app[2] = {p0.x, q0.x}, aqq[2] = {p1.y, q1.y}, apq[2] = {p0.y, q0.y};
+                double cs2[2], sn2[2];
+                bool r2[2];
+                pair_rotation2(app, aqq, apq, cs2, sn2, r2);
+                const double cp = cs2[0], sp = sn2[0], cq = cs2[1], sq = sn2[1];
+                const bool rp = r2[0], rq = r2[1];
+                // column of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
+                u0[0] = a_ei[0] ? cp : sp;
+                u1[0] = a_ei[0] ? -sp : cp;
+                w0[0] = a_ej[0] ? cq : sq;
+                w1[0] = a_ej[0] ? -sq : cq;
+                di[0] = a_ei[0] ? p0.x : p1.y;
+                dj[0] = a_ej[0] ? q0.x : q1.y;
+                rot = rp || rq;
+            } else {
+                // lane t < n_blocks m computes the rotation of the pair holding
+                // position t; the entry lanes take the columns by cross-lane shuffles
+                const double2 bp = pair(Ac, t_rp), bq = pair(Ac, t_rq);
+                double c_t, sn_t;
+                rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
+                const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
+                const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
     #pragma unroll
                 for (int sl = 0; sl < kASlots; sl++) {
-                    if (sl < na_slots) {
-                        const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
-                        const double aij = a_ej[sl] ? row.x : row.y;
-                        const double d_i = __shfl(dd_t, a_li[sl]), d_j = __shfl(dd_t, a_lj[sl]);
-                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(d_i * d_j);
-                    }
+                    u0[sl] = __shfl(col0_t, a_li[sl]);
+                    u1[sl] = __shfl(col1_t, a_li[sl]);
+                    w0[sl] = __shfl(col0_t, a_lj[sl]);
+                    w1[sl] = __shfl(col1_t, a_lj[sl]);
+                    di[sl] = __shfl(dd_t, a_li[sl]);
+                    dj[sl] = __shfl(dd_t, a_lj[sl]);
                 }
-                if (__ballot(open) == 0ull) break;
             }
     #pragma unroll
             for (int sl = 0; sl < kASlots; sl++) {
@@ -705,19 +879,42 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                     const double r0 = fma(w0[sl], blk0[sl].x, w1[sl] * blk0[sl].y);
                     const double r1 = fma(w0[sl], blk1[sl].x, w1[sl] * blk1[sl].y);
                     const double v = fma(u0[sl], r0, u1[sl] * r1);
-                    Anext[a_w1[sl]] = v;
-                    Anext[a_w2[sl]] = v;
+                    An[a_w1[sl]] = v;
+                    An[a_w2[sl]] = v;
                     // V'(r, i) = V(r, 2P) u0 + V(r, 2P+1) u1, likewise at column j
-                    double* d0 = v0_ok[sl] ? Vnext + v0_w[sl] : s_sink + tid;
-                    double* d1 = v1_ok[sl] ? Vnext + v1_w[sl] : s_sink + kWave64 + tid;
+                    double* d0 = v0_ok[sl] ? Vn + v0_w[sl] : s_sink + tid;
+                    double* d1 = v1_ok[sl] ? Vn + v1_w[sl] : s_sink + kWave64 + tid;
                     *d0 = fma(u0[sl], vr0[sl].x, u1[sl] * vr0[sl].y);
                     *d1 = fma(w0[sl], vr1[sl].x, w1[sl] * vr1[sl].y);
                 }
             }
             wave_sync();
-            double* t = Acur; Acur = Anext; Anext = t;
-            t = Vcur; Vcur = Vnext; Vnext = t;
             moved = moved + 1 == k1 ? 0 : moved + 1;
+            if (__ballot(rot) != 0ull) return false;
+            // nothing rotated in this round: converged when no pair exceeds the
+            // threshold (another sweep would rotate nothing)
+            bool open = false;
+    #pragma unroll
+            for (int sl = 0; sl < kASlots; sl++) {
+                if (sl < na_slots) {
+                    const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
+                    const double aij = a_ej[sl] ? row.x : row.y;
+                    open |= a_off[sl] && aij * aij > 1e-30 * fabs(di[sl] * dj[sl]);
+                }
+            }
+            return __ballot(open) == 0ull;
+        };
+        // the rounds alternate between two buffer pairs; the result is in the
+        // pair the last round wrote
+        const double* Acur = s_A;
+        const double* Vcur = s_V;
+        for (int it = 0; it < max_rounds; it += 2) {
+            if (jacobi_round(s_A, s_T, s_V, s_C)) {
+                Acur = s_T;
+                Vcur = s_C;
+                break;
+            }
+            if (jacobi_round(s_T, s_A, s_C, s_V)) break;
         }
         // final position of every index; 6. D = sqrt(eigenvalues) with a
         // floor at 1e-20 * max (the maximum by a butterfly over the lanes,
@@ -730,8 +927,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             s_pos[tid] = p;
             ev = Acur[tb * mm + p * m + p];
         }
-        double emax = tid < n ? fmax(0.0, ev) : 0.0;
-        for (int off = kWave64 / 2; off > 0; off >>= 1) emax = fmax(emax, __shfl_xor(emax, off));
+        const double emax = wave_max_f64(tid < n ? fmax(0.0, ev) : 0.0, tid);
         const double floor_v = 1e-20 * emax;
         const bool floored = tid < n && !(ev >= floor_v);
         if (tid < n) {
