@@ -10,6 +10,12 @@ Block-diagonal covariance for the bi-manual case follows Sec. III-B.
 Random numbers: Philox4x32-10 (Salmon et al., SC'11) counter-based generator,
 key = seed, counter = (group j, candidate k, generation g, 0); each 4x32-bit
 output gives two Box-Muller pairs for dimensions 4j..4j+3.
+
+Sampling square root: y = L z with L the (lower) Cholesky factor of C, which
+gives y ~ N(0, C) exactly as the tutorial's y = B D z does (any A with
+A A^T = C does).  The eigendecomposition C = B D^2 B^T still provides
+C^(-1/2) = B D^(-1) B^T for the conjugate evolution path; each update takes it
+from the covariance the candidates were drawn with.
 """
 from __future__ import annotations
 
@@ -78,9 +84,39 @@ def default_constants(n: int, lam: int, c_m_scale=1.0, c_mu_scale=1.0, c1_scale=
                 c1=c1, c_mu=c_mu, c_m=float(c_m_scale), chi_n=chi_n)
 
 
+def cholesky_floored(C: np.ndarray, n_blocks: int = 1):
+    """Lower Cholesky factor L of each diagonal block of C (L L^T = C), by the
+    row-by-row (Cholesky-Banachiewicz) recurrences written out: for column j,
+    s = C_jj - sum_{k<j} L_jk^2, L_jj = sqrt(s), L_ij = (C_ij - sum_{k<j} L_ik
+    L_jk) / L_jj for i > j.  A pivot s that is not above the floor
+    1e-20 * max_i C_ii (the analogue of the eigenvalue floor; rounding can
+    make a numerically singular C lose definiteness) is replaced by the floor.
+    Returns (L, floored)."""
+    n = C.shape[0]
+    nb = n // n_blocks
+    dmax = float(np.max(np.diag(C)))
+    floor = 1e-20 * dmax if dmax > 0.0 else 0.0
+    if not floor > 0.0:
+        floor = np.finfo(np.float64).tiny
+    L = np.zeros((n, n))
+    floored = False
+    for b in range(n_blocks):
+        o = b * nb
+        for j in range(nb):
+            s = C[o + j, o + j] - sum(L[o + j, o + k] ** 2 for k in range(j))
+            if not s > floor:
+                s, floored = floor, True
+            L[o + j, o + j] = math.sqrt(s)
+            for i in range(j + 1, nb):
+                t = C[o + i, o + j] - sum(L[o + i, o + k] * L[o + j, o + k] for k in range(j))
+                L[o + i, o + j] = t / L[o + j, o + j]
+    return L, floored
+
+
 class CMAES:
-    """State (m, sigma, C, B, D, p_sigma, p_c, g) in the normalised space;
-    physical candidates are theta = offset + scale * x."""
+    """State (m, sigma, C, L, p_sigma, p_c, g) in the normalised space, with
+    B, D the eigendecomposition of the covariance the last update whitened
+    with; physical candidates are theta = offset + scale * x."""
 
     def __init__(self, n, lam, mean0, sigma0, offset, scale, seed, c_m_scale=1.0, c_mu_scale=1.0,
                  c1_scale=1.0, n_blocks=1):
@@ -93,6 +129,7 @@ class CMAES:
         self.offset = np.array(offset, dtype=np.float64).copy()
         self.scale = np.array(scale, dtype=np.float64).copy()
         self.C = np.eye(n)
+        self.L = np.eye(n)
         self.B = np.eye(n)
         self.D = np.ones(n)
         self.p_sigma = np.zeros(n)
@@ -101,12 +138,17 @@ class CMAES:
         self.Z = None
         self.Y = None
         self.eig_floored = False
+        self.chol_floored = False
 
-    # sample: z ~ N(0, I), y = B D z, x = m + sigma y   (tutorial eqs. 38-40)
+    def set_covariance(self, C):
+        """Replace C (symmetric positive definite) and its sampling factor."""
+        self.C = np.array(C, dtype=np.float64).copy()
+        self.L, self.chol_floored = cholesky_floored(self.C, self.n_blocks)
+
+    # sample: z ~ N(0, I), y = L z (y ~ N(0, C)), x = m + sigma y   (tutorial eqs. 38-40)
     def sample(self):
         self.Z = normals(self.seed, self.g, self.lam, self.n)
-        BD = self.B * self.D[None, :]
-        self.Y = self.Z @ BD.T
+        self.Y = self.Z @ self.L.T
         X = self.m[None, :] + self.sigma * self.Y
         theta = self.offset[None, :] + self.scale[None, :] * X
         return theta
@@ -126,6 +168,7 @@ class CMAES:
 
     def update(self, loss):
         k, n = self.k, self.n
+        self._decompose()                   # B, D of the covariance the candidates came from
         order = self.ranking(loss)
         ysel = self.Y[order[:k["mu"]]]
         w = k["weights"]
@@ -142,25 +185,26 @@ class CMAES:
         delta = (1.0 - h_sigma) * cc * (2.0 - cc)
         c1, cmu = k["c1"], k["c_mu"]
         rank_mu = (ysel * w[:, None]).T @ ysel
-        self.C = (1.0 - c1 - cmu * w.sum()) * self.C + c1 * (np.outer(self.p_c, self.p_c) + delta * self.C) \
+        C = (1.0 - c1 - cmu * w.sum()) * self.C + c1 * (np.outer(self.p_c, self.p_c) + delta * self.C) \
             + cmu * rank_mu
         self.sigma = self.sigma * math.exp((cs / k["d_sigma"]) * (ps_norm / k["chi_n"] - 1.0))
         self.g += 1
         self.h_sigma = h_sigma
-        self._decompose()
+        C = 0.5 * (C + C.T)
+        if self.n_blocks > 1:
+            C = np.where(self.block_mask(), C, 0.0)
+        self.set_covariance(C)
         return order
 
     def _decompose(self):
-        C = 0.5 * (self.C + self.C.T)
-        if self.n_blocks > 1:
-            C = np.where(self.block_mask(), C, 0.0)
-        self.C = C
+        """B, D: eigendecomposition of each diagonal block of C (numpy's eigh),
+        eigenvalues floored at 1e-20 times the largest."""
         nb = self.n // self.n_blocks
         B = np.zeros((self.n, self.n))
         ev = np.zeros(self.n)
         for b in range(self.n_blocks):
             s = slice(b * nb, (b + 1) * nb)
-            e, V = np.linalg.eigh(C[s, s])
+            e, V = np.linalg.eigh(self.C[s, s])
             ev[s] = e
             B[s, s] = V
         floor = 1e-20 * max(float(ev.max()), 0.0)

@@ -115,6 +115,8 @@ def test_covariance_stays_symmetric_pd():
     for _, _, C in hist:
         assert np.array_equal(C, C.T)
         assert np.linalg.eigvalsh(C).min() > 0
+    np.testing.assert_allclose(es.L @ es.L.T, es.C, atol=1e-13 * np.abs(es.C).max())
+    es._decompose()
     np.testing.assert_allclose(es.B @ np.diag(es.D ** 2) @ es.B.T, es.C, atol=1e-12 * np.abs(es.C).max())
     np.testing.assert_allclose(es.B.T @ es.B, np.eye(9), atol=1e-13)
 
@@ -127,6 +129,56 @@ def test_block_diagonal_keeps_zero_blocks():
     for _, _, C in hist:
         assert np.all(C[:9, 9:] == 0.0) and np.all(C[9:, :9] == 0.0)
     assert np.all(es.B[:9, 9:] == 0.0) and np.all(es.B[9:, :9] == 0.0)
+    assert np.all(es.L[:9, 9:] == 0.0) and np.all(es.L[9:, :9] == 0.0)
+
+
+# ---------------------------------------------------------------- sampling square root
+#
+# y = L z with L L^T = C: the oracle's recurrences against numpy's Cholesky
+# (a library routine), per block, and the pivot floor on a singular matrix.
+
+@pytest.mark.parametrize("n,nb", [(9, 1), (18, 2), (18, 1), (3, 1)])
+def test_cholesky_matches_library_routine(n, nb):
+    rng = np.random.default_rng(n + nb)
+    C = np.zeros((n, n))
+    s = n // nb
+    for b in range(nb):
+        A = rng.normal(size=(s, s))
+        C[b * s:(b + 1) * s, b * s:(b + 1) * s] = A @ A.T + 0.1 * np.eye(s)
+    L, floored = cmaes.cholesky_floored(C, nb)
+    assert not floored
+    assert np.all(np.triu(L, 1) == 0.0) and np.all(np.diag(L) > 0)
+    for b in range(nb):
+        blk = slice(b * s, (b + 1) * s)
+        np.testing.assert_allclose(L[blk, blk], np.linalg.cholesky(C[blk, blk]), rtol=0, atol=1e-13)
+    if nb > 1:
+        assert np.all(L[:s, s:] == 0.0) and np.all(L[s:, :s] == 0.0)
+
+
+def test_cholesky_floors_a_singular_pivot():
+    """C = [[1, 1, 0], [1, 1, 0], [0, 0, 4]] is positive semi-definite with an
+    exactly zero second pivot: it becomes the floor 1e-20 max C_ii, the flag is
+    set and L L^T = C + floor e_1 e_1^T."""
+    C = np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 0.0], [0.0, 0.0, 4.0]])
+    L, floored = cmaes.cholesky_floored(C)
+    floor = 1e-20 * 4.0
+    assert floored
+    assert L[1, 1] == math.sqrt(floor) and L[2, 2] == 2.0
+    E = np.zeros((3, 3))
+    E[1, 1] = floor
+    np.testing.assert_allclose(L @ L.T, C + E, rtol=0, atol=1e-15)
+    # a positive definite matrix is not floored
+    assert not cmaes.cholesky_floored(C + 1e-3 * np.eye(3))[1]
+
+
+def test_samples_have_covariance_C():
+    """y = L z over many draws has sample covariance C (5 standard errors)."""
+    _, _, C = _fixed_state(9, 5)
+    es = cmaes.CMAES(9, 20000, np.zeros(9), 1.0, np.zeros(9), np.ones(9), seed=8)
+    es.set_covariance(C)
+    es.sample()
+    cov = np.cov(es.Y.T)
+    assert np.all(np.abs(cov - C) <= _cov_bound(C, 20000))
 
 
 def test_update_matches_paper_equation_in_theta_form():
@@ -193,7 +245,7 @@ def _random_selection_trials(n, lam, p_sigma_stationary, p_c_stationary, seed=12
     out = {"dm": [], "ps": [], "C": [], "dlogs": []}
     for t in range(N_TRIALS):
         es = cmaes.CMAES(n, lam, m0, sigma0, np.zeros(n), np.ones(n), seed=1000 + t)
-        es.C, es.B, es.D = C.copy(), Q.copy(), np.sqrt(ev)
+        es.set_covariance(C)
         es.g = 1000                          # h_sigma's start-up correction has died out
         es.p_sigma = rng.normal(size=n) if p_sigma_stationary else np.zeros(n)
         es.p_c = Lc @ rng.normal(size=n) if p_c_stationary else np.zeros(n)
@@ -215,7 +267,7 @@ def _cov_bound(S, N):
 @pytest.mark.parametrize("lam", [16, 70])
 def test_random_selection_mean_step_has_covariance_C_over_mu_eff(lam):
     """m' - m = c_m sigma y_w with y_w ~ N(0, C / mu_eff): zero mean and
-    mu_eff * Cov = C (pins y = B D z and the normalised weights)."""
+    mu_eff * Cov = C (pins y = L z and the normalised weights)."""
     n = 9
     r, C, k = _random_selection_trials(n, lam, False, False)
     dm = r["dm"]
