@@ -119,16 +119,26 @@ typedef struct {
     int64_t total_bytes;
     int64_t gen;        /* int64 generation counter g */
     int64_t seed;       /* uint64 Philox key */
-    int64_t flags;      /* int32 bit 0: an eigenvalue was floored, bit 1: sigma not finite */
+    int64_t flags;      /* int32 bit 0: an eigenvalue or a Cholesky pivot was floored, bit 1: sigma or an
+                         * eigenvalue not finite, bit 2: an internal wait of the update kernel
+                         * exceeded its bound (the results of that update are not valid) */
     int64_t sigma, c_sigma, d_sigma, c_c, c1, c_mu, c_m, mu_eff, chi_n, h_sigma;
     int64_t weights;    /* [lambda] (first mu used) */
     int64_t mean, p_sigma, p_c, offset, scale, D;   /* [n] */
-    int64_t C, B;       /* [n][n]; B columns are eigenvectors, D their sqrt eigenvalues */
-    int64_t Z, Y;       /* [lambda][n] last draws z and y = B D z */
+    int64_t C, B;       /* [n][n]; C the covariance the next candidates are drawn with; B, D the
+                         * eigendecomposition (B columns eigenvectors, D square roots of the
+                         * eigenvalues) of the covariance the last update whitened with, i.e. the
+                         * one before it (identity after initialisation) */
+    int64_t Z, Y;       /* [lambda][n] last draws z and y = L z */
     int64_t order;      /* int32 [lambda] ranking of the last update */
-    int64_t z_gen;      /* int64 generation g whose draws Z holds for every candidate (-1: none);
-                         * an update draws the next generation's z while it runs its
-                         * eigendecomposition, and the ask-eval form then reads them */
+    int64_t z_gen;      /* int64 generation g whose draws Z holds for every candidate (-1: none,
+                         * or older than the draws in Z).  An update with n <= 9 draws the
+                         * next generation's z beside its eigendecomposition and the
+                         * ask-eval form then reads them; otherwise the ask-eval prologue
+                         * draws them itself (and does not tag them), as do the sampler
+                         * and the tell-ask form (which tag them) */
+    int64_t L;          /* [n][n] lower Cholesky factor of C per diagonal block (L L^T = C; zero
+                         * above the diagonal and off the blocks), the sampling square root */
 } tk_cmaes_layout;
 
 /* Size in bytes of a state blob for dimension n (1..18) and population
@@ -138,7 +148,7 @@ tk_status tk_cmaes_layout_get(int32_t n, int32_t lambda, tk_cmaes_layout* out);
 
 /* Initialise a state blob (Sec. III-A.1; Sec. IV: Sigma^(0) = I in the
  * normalised space): m = mean0 (normalised space, host [n]), sigma = sigma0,
- * C = B = I, D = 1, p_sigma = p_c = 0, g = 0.  Physical candidates are
+ * C = L = B = I, D = 1, p_sigma = p_c = 0, g = 0.  Physical candidates are
  * theta = offset + scale * x (host [n] each).  p may be NULL for defaults.
  * n must be divisible by p->n_blocks. */
 tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* mean0, double sigma0,
@@ -155,7 +165,7 @@ tk_status tk_cmaes_init(void* d_state, int32_t n, int32_t lambda, const double* 
  * (limits from chains, host [n_arms]) for the joints; where readings (host
  * [n_arms][3] unconstrained joint coordinates, may be NULL) are given they
  * replace the joint offsets.  Otherwise as tk_cmaes_init with mean0 = 0:
- * sigma = sigma0, scale (host [n]), C = B = I, D = 1, paths 0, g = 0, seed,
+ * sigma = sigma0, scale (host [n]), C = L = B = I, D = 1, paths 0, g = 0, seed,
  * p (may be NULL).  d_est is read by the launched kernel, in stream order.
  * Errors: TK_ERR_INVALID_ARGUMENT on sizes, NULL pointers, non-finite scale or
  * readings, joint limits with lb >= ub; nothing is launched then. */
@@ -169,16 +179,18 @@ tk_status tk_cmaes_set_mean(void* d_state, int32_t n, int32_t lambda, const doub
 
 /* Sample lambda candidates from N(m, sigma^2 C) (Sec. III-A.1, Eq.
  * expected_fitness): z from Philox4x32-10 (key = seed, counter = (j, k, g, 0))
- * with Box-Muller, y = B D z, x = m + sigma y.  Writes d_X[lambda][n] FP32
+ * with Box-Muller, y = L z (L L^T = C, so y ~ N(0, C)), x = m + sigma y.  Writes d_X[lambda][n] FP32
  * physical candidates theta = offset + scale * x and keeps z, y in the state. */
 tk_status tk_cmaes_sample(void* d_state, int32_t n, int32_t lambda, float* d_X, tk_stream s);
 
 /* One CMA-ES update from the losses of the last sample (Sec. III-A.1, Eq.
  * cmaes_update, completed by Hansen's tutorial): rank by (loss, index) with
  * NaN as +inf, weighted recombination of the mu = lambda/2 best, cumulative
- * step-size adaptation, rank-one + rank-mu covariance update, symmetrisation,
- * optional block-diagonal masking (Sec. III-B), Jacobi eigendecomposition.
- * d_loss: device FP64 [lambda]. */
+ * step-size adaptation with C^(-1/2) from the Jacobi eigendecomposition of the
+ * covariance the candidates were drawn with, rank-one + rank-mu covariance
+ * update, symmetrisation, optional block-diagonal masking (Sec. III-B), and
+ * the Cholesky factor L of the new covariance for the next draws (pivots
+ * floored at 1e-20 max_i C_ii).  d_loss: device FP64 [lambda]. */
 tk_status tk_cmaes_update(void* d_state, int32_t n, int32_t lambda, const double* d_loss, tk_stream s);
 
 /* Loss composition and update in one launch ("tell"), identical to

@@ -105,6 +105,7 @@ __global__ __launch_bounds__(256) void cmaes_init_kernel(void* blob, InitArgs a)
         const double v = (i / n == i % n) ? 1.0 : 0.0;
         S.C[i] = v;
         S.B[i] = v;
+        S.L[i] = v;
     }
     for (int i = tid; i < lam * n; i += blockDim.x) {
         S.Z[i] = 0.0;
@@ -123,13 +124,13 @@ __global__ void cmaes_set_mean_kernel(void* blob, MeanArgs a) {
 
 // A 64-thread workgroup samples kSampCand candidates: first one thread per
 // (candidate, group of four dimensions) draws z with Philox + Box-Muller, then
-// one thread per (candidate, dimension) forms y = B D z, x = m + sigma y and
+// one thread per (candidate, dimension) forms y = L z, x = m + sigma y and
 // theta = offset + scale * x.
 constexpr int kSampCand = 8;
 
 __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int lam, float* __restrict__ X) {
     __shared__ double s_z[kSampCand][kMaxN + 3];
-    __shared__ double s_BD[kMaxN * kMaxN];
+    __shared__ double s_Lf[kMaxN * kMaxN];   // the sampling factor L
     StateView S = state_view(blob, n, lam);
     const int tid = threadIdx.x;
     const int k0 = blockIdx.x * kSampCand;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
     const uint64_t seed = S.hdr->seed;
     const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
     const int groups = (n + 3) / 4;
-    for (int e = tid; e < n * n; e += 64) s_BD[e] = S.B[e] * S.D[e % n];
+    for (int e = tid; e < n * n; e += 64) s_Lf[e] = S.L[e];
     for (int task = tid; task < kSampCand * groups; task += 64) {
         const int kk = task / groups, j = task % groups, k = k0 + kk;
         if (k >= lam) continue;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
         const int kk = task / n, i = task % n, k = k0 + kk;
         if (k >= lam) continue;
         double y;
-        X[k * n + i] = candidate_coord(s_BD, s_z[kk], n, i, S.mean[i], sigma, S.offset[i], S.scale[i], &y);
+        X[k * n + i] = candidate_coord(s_Lf, s_z[kk], n, i, S.mean[i], sigma, S.offset[i], S.scale[i], &y);
         S.Z[k * n + i] = s_z[kk][i];
         S.Y[k * n + i] = y;
     }
@@ -169,12 +170,13 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The rotations below use the hardware FP64 reciprocal square root refined by
-// Newton steps r <- r (1.5 - 0.5 x r^2) (explicit fused multiply-adds, the
-// same in every form of the path): one step for sqrt(d^2 + 4 a_pq^2),
-// which only sets the angle, and two for the normalisation, so that c and s
-// are orthogonal to working precision, at a fraction of the latency of the
-// correctly rounded square root and division.
+// The rotations below use the hardware FP64 reciprocal square root (relative
+// error at most about 5e-8) refined by Newton steps r <- r (1.5 - 0.5 x r^2)
+// (explicit fused multiply-adds, the same in every form of the path): one step
+// for sqrt(d^2 + 4 a_pq^2), which only sets the angle, and two for the
+// normalisation, so that c and s are orthogonal to working precision, at a
+// fraction of the latency of the correctly rounded square root and division.
+// (Without the first step the iteration took about one round more.)
 // The symmetric Schur rotation of the pair (p, q) = (2P, 2P+1), from its 2x2
 // diagonal block: J(p, p) = J(q, q) = c, J(q, p) = s'_p = -s, J(p, q) =
 // s'_q = +s, where tan(theta) = t zeroes the (p, q) entry of J^T A J:
@@ -422,6 +424,121 @@ struct UpdateJob {
     TellAskArgs ta;
 };
 
+// A barrier over a group of n_waves waves of the workgroup through LDS (the
+// update's waves on SIMDs other than wave 0's synchronise so while wave 0 runs
+// the eigendecomposition, which a workgroup barrier would wait for).  bar:
+// arrivals, generation, and a flag set if a wait ever exceeded its bound
+// (about 0.1 s; it then goes on, so the kernel always ends).
+constexpr int kWaitBound = 1 << 22;
+__device__ __forceinline__ void wave_group_barrier(int* bar, int n_waves) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & (kWave64 - 1)) == 0) {
+        const int g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == n_waves - 1) {
+            __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            int spin = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == g) {
+                if (++spin == kWaitBound) {
+                    __hip_atomic_store(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Covariance update of the upper-triangle entries e = tid0, tid0 + stride, ...
+// (rank-one + rank-mu from the partial sums, symmetric, block-masked) into Cn.
+__device__ __forceinline__ void covariance_entries(int tid0, int stride, int n, int nb, int ntri, double keep,
+                                                   double c1, double cmu, double delta, const double* pc,
+                                                   const double* C, const double* partc, double* Cn) {
+    for (int e = tid0; e < ntri; e += stride) {
+        const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
+        double rmu = 0.0;
+        for (int part = 0; part < kParts; part++) rmu += partc[part * ntri + e];
+        const double cij = keep * C[i * n + j] + c1 * (pc[i] * pc[j] + delta * C[i * n + j]) + cmu * rmu;
+        const double cji = keep * C[j * n + i] + c1 * (pc[j] * pc[i] + delta * C[j * n + i]) + cmu * rmu;
+        double v = 0.5 * (cij + cji);
+        if (i / nb != j / nb) v = 0.0;   // block-diagonal covariance
+        Cn[i * n + j] = v;
+        Cn[j * n + i] = v;
+    }
+}
+
+// Lower Cholesky factor of each diagonal block of C (n x n) into L (n x n,
+// zero elsewhere), by one wave, with A as working copy: column k of every block at once,
+// L_kk = sqrt(max'(A_kk)), L_ik = A_ik / L_kk, then A_ij -= L_ik L_jk for
+// i >= j > k.  A pivot not above 1e-20 max_i A_ii is replaced by that floor.
+// Returns (in every lane) whether a pivot was floored.
+template <int CS>
+__device__ __forceinline__ bool wave_cholesky(const double* C, double* A, double* L, int n, int nb, int lane) {
+    const int n_blocks = n / nb, ntri_b = nb * (nb + 1) / 2, n_l = n_blocks * ntri_b;
+    double dmax = 0.0;
+    for (int i = lane; i < n; i += kWave64) dmax = fmax(dmax, C[i * n + i]);
+    dmax = wave_max_f64(dmax, lane);
+    double floor_v = 1e-20 * dmax;
+    if (!(floor_v > 0.0)) floor_v = 2.2250738585072014e-308;   // smallest normal double
+    for (int e = lane; e < n * n; e += kWave64) {
+        L[e] = 0.0;
+        A[e] = C[e];
+    }
+    // lane slots: entry (i, j), i >= j, of block b (lower triangle, row by row)
+    int gi[CS], gj[CS];
+    bool ok[CS];
+#pragma unroll
+    for (int sl = 0; sl < CS; sl++) {
+        const int e = min(lane + kWave64 * sl, n_l - 1);
+        const int b = div_small(e, ntri_b), eb = e - b * ntri_b;
+        // row i holds i + 1 entries, starting at i (i + 1) / 2
+        int i = int(0.5f * (sqrtf(8.0f * float(eb) + 1.0f) - 1.0f));
+        i += ((i + 1) * (i + 2) / 2 <= eb) ? 1 : 0;
+        i -= (i * (i + 1) / 2 > eb) ? 1 : 0;
+        gi[sl] = b * nb + i;
+        gj[sl] = b * nb + (eb - i * (i + 1) / 2);
+        ok[sl] = lane + kWave64 * sl < n_l;
+    }
+    wave_sync();
+    bool floored = false;
+    for (int k = 0; k < nb; k++) {
+#pragma unroll
+        for (int sl = 0; sl < CS; sl++) {
+            const int bk = gj[sl] - gj[sl] % nb + k;    // column k of the slot's block
+            if (ok[sl] && gj[sl] == bk) {
+                double piv = A[bk * n + bk];
+                const bool fl = !(piv > floor_v);
+                piv = fl ? floor_v : piv;
+                const double lkk = sqrt(piv);
+                L[gi[sl] * n + bk] = gi[sl] == bk ? lkk : A[gi[sl] * n + bk] / lkk;
+                floored |= fl && gi[sl] == bk;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int sl = 0; sl < CS; sl++) {
+            const int bk = gj[sl] - gj[sl] % nb + k;
+            if (ok[sl] && gj[sl] > bk)
+                A[gi[sl] * n + gj[sl]] -= L[gi[sl] * n + bk] * L[gj[sl] * n + bk];
+        }
+        wave_sync();
+    }
+    return __ballot(floored) != 0ull;
+}
+
+// The update of one problem (Sec. III-A.1, Eq. (3)-(4), completed by Hansen's
+// tutorial), in one workgroup.  The candidates were drawn as y = L z with
+// L L^T = C; the conjugate path whitens with C^(-1/2) = B D^(-1) B^T from the
+// eigendecomposition of that same C.  So wave 0 starts the eigendecomposition
+// (Jacobi, warm-started from the previous B) as soon as the kernel starts,
+// while the waves on the other SIMDs rank the candidates, recombine, form the
+// rank-mu sums and, assuming h_sigma = 1, the new covariance and its Cholesky
+// factor.  The two parts meet for the conjugate path; when h_sigma turns out
+// 0 the covariance and factor are formed again with it.
+//
 // AS / VS: Jacobi entries per lane (upper-triangle / all within-block entries
 // over 64 lanes); NT: threads of the workgroup; COMPOSE: losses composed from
 // counts (tell); ASK: the next generation drawn at the end (tell-ask).
@@ -429,150 +546,89 @@ template <int AS, int VS, int NT, bool COMPOSE, bool ASK>
 __device__ __forceinline__ void update_body(void* blob, const int n, const int lam, const double* __restrict__ loss,
                                             const TellAskArgs& ta) {
     extern __shared__ double s_elite[];  // [mu][n]
-    __shared__ RankRec s_rec[kMaxLambda];   // the waves' sorted lists of 64
+    __shared__ RankRec s_rec[kMaxLambda];   // the sorted lists of 64
     __shared__ double s_w[kMaxLambda / 2];
-    // 16-byte aligned: the Jacobi loop reads them as pairs of adjacent entries
+    // the eigendecomposition (wave 0): Jacobi buffers, the C the candidates
+    // were drawn with, the previous eigenvectors, C B, the result
     __shared__ __align__(16) double s_A[kMaxN * kMaxN];
-    __shared__ __align__(16) double s_V[kMaxN * kMaxN];
     __shared__ __align__(16) double s_T[kMaxN * kMaxN];
+    __shared__ __align__(16) double s_V[kMaxN * kMaxN];
+    __shared__ __align__(16) double s_Vn[kMaxN * kMaxN];
+    __shared__ double s_Ce[kMaxN * kMaxN];
+    __shared__ double s_Bw[kMaxN * kMaxN];
+    __shared__ double s_X[kMaxN * kMaxN];
     __shared__ double s_B[kMaxN * kMaxN];
-    __shared__ __align__(16) double s_C[kMaxN * kMaxN];
+    __shared__ double s_D[kMaxN];
+    __shared__ int s_pos[kMaxN];             // final Jacobi position of each index
+    __shared__ int s_vsel;                   // the V buffer that holds the result
+    __shared__ double s_sink[2 * kWave64];   // target of the V stores of lanes with no V entry
+    // the other waves: C, the new covariance and its factor
+    __shared__ double s_C[kMaxN * kMaxN];
+    __shared__ double s_Cn[kMaxN * kMaxN];
+    __shared__ double s_Cw[kMaxN * kMaxN];   // working copy of the factorisation
+    __shared__ double s_L[kMaxN * kMaxN];
     __shared__ double s_part[kParts * kMaxN];                     // recombination partial sums
     __shared__ double s_partc[kParts * kMaxN * (kMaxN + 1) / 2];  // rank-mu partial sums
-    __shared__ double s_X[kMaxN * kMaxN];                         // C' B
-    __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_ps[kMaxN], s_D[kMaxN];
+    __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_pc1[kMaxN], s_ps[kMaxN], s_mean[kMaxN];
     __shared__ double s_scal[4];
-    __shared__ double s_mean[kMaxN];
-    __shared__ int s_pos[kMaxN];          // final Jacobi position of each index
-    __shared__ double s_sink[2 * kWave64];   // target of the V stores of lanes with no V entry
+    __shared__ int s_wbar[5];                // worker barrier: arrivals, generation, wait bound hit; y_w ready; V final
+    __shared__ int s_flag[2];                // [0] eigenvalue floored, [1] Cholesky pivot floored / emax not finite
 
     StateView S = state_view(blob, n, lam);
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave64 - 1), wave = tid / kWave64;
     const int mu = S.hdr->mu;
     const int n_blocks = S.hdr->n_blocks;
     const int nb = n / n_blocks;
     const int nn = n * n;
     const int ntri = n * (n + 1) / 2;
-
-    // 0. stage the state, the losses and the candidates' y.  The state goes
-    //    through registers into LDS after the sort, so that its loads, the
-    //    count loads and the loss composition are in flight together.  Lane
-    //    tid holds candidates k = tid + r NT (r < R), i.e. entry `lane` of
-    //    list l = wave + r NW of 64 candidates, with their keys and rows of Y.
-    //    Keys past lambda are +inf, and their indices order them last.
-    constexpr int R = kMaxLambda / NT;
     constexpr int NW = NT / kWave64;
+    constexpr int NWW = NW - NW / 4;            // worker waves: w mod 4 != 0
+    constexpr int NWK = NWW * kWave64;          // worker lanes
+    constexpr int R = (kMaxLambda + NWK - 1) / NWK;   // candidates per worker lane
     constexpr int NMAX = AS == 1 ? 9 : kMaxN;   // n of the variant (n <= 9 uses AS = 1)
-    const int lane = tid & (kWave64 - 1), wave = tid / kWave64;
-    uint64_t kr[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int k = tid + r * NT;
-        double v = INFINITY;
-        if (k < lam) {
-            if (COMPOSE) {
-                v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
-                                     ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
-                if (ta.loss) ta.loss[k] = v;
-            } else {
-                v = loss[k];
-            }
-        }
-        kr[r] = order_key(v);
-    }
-    const double st_w = tid < mu ? S.weights[tid] : 0.0;
-    const double st_b = tid < nn ? S.B[tid] : 0.0;
-    const double st_c = tid < nn ? S.C[tid] : 0.0;
-    double st_pc = 0.0, st_ps = 0.0, st_d = 0.0;
-    if (tid < n) {
-        st_pc = S.p_c[tid];
-        st_ps = S.p_sigma[tid];
-        st_d = S.D[tid];
-    }
-    double yr[R][NMAX];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int k = tid + r * NT;
-#pragma unroll
-        for (int i = 0; i < NMAX; i++) yr[r][i] = (k < lam && i < n) ? S.Y[size_t(k) * n + i] : 0.0;
-    }
-    // 1a. each wave sorts its lists of 64 (key, index) pairs in registers
-    //     (NaN ranks as +inf) and stores them in LDS
-    int ir[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int l = wave + r * NW;
-        ir[r] = tid + r * NT;
-        if (64 * l < lam) {   // uniform over the wave
-            wave_sort64(kr[r], ir[r], lane);
-            s_rec[64 * l + lane] = RankRec{kr[r], ir[r], 0};
-        }
-    }
-    if (tid < mu) s_w[tid] = st_w;
-    if (tid < nn) {
-        s_B[tid] = st_b;
-        s_C[tid] = st_c;
-    }
-    if (tid < n) {
-        s_pc[tid] = st_pc;
-        s_ps[tid] = st_ps;
-        s_D[tid] = st_d;
-    }
+    constexpr bool kDrawZ = NMAX <= 9;          // the next generation's z drawn here
+    constexpr int CS = (NMAX * (NMAX + 1) / 2 + kWave64 - 1) / kWave64;   // Cholesky entries per lane
+    static_assert(NT >= 4 * kWave64, "wave 0 and three worker waves at least");
+    const bool worker = (wave & 3) != 0;
+    const int wi = wave - 1 - wave / 4;         // worker wave index (workers only)
+    const int wk = wi * kWave64 + lane;         // worker lane index
+
     const double sigma = *S.sigma, c_m = *S.c_m, mu_eff = *S.mu_eff, cs = *S.c_sigma, cc = *S.c_c;
     const double c1 = *S.c1, cmu = *S.c_mu, chi_n = *S.chi_n, ds = *S.d_sigma;
     const int64_t gen = S.hdr->gen;
     // the h_sigma denominator of this generation when the previous update
-    // cached it (same expression, same bits), else it is computed in step 3
+    // cached it (same expression, same bits)
     const int64_t denom_gen = S.hdr->denom_gen;
     const double denom_cached = S.hdr->denom;
-    __syncthreads();
-
-    // 1b. rank = position in the own sorted list + the number of records
-    //     ordered before it in each other list (four searches side by side).
-    //     The rank goes back to the lane that holds the candidate's row of Y
-    //     (a lane of the same wave), which writes it to the elite rows.
-    const int n_lists = (lam + 63) / 64;
+    // wave 0: C and the previous eigenvectors (the warm start of the
+    // eigendecomposition) from the state, in flight across the barrier below;
+    // in LDS as NMAX x NMAX matrices padded with zeros, so that the products
+    // of the warm start run over a fixed count (the padding adds exact zeros
+    // after the terms of the sums)
+    constexpr int GE = (NMAX * NMAX + kWave64 - 1) / kWave64;
+    double cr[GE], br[GE];
+    if (wave == 0) {
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int l = wave + r * NW;
-        if (64 * l < lam) {
-            const int idx = ir[r];
-            const uint64_t key = kr[r];
-            int rank = lane;
-            for (int l0 = 0; l0 < n_lists; l0 += 4) {   // uniform trip count
-                const RankRec* lists[4];
-                int b[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) lists[q] = s_rec + 64 * min(l0 + q, n_lists - 1);
-                count_before64x4(lists, key, idx, b);
-#pragma unroll
-                for (int q = 0; q < 4; q++) rank += (l0 + q >= n_lists || l0 + q == l) ? 0 : b[q];
-            }
-            if (idx < lam) S.order[rank] = idx;
-            // sorted lane -> the lane of candidate idx (idx mod 64): its rank
-            const int my_rank = __builtin_amdgcn_ds_permute(4 * (idx & (kWave64 - 1)), rank);
-            if (my_rank < mu && tid + r * NT < lam) {
-#pragma unroll
-                for (int i = 0; i < NMAX; i++)
-                    if (i < n) s_elite[my_rank * n + i] = yr[r][i];
-            }
+        for (int g = 0; g < GE; g++) {
+            const int e = lane + g * kWave64, i = e / NMAX, j = e % NMAX;
+            const bool in = e < NMAX * NMAX && i < n && j < n;
+            cr[g] = in ? S.C[i * n + j] : 0.0;
+            br[g] = in ? S.B[i * n + j] : 0.0;
         }
     }
-    __syncthreads();
-
-    // 2. weighted recombination y_w = sum_r w_r y_{r:lambda}
-    for (int task = tid; task < kParts * n; task += NT) {
-        const int part = task / n, i = task % n;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i];
-        s_part[part * n + i] = acc;
+    if (tid == 0) {
+        s_wbar[0] = 0;
+        s_wbar[1] = 0;
+        s_wbar[2] = 0;
+        s_wbar[3] = 0;
+        s_wbar[4] = 0;
+        s_flag[0] = 0;
+        s_flag[1] = 0;
     }
     __syncthreads();
-    // The mean, the paths and sigma (through step 3) are short chains on a
-    // single wave: wave 1 runs them with wave-level synchronisation, while
-    // wave 0 sets up the per-lane layout of the eigendecomposition (step 5),
-    // which depends on n and the block structure only.
+
+    // ---------------------------------------------------------- eigendecomposition (wave 0)
     const int m = nb + (nb & 1);
     const int k1 = m - 1;                      // rounds per sweep
     const int mm = m * m;
@@ -585,28 +641,28 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         if (p & 1) return p + 2 <= m - 1 ? p + 2 : m - 2;
         return p - 2;
     };
-    constexpr int kASlots = AS;
-    static_assert(VS == 2 * AS, "two V entries per A entry");
-    const int na_slots = (n_a + kWave64 - 1) / kWave64;
-    // A lane holds the entry (i, j), i <= j, of block b of A, and two V
-    // entries, in columns i and j: row j - i of column i and row
-    // m - j + i of column j (when < nb), which covers rows 0..m of every
-    // column exactly once over a block's entries.  What it reads comes in
-    // aligned pairs of adjacent columns (c & ~1, c | 1) of one row, at
-    // fixed offsets (in doubles, all even since m is even): rows i and
-    // i^1 at columns j&~1 (its entry and the partner entries), rows i,
-    // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
-    // rotations), and the two V rows at i&~1 and j&~1; it writes its
-    // entry (mirrored) and its V entries at their next positions.
-    int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
-    int a_w1[kASlots], a_w2[kASlots];
-    int a_dp[kASlots], a_dq[kASlots];      // diagonal blocks of the pairs of positions i and j
-    int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
-    bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
-    if (tid < kWave64) {
-    #pragma unroll
+    if (wave == 0) {
+        constexpr int kASlots = AS;
+        static_assert(VS == 2 * AS, "two V entries per A entry");
+        const int na_slots = (n_a + kWave64 - 1) / kWave64;
+        // A lane holds the entry (i, j), i <= j, of block b of A, and two V
+        // entries, in columns i and j: row j - i of column i and row
+        // m - j + i of column j (when < nb), which covers rows 0..m of every
+        // column exactly once over a block's entries.  What it reads comes in
+        // aligned pairs of adjacent columns (c & ~1, c | 1) of one row, at
+        // fixed offsets (in doubles, all even since m is even): rows i and
+        // i^1 at columns j&~1 (its entry and the partner entries), rows i,
+        // i^1 at i&~1 and rows j, j^1 at j&~1 (the operands of the two
+        // rotations), and the two V rows at i&~1 and j&~1; it writes its
+        // entry (mirrored) and its V entries at their next positions.
+        int a_rij[kASlots], a_rpj[kASlots], a_li[kASlots], a_lj[kASlots];
+        int a_w1[kASlots], a_w2[kASlots];
+        int a_dp[kASlots], a_dq[kASlots];      // diagonal blocks of the pairs of positions i and j
+        int v0_r[kASlots], v0_w[kASlots], v1_r[kASlots], v1_w[kASlots];
+        bool a_ok[kASlots], a_off[kASlots], a_ei[kASlots], a_ej[kASlots], v0_ok[kASlots], v1_ok[kASlots];
+#pragma unroll
         for (int sl = 0; sl < kASlots; sl++) {
-            const int e = min(tid + kWave64 * sl, n_a - 1);
+            const int e = min(lane + kWave64 * sl, n_a - 1);
             const int b = div_small(e, ntri_m), eb = e - b * ntri_m;
             const int i = tri_row(eb, m);
             const int j = i + eb - (i * m - (i * (i - 1)) / 2), base = b * mm, vbase = b * nb * m;
@@ -619,7 +675,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             a_dq[sl] = base + je * m + je;
             a_w1[sl] = base + move(i) * m + move(j);
             a_w2[sl] = base + move(j) * m + move(i);
-            a_ok[sl] = tid + kWave64 * sl < n_a;
+            a_ok[sl] = lane + kWave64 * sl < n_a;
             a_off[sl] = a_ok[sl] && i != j;
             a_ei[sl] = (i & 1) == 0;
             a_ej[sl] = (j & 1) == 0;
@@ -631,340 +687,516 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             v1_r[sl] = vbase + min(r1, nb - 1) * m + je;
             v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
-    }
-    static_assert(NT >= 4 * kWave64, "waves 1..3 have their own tasks while wave 0 sets up the eigendecomposition");
-    const int t1 = tid - kWave64;              // lane within wave 1
-    const bool on_w1 = (tid >> 6) == 1;
-    const int wv = tid >> 6;
-    if (on_w1) {
-        if (t1 < n) {
-            double acc = 0.0;
-            for (int part = 0; part < kParts; part++) acc += s_part[part * n + t1];
-            s_yw[t1] = acc;
-            s_mean[t1] = S.mean[t1] + c_m * sigma * acc;
-            S.mean[t1] = s_mean[t1];
+#pragma unroll
+        for (int g = 0; g < GE; g++) {
+            const int e = lane + g * kWave64;
+            if (e < NMAX * NMAX) {
+                s_Ce[e] = cr[g];
+                s_Bw[e] = br[g];
+            }
         }
         wave_sync();
-        // 3. C^{-1/2} y_w = B D^{-1} B^T y_w, then the evolution paths
-        if (t1 < n) {
-            double acc = 0.0;
-            for (int j = 0; j < n; j++) acc += s_B[j * n + t1] * s_yw[j];
-            s_t[t1] = acc / s_D[t1];
+        // warm start: A = B^T C B (nearly diagonal when C changed little), V = B;
+        // every rotation applies A <- J^T A J and V <- V J, so C = V diag(A) V^T at the end
+        for (int e = lane; e < NMAX * NMAX; e += kWave64) {
+            const int i = e / NMAX, j = e % NMAX;
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMAX; k++) t += s_Ce[i * NMAX + k] * s_Bw[k * NMAX + j];
+            s_X[e] = t;                                   // C B
         }
-        wave_sync();
-        if (t1 < n) {
-            double acc = 0.0;
-            for (int j = 0; j < n; j++) acc += s_B[t1 * n + j] * s_t[j];
-            s_ps[t1] = (1.0 - cs) * s_ps[t1] + sqrt(cs * (2.0 - cs) * mu_eff) * acc;
-            S.p_sigma[t1] = s_ps[t1];
-        }
-        wave_sync();
-        if (t1 == 0) {
-            double ss = 0.0;
-            for (int i = 0; i < n; i++) ss += s_ps[i] * s_ps[i];
-            const double ps_norm = sqrt(ss);
-            const double denom =
-                denom_gen == gen ? denom_cached : sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
-            const double h = (ps_norm / denom < (1.4 + 2.0 / (n + 1.0)) * chi_n) ? 1.0 : 0.0;
-            s_scal[0] = ps_norm;
-            s_scal[1] = h;
-            *S.h_sigma = h;
-            s_scal[3] = sigma * exp((cs / ds) * (ps_norm / chi_n - 1.0));
-            *S.sigma = s_scal[3];
-            S.hdr->gen = gen + 1;
-        }
-        wave_sync();
-        if (t1 < n) {
-            s_pc[t1] = (1.0 - cc) * s_pc[t1] + s_scal[1] * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[t1];
-            S.p_c[t1] = s_pc[t1];
-        }
-    } else if (wv == 2) {
-        // sum of the recombination weights: strided partial sums, then a fixed butterfly
-        const int t2 = tid & (kWave64 - 1);
-        double sw = 0.0;
-        for (int r = t2; r < mu; r += kWave64) sw += s_w[r];
-        for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
-        if (t2 == 0) s_scal[2] = sw;
-    } else if (wv == 3) {
-        // V = B in the positional layout of the eigendecomposition (step 5):
-        // index l of block b starts at position l (the dummy column is zero)
-        for (int e = tid & (kWave64 - 1); e < n_v; e += kWave64) {
+        for (int e = lane; e < n_v; e += kWave64) {
+            // V = B in the positional layout: index l of block b starts at position l
             const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
-            s_V[e] = j < nb ? s_B[(b * nb + r) * n + b * nb + j] : 0.0;
+            s_V[e] = j < nb ? s_Bw[(b * nb + r) * NMAX + b * nb + j] : 0.0;
         }
-    }
-    // 4a. (waves 2 and up, beside the paths) rank-mu partial sums of the
-    //     upper triangle, which do not depend on the paths
-    if (wv >= 2) {
-        for (int task = tid - 2 * kWave64; task < kParts * ntri; task += NT - 2 * kWave64) {
-            const int part = task / ntri, e = task - part * ntri;
-            const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
+        wave_sync();
+        // A = B^T C B in the positional layout, symmetrised: 0.5 (A_ij + A_ji)
+        // from both products (each summed over k in order); dummy rows and columns zero
+        for (int e = lane; e < n_blocks * mm; e += kWave64) {
+            const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
+            const int gi = b * nb + min(i, nb - 1), gj = b * nb + min(j, nb - 1);
+            double tij = 0.0, tji = 0.0;
+#pragma unroll
+            for (int k = 0; k < NMAX; k++) {
+                tij += s_Bw[k * NMAX + gi] * s_X[k * NMAX + gj];
+                tji += s_Bw[k * NMAX + gj] * s_X[k * NMAX + gi];
+            }
+            s_A[e] = (i < nb && j < nb) ? 0.5 * (tij + tji) : 0.0;
+        }
+        wave_sync();
+        {
+            // Cyclic Jacobi in tournament order with a fixed pairing, run by wave 0
+            // alone.  Each block is held in m = nb + (nb odd) positions (an odd
+            // block gets a zero dummy index, which never rotates): A as an m x m
+            // matrix and V as nb rows x m position columns.  In every round the
+            // pairs are the positions (2k, 2k+1); after the round, indices move to
+            // new positions (0 stays, 1 -> 3, 2 -> 1, other even p -> p - 2, other
+            // odd p -> p + 2, the last odd position -> m - 2), a round-robin in
+            // which every two indices of a block meet once per m - 1 rounds and the
+            // layout returns to the start.  The rotated A and V are written straight
+            // into their next positions, so every lane reads and writes the same LDS
+            // addresses in every round and computes them once.  Per round:
+            //   - the rotations of the pairs holding positions i and j of the lane's
+            //     entry (i, j), from the pairs' 2x2 diagonal blocks: computed in the
+            //     lane itself (one entry per lane) or taken from the lane of each
+            //     position by cross-lane shuffles (several);
+            //   - the entry of A' = J^T A J (mirrored) and two entries of V' = V J,
+            //     written into the other buffer at the next round's positions (with
+            //     no rotation this only moves the indices);
+            //   - when nothing rotated, the test whether any pair exceeds the
+            //     rotation threshold; if none does, the iteration has converged
+            //     (another sweep would rotate nothing).
+            const int max_rounds = kMaxSweeps * k1;   // even (kMaxSweeps is)
+            // constants of the conjugate path and the step size, ahead of need
+            const double ps_gain = sqrt(cs * (2.0 - cs) * mu_eff);
+            const double denom = denom_gen == gen ? denom_cached : sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 1)));
+            const double h_bound = (1.4 + 2.0 / (n + 1.0)) * chi_n;
+            const double cs_ds = cs / ds;
+            int moved = 0;                             // rounds applied (index moves) modulo k1
+            // (several entries per lane) lane t < n_blocks m computes the rotation
+            // of the pair holding position t, from the pair's 2x2 diagonal block
+            // (rows 2P, 2P+1 at column 2P)
+            const int n_pos = n_blocks * m;
+            const int t_pos = min(tid, n_pos - 1);
+            const int t_b = div_small(t_pos, m), t_p = t_pos - t_b * m, t_2P = t_p & ~1;
+            const int t_rp = t_b * mm + t_2P * m + t_2P, t_rq = t_rp + m;
+            const bool t_even = (t_p & 1) == 0;
+            auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
+            // One round from (Ac, Vc) into (An, Vn); true when it found the
+            // iteration converged.  Every round rotates and moves the indices (with
+            // no rotation this only moves them); the test whether to stop follows
+            // the stores, so that it is not on the path from one round to the next.
+            auto jacobi_round = [&](const double* Ac, double* An, const double* Vc, double* Vn) -> bool {
+                // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1) and the
+                // two V rows at columns 2P and 2Q, read with no branch (every slot's
+                // offsets are valid; slots past the last entry repeat it)
+                double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
+        #pragma unroll
+                for (int sl = 0; sl < kASlots; sl++) {
+                    blk0[sl] = pair(Ac, a_rij[sl]);
+                    blk1[sl] = pair(Ac, a_rpj[sl]);
+                    vr0[sl] = pair(Vc, v0_r[sl]);
+                    vr1[sl] = pair(Vc, v1_r[sl]);
+                }
+                // the rotation columns u, w of positions i and j, and A(i, i), A(j, j)
+                double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots], di[kASlots], dj[kASlots];
+                bool rot;
+                if constexpr (AS == 1) {
+                    // one entry per lane: the lane computes both rotations itself
+                    // from the pairs' diagonal blocks (read with its other operands),
+                    // with no exchange between lanes
+                    const double2 p0 = pair(Ac, a_dp[0]), p1 = pair(Ac, a_dp[0] + m);
+                    const double2 q0 = pair(Ac, a_dq[0]), q1 = pair(Ac, a_dq[0] + m);
+                    const double app[2] = {p0.x, q0.x}, aqq[2] = {p1.y, q1.y}, apq[2] = {p0.y, q0.y};
+                    double cs2[2], sn2[2];
+                    bool r2[2];
+                    pair_rotation2(app, aqq, apq, cs2, sn2, r2);
+                    const double cp = cs2[0], sp = sn2[0], cq = cs2[1], sq = sn2[1];
+                    const bool rp = r2[0], rq = r2[1];
+                    // column of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
+                    u0[0] = a_ei[0] ? cp : sp;
+                    u1[0] = a_ei[0] ? -sp : cp;
+                    w0[0] = a_ej[0] ? cq : sq;
+                    w1[0] = a_ej[0] ? -sq : cq;
+                    di[0] = a_ei[0] ? p0.x : p1.y;
+                    dj[0] = a_ej[0] ? q0.x : q1.y;
+                    rot = rp || rq;
+                } else {
+                    // lane t < n_blocks m computes the rotation of the pair holding
+                    // position t; the entry lanes take the columns by cross-lane shuffles
+                    const double2 bp = pair(Ac, t_rp), bq = pair(Ac, t_rq);
+                    double c_t, sn_t;
+                    rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
+                    const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
+                    const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
+        #pragma unroll
+                    for (int sl = 0; sl < kASlots; sl++) {
+                        u0[sl] = __shfl(col0_t, a_li[sl]);
+                        u1[sl] = __shfl(col1_t, a_li[sl]);
+                        w0[sl] = __shfl(col0_t, a_lj[sl]);
+                        w1[sl] = __shfl(col1_t, a_lj[sl]);
+                        di[sl] = __shfl(dd_t, a_li[sl]);
+                        dj[sl] = __shfl(dd_t, a_lj[sl]);
+                    }
+                }
+        #pragma unroll
+                for (int sl = 0; sl < kASlots; sl++) {
+                    if (sl < na_slots) {
+                        // A'(i, j) = u^T B w; a lane past the last entry recomputes the
+                        // last entry, so its duplicate stores write the same value
+                        const double r0 = fma(w0[sl], blk0[sl].x, w1[sl] * blk0[sl].y);
+                        const double r1 = fma(w0[sl], blk1[sl].x, w1[sl] * blk1[sl].y);
+                        const double v = fma(u0[sl], r0, u1[sl] * r1);
+                        An[a_w1[sl]] = v;
+                        An[a_w2[sl]] = v;
+                        // V'(r, i) = V(r, 2P) u0 + V(r, 2P+1) u1, likewise at column j
+                        double* d0 = v0_ok[sl] ? Vn + v0_w[sl] : s_sink + tid;
+                        double* d1 = v1_ok[sl] ? Vn + v1_w[sl] : s_sink + kWave64 + tid;
+                        *d0 = fma(u0[sl], vr0[sl].x, u1[sl] * vr0[sl].y);
+                        *d1 = fma(w0[sl], vr1[sl].x, w1[sl] * vr1[sl].y);
+                    }
+                }
+                wave_sync();
+                moved = moved + 1 == k1 ? 0 : moved + 1;
+                if (__ballot(rot) != 0ull) return false;
+                // nothing rotated in this round: converged when no pair exceeds the
+                // threshold (another sweep would rotate nothing)
+                bool open = false;
+        #pragma unroll
+                for (int sl = 0; sl < kASlots; sl++) {
+                    if (sl < na_slots) {
+                        const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
+                        const double aij = a_ej[sl] ? row.x : row.y;
+                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(di[sl] * dj[sl]);
+                    }
+                }
+                return __ballot(open) == 0ull;
+            };
+            // the rounds alternate between two buffer pairs; the result is in the
+            // pair the last round wrote
+            const double* Acur = s_A;
+            const double* Vcur = s_V;
+            for (int it = 0; it < max_rounds; it += 2) {
+                if (jacobi_round(s_A, s_T, s_V, s_Vn)) {
+                    Acur = s_T;
+                    Vcur = s_Vn;
+                    break;
+                }
+                if (jacobi_round(s_T, s_A, s_Vn, s_V)) break;
+            }
+            // final position of every index; D = sqrt(eigenvalues) with a floor
+            // at 1e-20 * max (the maximum over the lanes ignores NaN like a
+            // running fmax from 0).  B is V with its columns in index order,
+            // gathered after the workgroup barrier below; the conjugate path
+            // reads V through the positions.
+            if (lane == 0) s_vsel = Vcur == s_V ? 0 : 1;
+            double ev = 0.0;
+            int pos_l = 0;
+            if (lane < n) {
+                const int tb = div_small(lane, nb);
+                pos_l = lane - tb * nb;
+                for (int r = 0; r < moved; r++) pos_l = move(pos_l);
+                s_pos[lane] = pos_l;
+                ev = Acur[tb * mm + pos_l * m + pos_l];
+            }
+            const double emax = wave_max_f64(lane < n ? fmax(0.0, ev) : 0.0, lane);
+            const double floor_v = 1e-20 * emax;
+            const bool floored = lane < n && !(ev >= floor_v);
+            const double d_l = sqrt(floored ? floor_v : ev);
+            if (lane < n) s_D[lane] = d_l;
+            if (lane == 0) s_flag[0] = (__ballot(floored) != 0ull ? 1 : 0) | (emax < INFINITY ? 0 : 2);
+            // V, the positions and D are final: a worker wave gathers B
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) __hip_atomic_store(&s_wbar[4], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // 5. the conjugate path p_sigma with C^(-1/2) y_w = B D^(-1) B^T y_w
+            //    (y_w from the first worker wave, long done by now), its length,
+            //    h_sigma and sigma
+            if (lane == 0) {
+                int spin = 0;
+                while (__hip_atomic_load(&s_wbar[3], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                    if (++spin == kWaitBound) {
+                        __hip_atomic_store(&s_wbar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            // (B^T y_w)_l = sum_i V(i, pos l) y_w,i over the rows i of l's block;
+            // (B t)_l = sum_j V(l, pos j) t_j over the indices j of l's block (the
+            // other blocks' terms of the full sums are exact zeros)
+            const int lb = lane < n ? div_small(lane, nb) : 0;
+            const int l_row = lane < n ? lane - lb * nb : 0;
+            const double* Vb = Vcur + lb * nb * m;
+            if (lane < n) {
+                double acc = 0.0;
+    #pragma unroll
+                for (int i = 0; i < NMAX; i++)
+                    if (i < nb) acc += Vb[i * m + pos_l] * s_yw[lb * nb + i];
+                s_t[lane] = acc / d_l;
+            }
+            wave_sync();
+            double ps_l = 0.0;
+            if (lane < n) {
+                double acc = 0.0;
+    #pragma unroll
+                for (int j = 0; j < NMAX; j++)
+                    if (j < nb) acc += Vb[l_row * m + s_pos[lb * nb + j]] * s_t[lb * nb + j];
+                ps_l = (1.0 - cs) * s_ps[lane] + ps_gain * acc;
+                s_ps[lane] = ps_l;
+            }
+            // ||p_sigma||^2 by a fixed butterfly over the lanes
+            double ss = ps_l * ps_l;
+            ss += lane_xor_f64<32>(ss, lane);
+            ss += lane_xor_f64<16>(ss, lane);
+            ss += lane_xor_f64<8>(ss, lane);
+            ss += lane_xor_f64<4>(ss, lane);
+            ss += lane_xor_f64<2>(ss, lane);
+            ss += lane_xor_f64<1>(ss, lane);
+            if (lane == 0) {
+                const double ps_norm = sqrt(ss);
+                s_scal[0] = ps_norm;
+                s_scal[1] = (ps_norm / denom < h_bound) ? 1.0 : 0.0;
+                const double sg = sigma * exp(cs_ds * (ps_norm / chi_n - 1.0));
+                s_scal[3] = sg;
+                if (!(sg > 0.0 && sg < INFINITY)) s_flag[0] |= 2;
+            }
+        }
+    } else if (worker) {
+        // ------------------------------------------------------ ranking and the covariance (waves on other SIMDs)
+        // 0. Worker lane wk holds candidates k = wk + r NWK (r < R), i.e. entry
+        //    `lane` of list l = wi + r NWW of 64 candidates, with their keys
+        //    and rows of Y; keys past lambda are +inf, and their indices order
+        //    them last.  The state goes through registers into LDS after the
+        //    sort, so that its loads and the count loads are in flight together.
+        uint64_t kr[R];
+        int ir[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int k = wk + r * NWK;
+            double v = INFINITY;
+            if (k < lam) {
+                if (COMPOSE) {
+                    v = compose_loss_one(ta.counts[2 * k], ta.counts[2 * k + 1], *ta.target_count,
+                                         ta.kp ? ta.kp + size_t(k) * ta.la.n_arms * 8 : nullptr, ta.kp_ref, ta.la);
+                    if (ta.loss) ta.loss[k] = v;
+                } else {
+                    v = loss[k];
+                }
+            }
+            kr[r] = order_key(v);
+            ir[r] = k;
+        }
+        double yr[R][NMAX];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int k = wk + r * NWK;
+#pragma unroll
+            for (int i = 0; i < NMAX; i++) yr[r][i] = (k < lam && i < n) ? S.Y[size_t(k) * n + i] : 0.0;
+        }
+        // 1a. each worker wave sorts its lists of 64 (key, index) pairs in
+        //     registers (NaN ranks as +inf) and stores them in LDS
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int l = wi + r * NWW;
+            if (64 * l < lam) {   // uniform over the wave
+                wave_sort64(kr[r], ir[r], lane);
+                s_rec[64 * l + lane] = RankRec{kr[r], ir[r], 0};
+            }
+        }
+        for (int i = wk; i < mu; i += NWK) s_w[i] = S.weights[i];
+        for (int e = wk; e < nn; e += NWK) s_C[e] = S.C[e];
+        if (wk < n) {
+            s_pc[wk] = S.p_c[wk];
+            s_ps[wk] = S.p_sigma[wk];
+            s_mean[wk] = S.mean[wk];
+        }
+        wave_group_barrier(s_wbar, NWW);
+
+        // 1b. rank = position in the own sorted list + the number of records
+        //     ordered before it in each other list (four searches side by
+        //     side).  The rank goes back to the lane that holds the candidate's
+        //     row of Y (a lane of the same wave), which writes the elite rows.
+        const int n_lists = (lam + 63) / 64;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int l = wi + r * NWW;
+            if (64 * l < lam) {
+                const int idx = ir[r];
+                const uint64_t key = kr[r];
+                int rank = lane;
+                for (int l0 = 0; l0 < n_lists; l0 += 4) {   // uniform trip count
+                    const RankRec* lists[4];
+                    int b[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) lists[q] = s_rec + 64 * min(l0 + q, n_lists - 1);
+                    count_before64x4(lists, key, idx, b);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) rank += (l0 + q >= n_lists || l0 + q == l) ? 0 : b[q];
+                }
+                if (idx < lam) S.order[rank] = idx;
+                // sorted lane -> the lane of candidate idx (idx mod 64): its rank
+                const int my_rank = __builtin_amdgcn_ds_permute(4 * (idx & (kWave64 - 1)), rank);
+                if (my_rank < mu && wk + r * NWK < lam) {
+#pragma unroll
+                    for (int i = 0; i < NMAX; i++)
+                        if (i < n) s_elite[my_rank * n + i] = yr[r][i];
+                }
+            }
+        }
+        wave_group_barrier(s_wbar, NWW);
+
+        // 2. weighted recombination y_w = sum_r w_r y_{r:lambda}: partial sums
+        for (int task = wk; task < kParts * n; task += NWK) {
+            const int part = task / n, i = task % n;
             double acc = 0.0;
 #pragma unroll 4
-            for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
-            s_partc[part * ntri + e] = acc;
+            for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i];
+            s_part[part * n + i] = acc;
         }
-    }
-    __syncthreads();
-    const double h_sigma = s_scal[1], sum_w = s_scal[2];
+        wave_group_barrier(s_wbar, NWW);
 
-    // 4b. covariance: rank-one + rank-mu, symmetric, block-masked (into s_T)
-    const double delta = (1.0 - h_sigma) * cc * (2.0 - cc);
-    const double keep = 1.0 - c1 - cmu * sum_w;
-    for (int e = tid; e < ntri; e += NT) {
-        const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
-        double rmu = 0.0;
-        for (int part = 0; part < kParts; part++) rmu += s_partc[part * ntri + e];
-        const double cij = keep * s_C[i * n + j] + c1 * (s_pc[i] * s_pc[j] + delta * s_C[i * n + j]) + cmu * rmu;
-        const double cji = keep * s_C[j * n + i] + c1 * (s_pc[j] * s_pc[i] + delta * s_C[j * n + i]) + cmu * rmu;
-        double v = 0.5 * (cij + cji);
-        if (i / nb != j / nb) v = 0.0;   // block-diagonal covariance
-        s_T[i * n + j] = v;
-        s_T[j * n + i] = v;
-    }
-    __syncthreads();
-
-    // 5. Jacobi eigendecomposition, warm-started from the previous eigenvectors:
-    //    A = B^T C B (nearly diagonal when C changed little), V = B; every
-    //    rotation applies A <- J^T A J and V <- V J, so C = V diag(A) V^T at the end.
-    for (int e = tid; e < nn; e += NT) {
-        const int i = e / n, j = e % n;
-        double t = 0.0;
-        for (int k = 0; k < n; k++) t += s_T[i * n + k] * s_B[k * n + j];
-        s_X[e] = t;                                   // C B
-        S.C[e] = s_T[e];
-    }
-    __syncthreads();
-    // A = B^T C B in the positional layout, symmetrised: 0.5 (A_ij + A_ji)
-    // from both products (each summed over k in order); dummy rows and columns zero
-    for (int e = tid; e < n_blocks * mm; e += NT) {
-        const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
-        double v = 0.0;
-        if (i < nb && j < nb) {
-            const int gi = b * nb + i, gj = b * nb + j;
-            double tij = 0.0, tji = 0.0;
-            for (int k = 0; k < n; k++) {
-                tij += s_B[k * n + gi] * s_X[k * n + gj];
-                tji += s_B[k * n + gj] * s_X[k * n + gi];
+        // 3. (worker wave 0) y_w, the mean, and the evolution path p_c as it is
+        //    when h_sigma = 1; (the others) the sum of the weights and the
+        //    rank-mu partial sums of the upper triangle
+        if (wi == 0) {
+            if (lane < n) {
+                double acc = 0.0;
+                for (int part = 0; part < kParts; part++) acc += s_part[part * n + lane];
+                s_yw[lane] = acc;
+                const double mnew = s_mean[lane] + c_m * sigma * acc;
+                s_mean[lane] = mnew;
+                S.mean[lane] = mnew;
+                s_pc1[lane] = (1.0 - cc) * s_pc[lane] + 1.0 * sqrt(cc * (2.0 - cc) * mu_eff) * acc;
             }
-            v = 0.5 * (tij + tji);
+            // y_w is ready for the conjugate path (wave 0)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) __hip_atomic_store(&s_wbar[3], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            if (wi == 1) {
+                // sum of the recombination weights: strided partial sums, then a fixed butterfly
+                double sw = 0.0;
+                for (int r = lane; r < mu; r += kWave64) sw += s_w[r];
+                for (int off = kWave64 / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off);
+                if (lane == 0) s_scal[2] = sw;
+            }
+            for (int task = wk - kWave64; task < kParts * ntri; task += NWK - kWave64) {
+                const int part = task / ntri, e = task - part * ntri;
+                const int i = tri_row(e, n), j = i + e - (i * n - (i * (i - 1)) / 2);
+                double acc = 0.0;
+#pragma unroll 4
+                for (int r = part; r < mu; r += kParts) acc += s_w[r] * s_elite[r * n + i] * s_elite[r * n + j];
+                s_partc[part * ntri + e] = acc;
+            }
         }
-        s_A[e] = v;
+        wave_group_barrier(s_wbar, NWW);
+
+        // 4. the new covariance for h_sigma = 1 (rank-one term from that p_c,
+        //    no h_sigma correction), then its Cholesky factor (worker wave 0)
+        //    while the other workers draw the next generation's z
+        covariance_entries(wk, NWK, n, nb, ntri, 1.0 - c1 - cmu * s_scal[2], c1, cmu, 0.0, s_pc1, s_C, s_partc,
+                           s_Cn);
+        wave_group_barrier(s_wbar, NWW);
+        if (wi == 0) {
+            const bool fl = wave_cholesky<CS>(s_Cn, s_Cw, s_L, n, nb, lane);
+            if (lane == 0) s_flag[1] = fl ? 1 : 0;
+            // the new C, its factor and p_c as they are when h_sigma = 1 (written
+            // again below otherwise)
+            if (lane < n) S.p_c[lane] = s_pc1[lane];
+            for (int e = lane; e < nn; e += kWave64) {
+                S.C[e] = s_Cn[e];
+                S.L[e] = s_L[e];
+            }
+        } else {
+            // the next generation's h_sigma denominator, cached in the state with
+            // its generation, and (n <= 9) its z, exactly as a sampler would draw
+            // them (they depend on the seed and generation only).  With up to 18
+            // dimensions the draws (5 per candidate) would outlast the
+            // eigendecomposition on these waves; the next generation's draw
+            // (ask-eval prologue, sampler, or the tell-ask tail) makes them then.
+            if (wk == kWave64) {
+                S.hdr->denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 2)));
+                S.hdr->denom_gen = gen + 1;
+                if (kDrawZ) S.hdr->z_gen = gen + 1;   // the loop below has written Z when the kernel ends
+            }
+            if (kDrawZ) {
+                const uint32_t gnext = uint32_t(gen + 1);
+                const uint64_t seed = S.hdr->seed;
+                const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
+                const int groups = (n + 3) / 4;
+                for (int task = wk - kWave64; task < lam * groups; task += NWK - kWave64) {
+                    const int k = div_small(task, groups), j = task - k * groups;
+                    double z[4];
+                    draw_normals(key0, key1, gnext, k, j, z);
+                    for (int t = 0; t < 4; t++)
+                        if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
+                }
+            }
+            if (wi == 1) {
+                // B = V with its columns in index order (position s_pos[j] holds
+                // index j), and D, once wave 0 has them
+                if (lane == 0) {
+                    int spin = 0;
+                    while (__hip_atomic_load(&s_wbar[4], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {
+                        if (++spin == kWaitBound) {
+                            __hip_atomic_store(&s_wbar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const double* Vres = s_vsel ? s_Vn : s_V;
+                for (int e = lane; e < nn; e += kWave64) {
+                    const int i = div_small(e, n), j = e - i * n, b = div_small(i, nb);
+                    const double v = b == div_small(j, nb) ? Vres[b * nb * m + (i - b * nb) * m + s_pos[j]] : 0.0;
+                    s_B[e] = v;
+                    S.B[e] = v;
+                }
+                if (lane < n) S.D[lane] = s_D[lane];
+            }
+        }
     }
     __syncthreads();
+    const double h_sigma = s_scal[1];
 
-    // Cyclic Jacobi in tournament order with a fixed pairing, run by wave 0
-    // alone (no workgroup barriers).  Each block is held in m = nb + (nb odd)
-    // positions (an odd block gets a zero dummy index, which never rotates):
-    // A as an m x m matrix and V as nb rows x m position columns.  In every
-    // round the pairs are the positions (2k, 2k+1); after the round, indices
-    // move to new positions (0 stays, 1 -> 3, 2 -> 1, other even p -> p - 2,
-    // other odd p -> p + 2, the last odd position -> m - 2), a round-robin in
-    // which every two indices of a block meet once per m - 1 rounds and the
-    // layout returns to the start.  The rotated A and V are written straight
-    // into their next positions, so every lane reads and writes the same LDS
-    // addresses in every round and computes them once.  Per round:
-    //   - lane t < n_blocks m computes the rotation of the pair holding
-    //     position t from the pair's 2x2 diagonal block;
-    //   - every lane holding an upper-triangle entry (i, j) of A takes the
-    //     rotations of positions i and j from those lanes (cross-lane
-    //     shuffles) and reads its entry's 2x2 neighbourhood and its V entries;
-    //   - when nothing rotates anywhere, it tests its entry against the
-    //     rotation threshold; if no pair exceeds it the iteration has
-    //     converged (another sweep would rotate nothing);
-    //   - it writes its entry of A' = J^T A J (mirrored) and two entries of
-    //     V' = V J into the other buffer, at the next round's positions (with
-    //     no rotation this only moves the indices).
-    if (tid == kWave64) {
-        // while wave 0 runs the eigendecomposition: the next generation's
-        // h_sigma denominator, cached in the state with its generation
-        S.hdr->denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 2)));
-        S.hdr->denom_gen = gen + 1;
-        S.hdr->z_gen = gen + 1;   // the loop below has written Z when the kernel ends
+    if (h_sigma != 1.0) {
+        // h_sigma = 0: p_c without the y_w term, the covariance with the h_sigma
+        // correction, and its factor again
+        if (tid < n) s_pc1[tid] = (1.0 - cc) * s_pc[tid] + h_sigma * sqrt(cc * (2.0 - cc) * mu_eff) * s_yw[tid];
+        __syncthreads();
+        covariance_entries(tid, NT, n, nb, ntri, 1.0 - c1 - cmu * s_scal[2], c1, cmu, (1.0 - h_sigma) * cc * (2.0 - cc),
+                           s_pc1, s_C, s_partc, s_Cn);
+        __syncthreads();
+        if (wave == 0) {
+            const bool fl = wave_cholesky<CS>(s_Cn, s_Cw, s_L, n, nb, lane);
+            if (lane == 0) s_flag[1] = fl ? 1 : 0;
+        }
+        __syncthreads();
+        if (tid < n) S.p_c[tid] = s_pc1[tid];
+        for (int e = tid; e < nn; e += NT) {
+            S.C[e] = s_Cn[e];
+            S.L[e] = s_L[e];
+        }
     }
-    if (tid >= kWave64 && ((tid / kWave64) & 3) != 0) {
-        // meanwhile the waves that do not share wave 0's SIMD (under the
-        // usual round-robin placement) draw the next generation's z, exactly
-        // as a sampler would: they depend on the seed and generation only
-        constexpr int NW = NT / kWave64;
-        const int w = tid / kWave64;
-        const int li = (w - 1 - w / 4) * kWave64 + (tid & (kWave64 - 1));
-        const int stride = ((NW - 1) - (NW - 1) / 4) * kWave64;
+    // the rest of the state: p_sigma, sigma, h_sigma, generation, flags
+    if (tid < n) S.p_sigma[tid] = s_ps[tid];
+    if (tid == 0) {
+        *S.h_sigma = h_sigma;
+        *S.sigma = s_scal[3];
+        S.hdr->gen = gen + 1;
+    }
+    if (tid == 0) S.hdr->flags = ((s_flag[0] | s_flag[1]) & 1) | (s_flag[0] & 2) | (s_wbar[2] ? 4 : 0);
+    if (!ASK) return;
+
+    // 6. (tell-ask form) the next generation: the same draws and arithmetic as
+    //    the sample kernel (z by Philox + Box-Muller with the incremented
+    //    generation, y = L z, x = m + sigma y, theta = offset + scale x), then
+    //    the forward kinematics of every candidate and arm
+    const double sigma_next = s_scal[3];
+    if (!kDrawZ) {
+        // the next generation's z (not drawn beside the eigendecomposition)
         const uint32_t gnext = uint32_t(gen + 1);
         const uint64_t seed = S.hdr->seed;
         const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
         const int groups = (n + 3) / 4;
-        for (int task = li; task < lam * groups; task += stride) {
+        for (int task = tid; task < lam * groups; task += NT) {
             const int k = div_small(task, groups), j = task - k * groups;
             double z[4];
             draw_normals(key0, key1, gnext, k, j, z);
             for (int t = 0; t < 4; t++)
                 if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
         }
+        if (tid == 0) S.hdr->z_gen = gen + 1;
+        __syncthreads();
     }
-    if (tid < kWave64) {
-        const int max_rounds = kMaxSweeps * k1;   // even (kMaxSweeps is)
-        int moved = 0;                             // rounds applied (index moves) modulo k1
-        // (several entries per lane) lane t < n_blocks m computes the rotation
-        // of the pair holding position t, from the pair's 2x2 diagonal block
-        // (rows 2P, 2P+1 at column 2P)
-        const int n_pos = n_blocks * m;
-        const int t_pos = min(tid, n_pos - 1);
-        const int t_b = div_small(t_pos, m), t_p = t_pos - t_b * m, t_2P = t_p & ~1;
-        const int t_rp = t_b * mm + t_2P * m + t_2P, t_rq = t_rp + m;
-        const bool t_even = (t_p & 1) == 0;
-        auto pair = [](const double* base, int off) { return *reinterpret_cast<const double2*>(base + off); };
-        // One round from (Ac, Vc) into (An, Vn); true when it found the
-        // iteration converged.  Every round rotates and moves the indices (with
-        // no rotation this only moves them); the test whether to stop follows
-        // the stores, so that it is not on the path from one round to the next.
-        auto jacobi_round = [&](const double* Ac, double* An, const double* Vc, double* Vn) -> bool {
-            // the entry's 2x2 block B (rows 2P, 2P+1, columns 2Q, 2Q+1) and the
-            // two V rows at columns 2P and 2Q, read with no branch (every slot's
-            // offsets are valid; slots past the last entry repeat it)
-            double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
-    #pragma unroll
-            for (int sl = 0; sl < kASlots; sl++) {
-                blk0[sl] = pair(Ac, a_rij[sl]);
-                blk1[sl] = pair(Ac, a_rpj[sl]);
-                vr0[sl] = pair(Vc, v0_r[sl]);
-                vr1[sl] = pair(Vc, v1_r[sl]);
-            }
-            // the rotation columns u, w of positions i and j, and A(i, i), A(j, j)
-            double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots], di[kASlots], dj[kASlots];
-            bool rot;
-            if constexpr (AS == 1) {
-                // one entry per lane: the lane computes both rotations itself
-                // from the pairs' diagonal blocks (read with its other operands),
-                // with no exchange between lanes
-                const double2 p0 = pair(Ac, a_dp[0]), p1 = pair(Ac, a_dp[0] + m);
-                const double2 q0 = pair(Ac, a_dq[0]), q1 = pair(Ac, a_dq[0] + m);
-                const double app[2] = {p0.x, q0.x}, aqq[2] = {p1.y, q1.y}, apq[2] = {p0.y, q0.y};
-                double cs2[2], sn2[2];
-                bool r2[2];
-                pair_rotation2(app, aqq, apq, cs2, sn2, r2);
-                const double cp = cs2[0], sp = sn2[0], cq = cs2[1], sq = sn2[1];
-                const bool rp = r2[0], rq = r2[1];
-                // column of the pair rotation: (c, -s) at an even position, (s, c) at an odd one
-                u0[0] = a_ei[0] ? cp : sp;
-                u1[0] = a_ei[0] ? -sp : cp;
-                w0[0] = a_ej[0] ? cq : sq;
-                w1[0] = a_ej[0] ? -sq : cq;
-                di[0] = a_ei[0] ? p0.x : p1.y;
-                dj[0] = a_ej[0] ? q0.x : q1.y;
-                rot = rp || rq;
-            } else {
-                // lane t < n_blocks m computes the rotation of the pair holding
-                // position t; the entry lanes take the columns by cross-lane shuffles
-                const double2 bp = pair(Ac, t_rp), bq = pair(Ac, t_rq);
-                double c_t, sn_t;
-                rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
-                const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
-                const double col0_t = t_even ? c_t : sn_t, col1_t = t_even ? -sn_t : c_t;
-    #pragma unroll
-                for (int sl = 0; sl < kASlots; sl++) {
-                    u0[sl] = __shfl(col0_t, a_li[sl]);
-                    u1[sl] = __shfl(col1_t, a_li[sl]);
-                    w0[sl] = __shfl(col0_t, a_lj[sl]);
-                    w1[sl] = __shfl(col1_t, a_lj[sl]);
-                    di[sl] = __shfl(dd_t, a_li[sl]);
-                    dj[sl] = __shfl(dd_t, a_lj[sl]);
-                }
-            }
-    #pragma unroll
-            for (int sl = 0; sl < kASlots; sl++) {
-                if (sl < na_slots) {
-                    // A'(i, j) = u^T B w; a lane past the last entry recomputes the
-                    // last entry, so its duplicate stores write the same value
-                    const double r0 = fma(w0[sl], blk0[sl].x, w1[sl] * blk0[sl].y);
-                    const double r1 = fma(w0[sl], blk1[sl].x, w1[sl] * blk1[sl].y);
-                    const double v = fma(u0[sl], r0, u1[sl] * r1);
-                    An[a_w1[sl]] = v;
-                    An[a_w2[sl]] = v;
-                    // V'(r, i) = V(r, 2P) u0 + V(r, 2P+1) u1, likewise at column j
-                    double* d0 = v0_ok[sl] ? Vn + v0_w[sl] : s_sink + tid;
-                    double* d1 = v1_ok[sl] ? Vn + v1_w[sl] : s_sink + kWave64 + tid;
-                    *d0 = fma(u0[sl], vr0[sl].x, u1[sl] * vr0[sl].y);
-                    *d1 = fma(w0[sl], vr1[sl].x, w1[sl] * vr1[sl].y);
-                }
-            }
-            wave_sync();
-            moved = moved + 1 == k1 ? 0 : moved + 1;
-            if (__ballot(rot) != 0ull) return false;
-            // nothing rotated in this round: converged when no pair exceeds the
-            // threshold (another sweep would rotate nothing)
-            bool open = false;
-    #pragma unroll
-            for (int sl = 0; sl < kASlots; sl++) {
-                if (sl < na_slots) {
-                    const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
-                    const double aij = a_ej[sl] ? row.x : row.y;
-                    open |= a_off[sl] && aij * aij > 1e-30 * fabs(di[sl] * dj[sl]);
-                }
-            }
-            return __ballot(open) == 0ull;
-        };
-        // the rounds alternate between two buffer pairs; the result is in the
-        // pair the last round wrote
-        const double* Acur = s_A;
-        const double* Vcur = s_V;
-        for (int it = 0; it < max_rounds; it += 2) {
-            if (jacobi_round(s_A, s_T, s_V, s_C)) {
-                Acur = s_T;
-                Vcur = s_C;
-                break;
-            }
-            if (jacobi_round(s_T, s_A, s_C, s_V)) break;
-        }
-        // final position of every index; 6. D = sqrt(eigenvalues) with a
-        // floor at 1e-20 * max (the maximum by a butterfly over the lanes,
-        // which ignores NaN like a running fmax from 0), B = V
-        double ev = 0.0;
-        if (tid < n) {
-            const int tb = div_small(tid, nb);
-            int p = tid - tb * nb;
-            for (int r = 0; r < moved; r++) p = move(p);
-            s_pos[tid] = p;
-            ev = Acur[tb * mm + p * m + p];
-        }
-        const double emax = wave_max_f64(tid < n ? fmax(0.0, ev) : 0.0, tid);
-        const double floor_v = 1e-20 * emax;
-        const bool floored = tid < n && !(ev >= floor_v);
-        if (tid < n) {
-            const double d = sqrt(floored ? floor_v : ev);
-            S.D[tid] = d;
-            s_D[tid] = d;
-        }
-        const bool any_floored = __ballot(floored) != 0ull;
-        if (tid == 0) {
-            const double sg = *S.sigma;
-            int flags = any_floored ? 1 : 0;
-            if (!(sg > 0.0 && sg < INFINITY) || !(emax < INFINITY)) flags |= 2;
-            S.hdr->flags = flags;
-        }
-        wave_sync();
-        for (int e = tid; e < nn; e += kWave64) {
-            const int i = div_small(e, n), j = e - i * n, b = div_small(i, nb);
-            const double v = b == div_small(j, nb) ? Vcur[b * nb * m + (i - b * nb) * m + s_pos[j]] : 0.0;
-            S.B[e] = v;
-            s_B[e] = v;
-        }
-    }
-    if (!ASK) return;
-
-    // 7. (tell-ask form) the next generation: the same draws and arithmetic as
-    //    the sample kernel (z by Philox + Box-Muller with the incremented
-    //    generation, y = B D z, x = m + sigma y, theta = offset + scale x), then
-    //    the forward kinematics of every candidate and arm
-    __syncthreads();
-    // (z of the next generation were drawn during the eigendecomposition)
-    for (int e = tid; e < nn; e += NT) s_T[e] = s_B[e] * s_D[e % n];
-    __syncthreads();
-    const double sigma_next = s_scal[3];
     for (int task = tid; task < lam * n; task += NT) {
         const int k = task / n, i = task % n;
         double y;
-        ta.X[task] = candidate_coord(s_T, S.Z + size_t(k) * n, n, i, s_mean[i], sigma_next, S.offset[i],
+        ta.X[task] = candidate_coord(s_L, S.Z + size_t(k) * n, n, i, s_mean[i], sigma_next, S.offset[i],
                                      S.scale[i], &y);
         S.Y[task] = y;
     }

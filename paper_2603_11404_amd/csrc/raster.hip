@@ -518,7 +518,7 @@ struct RasterArgs {
 
 // Ask-eval prologue, run by wave 0 of workgroup b: candidate b of the current
 // generation is drawn exactly as the sample kernel draws it (same generator,
-// same B D product and arithmetic), written to X and the state's Z and Y, and
+// same factor L and arithmetic), written to X and the state's Z and Y, and
 // its forward kinematics (same device function as the FK kernel) goes to the
 // LDS transforms s_M and to link_xf_out / kp.  When the state already holds
 // this generation's z (drawn by the previous update), they are read instead
@@ -526,8 +526,8 @@ struct RasterArgs {
 __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
     const int n = a.n;
     StateView S = state_view(a.state, n, a.lam);
-    double* s_BD = reinterpret_cast<double*>(scratch);              // [n][n]
-    double* s_z = s_BD + kMaxN * kMaxN;                              // [n + 3]
+    double* s_L = reinterpret_cast<double*>(scratch);              // [n][n]
+    double* s_z = s_L + kMaxN * kMaxN;                              // [n + 3]
     float* s_X = reinterpret_cast<float*>(s_z + kMaxN + 3);         // [n]
     float* s_trig = s_X + kMaxN;                                     // [2][16]
     ChainK* s_ch = reinterpret_cast<ChainK*>(s_trig + 32);          // [kMaxArms]
@@ -555,7 +555,7 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
         z_l = S.Z[size_t(b) * n + lane];   // used when drawn
     }
     const double sigma = *S.sigma;
-    for (int e = lane; e < n * n; e += kWave) s_BD[e] = S.B[e] * S.D[e % n];
+    for (int e = lane; e < n * n; e += kWave) s_L[e] = S.L[e];
     if (drawn) {
         if (lane < n) s_z[lane] = z_l;
     } else if (lane < 2 * groups) {
@@ -567,7 +567,7 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
     double y_l = 0.0, z_out = 0.0;
     float x_l = 0.0f;
     if (lane < n) {
-        x_l = candidate_coord(s_BD, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y_l);
+        x_l = candidate_coord(s_L, s_z, n, lane, mean_l, sigma, off_l, scale_l, &y_l);
         z_out = s_z[lane];
         s_X[lane] = x_l;
     }

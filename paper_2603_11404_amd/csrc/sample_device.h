@@ -60,11 +60,12 @@ __device__ inline void draw_normals(uint32_t key0, uint32_t key1, uint32_t g, in
     box_muller(r.z, r.w, &z[2], &z[3]);
 }
 
-// y_i = sum_j (B D)_ij z_j, x_i = m_i + sigma y_i, theta_i = offset_i + scale_i x_i (FP32)
-__device__ inline float candidate_coord(const double* BD, const double* z, int n, int i, double mean_i, double sigma,
+// y_i = sum_j L_ij z_j (L: a square root of C, n x n row-major), x_i = m_i +
+// sigma y_i, theta_i = offset_i + scale_i x_i (FP32)
+__device__ inline float candidate_coord(const double* L, const double* z, int n, int i, double mean_i, double sigma,
                                         double offset_i, double scale_i, double* y_out) {
     double y = 0.0;
-    for (int j = 0; j < n; j++) y += BD[i * n + j] * z[j];
+    for (int j = 0; j < n; j++) y += L[i * n + j] * z[j];
     *y_out = y;
     const double x = mean_i + sigma * y;
     return float(offset_i + scale_i * x);

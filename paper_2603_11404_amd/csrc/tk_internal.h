@@ -82,6 +82,7 @@ __host__ __device__ inline void cmaes_layout(int32_t n, int32_t lam, tk_cmaes_la
     L->Z = take(8 * int64_t(lam) * n);
     L->Y = take(8 * int64_t(lam) * n);
     L->order = take(4 * int64_t(lam));
+    L->L = take(8 * int64_t(n) * n);
     L->total_bytes = (o + 255) & ~int64_t(255);
 }
 
@@ -89,7 +90,7 @@ __host__ __device__ inline void cmaes_layout(int32_t n, int32_t lam, tk_cmaes_la
 struct StateView {
     StateHeader* hdr;
     double *sigma, *c_sigma, *d_sigma, *c_c, *c1, *c_mu, *c_m, *mu_eff, *chi_n, *h_sigma;
-    double *weights, *mean, *p_sigma, *p_c, *offset, *scale, *D, *C, *B, *Z, *Y;
+    double *weights, *mean, *p_sigma, *p_c, *offset, *scale, *D, *C, *B, *Z, *Y, *L;
     int32_t* order;
 };
 
@@ -102,7 +103,7 @@ __host__ __device__ inline StateView state_view(void* blob, int32_t n, int32_t l
 #define TK_F(f) v.f = reinterpret_cast<double*>(b + L.f)
     TK_F(sigma); TK_F(c_sigma); TK_F(d_sigma); TK_F(c_c); TK_F(c1); TK_F(c_mu); TK_F(c_m);
     TK_F(mu_eff); TK_F(chi_n); TK_F(h_sigma); TK_F(weights); TK_F(mean); TK_F(p_sigma);
-    TK_F(p_c); TK_F(offset); TK_F(scale); TK_F(D); TK_F(C); TK_F(B); TK_F(Z); TK_F(Y);
+    TK_F(p_c); TK_F(offset); TK_F(scale); TK_F(D); TK_F(C); TK_F(B); TK_F(Z); TK_F(Y); TK_F(L);
 #undef TK_F
     v.order = reinterpret_cast<int32_t*>(b + L.order);
     return v;

@@ -65,7 +65,7 @@ class CmaesParams(ctypes.Structure):
 
 _LAYOUT_FIELDS = ["total_bytes", "gen", "seed", "flags", "sigma", "c_sigma", "d_sigma", "c_c", "c1", "c_mu", "c_m",
                   "mu_eff", "chi_n", "h_sigma", "weights", "mean", "p_sigma", "p_c", "offset", "scale", "D", "C",
-                  "B", "Z", "Y", "order", "z_gen"]
+                  "B", "Z", "Y", "order", "z_gen", "L"]
 
 
 class CmaesLayout(ctypes.Structure):
@@ -448,7 +448,7 @@ def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:
     out["weights"] = f64(L["weights"], lam)
     for name in ("mean", "p_sigma", "p_c", "offset", "scale", "D"):
         out[name] = f64(L[name], n)
-    for name in ("C", "B"):
+    for name in ("C", "B", "L"):
         out[name] = f64(L[name], n * n).reshape(n, n)
     for name in ("Z", "Y"):
         out[name] = f64(L[name], lam * n).reshape(lam, n)
@@ -458,7 +458,7 @@ def cmaes_view(state: torch.Tensor, n: int, lam: int) -> dict:
 
 def cmaes_write(state: torch.Tensor, n: int, lam: int, **fields):
     """Overwrite FP64 fields of a state blob (e.g. restore a checkpoint or load
-    a given B, D).  Synchronous host-to-device copies."""
+    a given C, L).  Synchronous host-to-device copies."""
     L = cmaes_layout(n, lam)
     for name, val in fields.items():
         if name in ("gen", "z_gen"):

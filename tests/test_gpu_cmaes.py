@@ -1,9 +1,11 @@
 """GPU parity of the FP64 CMA-ES kernels against the numpy oracle.
 
-Given the same state (the oracle's m, sigma, B, D, p_sigma, p_c, C, g written
-into the device blob) and the same losses, sampling and update agree to 1e-12;
-eigen-decompositions are compared through invariants (reconstruction,
-orthonormality, C^{-1/2}) since eigenvector order and signs are not unique.
+Given the same state (the oracle's m, sigma, C, L, p_sigma, p_c, g written into
+the device blob, with its B as the Jacobi warm start) and the same losses,
+sampling and update agree to 1e-12, the new Cholesky factor L included (it is
+unique); eigen-decompositions are compared through invariants (reconstruction
+of the covariance they were taken of, orthonormality, eigenvalues) since
+eigenvector order and signs are not unique.
 """
 import numpy as np
 import pytest
@@ -33,7 +35,7 @@ def _pair(n, lam, seed=5, n_blocks=1, sigma0=0.8):
 
 
 def _push(es, st, n, lam):
-    tk().cmaes_write(st, n, lam, mean=es.m, sigma=[es.sigma], C=es.C, B=es.B, D=es.D, p_sigma=es.p_sigma,
+    tk().cmaes_write(st, n, lam, mean=es.m, sigma=[es.sigma], C=es.C, L=es.L, B=es.B, D=es.D, p_sigma=es.p_sigma,
                      p_c=es.p_c, gen=es.g)
 
 
@@ -47,6 +49,7 @@ def test_init_constants(n, lam):
     np.testing.assert_allclose(v["weights"][:lam // 2], es.k["weights"], rtol=1e-13)
     assert np.all(v["weights"][lam // 2:] == 0)
     np.testing.assert_array_equal(v["C"], np.eye(n))
+    np.testing.assert_array_equal(v["L"], np.eye(n))
     assert v["gen"] == 0 and v["flags"] == 0
 
 
@@ -101,13 +104,73 @@ def test_update_matches_oracle_given_state(n, lam, nb):
         np.testing.assert_allclose(v["p_c"], es.p_c, rtol=0, atol=tol)
         np.testing.assert_allclose(v["C"], es.C, rtol=0, atol=tol * np.abs(C_old).max())
         assert v["gen"] == es.g and v["h_sigma"] == es.h_sigma
-        # eigen-decomposition invariants
+        # the sampling factor of the new covariance: the oracle's (unique) Cholesky factor
+        Lg = v["L"]
+        assert np.all(np.triu(Lg, 1) == 0.0) and np.all(np.diag(Lg) > 0)
+        np.testing.assert_allclose(Lg, es.L, rtol=0, atol=tol * np.sqrt(np.abs(C_old).max()))
+        np.testing.assert_allclose(Lg @ Lg.T, v["C"], rtol=0, atol=1e-13 * np.abs(v["C"]).max())
+        # eigen-decomposition of the covariance the candidates were drawn with
         B, D = v["B"], v["D"]
         np.testing.assert_allclose(B.T @ B, np.eye(n), atol=1e-13)
-        np.testing.assert_allclose(B @ np.diag(D ** 2) @ B.T, v["C"], atol=1e-12 * np.abs(v["C"]).max())
+        np.testing.assert_allclose(B @ np.diag(D ** 2) @ B.T, C_old, atol=1e-12 * np.abs(C_old).max())
         np.testing.assert_allclose(np.sort(D), np.sort(es.D), rtol=1e-10)
+        assert v["flags"] == 0
         if nb > 1:
             assert np.all(v["C"][:9, 9:] == 0) and np.all(B[:9, 9:] == 0) and np.all(B[9:, :9] == 0)
+            assert np.all(Lg[:9, 9:] == 0) and np.all(Lg[9:, :9] == 0)
+
+
+def _one_update(es, st, n, lam, loss_fn):
+    T = tk()
+    _push(es, st, n, lam)
+    X = torch.empty(lam, n, dtype=torch.float32, device=DEV)
+    T.cmaes_sample(st, n, lam, X)
+    theta = es.sample()
+    loss = loss_fn((theta - es.offset) / es.scale)
+    C_old = es.C.copy()
+    es.update(loss)
+    T.cmaes_update(st, n, lam, torch.as_tensor(loss, device=DEV))
+    torch.cuda.synchronize()
+    return T.cmaes_view(st, n, lam), C_old
+
+
+@pytest.mark.parametrize("n,lam,nb", [(9, 256, 1), (18, 512, 2)])
+def test_update_with_h_sigma_zero_matches_oracle(n, lam, nb):
+    """A long conjugate path makes h_sigma = 0: the covariance and its factor
+    are then formed with the h_sigma correction (not the h_sigma = 1 form the
+    update prepares beside the eigendecomposition)."""
+    es, st = _pair(n, lam, n_blocks=nb)
+    es.p_sigma = np.full(n, 50.0)
+    es.p_c = np.linspace(-1.0, 1.0, n)
+    v, C_old = _one_update(es, st, n, lam, lambda x: np.sum(x * x, 1))
+    assert es.h_sigma == 0.0 and v["h_sigma"] == 0.0
+    tol = 1e-11
+    np.testing.assert_allclose(v["p_c"], es.p_c, rtol=0, atol=tol)
+    np.testing.assert_allclose(v["C"], es.C, rtol=0, atol=tol * np.abs(C_old).max())
+    np.testing.assert_allclose(v["L"], es.L, rtol=0, atol=tol)
+    assert v["sigma"] == pytest.approx(es.sigma, rel=1e-12)
+
+
+def test_update_floors_a_singular_covariance_like_the_oracle():
+    """C = diag(1, ..., 1, 0): its zero Cholesky pivot is floored, so the draws
+    reach that direction only at the floor's scale and the new covariance's
+    last pivot stays below its floor.  The zero eigenvalue and the pivots are
+    floored at 1e-20 of the largest, as in the oracle, and the flag says so."""
+    n, lam = 9, 16
+    es, st = _pair(n, lam)
+    C = np.eye(n)
+    C[n - 1, n - 1] = 0.0
+    es.set_covariance(C)
+    assert es.chol_floored
+    v, C_old = _one_update(es, st, n, lam, lambda x: np.sum(x * x, 1))
+    assert es.eig_floored and es.chol_floored
+    assert v["flags"] & 1
+    np.testing.assert_allclose(v["mean"], es.m, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(v["C"], es.C, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v["L"], es.L, rtol=0, atol=1e-11)
+    floor = 1e-20 * np.max(np.diag(es.C))
+    assert v["C"][n - 1, n - 1] < floor
+    assert v["L"][n - 1, n - 1] == pytest.approx(np.sqrt(floor), rel=1e-12)
 
 
 def _gpu_run(fun, n=9, lam=16, gens=200, seed=1, m0=3.0):
@@ -166,7 +229,7 @@ def test_deterministic_double_run():
     h1 = _gpu_run(lambda X: (X * X).sum(1).contiguous(), gens=10, seed=3)
     h2 = _gpu_run(lambda X: (X * X).sum(1).contiguous(), gens=10, seed=3)
     for a, b in zip(h1, h2):
-        for k in ("mean", "C", "B", "D", "Z", "Y", "p_sigma", "p_c"):
+        for k in ("mean", "C", "L", "B", "D", "Z", "Y", "p_sigma", "p_c"):
             assert np.array_equal(a[k], b[k]), k
 
 
