@@ -871,12 +871,20 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             // gathered after the workgroup barrier below; the conjugate path
             // reads V through the positions.
             if (lane == 0) s_vsel = Vcur == s_V ? 0 : 1;
+            // The moves keep position 0 and cycle the others through
+            // 1, 3, 5, ..., m - 1, m - 2, ..., 4, 2 (index c: odd p at
+            // (p - 1) / 2, even p at m - 1 - p / 2), so after `moved` rounds the
+            // index that started at p sits at cycle index (c + moved) mod (m - 1).
             double ev = 0.0;
             int pos_l = 0;
             if (lane < n) {
                 const int tb = div_small(lane, nb);
-                pos_l = lane - tb * nb;
-                for (int r = 0; r < moved; r++) pos_l = move(pos_l);
+                const int p0 = lane - tb * nb;
+                if (p0 != 0) {
+                    int c = ((p0 & 1) ? (p0 - 1) / 2 : m - 1 - p0 / 2) + moved;
+                    c -= c >= k1 ? k1 : 0;
+                    pos_l = c < m / 2 ? 2 * c + 1 : 2 * (m - 1 - c);
+                }
                 s_pos[lane] = pos_l;
                 ev = Acur[tb * mm + pos_l * m + pos_l];
             }

@@ -4,22 +4,29 @@
 // S in {0,1}^{H x W}; counts |S| and |S and M_ref| feed the render loss
 // (Eq. render_loss) and the mask error 1 - IoU (Sec. IV).
 //
-// Design (one workgroup per candidate, whole image mask in LDS):
-//   1. each lane takes one triangle: gathers its three vertices, applies the
-//      link transform of the candidate (FP32, no contraction), projects with
-//      the pinhole camera and snaps to Q8 fixed point; culls triangles with a
-//      vertex before the near plane, zero area or an empty pixel box;
-//      orients the triangle and builds three exact integer edge functions
-//      E(p) = dx*(p.y - y0) - dy*(p.x - x0) with the top-left bias; stores a
-//      64-byte record in the wave's LDS staging slot;
-//   2. the wave walks its valid triangles one by one; for every 8x8 pixel
-//      block of the triangle's box, each lane tests its pixel centre with the
-//      three edge functions (32-bit modular arithmetic, exact because the box
-//      bound keeps |E| < 2^31; a 64-bit path serves larger triangles) and
-//      the 64-lane ballot is the block's coverage word, ORed into the LDS
-//      mask with one ds_or_b64;
-//   3. after a barrier the mask is written out and/or reduced against the
-//      target with popcounts.
+// Design (one workgroup per candidate, its whole image mask in LDS as 8x8-pixel
+// u64 words):
+//   0. (ask-eval form) wave 0 draws the candidate from the CMA-ES state and
+//      evaluates its forward kinematics into LDS; the other waves clear the mask;
+//   1. (with a workspace) every vertex of the candidate is transformed (FP32, no
+//      contraction), tested against the near plane, projected and snapped to Q8
+//      once, into the workspace;
+//   2. triangles are numbered in chunks of 64 over all meshes; each wave starts
+//      on two chunks and claims later ones from an LDS counter, loading indices
+//      and snapped vertices ahead of use.  Each lane sets up one triangle: cull
+//      (flagged vertex, zero area, empty box; for a closed mesh whose vertices
+//      all passed the near plane, negative area too, since its positively
+//      oriented triangles alone cover the same pixel centres), orientation,
+//      exact integer edge functions E(p) = dx (p.y - y0) - dy (p.x - x0) at
+//      pixel centres with the top-left bias, the pixel box;
+//   3. small-box triangles (32-bit arithmetic) become lane tasks in two per-wave
+//      LDS ring queues (narrow boxes: 2 columns x 6 rows per task; wide boxes:
+//      8 columns x 4 rows), run in rounds of 64 tasks; each task updates its
+//      edge functions incrementally and ORs its covered pixels into at most
+//      2 x 2 mask words; triangles needing 64-bit edge functions are covered by
+//      the whole wave, 8x8 block by block, each block's word a 64-lane ballot;
+//   4. the mask is counted (|S|, |S and M|) against the target with popcounts
+//      and/or written out.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
