@@ -209,49 +209,59 @@ __device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq
 }
 
 // The rotations of two pairs at once, each with exactly the arithmetic of
-// pair_rotation, written step by step for both so that the two dependent
-// chains interleave in one wave's instruction stream.
-__device__ __forceinline__ void pair_rotation2(const double app[2], const double aqq[2], const double apq[2],
+// pair_rotation.  The two chains are carried as the two elements of a vector
+// and the steps are fenced against the instruction scheduler, so that the
+// chains interleave in the wave's instruction stream instead of following one
+// another (each step of one chain then fills the latency of the other's).
+typedef double pair_f64 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ pair_f64 rsq2(pair_f64 v) {
+    pair_f64 r;
+    r.x = __builtin_amdgcn_rsq(v.x);
+    r.y = __builtin_amdgcn_rsq(v.y);
+    return r;
+}
+
+__device__ __forceinline__ void pair_rotation2(const double app_[2], const double aqq_[2], const double apq_[2],
                                                double c_out[2], double sn_out[2], bool rot_out[2]) {
-    double d[2], p2[2], q[2], x[2], hx[2], r[2], w[2], y[2], hy[2], t[2];
+    const pair_f64 app = {app_[0], app_[1]}, aqq = {aqq_[0], aqq_[1]}, apq = {apq_[0], apq_[1]};
+    const pair_f64 one_half = {1.5, 1.5};
+    const pair_f64 d = aqq - app;
+    const pair_f64 p2 = apq * apq;
+    // the rotation tests and the signs of s, off the chains
+    bool rot[2];
+    double sgn[2];
 #pragma unroll
     for (int k = 0; k < 2; k++) {
-        d[k] = aqq[k] - app[k];
-        p2[k] = apq[k] * apq[k];
+        rot[k] = apq[k] != 0.0 && p2[k] > 1e-30 * fabs(app[k] * aqq[k]);
+        sgn[k] = d[k] >= 0.0 ? 2.0 * apq[k] : -2.0 * apq[k];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    const pair_f64 q = 4.0 * p2;
+    const pair_f64 x = __builtin_elementwise_fma(d, d, q);
+    __builtin_amdgcn_sched_barrier(0);
+    const pair_f64 hx = -0.5 * x;
+    pair_f64 r = rsq2(x);
+    __builtin_amdgcn_sched_barrier(0);
+    r = r * __builtin_elementwise_fma(hx * r, r, one_half);
+    __builtin_amdgcn_sched_barrier(0);
+    const pair_f64 w = __builtin_elementwise_fma(x, r, __builtin_elementwise_abs(d));
+    __builtin_amdgcn_sched_barrier(0);
+    const pair_f64 y = __builtin_elementwise_fma(w, w, q);
+    const pair_f64 hy = -0.5 * y;
+    __builtin_amdgcn_sched_barrier(0);
+    pair_f64 t = rsq2(y);
+    __builtin_amdgcn_sched_barrier(0);
+    t = t * __builtin_elementwise_fma(hy * t, t, one_half);
+    __builtin_amdgcn_sched_barrier(0);
+    t = t * __builtin_elementwise_fma(hy * t, t, one_half);
+    __builtin_amdgcn_sched_barrier(0);
+    const pair_f64 c = w * t;
 #pragma unroll
     for (int k = 0; k < 2; k++) {
-        q[k] = 4.0 * p2[k];
-        x[k] = fma(d[k], d[k], 4.0 * p2[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        hx[k] = -0.5 * x[k];
-        r[k] = __builtin_amdgcn_rsq(x[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 2; k++) r[k] = r[k] * fma(hx[k] * r[k], r[k], 1.5);
-#pragma unroll
-    for (int k = 0; k < 2; k++) w[k] = fma(x[k], r[k], fabs(d[k]));
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        y[k] = fma(w[k], w[k], q[k]);
-        hy[k] = -0.5 * y[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 2; k++) t[k] = __builtin_amdgcn_rsq(y[k]);
-#pragma unroll
-    for (int k = 0; k < 2; k++) t[k] = t[k] * fma(hy[k] * t[k], t[k], 1.5);
-#pragma unroll
-    for (int k = 0; k < 2; k++) t[k] = t[k] * fma(hy[k] * t[k], t[k], 1.5);
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        const double c = w[k] * t[k];
-        const double sn = (d[k] >= 0.0 ? 2.0 * apq[k] : -2.0 * apq[k]) * t[k];
-        const bool rot = apq[k] != 0.0 && p2[k] > 1e-30 * fabs(app[k] * aqq[k]);
-        c_out[k] = rot ? c : 1.0;
-        sn_out[k] = rot ? sn : 0.0;
-        rot_out[k] = rot;
+        c_out[k] = rot[k] ? c[k] : 1.0;
+        sn_out[k] = rot[k] ? sgn[k] * t[k] : 0.0;
+        rot_out[k] = rot[k];
     }
 }
 
@@ -572,6 +582,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     __shared__ double s_yw[kMaxN], s_t[kMaxN], s_pc[kMaxN], s_pc1[kMaxN], s_ps[kMaxN], s_mean[kMaxN];
     __shared__ double s_scal[4];
     __shared__ int s_wbar[5];                // worker barrier: arrivals, generation, wait bound hit; y_w ready; V final
+    __shared__ int s_zctr;                   // next z-draw task (chunks of 64 claimed by whole waves)
     __shared__ int s_flag[2];                // [0] eigenvalue floored, [1] Cholesky pivot floored / emax not finite
 
     StateView S = state_view(blob, n, lam);
@@ -602,19 +613,33 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
     const int64_t denom_gen = S.hdr->denom_gen;
     const double denom_cached = S.hdr->denom;
     // wave 0: C and the previous eigenvectors (the warm start of the
-    // eigendecomposition) from the state, in flight across the barrier below;
-    // in LDS as NMAX x NMAX matrices padded with zeros, so that the products
-    // of the warm start run over a fixed count (the padding adds exact zeros
-    // after the terms of the sums)
-    constexpr int GE = (NMAX * NMAX + kWave64 - 1) / kWave64;
+    // eigendecomposition) from the state, in flight across the barrier below:
+    //   n <= 9: in the operand layouts of the FP64 16x16x4 matrix instruction,
+    //   for the four k-steps s (lane (g, q) = (lane / 16, lane % 16) holds
+    //   C(q, 4s + g) and B(4s + g, q), zero outside n x n);
+    //   otherwise: row-major NMAX x NMAX, GE entries per lane.
+    constexpr bool kMfmaWarm = NMAX <= 16;
+    constexpr int GE = kMfmaWarm ? 4 : (NMAX * NMAX + kWave64 - 1) / kWave64;
     double cr[GE], br[GE];
     if (wave == 0) {
 #pragma unroll
         for (int g = 0; g < GE; g++) {
-            const int e = lane + g * kWave64, i = e / NMAX, j = e % NMAX;
-            const bool in = e < NMAX * NMAX && i < n && j < n;
-            cr[g] = in ? S.C[i * n + j] : 0.0;
-            br[g] = in ? S.B[i * n + j] : 0.0;
+            int i, j;
+            bool in;
+            if constexpr (kMfmaWarm) {
+                i = 4 * g + (lane >> 4);
+                j = lane & 15;
+                in = i < n && j < n;
+            } else {
+                const int e = lane + g * kWave64;
+                i = e / NMAX;
+                j = e % NMAX;
+                in = e < NMAX * NMAX && i < n && j < n;
+            }
+            const int ij = min(i, n - 1) * n + min(j, n - 1);   // in bounds; C is symmetric
+            const double c = S.C[ij], b = S.B[ij];
+            cr[g] = in ? c : 0.0;
+            br[g] = in ? b : 0.0;
         }
     }
     if (tid == 0) {
@@ -623,6 +648,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         s_wbar[2] = 0;
         s_wbar[3] = 0;
         s_wbar[4] = 0;
+        s_zctr = 0;
         s_flag[0] = 0;
         s_flag[1] = 0;
     }
@@ -641,7 +667,42 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         if (p & 1) return p + 2 <= m - 1 ? p + 2 : m - 2;
         return p - 2;
     };
+    // (n <= 9) the next generation's z, exactly as a sampler would draw them
+    // (they depend on the seed and generation only): one Philox block per
+    // task, tasks in block-major order (so that a chunk holds one block index
+    // j and the last block's unused normals are not computed), in chunks of
+    // 64 tasks claimed by whole waves from an LDS counter.  The three waves
+    // that share SIMD 0 with the eigendecomposition take chunks from the
+    // start at the lowest priority, which leaves that wave's dependent chain
+    // the issue slots; worker wave 0 joins after the Cholesky factor, worker
+    // wave 1 only until V and D are final (it gathers B then), the other
+    // workers after the covariance.  With up to 18 dimensions the draws would
+    // outlast the eigendecomposition; the next generation's draw (ask-eval
+    // prologue, sampler, or the tell-ask tail) makes them then.
+    auto draw_z = [&](bool until_v_final) {
+        const uint32_t gnext = uint32_t(gen + 1);
+        const uint64_t seed = S.hdr->seed;
+        const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
+        const int n_tasks = lam * ((n + 3) / 4);
+        for (;;) {
+            if (until_v_final && __hip_atomic_load(&s_wbar[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+                break;
+            int base = 0;
+            if (lane == 0) base = __hip_atomic_fetch_add(&s_zctr, kWave64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= n_tasks) break;
+            const int task = base + lane;
+            if (task < n_tasks) {
+                const int j = div_small(task, lam), k = task - j * lam;
+                double z[4];
+                const int cnt = min(4, n - 4 * j);
+                draw_normals_first(key0, key1, gnext, k, j, cnt, z);
+                for (int t = 0; t < cnt; t++) S.Z[k * n + 4 * j + t] = z[t];
+            }
+        }
+    };
     if (wave == 0) {
+        __builtin_amdgcn_s_setprio(3);            // ahead of the drawing waves on this SIMD
         constexpr int kASlots = AS;
         static_assert(VS == 2 * AS, "two V entries per A entry");
         const int na_slots = (n_a + kWave64 - 1) / kWave64;
@@ -687,42 +748,82 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             v1_r[sl] = vbase + min(r1, nb - 1) * m + je;
             v1_w[sl] = vbase + min(r1, nb - 1) * m + move(j);
         }
-#pragma unroll
-        for (int g = 0; g < GE; g++) {
-            const int e = lane + g * kWave64;
-            if (e < NMAX * NMAX) {
-                s_Ce[e] = cr[g];
-                s_Bw[e] = br[g];
-            }
-        }
-        wave_sync();
         // warm start: A = B^T C B (nearly diagonal when C changed little), V = B;
         // every rotation applies A <- J^T A J and V <- V J, so C = V diag(A) V^T at the end
-        for (int e = lane; e < NMAX * NMAX; e += kWave64) {
-            const int i = e / NMAX, j = e % NMAX;
-            double t = 0.0;
+        if constexpr (kMfmaWarm) {
+            // X = C B and A' = B^T X on the matrix cores, n x n padded to 16 x 16.
+            // The product's register r holds row g + 4r of column q, so X's
+            // register s is exactly the second product's B operand at k-step s,
+            // and B(4s + g, q) its A operand (B^T at (q, 4s + g)).
+            typedef double f64x4 __attribute__((ext_vector_type(4)));
+            f64x4 X = {0.0, 0.0, 0.0, 0.0}, Ap = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int k = 0; k < NMAX; k++) t += s_Ce[i * NMAX + k] * s_Bw[k * NMAX + j];
-            s_X[e] = t;                                   // C B
-        }
-        for (int e = lane; e < n_v; e += kWave64) {
-            // V = B in the positional layout: index l of block b starts at position l
-            const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
-            s_V[e] = j < nb ? s_Bw[(b * nb + r) * NMAX + b * nb + j] : 0.0;
-        }
-        wave_sync();
-        // A = B^T C B in the positional layout, symmetrised: 0.5 (A_ij + A_ji)
-        // from both products (each summed over k in order); dummy rows and columns zero
-        for (int e = lane; e < n_blocks * mm; e += kWave64) {
-            const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
-            const int gi = b * nb + min(i, nb - 1), gj = b * nb + min(j, nb - 1);
-            double tij = 0.0, tji = 0.0;
+            for (int st = 0; st < 4; st++) X = __builtin_amdgcn_mfma_f64_16x16x4f64(cr[st], br[st], X, 0, 0, 0);
 #pragma unroll
-            for (int k = 0; k < NMAX; k++) {
-                tij += s_Bw[k * NMAX + gi] * s_X[k * NMAX + gj];
-                tji += s_Bw[k * NMAX + gj] * s_X[k * NMAX + gi];
+            for (int st = 0; st < 4; st++) Ap = __builtin_amdgcn_mfma_f64_16x16x4f64(br[st], X[st], Ap, 0, 0, 0);
+            const int g = lane >> 4, q = lane & 15;
+#pragma unroll
+            for (int st = 0; st < 4; st++) {
+                const int row = g + 4 * st;                   // A'(row, q) in register st; B(row, q) in br[st]
+                if (row < n && q < n) {
+                    s_X[row * NMAX + q] = Ap[st];
+                    // V = B in the positional layout: index l of block b starts at position l
+                    const int b = div_small(row, nb);
+                    if (div_small(q, nb) == b) s_V[b * nb * m + (row - b * nb) * m + q - b * nb] = br[st];
+                }
             }
-            s_A[e] = (i < nb && j < nb) ? 0.5 * (tij + tji) : 0.0;
+            if (m > nb && lane < n) {
+                // the dummy index's column (odd blocks) starts at zero
+                const int b = div_small(lane, nb);
+                s_V[b * nb * m + (lane - b * nb) * m + nb] = 0.0;
+            }
+            wave_sync();
+            // A in the positional layout, symmetrised: 0.5 (A'_ij + A'_ji); dummy
+            // rows and columns zero
+            for (int e = lane; e < n_blocks * mm; e += kWave64) {
+                const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
+                const int gi = b * nb + min(i, nb - 1), gj = b * nb + min(j, nb - 1);
+                s_A[e] = (i < nb && j < nb) ? 0.5 * (s_X[gi * NMAX + gj] + s_X[gj * NMAX + gi]) : 0.0;
+            }
+        } else {
+            // in LDS as NMAX x NMAX matrices padded with zeros, so that the
+            // products run over a fixed count (the padding adds exact zeros
+            // after the terms of the sums)
+#pragma unroll
+            for (int g = 0; g < GE; g++) {
+                const int e = lane + g * kWave64;
+                if (e < NMAX * NMAX) {
+                    s_Ce[e] = cr[g];
+                    s_Bw[e] = br[g];
+                }
+            }
+            wave_sync();
+            for (int e = lane; e < NMAX * NMAX; e += kWave64) {
+                const int i = e / NMAX, j = e % NMAX;
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < NMAX; k++) t += s_Ce[i * NMAX + k] * s_Bw[k * NMAX + j];
+                s_X[e] = t;                                   // C B
+            }
+            for (int e = lane; e < n_v; e += kWave64) {
+                // V = B in the positional layout: index l of block b starts at position l
+                const int b = div_small(e, nb * m), rr = e - b * nb * m, r = div_small(rr, m), j = rr - r * m;
+                s_V[e] = j < nb ? s_Bw[(b * nb + r) * NMAX + b * nb + j] : 0.0;
+            }
+            wave_sync();
+            // A = B^T C B in the positional layout, symmetrised: 0.5 (A_ij + A_ji)
+            // from both products (each summed over k in order); dummy rows and columns zero
+            for (int e = lane; e < n_blocks * mm; e += kWave64) {
+                const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
+                const int gi = b * nb + min(i, nb - 1), gj = b * nb + min(j, nb - 1);
+                double tij = 0.0, tji = 0.0;
+#pragma unroll
+                for (int k = 0; k < NMAX; k++) {
+                    tij += s_Bw[k * NMAX + gi] * s_X[k * NMAX + gj];
+                    tji += s_Bw[k * NMAX + gj] * s_X[k * NMAX + gi];
+                }
+                s_A[e] = (i < nb && j < nb) ? 0.5 * (tij + tji) : 0.0;
+            }
         }
         wave_sync();
         {
@@ -772,13 +873,15 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 // two V rows at columns 2P and 2Q, read with no branch (every slot's
                 // offsets are valid; slots past the last entry repeat it)
                 double2 blk0[kASlots], blk1[kASlots], vr0[kASlots], vr1[kASlots];
+                auto read_blocks = [&]() {
         #pragma unroll
-                for (int sl = 0; sl < kASlots; sl++) {
-                    blk0[sl] = pair(Ac, a_rij[sl]);
-                    blk1[sl] = pair(Ac, a_rpj[sl]);
-                    vr0[sl] = pair(Vc, v0_r[sl]);
-                    vr1[sl] = pair(Vc, v1_r[sl]);
-                }
+                    for (int sl = 0; sl < kASlots; sl++) {
+                        blk0[sl] = pair(Ac, a_rij[sl]);
+                        blk1[sl] = pair(Ac, a_rpj[sl]);
+                        vr0[sl] = pair(Vc, v0_r[sl]);
+                        vr1[sl] = pair(Vc, v1_r[sl]);
+                    }
+                };
                 // the rotation columns u, w of positions i and j, and A(i, i), A(j, j)
                 double u0[kASlots], u1[kASlots], w0[kASlots], w1[kASlots], di[kASlots], dj[kASlots];
                 bool rot;
@@ -788,6 +891,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                     // with no exchange between lanes
                     const double2 p0 = pair(Ac, a_dp[0]), p1 = pair(Ac, a_dp[0] + m);
                     const double2 q0 = pair(Ac, a_dq[0]), q1 = pair(Ac, a_dq[0] + m);
+                    read_blocks();   // issued behind the diagonal blocks, consumed after the rotations
                     const double app[2] = {p0.x, q0.x}, aqq[2] = {p1.y, q1.y}, apq[2] = {p0.y, q0.y};
                     double cs2[2], sn2[2];
                     bool r2[2];
@@ -806,6 +910,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                     // lane t < n_blocks m computes the rotation of the pair holding
                     // position t; the entry lanes take the columns by cross-lane shuffles
                     const double2 bp = pair(Ac, t_rp), bq = pair(Ac, t_rq);
+                    read_blocks();
                     double c_t, sn_t;
                     rot = pair_rotation(bp.x, bq.y, bp.y, tid < n_pos, &c_t, &sn_t);
                     const double dd_t = t_even ? bp.x : bq.y;       // A(t, t)
@@ -822,7 +927,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 }
         #pragma unroll
                 for (int sl = 0; sl < kASlots; sl++) {
-                    if (sl < na_slots) {
+                    if (sl == 0 || sl < na_slots) {   // slot 0 always holds an entry (n >= 1)
                         // A'(i, j) = u^T B w; a lane past the last entry recomputes the
                         // last entry, so its duplicate stores write the same value
                         const double r0 = fma(w0[sl], blk0[sl].x, w1[sl] * blk0[sl].y);
@@ -845,7 +950,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 bool open = false;
         #pragma unroll
                 for (int sl = 0; sl < kASlots; sl++) {
-                    if (sl < na_slots) {
+                    if (sl == 0 || sl < na_slots) {   // slot 0 always holds an entry (n >= 1)
                         const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
                         const double aij = a_ej[sl] ? row.x : row.y;
                         open |= a_off[sl] && aij * aij > 1e-30 * fabs(di[sl] * dj[sl]);
@@ -877,17 +982,28 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             // index that started at p sits at cycle index (c + moved) mod (m - 1).
             double ev = 0.0;
             int pos_l = 0;
-            if (lane < n) {
-                const int tb = div_small(lane, nb);
-                const int p0 = lane - tb * nb;
-                if (p0 != 0) {
-                    int c = ((p0 & 1) ? (p0 - 1) / 2 : m - 1 - p0 / 2) + moved;
-                    c -= c >= k1 ? k1 : 0;
-                    pos_l = c < m / 2 ? 2 * c + 1 : 2 * (m - 1 - c);
-                }
-                s_pos[lane] = pos_l;
-                ev = Acur[tb * mm + pos_l * m + pos_l];
+            const int lb = lane < n ? div_small(lane, nb) : 0;     // block of index `lane`
+            const int l_row = lane < n ? lane - lb * nb : 0;       // its row within the block
+            if (l_row != 0) {
+                int c = ((l_row & 1) ? (l_row - 1) / 2 : m - 1 - l_row / 2) + moved;
+                c -= c >= k1 ? k1 : 0;
+                pos_l = c < m / 2 ? 2 * c + 1 : 2 * (m - 1 - c);
             }
+            if (lane < n) s_pos[lane] = pos_l;
+            // the V entries of the conjugate path, read now (this wave's own
+            // data): column pos_l of the lane's block for B^T y_w, and row l_row
+            // at the positions of the block's indices for B t (the position of
+            // index j of a block is the same in every block: lane j's)
+            const double* Vb = Vcur + lb * nb * m;
+            double vcol[NMAX], vrow[NMAX];
+#pragma unroll
+            for (int i = 0; i < NMAX; i++) {
+                const int ic = min(i, nb - 1);
+                const int pos_i = __builtin_amdgcn_readlane(pos_l, ic);
+                vcol[i] = Vb[ic * m + pos_l];
+                vrow[i] = Vb[l_row * m + pos_i];
+            }
+            ev = Acur[lb * mm + pos_l * m + pos_l];
             const double emax = wave_max_f64(lane < n ? fmax(0.0, ev) : 0.0, lane);
             const double floor_v = 1e-20 * emax;
             const bool floored = lane < n && !(ev >= floor_v);
@@ -915,14 +1031,11 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             // (B^T y_w)_l = sum_i V(i, pos l) y_w,i over the rows i of l's block;
             // (B t)_l = sum_j V(l, pos j) t_j over the indices j of l's block (the
             // other blocks' terms of the full sums are exact zeros)
-            const int lb = lane < n ? div_small(lane, nb) : 0;
-            const int l_row = lane < n ? lane - lb * nb : 0;
-            const double* Vb = Vcur + lb * nb * m;
             if (lane < n) {
                 double acc = 0.0;
     #pragma unroll
                 for (int i = 0; i < NMAX; i++)
-                    if (i < nb) acc += Vb[i * m + pos_l] * s_yw[lb * nb + i];
+                    if (i < nb) acc += vcol[i] * s_yw[lb * nb + i];
                 s_t[lane] = acc / d_l;
             }
             wave_sync();
@@ -931,7 +1044,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 double acc = 0.0;
     #pragma unroll
                 for (int j = 0; j < NMAX; j++)
-                    if (j < nb) acc += Vb[l_row * m + s_pos[lb * nb + j]] * s_t[lb * nb + j];
+                    if (j < nb) acc += vrow[j] * s_t[lb * nb + j];
                 ps_l = (1.0 - cs) * s_ps[lane] + ps_gain * acc;
                 s_ps[lane] = ps_l;
             }
@@ -1097,31 +1210,16 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 S.C[e] = s_Cn[e];
                 S.L[e] = s_L[e];
             }
+            if (kDrawZ) draw_z(false);
         } else {
             // the next generation's h_sigma denominator, cached in the state with
-            // its generation, and (n <= 9) its z, exactly as a sampler would draw
-            // them (they depend on the seed and generation only).  With up to 18
-            // dimensions the draws (5 per candidate) would outlast the
-            // eigendecomposition on these waves; the next generation's draw
-            // (ask-eval prologue, sampler, or the tell-ask tail) makes them then.
+            // its generation
             if (wk == kWave64) {
                 S.hdr->denom = sqrt(1.0 - pow(1.0 - cs, 2.0 * double(gen + 2)));
                 S.hdr->denom_gen = gen + 1;
-                if (kDrawZ) S.hdr->z_gen = gen + 1;   // the loop below has written Z when the kernel ends
+                if (kDrawZ) S.hdr->z_gen = gen + 1;   // every task of Z is claimed and written before the kernel ends
             }
-            if (kDrawZ) {
-                const uint32_t gnext = uint32_t(gen + 1);
-                const uint64_t seed = S.hdr->seed;
-                const uint32_t key0 = uint32_t(seed), key1 = uint32_t(seed >> 32);
-                const int groups = (n + 3) / 4;
-                for (int task = wk - kWave64; task < lam * groups; task += NWK - kWave64) {
-                    const int k = div_small(task, groups), j = task - k * groups;
-                    double z[4];
-                    draw_normals(key0, key1, gnext, k, j, z);
-                    for (int t = 0; t < 4; t++)
-                        if (4 * j + t < n) S.Z[k * n + 4 * j + t] = z[t];
-                }
-            }
+            if (kDrawZ) draw_z(wi == 1);
             if (wi == 1) {
                 // B = V with its columns in index order (position s_pos[j] holds
                 // index j), and D, once wave 0 has them
@@ -1147,6 +1245,8 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 if (lane < n) S.D[lane] = s_D[lane];
             }
         }
+    } else if (kDrawZ) {
+        draw_z(false);                            // the waves beside wave 0 on SIMD 0 (priority 0)
     }
     __syncthreads();
     const double h_sigma = s_scal[1];

@@ -33,11 +33,21 @@ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
-__device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
+// Box-Muller: radius sqrt(-2 ln u1) and angle 2 pi u2 from two 32-bit words
+// mapped to the open interval (0, 1).
+__device__ inline double bm_radius(uint32_t a) {
     const double u1 = (double(a) + 0.5) * 0x1p-32;
+    return sqrt(-2.0 * log(u1));
+}
+
+__device__ inline double bm_angle(uint32_t b) {
     const double u2 = (double(b) + 0.5) * 0x1p-32;
-    const double r = sqrt(-2.0 * log(u1));
-    const double t = (2.0 * kPi) * u2;
+    return (2.0 * kPi) * u2;
+}
+
+__device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
+    const double r = bm_radius(a);
+    const double t = bm_angle(b);
     *z0 = r * cos(t);
     *z1 = r * sin(t);
 }
@@ -58,6 +68,23 @@ __device__ inline void draw_normals(uint32_t key0, uint32_t key1, uint32_t g, in
     const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
     box_muller(r.x, r.y, &z[0], &z[1]);
     box_muller(r.z, r.w, &z[2], &z[3]);
+}
+
+// The first `count` (1 ... 4) of those normals, each with exactly the
+// arithmetic of box_muller; the others are not computed.
+__device__ inline void draw_normals_first(uint32_t key0, uint32_t key1, uint32_t g, int k, int j, int count,
+                                          double z[4]) {
+    const U4 r = philox4x32_10(U4{uint32_t(j), uint32_t(k), g, 0u}, key0, key1);
+    const uint32_t a[2] = {r.x, r.z}, b[2] = {r.y, r.w};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        if (2 * h < count) {
+            const double rad = bm_radius(a[h]);
+            const double t = bm_angle(b[h]);
+            z[2 * h] = rad * cos(t);
+            if (2 * h + 1 < count) z[2 * h + 1] = rad * sin(t);
+        }
+    }
 }
 
 // y_i = sum_j L_ij z_j (L: a square root of C, n x n row-major), x_i = m_i +
