@@ -761,29 +761,26 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             for (int st = 0; st < 4; st++) X = __builtin_amdgcn_mfma_f64_16x16x4f64(cr[st], br[st], X, 0, 0, 0);
 #pragma unroll
             for (int st = 0; st < 4; st++) Ap = __builtin_amdgcn_mfma_f64_16x16x4f64(br[st], X[st], Ap, 0, 0, 0);
+            // A' and V = B straight into the positional layouts (index l of
+            // block b starts at position l); A' is symmetric up to rounding, and
+            // the first round writes its rotated entries mirrored
             const int g = lane >> 4, q = lane & 15;
+            const int bq = div_small(min(q, n - 1), nb);
 #pragma unroll
             for (int st = 0; st < 4; st++) {
-                const int row = g + 4 * st;                   // A'(row, q) in register st; B(row, q) in br[st]
-                if (row < n && q < n) {
-                    s_X[row * NMAX + q] = Ap[st];
-                    // V = B in the positional layout: index l of block b starts at position l
-                    const int b = div_small(row, nb);
-                    if (div_small(q, nb) == b) s_V[b * nb * m + (row - b * nb) * m + q - b * nb] = br[st];
+                const int row = g + 4 * st;               // A'(row, q) in register st; B(row, q) in br[st]
+                if (row < n && q < n && div_small(row, nb) == bq) {
+                    const int r = row - bq * nb, c = q - bq * nb;
+                    s_A[bq * mm + r * m + c] = Ap[st];
+                    s_V[bq * nb * m + r * m + c] = br[st];
                 }
             }
-            if (m > nb && lane < n) {
-                // the dummy index's column (odd blocks) starts at zero
-                const int b = div_small(lane, nb);
-                s_V[b * nb * m + (lane - b * nb) * m + nb] = 0.0;
-            }
-            wave_sync();
-            // A in the positional layout, symmetrised: 0.5 (A'_ij + A'_ji); dummy
-            // rows and columns zero
-            for (int e = lane; e < n_blocks * mm; e += kWave64) {
-                const int b = div_small(e, mm), r = e - b * mm, i = div_small(r, m), j = r - i * m;
-                const int gi = b * nb + min(i, nb - 1), gj = b * nb + min(j, nb - 1);
-                s_A[e] = (i < nb && j < nb) ? 0.5 * (s_X[gi * NMAX + gj] + s_X[gj * NMAX + gi]) : 0.0;
+            if (m > nb && lane < n_blocks * m) {
+                // the dummy index of odd blocks: zero row and column of A, zero column of V
+                const int b = div_small(lane, m), i = lane - b * m;
+                s_A[b * mm + nb * m + i] = 0.0;
+                s_A[b * mm + i * m + nb] = 0.0;
+                if (i < nb) s_V[b * nb * m + i * m + nb] = 0.0;
             }
         } else {
             // in LDS as NMAX x NMAX matrices padded with zeros, so that the
@@ -1046,7 +1043,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 for (int j = 0; j < NMAX; j++)
                     if (j < nb) acc += vrow[j] * s_t[lb * nb + j];
                 ps_l = (1.0 - cs) * s_ps[lane] + ps_gain * acc;
-                s_ps[lane] = ps_l;
+                S.p_sigma[lane] = ps_l;
             }
             // ||p_sigma||^2 by a fixed butterfly over the lanes
             double ss = ps_l * ps_l;
@@ -1063,6 +1060,9 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                 const double sg = sigma * exp(cs_ds * (ps_norm / chi_n - 1.0));
                 s_scal[3] = sg;
                 if (!(sg > 0.0 && sg < INFINITY)) s_flag[0] |= 2;
+                // (every read of the old p_sigma and sigma precedes the y_w flag)
+                *S.h_sigma = s_scal[1];
+                *S.sigma = sg;
             }
         }
     } else if (worker) {
@@ -1270,14 +1270,12 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             S.L[e] = s_L[e];
         }
     }
-    // the rest of the state: p_sigma, sigma, h_sigma, generation, flags
-    if (tid < n) S.p_sigma[tid] = s_ps[tid];
+    // the rest of the state (p_sigma, sigma and h_sigma are written by wave 0):
+    // generation, flags
     if (tid == 0) {
-        *S.h_sigma = h_sigma;
-        *S.sigma = s_scal[3];
         S.hdr->gen = gen + 1;
+        S.hdr->flags = ((s_flag[0] | s_flag[1]) & 1) | (s_flag[0] & 2) | (s_wbar[2] ? 4 : 0);
     }
-    if (tid == 0) S.hdr->flags = ((s_flag[0] | s_flag[1]) & 1) | (s_flag[0] & 2) | (s_wbar[2] ? 4 : 0);
     if (!ASK) return;
 
     // 6. (tell-ask form) the next generation: the same draws and arithmetic as
