@@ -89,8 +89,10 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": f"bench.py measures the single-GPU path only; --gpus {args.gpus} "
-                                   f"(WORLD_SIZE {world}) is not supported by this build. How the path would "
-                                   "shard over several GPUs is described in DESIGN.md."}))
+                                   f"(WORLD_SIZE {world}) is not supported. Across GPUs a generation would "
+                                   "shard by candidates, every GPU drawing its own slice from the counter-based "
+                                   "generator, with one all-gather of the per-candidate counts before the "
+                                   "identical update on every GPU."}))
         sys.exit(2)
 
     import torch
@@ -319,7 +321,7 @@ def main():
     # triangle set-up, 3 edge functions x 8 operations per pixel centre tested
     # inside a drawn triangle's clamped box
     ops = 25.0 * vert_all + 40.0 * tri_all + 24.0 * box_px
-    # the finer count of the design doc: 22 per vertex, 10 per triangle cull test,
+    # a finer count: 22 per vertex, 10 per triangle cull test,
     # 40 per kept triangle set-up, 5 per tested pixel centre
     ops_fine = 22.0 * vert_all + 10.0 * tri_all + 40.0 * kept + 5.0 * box_px
     peak_ops = 256 * 64 * 2.4e9
