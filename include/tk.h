@@ -438,6 +438,16 @@ tk_status tk_adam_reset(void* d_adam, int32_t n, tk_stream s);
 tk_status tk_cmaes_adam(void* d_state, int32_t n, int32_t lambda, const float* d_grad_theta, void* d_adam,
                         double lr, double beta1, double beta2, double eps, tk_stream s);
 
+/* One refinement step in one launch: when d_grad_theta is not NULL, the Adam
+ * step of tk_cmaes_adam (same arithmetic, d_adam required); then the mean as
+ * an FP32 candidate (tk_cmaes_mean_candidate) into d_X [9 n_arms] and, when
+ * d_link_xf is not NULL, its link transforms [n_arms][4][12]
+ * (tk_fk_transform of that candidate; chains: host [n_arms]).  n must be
+ * 9 n_arms.  Bit-identical to the separate calls in that order. */
+tk_status tk_cmaes_adam_transform(void* d_state, int32_t n, int32_t lambda, const float* d_grad_theta,
+                                  void* d_adam, double lr, double beta1, double beta2, double eps, int32_t n_arms,
+                                  const tk_chain* chains, float* d_X, float* d_link_xf, tk_stream s);
+
 /* ------------------------------------------------------- temporal filter */
 
 /* Constant-velocity Kalman filter of the per-frame estimates (Sec. III-A.4,

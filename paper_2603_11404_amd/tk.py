@@ -83,7 +83,7 @@ EXPORTS = [
     "tk_batch_table_bytes", "tk_batch_describe", "tk_batch_ask_eval", "tk_batch_tell",
     "tk_kf_state_bytes", "tk_kf_init", "tk_kf_step", "tk_cmaes_estimate",
     "tk_soft_workspace_bytes", "tk_soft_forward", "tk_soft_backward", "tk_cmaes_mean_candidate", "tk_adam_reset",
-    "tk_cmaes_adam", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order", "tk_bench_copy",
+    "tk_cmaes_adam", "tk_cmaes_adam_transform", "tk_mesh_chunk_order", "tk_mesh_closed", "tk_mesh_plane_order", "tk_bench_copy",
     "tk_bench_lds", "tk_batch_ask_eval_persistent",
 ]
 
@@ -145,6 +145,7 @@ def lib():
         L.tk_cmaes_mean_candidate.argtypes = [P, i32, i32, P, P]
         L.tk_adam_reset.argtypes = [P, i32, P]
         L.tk_cmaes_adam.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, P]
+        L.tk_cmaes_adam_transform.argtypes = [P, i32, i32, P, P, f64, f64, f64, f64, i32, P, P, P, P]
         L.tk_mesh_chunk_order.argtypes = [P, i32, P, i32, P]
         L.tk_mesh_closed.argtypes = [P, i32, i32, P]
         L.tk_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
@@ -553,6 +554,14 @@ def adam_reset(adam, n, stream=None):
 def cmaes_adam(state, n, lam, grad_theta, adam, lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().tk_cmaes_adam(_ptr(state), n, lam, _ptr(grad_theta), _ptr(adam), float(lr), float(beta1),
                                float(beta2), float(eps), _stream(stream)))
+
+
+def cmaes_adam_transform(state, n, lam, grad_theta, adam, chains, X, link_xf=None, lr=0.1, beta1=0.9,
+                         beta2=0.999, eps=1e-8, stream=None):
+    ch = (Chain * len(chains))(*[chain(c) for c in chains])
+    _check(lib().tk_cmaes_adam_transform(_ptr(state), n, lam, _ptr(grad_theta), _ptr(adam), float(lr), float(beta1),
+                                         float(beta2), float(eps), len(chains), ch, _ptr(X), _ptr(link_xf),
+                                         _stream(stream)))
 
 
 def raster_silhouette(link_xf, batch, meshes, cam, masks, ws=None, stream=None):

@@ -154,8 +154,10 @@ class Generation:
         steps (Kingma and Ba defaults, learning rate lr in the normalised
         space, moments restarted for every call) on the soft-silhouette loss
         of the mean, each one tk_cmaes_mean_candidate -> tk_fk_transform ->
-        tk_soft_forward -> tk_soft_backward -> tk_cmaes_adam.  Returns the
-        device FP64 loss of the last evaluated mean."""
+        tk_soft_forward -> tk_soft_backward -> tk_cmaes_adam, with each Adam
+        step and the next mean candidate and its transforms in one launch
+        (tk_cmaes_adam_transform).  Returns the device FP64 loss of the last
+        evaluated mean."""
         p = self.p
         if getattr(self, "_soft", None) is None or self._soft[0] != sigma:
             d = p.device
@@ -167,11 +169,13 @@ class Generation:
                           tk.adam_alloc(self.n, d))
         _, ws, X1, xf1, loss1, g1, adam = self._soft
         tk.adam_reset(adam, self.n)
-        for _ in range(steps):
-            tk.cmaes_mean_candidate(self.state, self.n, self.lam, X1)
-            tk.fk_transform(X1, 1, p.n_arms, p.chains, xf1)
+        # each launch takes the previous step's Adam step (none before the
+        # first) and forms the next mean candidate and its transforms
+        for k in range(steps):
+            tk.cmaes_adam_transform(self.state, self.n, self.lam, g1 if k > 0 else None, adam, p.chains, X1, xf1, lr)
             tk.soft_forward(xf1, 1, p.soft_meshes, p.cam, sigma, p.target, loss1, ws)
             tk.soft_backward(X1, 1, p.chains, p.soft_meshes, p.cam, sigma, g1, ws)
+        if steps > 0:
             tk.cmaes_adam(self.state, self.n, self.lam, g1, adam, lr)
         return loss1
 

@@ -163,6 +163,41 @@ def test_cmaes_adam_matches_the_update_formula():
     np.testing.assert_array_equal(X.cpu().numpy(), (offset + scale * got).astype(np.float32))
 
 
+@pytest.mark.parametrize("n_arms", [1, 2])
+def test_adam_transform_equals_the_separate_calls(n_arms):
+    """tk_cmaes_adam_transform (the optional Adam step, the mean candidate and
+    its link transforms in one launch) against tk_cmaes_adam,
+    tk_cmaes_mean_candidate and tk_fk_transform, bit for bit, over several
+    steps, one and two arms."""
+    dev = torch.device("cuda:0")
+    n, lam = 9 * n_arms, 16
+    rng = np.random.default_rng(6 + n_arms)
+    chains = [scenes.chain(), scenes.chain(jaw_scale=1.3)][:n_arms]
+    offset = np.tile(scenes.true_pose(rng, scenes.camera(640, 480)), n_arms)
+    scale = np.tile(scenes.DEFAULT_SCALE, n_arms)
+    mean0 = rng.normal(size=n)
+    st = [tk.cmaes_alloc(n, lam, dev) for _ in range(2)]
+    ad = [tk.adam_alloc(n, dev) for _ in range(2)]
+    for s_, a_ in zip(st, ad):
+        tk.cmaes_init(s_, n, lam, mean0, 1.0, offset, scale, 3, n_blocks=n_arms)
+        tk.adam_reset(a_, n)
+    X = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(2)]
+    xf = [torch.empty(n_arms, 4, 12, dtype=torch.float32, device=dev) for _ in range(2)]
+    for k in range(5):
+        g = torch.as_tensor(rng.normal(size=n).astype(np.float32), device=dev) if k > 0 else None
+        tk.cmaes_adam_transform(st[0], n, lam, g, ad[0], chains, X[0], xf[0])
+        if g is not None:
+            tk.cmaes_adam(st[1], n, lam, g, ad[1])
+        tk.cmaes_mean_candidate(st[1], n, lam, X[1])
+        tk.fk_transform(X[1], 1, n_arms, chains, xf[1])
+        torch.cuda.synchronize()
+        assert torch.equal(X[0], X[1]), k
+        assert torch.equal(xf[0].view(torch.int32), xf[1].view(torch.int32)), k
+        assert torch.equal(ad[0].view(torch.int64), ad[1].view(torch.int64)), k
+        v0, v1 = tk.cmaes_view(st[0], n, lam), tk.cmaes_view(st[1], n, lam)
+        assert np.array_equal(np.asarray(v0["mean"]).view(np.int64), np.asarray(v1["mean"]).view(np.int64)), k
+
+
 def test_refinement_lowers_the_soft_loss():
     dev = torch.device("cuda:0")
     wl = scenes.workload("small")
