@@ -44,18 +44,21 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------- vertex transform
 
 // FP32 transform p = M [v; 1], pinhole projection and Q8 snap (round half to
-// even).  Returns false when the vertex is culled (Z < z_near or NaN).  The
-// perspective divide is one hardware reciprocal (1 ulp) and two products:
-// within 3 ulp of the quotients, far inside the FP32 bound of the transform.
+// even).  Returns false when the vertex is culled (Z < z_near or NaN).  Every
+// form of the raster path calls this one function, so they snap identically.
+// The transform rows are three explicit fused multiply-adds each, and the
+// perspective divide is one hardware reciprocal (1 ulp) and two products,
+// within 3 ulp of the quotients: all far inside the FP32 bound of the
+// transform.
 __device__ __forceinline__ bool project_snap(const float* __restrict__ M, float vx, float vy, float vz,
                                              const CamK& cam, int32_t& X, int32_t& Y) {
 #pragma clang fp contract(off)
-    const float px = ((M[0] * vx + M[1] * vy) + M[2] * vz) + M[3];
-    const float py = ((M[4] * vx + M[5] * vy) + M[6] * vz) + M[7];
-    const float pz = ((M[8] * vx + M[9] * vy) + M[10] * vz) + M[11];
+    const float px = fmaf(M[0], vx, fmaf(M[1], vy, fmaf(M[2], vz, M[3])));
+    const float py = fmaf(M[4], vx, fmaf(M[5], vy, fmaf(M[6], vz, M[7])));
+    const float pz = fmaf(M[8], vx, fmaf(M[9], vy, fmaf(M[10], vz, M[11])));
     const float rz = __builtin_amdgcn_rcpf(pz);
-    float u = cam.fx * (px * rz) + cam.cx;
-    float v = cam.fy * (py * rz) + cam.cy;
+    float u = fmaf(cam.fx, px * rz, cam.cx);
+    float v = fmaf(cam.fy, py * rz, cam.cy);
     const bool ok = (pz >= cam.z_near) && (u == u) && (v == v);
     u = fminf(fmaxf(u, -32768.0f), 32768.0f);
     v = fminf(fmaxf(v, -32768.0f), 32768.0f);
