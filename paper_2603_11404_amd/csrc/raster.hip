@@ -811,16 +811,46 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b, un
         // transform, project and snap every vertex of this candidate once into the workspace
         int2* out = reinterpret_cast<int2*>(const_cast<int32_t*>(a.snapped)) + size_t(b) * TV;
         int culled = 0;   // bit m: one of this lane's vertices of mesh m failed the near plane
-        for (int gv = tid; gv < TV; gv += NT) {
-            const bool second = two && gv >= m1.vertex_offset;
-            const int v = gv - (second ? m1.vertex_offset : m0.vertex_offset);
-            const float* p = (second ? m1.vertices : m0.vertices) + size_t(v) * 3;
-            // the link transforms in s_M: 48 floats per mesh, 12 per link
-            const int off = (second ? 48 : 0) + 12 * int((second ? m1.vertex_link : m0.vertex_link)[v]);
-            int32_t X, Y;
-            const bool ok = project_snap(s_M + off, p[0], p[1], p[2], cam, X, Y);
-            culled |= ok ? 0 : (second ? 2 : 1);
-            out[gv] = make_int2(X, Y);
+        // each lane's next vertex and link index are loaded (from a clamped,
+        // valid index, with no branch) while it projects the current one
+        struct VtxIn {
+            float x, y, z;
+            int off;      // the link transform in s_M: 48 floats per mesh, 12 per link
+            bool second;
+        };
+        auto load_vtx = [&](int gv) {
+            const int g = min(gv, TV - 1);
+            VtxIn r;
+            r.second = two && g >= m1.vertex_offset;
+            const int v = g - (r.second ? m1.vertex_offset : m0.vertex_offset);
+            const float* p = (r.second ? m1.vertices : m0.vertices) + size_t(v) * 3;
+            r.x = p[0];
+            r.y = p[1];
+            r.z = p[2];
+            r.off = (r.second ? 48 : 0) + 12 * int((r.second ? m1.vertex_link : m0.vertex_link)[v]);
+            return r;
+        };
+        if (!two) {
+            // one mesh: uniform bases, the vertex index is the lane's own
+            const float* __restrict__ V = m0.vertices;
+            const uint8_t* __restrict__ Lk = m0.vertex_link;
+            for (int gv = tid; gv < TV; gv += NT) {
+                int32_t X, Y;
+                const bool ok = project_snap(s_M + 12 * int(Lk[gv]), V[3 * gv], V[3 * gv + 1], V[3 * gv + 2], cam,
+                                             X, Y);
+                culled |= ok ? 0 : 1;
+                out[gv] = make_int2(X, Y);
+            }
+        } else {
+            VtxIn cur = load_vtx(tid);
+            for (int gv = tid; gv < TV; gv += NT) {
+                const VtxIn nxt = load_vtx(gv + NT);
+                int32_t X, Y;
+                const bool ok = project_snap(s_M + cur.off, cur.x, cur.y, cur.z, cam, X, Y);
+                culled |= ok ? 0 : (cur.second ? 2 : 1);
+                out[gv] = make_int2(X, Y);
+                cur = nxt;
+            }
         }
         const unsigned long long c0 = __ballot(culled & 1), c1 = __ballot(culled & 2);
         if (lane == 0 && (c0 | c1)) atomicOr(&s_ctl[1], (c0 ? 1 : 0) | (c1 ? 2 : 0));
