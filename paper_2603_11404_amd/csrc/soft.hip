@@ -22,8 +22,7 @@
 // 8x8-pixel tiles (LDS counters; a face covering more than 32 tiles goes to a
 // per-candidate list that every tile scans); one wave per tile sums the logs
 // of its pixels over the tile's faces in 64-bit fixed point (2^-32), so the
-// order of the lists does not change a bit of the result; the wave that
-// finishes a candidate's last tile sums the tile losses in a fixed order.
+// order of the lists does not change a bit of the result.
 // Backward (face-major): one lane per face walks the pixels of its band,
 // accumulates dL/d(corner) from G, projects it through the pinhole Jacobian
 // into dL/dM_l (the 3x4 link transforms), reduced per workgroup in a fixed
@@ -63,8 +62,8 @@ struct FaceRec {              // 48 bytes
 static_assert(sizeof(FaceRec) == 48, "face record is 48 bytes");
 
 struct SoftLayout {
-    size_t verts, faces, tile_off, tile_cnt, tile_tot, chunks, chunk_n, facc, done, lists, big, big_n, G, tloss,
-        tiles_fin, part, gsum, total;
+    size_t verts, faces, tile_off, tile_cnt, tile_tot, chunks, chunk_n, facc, done, lists, big, big_n, G, tloss, part,
+        gsum, total;
     int32_t tiles_x, tiles_y, n_tiles, n_blocks, chunk_cap, fwd_chunk;
 };
 
@@ -91,7 +90,6 @@ struct SoftArgs {
     int32_t* big_n;       // [batch]
     float* G;             // [batch][H * W]
     double* tloss;        // [batch][n_tiles]
-    int32_t* tiles_fin;   // [batch] tiles finished by the forward pass
     float* part;          // [batch][n_blocks][kSoftGrad]
     double* gsum;         // [batch][kSoftReduceGroups][kMaxArms][kSoftGrad] sums of slices of the partials
 };
@@ -130,7 +128,6 @@ SoftLayout soft_layout(int32_t batch, const MeshSet& ms, int32_t total_faces, in
     L.big_n = take(B * sizeof(int32_t));
     L.G = take(B * size_t(W) * size_t(H) * sizeof(float));
     L.tloss = take(B * size_t(L.n_tiles) * sizeof(double));
-    L.tiles_fin = take(B * sizeof(int32_t));
     L.part = take(B * size_t(L.n_blocks) * kSoftGrad * sizeof(float));
     L.gsum = take(B * kSoftReduceGroups * kMaxArms * kSoftGrad * sizeof(double));
     L.total = o;
@@ -448,7 +445,6 @@ __global__ __launch_bounds__(kSoftBinThreads) void soft_plan_kernel(SoftArgs a, 
     if (tid == kSoftBinThreads - 1) {
         if (from_totals) off[nt] = s_c[tid];
         a.chunk_n[b] = s_k[tid];
-        a.tiles_fin[b] = 0;
     }
 }
 
@@ -501,8 +497,7 @@ __global__ __launch_bounds__(64, 8) void soft_fwd_kernel(SoftArgs a, const FaceR
                                                      const int32_t* __restrict__ off_all,
                                                      const int2* __restrict__ items_all,
                                                      const int32_t* __restrict__ big_all,
-                                                     const uint64_t* __restrict__ target, float* __restrict__ S_out,
-                                                     double* __restrict__ loss) {
+                                                     const uint64_t* __restrict__ target, float* __restrict__ S_out) {
     const int b = blockIdx.y;
     const int lane = threadIdx.x;
     const FaceRec* __restrict__ faces = faces_all + size_t(b) * a.total_faces;
@@ -512,7 +507,6 @@ __global__ __launch_bounds__(64, 8) void soft_fwd_kernel(SoftArgs a, const FaceR
     const int32_t n_items = a.chunk_n[b];
     const int32_t nb = a.big_n[b];
     const int32_t* __restrict__ big = big_all + size_t(b) * a.total_faces;
-    bool last_tile = false;   // (lane 0) this wave finished the candidate's last tile
     for (int32_t c = blockIdx.x; c < n_items; c += gridDim.x) {
         const int2 it = items[c];
         const int t = it.x, k = it.y;
@@ -545,24 +539,23 @@ __global__ __launch_bounds__(64, 8) void soft_fwd_kernel(SoftArgs a, const FaceR
                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             }
         }
-        if (finish) {
-            fwd_finish(a, target, S_out, b, t, lane, acc);
-            __threadfence();
-            if (lane == 0) last_tile |= atomicAdd(&a.tiles_fin[b], 1) == a.n_tiles - 1;
-        }
+        if (finish) fwd_finish(a, target, S_out, b, t, lane, acc);
     }
-    // the wave that finished the candidate's last tile sums the tile losses in
-    // a fixed order: lane l over tiles l, l + 64, ..., then a butterfly (lane
-    // 0's sum is used)
-    if (__shfl(last_tile ? 1 : 0, 0) != 0) {
-        __threadfence();
-        const double* tl = a.tloss + size_t(b) * a.n_tiles;
-        double sum = 0.0;
-        for (int u = lane; u < a.n_tiles; u += 64)
-            sum += __hip_atomic_load(tl + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-        if (lane == 0) loss[b] = sum;
+}
+
+__global__ __launch_bounds__(256) void soft_loss_kernel(SoftArgs a, double* __restrict__ loss) {
+    __shared__ double s[256];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const double* tl = a.tloss + size_t(b) * a.n_tiles;
+    double acc = 0.0;
+    for (int t = tid; t < a.n_tiles; t += 256) acc += tl[t];
+    s[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
     }
+    if (tid == 0) loss[b] = s[0];
 }
 
 // ---------------------------------------------------------------- backward kernels
@@ -888,7 +881,6 @@ tk_status make_soft_args(int32_t batch, const tk_mesh* meshes, int32_t n_meshes,
     a->big_n = reinterpret_cast<int32_t*>(w + L->big_n);
     a->G = reinterpret_cast<float*>(w + L->G);
     a->tloss = reinterpret_cast<double*>(w + L->tloss);
-    a->tiles_fin = reinterpret_cast<int32_t*>(w + L->tiles_fin);
     a->part = reinterpret_cast<float*>(w + L->part);
     a->gsum = reinterpret_cast<double*>(w + L->gsum);
     return TK_OK;
@@ -935,7 +927,8 @@ tk_status tk_soft_forward(const float* d_link_xf, int32_t batch, const tk_mesh* 
     // tiles), looping when a candidate has more items than the grid
     const int fwd_groups = std::min(a.chunk_cap, 2 * a.n_tiles);
     hipLaunchKernelGGL(soft_fwd_kernel, dim3(fwd_groups, batch), dim3(64), 0, st, a, a.faces, a.lists, a.tile_off,
-                       a.chunks, a.big, d_target, d_S, d_loss);
+                       a.chunks, a.big, d_target, d_S);
+    hipLaunchKernelGGL(soft_loss_kernel, dim3(batch), dim3(256), 0, st, a, d_loss);
     return check_launch("tk_soft_forward");
 }
 
