@@ -40,14 +40,14 @@ sys.path.insert(0, ROOT)
 #     the LDS occupancy expressed as bytes at the microbenchmark's rate;
 #   lds_insts, lds_bank_conflict_frac: SQ_INSTS_LDS per launch and
 #     SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.
-RASTER_TRAFFIC = {"bytes_per_launch": 44462505.1, "read_bytes": 23711544.3, "write_bytes": 20750960.8,
-                  "valu_busy": 0.904,
-                  "lds_equiv_bytes": 605250199.0, "lds_insts": 751416.0, "lds_bank_conflict_frac": 0.235,
+RASTER_TRAFFIC = {"bytes_per_launch": 44468864.7, "read_bytes": 23717903.9, "write_bytes": 20750960.8,
+                  "valu_busy": 0.890,
+                  "lds_equiv_bytes": 600908217.0, "lds_insts": 745700.0, "lds_bank_conflict_frac": 0.236,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
                               "paper_2603_11404_amd/csrc/sample_device.h"),
-                  "sha256": "6882bdc5319c4eb65b3afd83b6e59e8f9f825a36186188ed70a6c788ddfab29c"}
+                  "sha256": "398a03633cffdd73a694257024a4baa4d58466cc9ee967877670c5f04e37c6c0"}
 
 
 def raster_profile_valid():
