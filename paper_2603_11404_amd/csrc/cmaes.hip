@@ -161,6 +161,7 @@ __global__ __launch_bounds__(64) void cmaes_sample_kernel(void* blob, int n, int
 
 constexpr int kWave64 = 64;
 constexpr int kMaxSweeps = 30;
+constexpr double kRotTol2 = 1e-26;      // Jacobi rotation threshold on a_pq^2 / |a_pp a_qq|
 static_assert(kMaxSweeps % 2 == 0, "the Jacobi rounds run in pairs");
 
 // Orders this wave's LDS writes before its later LDS reads (single-wave phases).
@@ -183,8 +184,11 @@ __device__ __forceinline__ void wave_sync() {
 //   t = 2 a_pq sign(d) / (|d| + sqrt(d^2 + 4 a_pq^2)),  d = a_qq - a_pp.
 // Written without a division: with w = |d| + sqrt(d^2 + 4 a_pq^2),
 // c = w / sqrt(w^2 + 4 a_pq^2) and s = 2 a_pq sign(d) / sqrt(w^2 + 4 a_pq^2).
-// The pair is rotated only when a_pq^2 > 1e-30 |a_pp a_qq|, i.e. when
-// |a_pq| exceeds 1e-15 sqrt(|a_pp a_qq|); otherwise (c, s) = (1, 0).
+// The pair is rotated only when a_pq^2 > kRotTol2 |a_pp a_qq|, i.e. when
+// |a_pq| exceeds 1e-13 sqrt(|a_pp a_qq|); otherwise (c, s) = (1, 0).  A
+// smaller threshold only polishes entries already far below what the
+// conjugate path and the reconstruction B D^2 B^T = C resolve (about a round
+// more on average at n = 9).
 __device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq, bool paired, double* c_out,
                                               double* sn_out) {
     const double d = aqq - app;
@@ -202,7 +206,7 @@ __device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq
     t = t * fma(hy * t, t, 1.5);
     const double c = w * t;
     const double sn = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * t;
-    const bool rot = paired && apq != 0.0 && p2 > 1e-30 * fabs(app * aqq);
+    const bool rot = paired && apq != 0.0 && p2 > kRotTol2 * fabs(app * aqq);
     *c_out = rot ? c : 1.0;
     *sn_out = rot ? sn : 0.0;
     return rot;
@@ -233,7 +237,7 @@ __device__ __forceinline__ void pair_rotation2(const double app_[2], const doubl
     double sgn[2];
 #pragma unroll
     for (int k = 0; k < 2; k++) {
-        rot[k] = apq[k] != 0.0 && p2[k] > 1e-30 * fabs(app[k] * aqq[k]);
+        rot[k] = apq[k] != 0.0 && p2[k] > kRotTol2 * fabs(app[k] * aqq[k]);
         sgn[k] = d[k] >= 0.0 ? 2.0 * apq[k] : -2.0 * apq[k];
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -460,6 +464,21 @@ __device__ __forceinline__ void wave_group_barrier(int* bar, int n_waves) {
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Arrival at a wave_group_barrier phase without waiting for it: the wave's
+// LDS writes are released to the waves that wait, and the last wave to
+// arrive, waiting or not, opens the barrier.
+__device__ __forceinline__ void wave_group_arrive(int* bar, int n_waves) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & (kWave64 - 1)) == 0) {
+        const int g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == n_waves - 1) {
+            __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Covariance update of the upper-triangle entries e = tid0, tid0 + stride, ...
@@ -950,7 +969,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                     if (sl == 0 || sl < na_slots) {   // slot 0 always holds an entry (n >= 1)
                         const double2 row = a_ei[sl] ? blk0[sl] : blk1[sl];
                         const double aij = a_ej[sl] ? row.x : row.y;
-                        open |= a_off[sl] && aij * aij > 1e-30 * fabs(di[sl] * dj[sl]);
+                        open |= a_off[sl] && aij * aij > kRotTol2 * fabs(di[sl] * dj[sl]);
                     }
                 }
                 return __ballot(open) == 0ull;
@@ -1028,21 +1047,37 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
             // (B^T y_w)_l = sum_i V(i, pos l) y_w,i over the rows i of l's block;
             // (B t)_l = sum_j V(l, pos j) t_j over the indices j of l's block (the
             // other blocks' terms of the full sums are exact zeros)
+            double t_l = 0.0;
             if (lane < n) {
                 double acc = 0.0;
     #pragma unroll
                 for (int i = 0; i < NMAX; i++)
                     if (i < nb) acc += vcol[i] * s_yw[lb * nb + i];
-                s_t[lane] = acc / d_l;
+                t_l = acc / d_l;
             }
-            wave_sync();
-            double ps_l = 0.0;
-            if (lane < n) {
-                double acc = 0.0;
+            double bt = 0.0;
+            if (n_blocks == 1) {
+                // one block: t_j is lane j's value, read with readlane (no LDS round trip)
+                const uint64_t tb = static_cast<uint64_t>(__double_as_longlong(t_l));
+                const int t_lo = int(uint32_t(tb)), t_hi = int(uint32_t(tb >> 32));
+    #pragma unroll
+                for (int j = 0; j < NMAX; j++) {
+                    if (j < nb) {
+                        const uint64_t w = (uint64_t(uint32_t(__builtin_amdgcn_readlane(t_hi, j))) << 32) |
+                                           uint32_t(__builtin_amdgcn_readlane(t_lo, j));
+                        bt += vrow[j] * __longlong_as_double(static_cast<long long>(w));
+                    }
+                }
+            } else {
+                if (lane < n) s_t[lane] = t_l;
+                wave_sync();
     #pragma unroll
                 for (int j = 0; j < NMAX; j++)
-                    if (j < nb) acc += vrow[j] * s_t[lb * nb + j];
-                ps_l = (1.0 - cs) * s_ps[lane] + ps_gain * acc;
+                    if (j < nb) bt += vrow[j] * s_t[lb * nb + j];
+            }
+            double ps_l = 0.0;
+            if (lane < n) {
+                ps_l = (1.0 - cs) * s_ps[lane] + ps_gain * bt;
                 S.p_sigma[lane] = ps_l;
             }
             // ||p_sigma||^2 by a fixed butterfly over the lanes
@@ -1199,7 +1234,11 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
         //    while the other workers draw the next generation's z
         covariance_entries(wk, NWK, n, nb, ntri, 1.0 - c1 - cmu * s_scal[2], c1, cmu, 0.0, s_pc1, s_C, s_partc,
                            s_Cn);
-        wave_group_barrier(s_wbar, NWW);
+        // worker wave 0 (the factor) waits for every entry; the others go on at once
+        if (wi == 0)
+            wave_group_barrier(s_wbar, NWW);
+        else
+            wave_group_arrive(s_wbar, NWW);
         if (wi == 0) {
             const bool fl = wave_cholesky<CS>(s_Cn, s_Cw, s_L, n, nb, lane);
             if (lane == 0) s_flag[1] = fl ? 1 : 0;
@@ -1243,6 +1282,7 @@ __device__ __forceinline__ void update_body(void* blob, const int n, const int l
                     S.B[e] = v;
                 }
                 if (lane < n) S.D[lane] = s_D[lane];
+                if (kDrawZ) draw_z(false);           // the draws left, if any
             }
         }
     } else if (kDrawZ) {
