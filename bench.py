@@ -40,14 +40,14 @@ sys.path.insert(0, ROOT)
 #     the LDS occupancy expressed as bytes at the microbenchmark's rate;
 #   lds_insts, lds_bank_conflict_frac: SQ_INSTS_LDS per launch and
 #     SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.
-RASTER_TRAFFIC = {"bytes_per_launch": 44468864.7, "read_bytes": 23717903.9, "write_bytes": 20750960.8,
-                  "valu_busy": 0.890,
-                  "lds_equiv_bytes": 600908217.0, "lds_insts": 745700.0, "lds_bank_conflict_frac": 0.236,
+RASTER_TRAFFIC = {"bytes_per_launch": 44451646.7, "read_bytes": 23700696.3, "write_bytes": 20750950.4,
+                  "valu_busy": 0.879,
+                  "lds_equiv_bytes": 600922009.4, "lds_insts": 745709.7, "lds_bank_conflict_frac": 0.236,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
                               "paper_2603_11404_amd/csrc/sample_device.h"),
-                  "sha256": "398a03633cffdd73a694257024a4baa4d58466cc9ee967877670c5f04e37c6c0"}
+                  "sha256": "1ee8f9d12dbb8c25ed15b66ced88cb756eb2384d997a71ba6ec1a85cc275951b"}
 
 
 def raster_profile_valid():

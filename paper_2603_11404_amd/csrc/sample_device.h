@@ -34,22 +34,25 @@ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 }
 
 // Box-Muller: radius sqrt(-2 ln u1) and angle 2 pi u2 from two 32-bit words
-// mapped to the open interval (0, 1).
+// mapped to the open interval (0, 1).  The angle is taken in half turns,
+// 2 u2 (exact), through sincospi: the cosine and sine of 2 pi u2 without
+// rounding that product, and with a trivial argument reduction.
 __device__ inline double bm_radius(uint32_t a) {
     const double u1 = (double(a) + 0.5) * 0x1p-32;
     return sqrt(-2.0 * log(u1));
 }
 
-__device__ inline double bm_angle(uint32_t b) {
+__device__ inline double bm_half_turns(uint32_t b) {
     const double u2 = (double(b) + 0.5) * 0x1p-32;
-    return (2.0 * kPi) * u2;
+    return 2.0 * u2;
 }
 
 __device__ inline void box_muller(uint32_t a, uint32_t b, double* z0, double* z1) {
     const double r = bm_radius(a);
-    const double t = bm_angle(b);
-    *z0 = r * cos(t);
-    *z1 = r * sin(t);
+    double s, c;
+    sincospi(bm_half_turns(b), &s, &c);
+    *z0 = r * c;
+    *z1 = r * s;
 }
 
 // Normals 4j + 2h, 4j + 2h + 1 (h = 0, 1) of candidate k in generation g:
@@ -80,9 +83,10 @@ __device__ inline void draw_normals_first(uint32_t key0, uint32_t key1, uint32_t
     for (int h = 0; h < 2; h++) {
         if (2 * h < count) {
             const double rad = bm_radius(a[h]);
-            const double t = bm_angle(b[h]);
-            z[2 * h] = rad * cos(t);
-            if (2 * h + 1 < count) z[2 * h + 1] = rad * sin(t);
+            double sn, cs;
+            sincospi(bm_half_turns(b[h]), &sn, &cs);   // the same call as box_muller: the same bits
+            z[2 * h] = rad * cs;
+            if (2 * h + 1 < count) z[2 * h + 1] = rad * sn;
         }
     }
 }
