@@ -40,14 +40,14 @@ sys.path.insert(0, ROOT)
 #     the LDS occupancy expressed as bytes at the microbenchmark's rate;
 #   lds_insts, lds_bank_conflict_frac: SQ_INSTS_LDS per launch and
 #     SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.
-RASTER_TRAFFIC = {"bytes_per_launch": 44451646.7, "read_bytes": 23700696.3, "write_bytes": 20750950.4,
-                  "valu_busy": 0.879,
-                  "lds_equiv_bytes": 600922009.4, "lds_insts": 745709.7, "lds_bank_conflict_frac": 0.236,
+RASTER_TRAFFIC = {"bytes_per_launch": 44476221.2, "read_bytes": 23725270.8, "write_bytes": 20750950.4,
+                  "valu_busy": 0.892,
+                  "lds_equiv_bytes": 600897308.7, "lds_insts": 745702.4, "lds_bank_conflict_frac": 0.236,
                   "sources": ("paper_2603_11404_amd/csrc/raster.hip",
                               "paper_2603_11404_amd/csrc/tk_internal.h",
                               "paper_2603_11404_amd/csrc/fitness_device.h",
                               "paper_2603_11404_amd/csrc/sample_device.h"),
-                  "sha256": "1ee8f9d12dbb8c25ed15b66ced88cb756eb2384d997a71ba6ec1a85cc275951b"}
+                  "sha256": "1ce4e11ede9e5a72d1fe1ea513cc2e8b9132e4a9c4c765ebea931becb9b42699"}
 
 
 def raster_profile_valid():

@@ -530,10 +530,17 @@ struct RasterArgs {
 // generation is drawn exactly as the sample kernel draws it (same generator,
 // same factor L and arithmetic), written to X and the state's Z and Y, and
 // its forward kinematics (same device function as the FK kernel) goes to the
-// LDS transforms s_M and to link_xf_out / kp.  When the state already holds
-// this generation's z (drawn by the previous update), they are read instead
-// of drawn.  scratch: >= 3.2 KB of LDS.
-__device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
+// LDS transforms s_M and to kp; the lane's coordinates are returned for
+// ask_store.  When the state already holds this generation's z (drawn by the
+// previous update), they are read instead of drawn.  scratch: >= 3.2 KB of
+// LDS.
+struct AskOut {
+    double y = 0.0, z = 0.0;   // lane < n: y and z of the candidate
+    float x = 0.0f;            // lane < n: its coordinate
+    bool drawn = false;        // z came from the state (not to be written back)
+};
+
+__device__ __forceinline__ AskOut ask_candidate(const RasterArgs& a, int b, int lane, float* s_M, char* scratch) {
     const int n = a.n;
     StateView S = state_view(a.state, n, a.lam);
     double* s_L = reinterpret_cast<double*>(scratch);              // [n][n]
@@ -638,12 +645,26 @@ __device__ __forceinline__ void ask_candidate(const RasterArgs& a, int b, int la
             fk_keypoint(M, ch, part, a.fk.cam, a.kp + (size_t(b) * n_arms + arm) * 8 + 2 * part);
         }
     }
-    wave_sync();
+    AskOut o;
+    o.y = y_l;
+    o.z = z_out;
+    o.x = x_l;
+    o.drawn = drawn;
+    return o;
+}
+
+// The candidate's global outputs (Z unless it was read, Y, X, the link
+// transforms), written by wave 0 after the workgroup barrier that publishes
+// s_M, so that the other waves do not wait while they are issued.
+__device__ __forceinline__ void ask_store(const RasterArgs& a, int b, int lane, const float* s_M, const AskOut& o) {
+    const int n = a.n;
+    StateView S = state_view(a.state, n, a.lam);
     if (lane < n) {
-        if (!drawn) S.Z[size_t(b) * n + lane] = z_out;
-        S.Y[size_t(b) * n + lane] = y_l;
-        a.X[size_t(b) * n + lane] = x_l;
+        if (!o.drawn) S.Z[size_t(b) * n + lane] = o.z;
+        S.Y[size_t(b) * n + lane] = o.y;
+        a.X[size_t(b) * n + lane] = o.x;
     }
+    const int n_arms = a.fk.n_arms;
     for (int e = lane; e < n_arms * 48; e += kWave) a.link_xf_out[size_t(b) * n_arms * 48 + e] = s_M[e];
 }
 
@@ -793,14 +814,23 @@ __device__ __forceinline__ void raster_body(const RasterArgs& a, const int b, un
         s_ctl[1] = 0;
     }
 
-    for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
-    if (a.ask) {
-        if (wave == 0) ask_candidate(a, b, lane, s_M, ql.base);   // wave 0's queues are not in use yet
-    } else if (!FROM_SNAPPED || a.pretransform) {
-        for (int i = tid; i < a.meshes.n_meshes * 48; i += NT)
-            s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
+    AskOut ao;
+    if (a.ask && NT > kWave) {
+        // wave 0 starts on the candidate at once (its queues are not in use
+        // yet); the other waves clear the mask
+        if (wave == 0) ao = ask_candidate(a, b, lane, s_M, ql.base);
+        else for (int w = tid - kWave; w < words; w += NT - kWave) s_mask[w] = 0ull;
+    } else {
+        for (int w = tid; w < words; w += NT) s_mask[w] = 0ull;
+        if (a.ask) {
+            if (wave == 0) ao = ask_candidate(a, b, lane, s_M, ql.base);
+        } else if (!FROM_SNAPPED || a.pretransform) {
+            for (int i = tid; i < a.meshes.n_meshes * 48; i += NT)
+                s_M[i] = a.link_xf[size_t(b) * a.meshes.n_meshes * 48 + i];
+        }
     }
     __syncthreads();
+    if (a.ask && wave == 0) ask_store(a, b, lane, s_M, ao);
     // the vertex indices of the wave's first two chunks
     int32_t idx_cur[3], idx_nxt[3];   // read only for chunks < C
     if (C > 0) {   // no triangles at all: nothing to load
